@@ -1,0 +1,131 @@
+"""Seeded, synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module holds problem *parameters* and random *input vectors* only.  It contains
+none of the method's arithmetic (no mesh, no quadrature, no solver); both the oracle
+and the HIP path receive what it returns and compute independently.
+
+Problem family (Example 4.1 / 4.2 of the paper, generalised to 2D and to an
+anisotropic harmonic potential): find (lambda, u) with
+
+    -Laplace(u) + W u + zeta u^3 = lambda u  in  [0,1]^dim,  u = 0 on the boundary,
+    int u^2 = 1,        W(x) = sum_k w_quad[k] x_k^2 + w_const.
+
+Meshes are nested uniform meshes: level l (1-based) has n_l = n_coarse * 2^(l-1)
+cells per side; the finest level has n = n_coarse * 2^n_refine.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Problem:
+    dim: int
+    n_coarse: int
+    n_refine: int
+    w_quad: tuple = (1.0, 1.0, 1.0)
+    w_const: float = 0.0
+    zeta: float = 1.0
+
+    @property
+    def n_fine(self) -> int:
+        return self.n_coarse << self.n_refine
+
+    @property
+    def levels(self) -> int:
+        return self.n_refine + 1
+
+    def n_level(self, l: int) -> int:
+        """Cells per side on level l (1-based)."""
+        return self.n_coarse << (l - 1)
+
+    def dofs(self, l: int | None = None) -> int:
+        n = self.n_fine if l is None else self.n_level(l)
+        return (n - 1) ** self.dim
+
+
+@dataclasses.dataclass(frozen=True)
+class Options:
+    m: int = 1                 # V-cycles per correction step, (3.5)
+    p: int = 2                 # correction steps per level, Algorithm 3.2
+    nu_pre: int = 2            # symmetric Gauss-Seidel sweeps before coarse correction
+    nu_post: int = 2           # ... and after
+    tol_lambda: float = 0.0    # >0: extra finest-level steps until |dlambda|/lambda <= tol
+    max_final_steps: int = 60
+    scf_max_iter: int = 200
+    scf_tol: float = 1e-13
+    precision: str = "fp64"    # "fp64" or "mixed" (FP32 V-cycle inside FP64 refinement)
+
+
+# --- fixed workloads --------------------------------------------------------------------
+# 2D, coarsest h=1/8 refined 4x to h=1/128, W = x^2+y^2, zeta = 1, 2 correction steps
+# per level, SGS(2,2) V-cycles.
+SMALL_2D = Problem(dim=2, n_coarse=8, n_refine=4, w_quad=(1.0, 1.0, 0.0), zeta=1.0)
+# 2D, coarsest h=1/16 refined 7x to h=1/2048 (4,190,209 DOF), zeta = 100.
+LARGE_2D = Problem(dim=2, n_coarse=16, n_refine=7, w_quad=(1.0, 1.0, 0.0), zeta=100.0)
+# 3D Kuhn mesh, coarsest 4^3 refined 6x to 256^3 (16,581,375 DOF), zeta = 10.
+LARGE_3D = Problem(dim=3, n_coarse=4, n_refine=6, w_quad=(1.0, 1.0, 1.0), zeta=10.0)
+# The paper's Example 4.1 / 4.2: 3D, coarsest h = 1/8, zeta = 1 or 100.
+PAPER_EX41 = Problem(dim=3, n_coarse=8, n_refine=4, w_quad=(1.0, 1.0, 1.0), zeta=1.0)
+PAPER_EX42 = Problem(dim=3, n_coarse=8, n_refine=4, w_quad=(1.0, 1.0, 1.0), zeta=100.0)
+
+DEFAULT_OPTIONS = Options()
+
+
+def batch_instances(count: int = 64, seed: int = 0) -> list[Problem]:
+    """Uneven 2D batch: n ~ U{256,512,1024}, zeta log-uniform in [0.1, 1000],
+    W = a x^2 + b y^2 with a, b ~ U[0.5, 2], coarsest h = 1/16."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice([256, 512, 1024]))
+        zeta = float(10.0 ** rng.uniform(-1.0, 3.0))
+        a, b = (float(v) for v in rng.uniform(0.5, 2.0, size=2))
+        out.append(Problem(dim=2, n_coarse=16, n_refine=int(round(math.log2(n // 16))),
+                           w_quad=(a, b, 0.0), zeta=zeta))
+    return out
+
+
+def serving_requests(count: int, seed: int = 1, frac_2d: float = 0.7,
+                     max_2d_exp: int = 11, sizes_3d=(64, 128, 192)) -> list[Problem]:
+    """Mixed request stream: 70% 2D with n = 2^k, k ~ U{7..max_2d_exp} (coarsest 1/16);
+    30% 3D with n ~ U(sizes_3d) (coarsest 1/8, or 1/6 for 192);
+    zeta log-uniform [0.1, 1000]; W = sum a_k x_k^2, a_k ~ U[0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        zeta = float(10.0 ** rng.uniform(-1.0, 3.0))
+        if rng.uniform() < frac_2d:
+            k = int(rng.integers(7, max_2d_exp + 1))
+            a = tuple(float(v) for v in rng.uniform(0.5, 2.0, size=2)) + (0.0,)
+            out.append(Problem(dim=2, n_coarse=16, n_refine=k - 4, w_quad=a, zeta=zeta))
+        else:
+            n = int(rng.choice(list(sizes_3d)))
+            nc = 6 if n % 8 else 8
+            a = tuple(float(v) for v in rng.uniform(0.5, 2.0, size=3))
+            out.append(Problem(dim=3, n_coarse=nc, n_refine=int(round(math.log2(n // nc))),
+                               w_quad=a, zeta=zeta))
+    return out
+
+
+def random_interior(dim: int, n: int, seed: int, positive: bool = False) -> np.ndarray:
+    """Random interior nodal vector of length (n-1)^dim, x-fastest ordering."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n - 1) ** dim)
+    return np.abs(v) + 0.1 if positive else v
+
+
+def smooth_interior(dim: int, n: int, seed: int) -> np.ndarray:
+    """A smooth positive bump plus small seeded noise (an eigenfunction-like input)."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(1, n) / n
+    g = [np.sin(np.pi * t) * (1.0 + 0.2 * rng.uniform() * t) for _ in range(dim)]
+    if dim == 2:
+        v = np.outer(g[1], g[0])
+    else:
+        v = np.einsum("k,j,i->kji", g[2], g[1], g[0])
+    v = v.ravel() * 2.0
+    return v + 1e-3 * rng.standard_normal(v.size)
