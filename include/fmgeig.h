@@ -1,0 +1,216 @@
+/*
+ * fmgeig.h -- C ABI of libfmgeig.so, an MI355X (gfx950) implementation of the full
+ * multigrid method for nonlinear eigenvalue problems of Jia, Xie, Xie and Xu
+ * ("A Full Multigrid Method for Nonlinear Eigenvalue Problems", arXiv:1502.04657).
+ *
+ * Problem (Section 2, (2.1) with the Gross-Pitaevskii nonlinearity of Example 4.1):
+ *     -Laplace(u) + W u + zeta u^3 = lambda u  in [0,1]^dim,  u = 0 on the boundary,
+ *     int u^2 = 1,   W(x) = sum_k w_quad[k] x_k^2 + w_const,
+ * discretised by P1 elements on nested uniform meshes (2D: cells cut along the
+ * (i,j)-(i+1,j+1) diagonal; 3D: cubes cut into 6 Kuhn tetrahedra), level l having
+ * n_l = n_coarse * 2^(l-1) cells per side (regular refinement, (3.1)-(3.2)).
+ *
+ * Conventions for every entry point
+ *   - All functions are extern "C" and never throw.  Return 0 on success or a negative
+ *     FMG_E* code; fmg_last_error() then returns a thread-local message.
+ *   - Pointers named d_* are DEVICE pointers (hipMalloc'd or torch CUDA tensors) on the
+ *     current HIP device.  The caller owns every buffer it passes in.  The library
+ *     allocates no device memory: fmg_solve works inside the caller's workspace.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on it;
+ *     fmg_solve returns after its result is complete, the fmg_op_* calls return
+ *     after enqueueing (they are asynchronous).
+ *   - "Compact" vectors hold the interior nodal values of one level, length (n-1)^dim,
+ *     node (i,j[,k]) (1 <= i,j,k <= n-1) at index (i-1) + (n-1)((j-1) + (n-1)(k-1)).
+ *   - "Level" arrays use the library's padded layout: (n+1)^dim nodes including the
+ *     Dirichlet ring, x fastest, rows padded to fmg_level_pitch(dim, n) elements; node
+ *     (i,j[,k]) sits at i + pitch*(j + (n+1)*k).  The ring must hold zeros; kernels
+ *     never write it.  fmg_pack / fmg_unpack convert between the two layouts.
+ */
+#ifndef FMGEIG_H
+#define FMGEIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FMG_OK = 0,
+    FMG_PENDING = 1,
+    FMG_EINVAL = -1,      /* invalid argument (sizes, non-finite inputs, layout)          */
+    FMG_ENOMEM = -2,      /* workspace smaller than fmg_workspace_bytes()                 */
+    FMG_ENOCONV = -3,     /* a nonlinear solve or the tolerance loop did not converge;    */
+                          /* u_out still holds the last iterate                           */
+    FMG_ENONFINITE = -4,  /* NaN/Inf appeared in lambda or in the small systems           */
+    FMG_EHIP = -5         /* a HIP runtime call failed                                    */
+};
+
+enum { FMG_FP64 = 0, FMG_MIXED = 1 };
+
+/* The problem of Example 4.1 generalised to dim = 2, 3 and an anisotropic harmonic W.
+ * (2.1), (4.1); the mesh sequence of (3.1)-(3.2).                                      */
+typedef struct {
+    int32_t dim;          /* 2 or 3; Omega = [0,1]^dim                                    */
+    int32_t n_coarse;     /* cells per side of the coarsest mesh T_{h_1} (= T_H), >= 2    */
+    int32_t n_refine;     /* regular refinements; finest n = n_coarse * 2^n_refine        */
+    int32_t reserved;
+    double  w_quad[3];    /* W(x) = sum_k w_quad[k] x_k^2 + w_const                        */
+    double  w_const;
+    double  zeta;         /* >= 0, coefficient of u^3                                     */
+} fmg_problem;
+
+/* Algorithm 3.1 / 3.2 parameters.                                                        */
+typedef struct {
+    double  tol_lambda;   /* > 0: after the p steps of the finest level, continue          */
+                          /* correction steps until |dlambda| <= tol_lambda * lambda;     */
+                          /* 0: fixed schedule                                            */
+    int32_t m;            /* V-cycles per correction step, MG(.,.,.,m) of (3.5), >= 1      */
+    int32_t p;            /* correction steps per level (Algorithm 3.2), >= 1              */
+    int32_t nu_pre;       /* symmetric Gauss-Seidel sweeps before / after the coarse       */
+    int32_t nu_post;      /* correction of each V-cycle level                             */
+    int32_t max_final_steps; /* cap on the tolerance loop                                   */
+    int32_t newton_max_iter; /* cap per nonlinear solve (Newton iterations)                 */
+    double  newton_tol;   /* relative residual at which a Newton solve stops (e.g. 1e-13)  */
+    int32_t precision;    /* FMG_FP64, or FMG_MIXED: FP32 V-cycles inside an FP64          */
+                          /* iterative-refinement loop (residual, quadratures, Rayleigh   */
+                          /* quotient and the small eigensolves stay FP64)                */
+    int32_t reserved;
+} fmg_options;
+
+#define FMG_HISTORY_MAX 512
+
+typedef struct {
+    double  lambda;       /* final eigenvalue: the augmented-problem eigenvalue of (3.6)  */
+    double  lambda_rq;    /* a(u,u)/b(u,u) of (2.2) evaluated on the finest level         */
+    double  norm;         /* b(u,u) of the returned u (1 up to rounding)                  */
+    double  dlambda;      /* |lambda_last - lambda_previous| / lambda of the last step     */
+    int32_t status;       /* 0 or FMG_E*                                                   */
+    int32_t levels;
+    int32_t steps_total;  /* correction steps executed (all levels)                       */
+    int32_t newton_total; /* Newton iterations (coarse step + every augmented solve)      */
+    double  seconds;      /* host wall time of the call                                   */
+    int32_t history_len;  /* entries in history[]                                         */
+    int32_t reserved;
+    double  history[FMG_HISTORY_MAX]; /* lambda after the coarse step and after every      */
+                                      /* correction step, in execution order              */
+} fmg_result;
+
+const char* fmg_last_error(void);
+const char* fmg_version(void);
+
+/* ---- whole solve (Algorithm 3.2) ---------------------------------------------------- */
+
+/* Bytes of device workspace fmg_solve needs for this problem and options.  Pure function.
+ * Returns FMG_EINVAL for invalid problems/options.                                       */
+int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t* bytes);
+
+/* Full multigrid eigensolve: coarse nonlinear solve (Algorithm 3.2 step 1), then on every
+ * finer level FMG prolongation and p correction steps (Algorithm 3.1: right-hand side of
+ * (3.4), m V-cycles (3.5), augmented nonlinear eigenproblem (3.6) on V_H + span{u~}),
+ * plus the tolerance loop on the finest level when opt->tol_lambda > 0.
+ *   d_workspace : device memory of at least fmg_workspace_bytes() bytes, 256-B aligned;
+ *                 contents on entry are ignored (the call initialises what it uses).
+ *   d_u_out     : device, compact layout, u_len = (n-1)^dim; receives u_h with
+ *                 b(u,u) = 1 and int u_h > 0.
+ *   out         : host struct, filled on return (also on FMG_ENOCONV).
+ * Errors: FMG_EINVAL (dim not 2/3, n_coarse < 2, n_refine < 0 or > 12, zeta < 0 or
+ * non-finite inputs, m/p < 1, nu_pre + nu_post < 1, u_len mismatch), FMG_ENOMEM
+ * (workspace too small), FMG_ENOCONV, FMG_ENONFINITE, FMG_EHIP.                            */
+int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* d_workspace,
+              size_t workspace_bytes, void* stream, double* d_u_out, int64_t u_len,
+              fmg_result* out);
+
+/* ---- level layout -------------------------------------------------------------------- */
+int64_t fmg_level_pitch(int32_t dim, int32_t n);   /* row pitch in elements, or -1          */
+int64_t fmg_level_elems(int32_t dim, int32_t n);   /* elements of one level array, or -1    */
+
+/* compact <-> level layout (FP64).  pack writes the interior only; the caller zeroes the
+ * ring of d_level once (e.g. at allocation).                                              */
+int fmg_pack(int32_t dim, int32_t n, const double* d_compact, double* d_level, void* stream);
+int fmg_unpack(int32_t dim, int32_t n, const double* d_level, double* d_compact, void* stream);
+
+/* ---- single steps of the method (level layout; for tests and custom schedules) -------- */
+
+/* Right-hand side of the auxiliary problem (3.4) with f(x,u) = W u + zeta u^3:
+ *   b_i = lambda (M u)_i - int W u_h phi_i - zeta int u_h^3 phi_i   (exact P1 integration)
+ * on the level with n cells per side.  FP64.                                             */
+int fmg_op_rhs(const fmg_problem* prob, int32_t n, double lambda, const double* d_u,
+               double* d_b, void* stream);
+
+/* Red-black symmetric Gauss-Seidel on K x = f (K: P1 stiffness matrix of a-hat, (2.5)):
+ * `sweeps` symmetric sweeps (forward red,black then backward black,red).  precision:
+ * FMG_FP64 (double*) or FMG_MIXED meaning FP32 (float* passed as void*).                 */
+int fmg_op_smooth(int32_t dim, int32_t n, int32_t precision, void* d_x, const void* d_f,
+                  int32_t sweeps, void* stream);
+
+/* r_c = P^T (f - K x): residual of the fine level (n cells) restricted to level n/2.      */
+int fmg_op_residual_restrict(int32_t dim, int32_t n, int32_t precision, const void* d_x,
+                             const void* d_f, void* d_rc, void* stream);
+
+/* x_f (+)= P x_c, P = P1 interpolation from level n/2 to level n; accumulate 0: overwrite */
+int fmg_op_prolong(int32_t dim, int32_t n, int32_t precision, const void* d_xc, void* d_xf,
+                   int32_t accumulate, void* stream);
+
+/* Exact solve K x = f on a coarsest level with n cells per side (n <= 64).               */
+int fmg_op_coarse_solve(int32_t dim, int32_t n, int32_t precision, const void* d_f, void* d_x,
+                        void* stream);
+
+/* One V(nu_pre, nu_post)-cycle for K x = f on level n = n_coarse * 2^(levels-1), using the
+ * library's level hierarchy in d_workspace (bytes from fmg_workspace_bytes of a problem with
+ * the same dim, n_coarse and n_refine = levels-1).  FP64.                                */
+int fmg_op_vcycle(int32_t dim, int32_t n_coarse, int32_t levels, int32_t nu_pre, int32_t nu_post,
+                  double* d_x, const double* d_f, void* d_workspace, size_t workspace_bytes,
+                  void* stream);
+
+/* Fine-grid quadratures that build the augmented problem (3.6) for V_H + span{u~}:
+ * for every coarse simplex E (index (cell * S + type), cell = I + nc*(J + nc*K), S = 2 (2D)
+ * or 6 (3D) simplices per cell in the order of the mesh description above), d_out receives
+ * fmg_moments_layout().per_element doubles:
+ *   int_E u~ l_p l_q l_r (p<=q<=r), int_E u~^2 l_p l_q (p<=q), int_E u~^3 l_p, int_E u~^4,
+ *   int_E u~ l_p, int_E u~^2, int_E W u~ l_p, int_E W u~^2, int_E grad u~ . grad l_p,
+ *   int_E |grad u~|^2
+ * (l_p: barycentric coordinates of E; multisets in lexicographic order).  d_ut is a level
+ * array with n cells per side; d_scratch holds scratch_bytes of fmg_moments_layout.      */
+int fmg_moments_layout(int32_t dim, int32_t n_coarse, int32_t n, int32_t* per_element,
+                       size_t* scratch_bytes);
+int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* d_ut, double* d_out,
+                   void* d_scratch, size_t scratch_bytes, void* stream);
+
+/* Device scratch (bytes) of the small nonlinear solves on the coarsest space.             */
+int fmg_small_scratch_bytes(int32_t dim, int32_t n_coarse, size_t* bytes);
+
+/* Dense augmented matrices of (3.6) in the basis [coarse hats (compact order), u~]:
+ * A = Z^T (K + M_W) Z, B = Z^T M Z, S = Z^T M_{(Zx)^2} Z, each (N+1)x(N+1) row-major,
+ * N = (n_coarse-1)^dim, from the moments of u~ and the coefficient vector d_x (N+1).     */
+int fmg_op_augmented_matrices(const fmg_problem* prob, const double* d_moments, const double* d_x,
+                              double* d_A, double* d_B, double* d_S, void* d_scratch,
+                              size_t scratch_bytes, void* stream);
+
+/* Ground state of the augmented problem (3.6) from the moments of u~ (Newton on the
+ * bordered system).  d_xc_level: coarsest level array (ring zero) receiving x_H; returns
+ * lambda, the u~ coefficient c (u = Pi x_H + c u~), the Newton iteration count and
+ * whether the ground-state inertia check passed.  Synchronises the stream.               */
+int fmg_op_augmented_solve(const fmg_problem* prob, const fmg_options* opt, const double* d_moments,
+                           double* d_xc_level, void* d_scratch, size_t scratch_bytes, void* stream,
+                           double* lambda, double* c, int32_t* newton_iters, int32_t* ground_state);
+
+/* Ground state on the coarsest space (Algorithm 3.2 step 1): x written into d_xc_level,
+ * lambda returned.  Synchronises the stream.                                             */
+int fmg_op_coarse_nonlinear(const fmg_problem* prob, const fmg_options* opt, double* d_xc_level,
+                            void* d_scratch, size_t scratch_bytes, void* stream, double* lambda,
+                            int32_t* newton_iters, int32_t* ground_state);
+
+/* u <- c u + Pi x_H on level n (Pi: P1 interpolation from the coarsest level). FP64.      */
+int fmg_op_form_u(int32_t dim, int32_t n_coarse, int32_t n, double c, const double* d_xc_level,
+                  double* d_u, void* d_scratch, void* stream);
+
+/* (u^T K u, u^T M_W u, u^T M u, int u_h^4) of a level array; d_scratch >= 4200 doubles.  */
+int fmg_op_forms(const fmg_problem* prob, int32_t n, const double* d_u, double* out4,
+                 void* d_scratch, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMGEIG_H */

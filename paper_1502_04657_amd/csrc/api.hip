@@ -1,0 +1,467 @@
+// C ABI and host schedule of the full multigrid eigensolver (Algorithm 3.2 driving
+// Algorithm 3.1).  Every arithmetic step runs in the HIP kernels; the host only carves the
+// caller's workspace, enqueues kernels on the caller's stream and, in tolerance mode,
+// reads the device-side convergence flag between finest-level correction steps.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/fmgeig.h"
+#include "kernels.h"
+
+namespace fmg {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static Phys make_phys(const fmg_problem* p) {
+    Phys ph;
+    for (int k = 0; k < 3; ++k) ph.w[k] = (k < p->dim) ? p->w_quad[k] : 0.0;
+    ph.wc = p->w_const;
+    ph.zeta = p->zeta;
+    return ph;
+}
+
+static int check_problem(const fmg_problem* p) {
+    if (!p) return set_error(FMG_EINVAL, "problem is NULL");
+    if (p->dim != 2 && p->dim != 3) return set_error(FMG_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->n_coarse < 2) return set_error(FMG_EINVAL, "n_coarse must be >= 2 (got %d)", p->n_coarse);
+    if (p->n_refine < 0 || p->n_refine > 12) return set_error(FMG_EINVAL, "n_refine out of range (got %d)", p->n_refine);
+    if (p->dim == 2 && p->n_coarse > 32) return set_error(FMG_EINVAL, "2D n_coarse must be <= 32");
+    if (p->dim == 3 && p->n_coarse > 16) return set_error(FMG_EINVAL, "3D n_coarse must be <= 16");
+    int64_t n = (int64_t)p->n_coarse << p->n_refine;
+    if (p->dim == 2 && n > 32768) return set_error(FMG_EINVAL, "finest 2D n too large");
+    if (p->dim == 3 && n > 1024) return set_error(FMG_EINVAL, "finest 3D n too large");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->w_quad[k])) return set_error(FMG_EINVAL, "w_quad[%d] is not finite", k);
+    if (!std::isfinite(p->w_const)) return set_error(FMG_EINVAL, "w_const is not finite");
+    if (!std::isfinite(p->zeta) || p->zeta < 0.0) return set_error(FMG_EINVAL, "zeta must be finite and >= 0");
+    return 0;
+}
+
+static int check_options(const fmg_options* o) {
+    if (!o) return set_error(FMG_EINVAL, "options is NULL");
+    if (o->m < 1 || o->p < 1) return set_error(FMG_EINVAL, "m and p must be >= 1");
+    if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1)
+        return set_error(FMG_EINVAL, "nu_pre, nu_post >= 0 with nu_pre + nu_post >= 1");
+    if (!(o->tol_lambda >= 0.0) || !std::isfinite(o->tol_lambda)) return set_error(FMG_EINVAL, "tol_lambda invalid");
+    if (o->max_final_steps < 0) return set_error(FMG_EINVAL, "max_final_steps must be >= 0");
+    if (o->newton_max_iter < 1) return set_error(FMG_EINVAL, "newton_max_iter must be >= 1");
+    if (!(o->newton_tol > 0.0)) return set_error(FMG_EINVAL, "newton_tol must be > 0");
+    if (o->precision != FMG_FP64 && o->precision != FMG_MIXED) return set_error(FMG_EINVAL, "precision invalid");
+    return 0;
+}
+
+// ----------------------------------------------------------------------------------------
+// workspace layout
+struct Layout {
+    int dim, nc, L, mixed;
+    std::vector<Grid> g;
+    size_t state, xc, mom, momscr, arena, forms;
+    std::vector<size_t> u, b, xv, fv;   // per level (u[0] = xc)
+    size_t total;
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static Layout make_layout(int dim, int nc, int levels, int mixed) {
+    Layout lo;
+    lo.dim = dim; lo.nc = nc; lo.L = levels; lo.mixed = mixed;
+    for (int l = 0; l < levels; ++l) lo.g.push_back(make_grid(dim, nc << l));
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    lo.state = take(sizeof(SmallState));
+    lo.xc = take(sizeof(double) * lo.g[0].elems);
+    const size_t ts = mixed ? sizeof(float) : sizeof(double);
+    lo.u.resize(levels); lo.b.resize(levels); lo.xv.resize(levels); lo.fv.resize(levels);
+    for (int l = 0; l < levels; ++l) {
+        lo.u[l] = (l == 0) ? lo.xc : take(sizeof(double) * lo.g[l].elems);
+        lo.b[l] = take(sizeof(double) * lo.g[l].elems);
+        // V-cycle work arrays; in FP64 mode the top level uses u/b directly
+        bool top_only = !mixed && l == levels - 1;
+        lo.xv[l] = top_only ? 0 : take(ts * lo.g[l].elems);
+        lo.fv[l] = top_only ? 0 : take(ts * lo.g[l].elems);
+    }
+    const int64_t ncell = dim == 2 ? (int64_t)nc * nc : (int64_t)nc * nc * nc;
+    const int ne = dim == 2 ? 2 : 6;
+    lo.mom = take(sizeof(double) * ncell * ne * moments_per_element(dim));
+    size_t ms = 0;
+    for (int l = 1; l < levels; ++l) ms = std::max(ms, moments_scratch_bytes(dim, nc, nc << l));
+    lo.momscr = take(std::max<size_t>(ms, 256));
+    lo.arena = take(small_arena_bytes(dim, nc));
+    lo.forms = take(sizeof(double) * (kReduceBlocks * 4 + 8));
+    lo.total = off;
+    return lo;
+}
+
+template <typename T>
+static T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+// ----------------------------------------------------------------------------------------
+// V-cycle: x_l (+)= MG step for K_l x = f_l; levels below l use the workspace arrays
+template <typename T>
+static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_pre, int nu_post, hipStream_t s) {
+    const Grid& g = lo.g[l];
+    if (l == 0) {
+        launch_coarse_solve<T>(g, f, x, s);
+        return;
+    }
+    if (nu_pre > 0) launch_smooth<T>(g, x, f, 2 * nu_pre + 1, 0, s);
+    T* xc = at<T>(ws, lo.xv[l - 1]);
+    T* fc = at<T>(ws, lo.fv[l - 1]);
+    launch_resid_restrict<T>(g, lo.g[l - 1], x, f, fc, s);
+    launch_fill<T>(xc, lo.g[l - 1].elems, T(0), s);
+    vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s);
+    launch_prolong<T>(lo.g[l - 1], g, xc, x, 1, s);
+    if (nu_post > 0) launch_smooth<T>(g, x, f, 2 * nu_post + 1, 0, s);
+}
+
+// one correction step (Algorithm 3.1) on level k
+static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, const fmg_options* opt, int k,
+                           int final_flag, hipStream_t s) {
+    const Grid& g = lo.g[k];
+    const Phys ph = make_phys(prob);
+    SmallState* st = at<SmallState>(ws, lo.state);
+    double* u = at<double>(ws, lo.u[k]);
+    double* b = at<double>(ws, lo.b[k]);
+    // (3.4): right-hand side lambda u - f(x, u) in the weak form
+    launch_rhs(g, ph, u, b, &st->lambda, 0.0, s);
+    // (3.5): m multigrid iterations started from u
+    for (int j = 0; j < opt->m; ++j) {
+        if (opt->precision == FMG_MIXED) {
+            float* r = at<float>(ws, lo.fv[k]);
+            float* e = at<float>(ws, lo.xv[k]);
+            launch_residual_demote(g, u, b, r, s);
+            launch_fill<float>(e, g.elems, 0.0f, s);
+            vcycle<float>(lo, ws, k, e, r, opt->nu_pre, opt->nu_post, s);
+            launch_add_promote(g, u, e, s);
+        } else {
+            vcycle<double>(lo, ws, k, u, b, opt->nu_pre, opt->nu_post, s);
+        }
+    }
+    // (3.6): augmented nonlinear eigenproblem on V_H + span{u~}
+    double* mom = at<double>(ws, lo.mom);
+    launch_moments(lo.dim, lo.nc, g, ph, u, at<double>(ws, lo.momscr), mom, s);
+    int rc = launch_aug_newton(lo.dim, lo.nc, ph, opt->newton_max_iter, opt->newton_tol, mom, at<double>(ws, lo.arena),
+                               at<double>(ws, lo.xc), st, final_flag, s);
+    if (rc) return set_error(rc, "augmented solve launch failed");
+    launch_form_u(g, lo.g[0], u, at<double>(ws, lo.xc), &st->c, s);
+    return 0;
+}
+
+}  // namespace fmg
+
+using namespace fmg;
+
+extern "C" {
+
+const char* fmg_last_error(void) { return g_err; }
+const char* fmg_version(void) { return "fmgeig 0.1 (gfx950)"; }
+
+int64_t fmg_level_pitch(int32_t dim, int32_t n) {
+    if ((dim != 2 && dim != 3) || n < 1) return -1;
+    return make_grid(dim, n).pitch;
+}
+int64_t fmg_level_elems(int32_t dim, int32_t n) {
+    if ((dim != 2 && dim != 3) || n < 1) return -1;
+    return make_grid(dim, n).elems;
+}
+
+int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t* bytes) {
+    if (int rc = check_problem(prob)) return rc;
+    if (int rc = check_options(opt)) return rc;
+    if (!bytes) return set_error(FMG_EINVAL, "bytes is NULL");
+    Layout lo = make_layout(prob->dim, prob->n_coarse, prob->n_refine + 1, opt->precision == FMG_MIXED);
+    *bytes = lo.total;
+    return 0;
+}
+
+int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t ws_bytes, void* stream, double* u_out,
+              int64_t u_len, fmg_result* out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = check_problem(prob)) return rc;
+    if (int rc = check_options(opt)) return rc;
+    if (!out) return set_error(FMG_EINVAL, "result is NULL");
+    std::memset(out, 0, sizeof(*out));
+    const int L = prob->n_refine + 1;
+    const int64_t n = (int64_t)prob->n_coarse << prob->n_refine;
+    const int64_t want = prob->dim == 2 ? (n - 1) * (n - 1) : (n - 1) * (n - 1) * (n - 1);
+    if (u_len != want) return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len, (long long)want);
+    if (!ws || !u_out) return set_error(FMG_EINVAL, "workspace and u_out must be device pointers");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(FMG_EINVAL, "workspace must be 256-byte aligned");
+    Layout lo = make_layout(prob->dim, prob->n_coarse, L, opt->precision == FMG_MIXED);
+    if (ws_bytes < lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, lo.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Phys ph = make_phys(prob);
+
+    // initial state and zeroed level arrays (the Dirichlet rings must be zero)
+    SmallState init;
+    std::memset(&init, 0, sizeof(init));
+    init.tol_lambda = opt->tol_lambda;
+    SmallState* st = at<SmallState>(ws, lo.state);
+    FMG_HIP_CHECK(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    {
+        const size_t first = lo.xc, last = lo.mom;
+        launch_fill<double>(at<double>(ws, first), (int64_t)((last - first) / sizeof(double)), 0.0, s);
+    }
+    // Algorithm 3.2 step 1
+    int rc = launch_coarse_newton(prob->dim, prob->n_coarse, ph, opt->newton_max_iter, opt->newton_tol,
+                                  at<double>(ws, lo.arena), at<double>(ws, lo.xc), st, s);
+    if (rc) return set_error(rc, "coarse solve launch failed");
+    // Algorithm 3.2 step 2
+    for (int k = 1; k < L; ++k) {
+        launch_prolong<double>(lo.g[k - 1], lo.g[k], at<double>(ws, lo.u[k - 1]), at<double>(ws, lo.u[k]), 0, s);
+        const bool finest = (k == L - 1);
+        const bool tol_mode = finest && opt->tol_lambda > 0.0;
+        for (int step = 0; step < opt->p; ++step) {
+            int flag = tol_mode && step >= std::max(1, opt->p - 1);
+            if ((rc = correction_step(lo, ws, prob, opt, k, flag, s))) return rc;
+        }
+        if (tol_mode) {
+            SmallState h;
+            for (int extra = 0;; ++extra) {
+                FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
+                FMG_HIP_CHECK(hipStreamSynchronize(s));
+                if (h.done || h.status != 0 || extra >= opt->max_final_steps) break;
+                if ((rc = correction_step(lo, ws, prob, opt, k, 1, s))) return rc;
+            }
+        }
+    }
+    // Rayleigh quotient of the returned u on the finest level, and the output copy
+    const Grid& gf = lo.g[L - 1];
+    double* forms = at<double>(ws, lo.forms);
+    launch_forms(gf, ph, at<double>(ws, lo.u[L - 1]), forms + 8, forms, s);
+    launch_unpack(gf, at<double>(ws, lo.u[L - 1]), u_out, s);
+    SmallState h;
+    double f4[4];
+    FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
+    FMG_HIP_CHECK(hipMemcpyAsync(f4, forms, sizeof(f4), hipMemcpyDeviceToHost, s));
+    FMG_HIP_CHECK(hipStreamSynchronize(s));
+    FMG_HIP_CHECK(hipGetLastError());
+    out->lambda = h.lambda;
+    out->norm = f4[2];
+    out->lambda_rq = (f4[0] + f4[1] + prob->zeta * f4[3]) / f4[2];
+    out->dlambda = h.dlambda;
+    out->levels = L;
+    out->steps_total = h.steps;
+    out->newton_total = h.newton_total;
+    out->history_len = std::min(h.hist_len, FMG_HISTORY_MAX);
+    for (int i = 0; i < out->history_len; ++i) out->history[i] = h.hist[i];
+    int status = h.status;
+    if (!status && !std::isfinite(h.lambda)) status = FMG_ENONFINITE;
+    if (!status && h.certify_fail) status = FMG_ENOCONV;
+    if (!status && opt->tol_lambda > 0.0 && !h.done) status = FMG_ENOCONV;
+    out->status = status;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status) {
+        static const char* why[] = {"", "zero pivot", "Newton did not converge", "non-finite value",
+                                    "singular border system", "not the ground state"};
+        if (h.fail_reason)
+            return set_error(status, "status %d: %s in the nonlinear solve after history entry %d (residual %.3e)",
+                             status, why[h.fail_reason > 5 ? 0 : h.fail_reason], h.fail_step, h.fail_residual);
+        return set_error(status, "status %d: tolerance %.3e not reached in %d final steps (last dlambda %.3e)",
+                         status, opt->tol_lambda, opt->max_final_steps, h.dlambda);
+    }
+    return 0;
+}
+
+// ---- single steps ----------------------------------------------------------------------
+int fmg_pack(int32_t dim, int32_t n, const double* c, double* lv, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 2 || !c || !lv) return set_error(FMG_EINVAL, "bad pack arguments");
+    launch_pack(make_grid(dim, n), c, lv, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "pack launch failed");
+}
+int fmg_unpack(int32_t dim, int32_t n, const double* lv, double* c, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 2 || !c || !lv) return set_error(FMG_EINVAL, "bad unpack arguments");
+    launch_unpack(make_grid(dim, n), lv, c, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "unpack launch failed");
+}
+
+int fmg_op_rhs(const fmg_problem* prob, int32_t n, double lambda, const double* u, double* b, void* stream) {
+    if (int rc = check_problem(prob)) return rc;
+    if (n < 2 || !u || !b) return set_error(FMG_EINVAL, "bad rhs arguments");
+    launch_rhs(make_grid(prob->dim, n), make_phys(prob), u, b, nullptr, lambda, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "rhs launch failed");
+}
+
+int fmg_op_smooth(int32_t dim, int32_t n, int32_t precision, void* x, const void* f, int32_t sweeps, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 2 || sweeps < 0 || !x || !f) return set_error(FMG_EINVAL, "bad smooth arguments");
+    Grid g = make_grid(dim, n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int hs = sweeps > 0 ? 2 * sweeps + 1 : 0;
+    if (precision == FMG_MIXED)
+        launch_smooth<float>(g, static_cast<float*>(x), static_cast<const float*>(f), hs, 0, s);
+    else
+        launch_smooth<double>(g, static_cast<double*>(x), static_cast<const double*>(f), hs, 0, s);
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "smooth launch failed");
+}
+
+int fmg_op_residual_restrict(int32_t dim, int32_t n, int32_t precision, const void* x, const void* f, void* rc,
+                             void* stream) {
+    if ((dim != 2 && dim != 3) || n < 4 || (n & 1) || !x || !f || !rc) return set_error(FMG_EINVAL, "bad restrict arguments");
+    Grid gf = make_grid(dim, n), gc = make_grid(dim, n / 2);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == FMG_MIXED)
+        launch_resid_restrict<float>(gf, gc, static_cast<const float*>(x), static_cast<const float*>(f),
+                                     static_cast<float*>(rc), s);
+    else
+        launch_resid_restrict<double>(gf, gc, static_cast<const double*>(x), static_cast<const double*>(f),
+                                      static_cast<double*>(rc), s);
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "restrict launch failed");
+}
+
+int fmg_op_prolong(int32_t dim, int32_t n, int32_t precision, const void* xc, void* xf, int32_t accumulate,
+                   void* stream) {
+    if ((dim != 2 && dim != 3) || n < 4 || (n & 1) || !xc || !xf) return set_error(FMG_EINVAL, "bad prolong arguments");
+    Grid gf = make_grid(dim, n), gc = make_grid(dim, n / 2);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == FMG_MIXED)
+        launch_prolong<float>(gc, gf, static_cast<const float*>(xc), static_cast<float*>(xf), accumulate, s);
+    else
+        launch_prolong<double>(gc, gf, static_cast<const double*>(xc), static_cast<double*>(xf), accumulate, s);
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "prolong launch failed");
+}
+
+int fmg_op_coarse_solve(int32_t dim, int32_t n, int32_t precision, const void* f, void* x, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 2 || (dim == 2 && n > 32) || (dim == 3 && n > 16) || !f || !x)
+        return set_error(FMG_EINVAL, "bad coarse solve arguments");
+    Grid g = make_grid(dim, n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == FMG_MIXED)
+        launch_coarse_solve<float>(g, static_cast<const float*>(f), static_cast<float*>(x), s);
+    else
+        launch_coarse_solve<double>(g, static_cast<const double*>(f), static_cast<double*>(x), s);
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "coarse solve launch failed");
+}
+
+int fmg_op_vcycle(int32_t dim, int32_t n_coarse, int32_t levels, int32_t nu_pre, int32_t nu_post, double* x,
+                  const double* f, void* ws, size_t ws_bytes, void* stream) {
+    fmg_problem p{};
+    p.dim = dim; p.n_coarse = n_coarse; p.n_refine = levels - 1;
+    if (int rc = check_problem(&p)) return rc;
+    if (nu_pre < 0 || nu_post < 0 || !x || !f || !ws) return set_error(FMG_EINVAL, "bad vcycle arguments");
+    Layout lo = make_layout(dim, n_coarse, levels, 0);
+    if (ws_bytes < lo.total) return set_error(FMG_ENOMEM, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int l = 0; l + 1 < levels; ++l) {
+        launch_fill<double>(at<double>(ws, lo.xv[l]), lo.g[l].elems, 0.0, s);
+        launch_fill<double>(at<double>(ws, lo.fv[l]), lo.g[l].elems, 0.0, s);
+    }
+    vcycle<double>(lo, ws, levels - 1, x, f, nu_pre, nu_post, s);
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "vcycle launch failed");
+}
+
+int fmg_moments_layout(int32_t dim, int32_t n_coarse, int32_t n, int32_t* per_element, size_t* scratch_bytes) {
+    if ((dim != 2 && dim != 3) || n_coarse < 2 || n < n_coarse || n % n_coarse) return set_error(FMG_EINVAL, "bad layout args");
+    if (per_element) *per_element = moments_per_element(dim);
+    if (scratch_bytes) *scratch_bytes = std::max<size_t>(moments_scratch_bytes(dim, n_coarse, n), 256);
+    return 0;
+}
+
+int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* ut, double* out, void* scratch,
+                   size_t scratch_bytes, void* stream) {
+    if (int rc = check_problem(prob)) return rc;
+    const int nc = prob->n_coarse;
+    if (n < nc || n % nc || ((n / nc) & (n / nc - 1)) || !ut || !out || !scratch)
+        return set_error(FMG_EINVAL, "bad moments arguments");
+    if (scratch_bytes < moments_scratch_bytes(prob->dim, nc, n)) return set_error(FMG_ENOMEM, "moments scratch too small");
+    launch_moments(prob->dim, nc, make_grid(prob->dim, n), make_phys(prob), ut, static_cast<double*>(scratch), out,
+                   static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "moments launch failed");
+}
+
+static size_t small_scratch(int dim, int nc) { return align256(sizeof(SmallState)) + align256(small_arena_bytes(dim, nc)); }
+
+int fmg_small_scratch_bytes(int32_t dim, int32_t n_coarse, size_t* bytes) {
+    if ((dim != 2 && dim != 3) || n_coarse < 2 || !bytes) return set_error(FMG_EINVAL, "bad arguments");
+    *bytes = small_scratch(dim, n_coarse);
+    return 0;
+}
+
+int fmg_op_augmented_matrices(const fmg_problem* prob, const double* mom, const double* x, double* A, double* B,
+                              double* S, void* scratch, size_t scratch_bytes, void* stream) {
+    if (int rc = check_problem(prob)) return rc;
+    if (!mom || !x || !A || !B || !S || !scratch) return set_error(FMG_EINVAL, "bad arguments");
+    if (scratch_bytes < small_scratch(prob->dim, prob->n_coarse)) return set_error(FMG_ENOMEM, "scratch too small");
+    double* arena = at<double>(scratch, align256(sizeof(SmallState)));
+    int rc = launch_aug_dump(prob->dim, prob->n_coarse, make_phys(prob), mom, x, arena, A, B, S,
+                             static_cast<hipStream_t>(stream));
+    return rc ? set_error(rc, "augmented dump launch failed") : 0;
+}
+
+static int small_common(const fmg_problem* prob, const fmg_options* opt, double* xc, void* scratch, size_t bytes,
+                        hipStream_t s, bool aug, const double* mom, double* lambda, double* c, int32_t* iters,
+                        int32_t* ground) {
+    if (int rc = check_problem(prob)) return rc;
+    if (int rc = check_options(opt)) return rc;
+    if (!xc || !scratch || (aug && !mom)) return set_error(FMG_EINVAL, "bad arguments");
+    if (bytes < small_scratch(prob->dim, prob->n_coarse)) return set_error(FMG_ENOMEM, "scratch too small");
+    SmallState init;
+    std::memset(&init, 0, sizeof(init));
+    SmallState* st = at<SmallState>(scratch, 0);
+    double* arena = at<double>(scratch, align256(sizeof(SmallState)));
+    FMG_HIP_CHECK(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    int rc = aug ? launch_aug_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter, opt->newton_tol,
+                                     mom, arena, xc, st, 0, s)
+                 : launch_coarse_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter,
+                                        opt->newton_tol, arena, xc, st, s);
+    if (rc) return set_error(rc, "small solve launch failed");
+    SmallState h;
+    FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+    FMG_HIP_CHECK(hipStreamSynchronize(s));
+    if (lambda) *lambda = h.lambda;
+    if (c) *c = h.c;
+    if (iters) *iters = h.newton_total;
+    if (ground) *ground = h.certify_fail == 0;
+    if (h.status)
+        return set_error(h.status, "nonlinear solve failed (reason %d, residual %.3e)", h.fail_reason, h.fail_residual);
+    return 0;
+}
+
+int fmg_op_augmented_solve(const fmg_problem* prob, const fmg_options* opt, const double* mom, double* xc,
+                           void* scratch, size_t bytes, void* stream, double* lambda, double* c, int32_t* iters,
+                           int32_t* ground) {
+    return small_common(prob, opt, xc, scratch, bytes, static_cast<hipStream_t>(stream), true, mom, lambda, c, iters,
+                        ground);
+}
+
+int fmg_op_coarse_nonlinear(const fmg_problem* prob, const fmg_options* opt, double* xc, void* scratch, size_t bytes,
+                            void* stream, double* lambda, int32_t* iters, int32_t* ground) {
+    return small_common(prob, opt, xc, scratch, bytes, static_cast<hipStream_t>(stream), false, nullptr, lambda,
+                        nullptr, iters, ground);
+}
+
+int fmg_op_form_u(int32_t dim, int32_t n_coarse, int32_t n, double c, const double* xc, double* u, void* scratch,
+                  void* stream) {
+    if ((dim != 2 && dim != 3) || n_coarse < 2 || n < n_coarse || n % n_coarse || !xc || !u || !scratch)
+        return set_error(FMG_EINVAL, "bad form_u arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* cd = static_cast<double*>(scratch);
+    FMG_HIP_CHECK(hipMemcpyAsync(cd, &c, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_form_u(make_grid(dim, n), make_grid(dim, n_coarse), u, xc, cd, s);
+    FMG_HIP_CHECK(hipStreamSynchronize(s));
+    return 0;
+}
+
+int fmg_op_forms(const fmg_problem* prob, int32_t n, const double* u, double* out4, void* scratch, void* stream) {
+    if (int rc = check_problem(prob)) return rc;
+    if (n < 2 || !u || !out4 || !scratch) return set_error(FMG_EINVAL, "bad forms arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* f = static_cast<double*>(scratch);
+    launch_forms(make_grid(prob->dim, n), make_phys(prob), u, f + 8, f, s);
+    FMG_HIP_CHECK(hipMemcpyAsync(out4, f, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FMG_HIP_CHECK(hipStreamSynchronize(s));
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,553 @@
+// Grid kernels of the multigrid hot path: red-black Gauss-Seidel smoothing, residual and
+// restriction, prolongation, exact coarsest solve, the right-hand side of the auxiliary
+// problem (3.4), mixed-precision refinement helpers and the Rayleigh-quotient reductions.
+//
+// Operators (P1 elements, (2.3)-(2.5); mesh families of the paper's regular refinement):
+//   2D  K = [4; -1 on E,W,N,S]                 (h-independent)
+//   3D  K = h [6; -1 on +-x,+-y,+-z]
+// Both are 2-colourable by the parity of i+j(+k), so a red-black half sweep updates all
+// nodes of one colour at once and equals a Gauss-Seidel pass in red-black order.
+// P is P1 interpolation: a fine node at a coarse node takes its value; any other fine node
+// is the midpoint of one coarse edge (2D: x, y or (1,1) direction; 3D: the 7 Kuhn edge
+// directions, which are exactly the nonzero parity patterns (i&1, j&1, k&1)).
+#include "kernels.h"
+
+namespace fmg {
+
+// ------------------------------------------------------------------------------------------
+// elementwise helpers
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t count, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+template <typename T>
+void launch_fill(T* p, int64_t count, T v, hipStream_t s) {
+    if (count <= 0) return;
+    unsigned blocks = (unsigned)std::min<int64_t>(cdiv(count, 256), 8192);
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, s, p, count, v);
+}
+template void launch_fill<double>(double*, int64_t, double, hipStream_t);
+template void launch_fill<float>(float*, int64_t, float, hipStream_t);
+
+__device__ inline int64_t compact_to_level(const Grid& g, int64_t c) {
+    const int64_t m = g.n - 1;
+    int64_t i = c % m + 1, r = c / m;
+    if (g.dim == 2) return i + g.pitch * (r + 1);
+    int64_t j = r % m + 1, k = r / m + 1;
+    return i + g.pitch * j + g.plane * k;
+}
+
+__global__ void k_pack(Grid g, const double* __restrict__ c, double* __restrict__ lv, int64_t total) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total) lv[compact_to_level(g, t)] = c[t];
+}
+__global__ void k_unpack(Grid g, const double* __restrict__ lv, double* __restrict__ c, int64_t total) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total) c[t] = lv[compact_to_level(g, t)];
+}
+
+static int64_t interior_count(const Grid& g) {
+    int64_t m = g.n - 1;
+    return g.dim == 2 ? m * m : m * m * m;
+}
+
+void launch_pack(const Grid& g, const double* compact, double* level, hipStream_t s) {
+    int64_t tot = interior_count(g);
+    if (tot > 0) hipLaunchKernelGGL(k_pack, dim3(cdiv(tot, 256)), dim3(256), 0, s, g, compact, level, tot);
+}
+void launch_unpack(const Grid& g, const double* level, double* compact, hipStream_t s) {
+    int64_t tot = interior_count(g);
+    if (tot > 0) hipLaunchKernelGGL(k_unpack, dim3(cdiv(tot, 256)), dim3(256), 0, s, g, level, compact, tot);
+}
+
+// ------------------------------------------------------------------------------------------
+// red-black Gauss-Seidel half sweep.  Thread (t, j[, k]) updates the t-th node of colour
+// `color` ((i+j+k) % 2 == color) in row j.  The update expression is fixed so that every
+// implementation of the sweep produces identical bits.
+template <typename T>
+__device__ inline T gs2(T f, T w, T e, T s, T n) {
+    return (f + ((w + e) + (s + n))) * T(0.25);
+}
+template <typename T>
+__device__ inline T gs3(T f, T inv_h, T w, T e, T s, T n, T b, T t) {
+    return (f * inv_h + (((w + e) + (s + n)) + (b + t))) * T(1.0 / 6.0);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_smooth_half(T* __restrict__ x, const T* __restrict__ f, Grid g,
+                                                     int color) {
+    const int n = g.n;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    if (j > n - 1) return;
+    const int i0 = (((1 + j + k) & 1) == color) ? 1 : 2;
+    const int i = i0 + 2 * (int)(blockIdx.x * 64 + threadIdx.x);
+    if (i > n - 1) return;
+    const int64_t P = g.pitch;
+    if (D == 2) {
+        const int64_t p = i + P * j;
+        x[p] = gs2<T>(f[p], x[p - 1], x[p + 1], x[p - P], x[p + P]);
+    } else {
+        const int64_t S = g.plane;
+        const int64_t p = i + P * j + S * k;
+        x[p] = gs3<T>(f[p], T(n), x[p - 1], x[p + 1], x[p - P], x[p + P], x[p - S], x[p + S]);
+    }
+}
+
+template <typename T>
+void launch_smooth_half(const Grid& g, T* x, const T* f, int color, hipStream_t s) {
+    const int n = g.n;
+    if (n < 2) return;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(n / 2 + 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_smooth_half<2, T>), grd, blk, 0, s, x, f, g, color);
+    else
+        hipLaunchKernelGGL((k_smooth_half<3, T>), grd, blk, 0, s, x, f, g, color);
+}
+
+template <typename T>
+void launch_smooth(const Grid& g, T* x, const T* f, int half_sweeps, int first, hipStream_t s) {
+    int c = first;
+    for (int h = 0; h < half_sweeps; ++h, c ^= 1) launch_smooth_half<T>(g, x, f, c, s);
+}
+template void launch_smooth_half<double>(const Grid&, double*, const double*, int, hipStream_t);
+template void launch_smooth_half<float>(const Grid&, float*, const float*, int, hipStream_t);
+template void launch_smooth<double>(const Grid&, double*, const double*, int, int, hipStream_t);
+template void launch_smooth<float>(const Grid&, float*, const float*, int, int, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// residual r = f - K x on the fine level, restricted by P^T to the coarse level:
+//   r_c(I) = r(2I) + 1/2 sum over the P1 edge neighbours d of r(2I +- d).
+template <int D, typename T>
+__device__ inline T resid_at(const T* __restrict__ x, const T* __restrict__ f, int64_t q, int64_t P, int64_t S,
+                             T h) {
+    if (D == 2) return f[q] - (T(4) * x[q] - ((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P])));
+    return f[q] - h * (T(6) * x[q] - (((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P])) + (x[q - S] + x[q + S])));
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(const T* __restrict__ x, const T* __restrict__ f,
+                                                        T* __restrict__ rc, Grid gf, Grid gc) {
+    const int I = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int J = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int Kz = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    const int nc = gc.n;
+    if (I > nc - 1 || J > nc - 1) return;
+    const int64_t P = gf.pitch, S = gf.plane;
+    const T h = T(gf.h);
+    if (D == 2) {
+        const int64_t p = 2 * I + P * 2 * J;
+        T c = resid_at<2, T>(x, f, p, P, S, h);
+        T e = (resid_at<2, T>(x, f, p - 1, P, S, h) + resid_at<2, T>(x, f, p + 1, P, S, h)) +
+              (resid_at<2, T>(x, f, p - P, P, S, h) + resid_at<2, T>(x, f, p + P, P, S, h)) +
+              (resid_at<2, T>(x, f, p - 1 - P, P, S, h) + resid_at<2, T>(x, f, p + 1 + P, P, S, h));
+        rc[I + gc.pitch * J] = c + T(0.5) * e;
+    } else {
+        const int64_t p = 2 * I + P * 2 * J + S * 2 * Kz;
+        const int64_t d[7] = {1, P, S, 1 + P, P + S, 1 + S, 1 + P + S};
+        T c = resid_at<3, T>(x, f, p, P, S, h);
+        T e = T(0);
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            e += resid_at<3, T>(x, f, p - d[q], P, S, h) + resid_at<3, T>(x, f, p + d[q], P, S, h);
+        rc[I + gc.pitch * J + gc.plane * Kz] = c + T(0.5) * e;
+    }
+}
+
+template <typename T>
+void launch_resid_restrict(const Grid& gf, const Grid& gc, const T* x, const T* f, T* rc, hipStream_t s) {
+    const int nc = gc.n;
+    if (nc < 2) return;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(nc - 1, 64), cdiv(nc - 1, 4), gf.dim == 3 ? nc - 1 : 1);
+    if (gf.dim == 2)
+        hipLaunchKernelGGL((k_resid_restrict<2, T>), grd, blk, 0, s, x, f, rc, gf, gc);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<3, T>), grd, blk, 0, s, x, f, rc, gf, gc);
+}
+template void launch_resid_restrict<double>(const Grid&, const Grid&, const double*, const double*, double*,
+                                            hipStream_t);
+template void launch_resid_restrict<float>(const Grid&, const Grid&, const float*, const float*, float*,
+                                           hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// prolongation x_f (+)= P x_c
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_prolong(const T* __restrict__ xc, T* __restrict__ xf, Grid gc, Grid gf,
+                                                 int accumulate) {
+    const int i = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    const int n = gf.n;
+    if (i > n - 1 || j > n - 1) return;
+    const int di = i & 1, dj = j & 1, dk = k & 1;
+    const int64_t q0 = (i >> 1) + gc.pitch * (j >> 1) + gc.plane * (k >> 1);
+    T v = xc[q0];
+    if (di | dj | dk) v = T(0.5) * (v + xc[q0 + di + gc.pitch * dj + gc.plane * dk]);
+    const int64_t p = i + gf.pitch * j + gf.plane * k;
+    if (accumulate)
+        xf[p] += v;
+    else
+        xf[p] = v;
+}
+
+template <typename T>
+void launch_prolong(const Grid& gc, const Grid& gf, const T* xc, T* xf, int accumulate, hipStream_t s) {
+    const int n = gf.n;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), gf.dim == 3 ? n - 1 : 1);
+    if (gf.dim == 2)
+        hipLaunchKernelGGL((k_prolong<2, T>), grd, blk, 0, s, xc, xf, gc, gf, accumulate);
+    else
+        hipLaunchKernelGGL((k_prolong<3, T>), grd, blk, 0, s, xc, xf, gc, gf, accumulate);
+}
+template void launch_prolong<double>(const Grid&, const Grid&, const double*, double*, int, hipStream_t);
+template void launch_prolong<float>(const Grid&, const Grid&, const float*, float*, int, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Exact coarsest-level solve.  K is the Kronecker sum of the 1D matrix tridiag(-1,2,-1)
+// (times h in 3D), diagonalised by the discrete sine transform S_ab = sin(pi a b / n):
+//   x = (2/n)^D (S x..x S) diag(1 / (h^(D-2) sum_k mu_k)) (S x..x S) f,
+//   mu_a = 4 sin^2(pi a / (2n)).
+// One workgroup; the m^D values (m = n-1) live in shared memory.  FP64 internally.
+__device__ void dst_axis(const double* __restrict__ src, double* __restrict__ dst, const double* __restrict__ S,
+                         int m, int D, int axis) {
+    int total = (D == 2) ? m * m : m * m * m;
+    int st = (axis == 0) ? 1 : (axis == 1 ? m : m * m);
+    for (int o = threadIdx.x; o < total; o += blockDim.x) {
+        int q = (o / st) % m;
+        int base = o - q * st;
+        double acc = 0.0;
+        for (int a = 0; a < m; ++a) acc += src[base + a * st] * S[a * m + q];
+        dst[o] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_solve(const T* __restrict__ f, T* __restrict__ x, Grid g) {
+    extern __shared__ double sm[];
+    const int n = g.n, m = n - 1, D = g.dim;
+    const int total = (D == 2) ? m * m : m * m * m;
+    double* S = sm;
+    double* mu = S + m * m;
+    double* A = mu + m;
+    double* B = A + total;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+        int a = t / m + 1, b = t % m + 1;
+        S[t] = sinpi((double)((a * b) % (2 * n)) / n);
+    }
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        double s = sinpi((double)(t + 1) / (2.0 * n));
+        mu[t] = 4.0 * s * s;
+    }
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int i = t % m + 1, r = t / m;
+        int64_t p = (D == 2) ? i + g.pitch * (r + 1) : i + g.pitch * (r % m + 1) + g.plane * (r / m + 1);
+        A[t] = (double)f[p];
+    }
+    __syncthreads();
+    dst_axis(A, B, S, m, D, 0);
+    __syncthreads();
+    dst_axis(B, A, S, m, D, 1);
+    __syncthreads();
+    double* cur = A;
+    double* oth = B;
+    if (D == 3) {
+        dst_axis(A, B, S, m, D, 2);
+        __syncthreads();
+        cur = B;
+        oth = A;
+    }
+    const double scale = (D == 2) ? (2.0 / n) * (2.0 / n) : (2.0 / n) * (2.0 / n) * (2.0 / n) * n;  // 1/h in 3D
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int a = t % m, r = t / m;
+        double lam = (D == 2) ? mu[a] + mu[r] : mu[a] + mu[r % m] + mu[r / m];
+        cur[t] = cur[t] * scale / lam;
+    }
+    __syncthreads();
+    dst_axis(cur, oth, S, m, D, 0);
+    __syncthreads();
+    dst_axis(oth, cur, S, m, D, 1);
+    __syncthreads();
+    double* res = cur;
+    if (D == 3) {
+        dst_axis(cur, oth, S, m, D, 2);
+        __syncthreads();
+        res = oth;
+    }
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int i = t % m + 1, r = t / m;
+        int64_t p = (D == 2) ? i + g.pitch * (r + 1) : i + g.pitch * (r % m + 1) + g.plane * (r / m + 1);
+        x[p] = (T)res[t];
+    }
+}
+
+template <typename T>
+void launch_coarse_solve(const Grid& g, const T* f, T* x, hipStream_t s) {
+    const int m = g.n - 1;
+    const int total = g.dim == 2 ? m * m : m * m * m;
+    size_t shm = sizeof(double) * ((size_t)m * m + m + 2 * (size_t)total);
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(256), shm, s, f, x, g);
+}
+template void launch_coarse_solve<double>(const Grid&, const double*, double*, hipStream_t);
+template void launch_coarse_solve<float>(const Grid&, const float*, float*, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Right-hand side of the auxiliary problem (3.4): b = lambda M u - M_W u - zeta N(u).
+// M and M_W rows come from the exact star moments (tables.h): with the node at X,
+//   (M_W)_{i,i+o} = h^D [ sum_k w_k (X_k^2 m0[o] + 2 X_k h m1[k][o] + h^2 m2[k][o]) + wc m0[o] ].
+// N(u)_i = int u_h^3 phi_i sums, over the elements e around node i, the exact value
+//   |e| D! 3! / (D+4)! (h_3 + u_i h_2 + u_i^2 h_1 + u_i^3),
+// h_k the complete homogeneous symmetric polynomials of the vertex values of e.
+template <int D>
+__device__ inline double cubic_term(double v0, double v1, double v2, double v3) {
+    double s1 = v0 + v1 + v2 + (D == 3 ? v3 : 0.0);
+    double p2 = v0 * v0 + v1 * v1 + v2 * v2 + (D == 3 ? v3 * v3 : 0.0);
+    double p3 = v0 * v0 * v0 + v1 * v1 * v1 + v2 * v2 * v2 + (D == 3 ? v3 * v3 * v3 : 0.0);
+    double h2 = 0.5 * (s1 * s1 + p2);
+    double h3 = (s1 * s1 * s1 + 3.0 * s1 * p2 + 2.0 * p3) * (1.0 / 6.0);
+    return h3 + v0 * h2 + v0 * v0 * s1 + v0 * v0 * v0;
+}
+
+template <int D>
+__device__ inline void node_forms(const double* __restrict__ u, const Grid& g, const Phys& ph, int i, int j, int k,
+                                  double& Mu, double& MWu, double& Nu, double& Ku) {
+    const int64_t P = g.pitch, S = g.plane;
+    const int64_t p = i + P * j + S * k;
+    const double h = g.h;
+    const double X[3] = {i * h, j * h, k * h};
+    constexpr int NS = (D == 2) ? kStencil2D : kStencil3D;
+    double mu = 0.0, mw = 0.0;
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+        int64_t q;
+        double m0, cw = 0.0;
+        if (D == 2) {
+            q = p + kOff2D[o][0] + P * kOff2D[o][1];
+            m0 = kM0_2D[o];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                cw += ph.w[a] * (X[a] * X[a] * m0 + 2.0 * X[a] * h * kM1_2D[a][o] + h * h * kM2_2D[a][o]);
+        } else {
+            q = p + kOff3D[o][0] + P * kOff3D[o][1] + S * kOff3D[o][2];
+            m0 = kM0_3D[o];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                cw += ph.w[a] * (X[a] * X[a] * m0 + 2.0 * X[a] * h * kM1_3D[a][o] + h * h * kM2_3D[a][o]);
+        }
+        cw += ph.wc * m0;
+        const double uq = u[q];
+        mu += m0 * uq;
+        mw += cw * uq;
+    }
+    const double hd = (D == 2) ? h * h : h * h * h;
+    Mu = hd * mu;
+    MWu = hd * mw;
+    const double u0 = u[p];
+    double nl = 0.0;
+    if (D == 2) {
+#pragma unroll
+        for (int e = 0; e < kStarElems2D; ++e) {
+            double v1 = u[p + kStarElem2D[e][0][0] + P * kStarElem2D[e][0][1]];
+            double v2 = u[p + kStarElem2D[e][1][0] + P * kStarElem2D[e][1][1]];
+            nl += cubic_term<2>(u0, v1, v2, 0.0);
+        }
+        Nu = nl * (h * h / 120.0);
+        Ku = 4.0 * u0 - ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P]));
+    } else {
+#pragma unroll
+        for (int e = 0; e < kStarElems3D; ++e) {
+            double v1 = u[p + kStarElem3D[e][0][0] + P * kStarElem3D[e][0][1] + S * kStarElem3D[e][0][2]];
+            double v2 = u[p + kStarElem3D[e][1][0] + P * kStarElem3D[e][1][1] + S * kStarElem3D[e][1][2]];
+            double v3 = u[p + kStarElem3D[e][2][0] + P * kStarElem3D[e][2][1] + S * kStarElem3D[e][2][2]];
+            nl += cubic_term<3>(u0, v1, v2, v3);
+        }
+        Nu = nl * (h * h * h / 840.0);
+        Ku = h * (6.0 * u0 - (((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P])) + (u[p - S] + u[p + S])));
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ u, double* __restrict__ b, Grid g, Phys ph,
+                                             const double* __restrict__ lam_dev, double lam_host) {
+    const int i = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    const int n = g.n;
+    if (i > n - 1 || j > n - 1) return;
+    const double lam = lam_dev ? *lam_dev : lam_host;
+    double Mu, MWu, Nu, Ku;
+    node_forms<D>(u, g, ph, i, j, k, Mu, MWu, Nu, Ku);
+    b[i + g.pitch * j + g.plane * k] = lam * Mu - MWu - ph.zeta * Nu;
+}
+
+void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev, double lam_host,
+                hipStream_t s) {
+    const int n = g.n;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_rhs<2>, grd, blk, 0, s, u, b, g, ph, lam_dev, lam_host);
+    else
+        hipLaunchKernelGGL(k_rhs<3>, grd, blk, 0, s, u, b, g, ph, lam_dev, lam_host);
+}
+
+// ------------------------------------------------------------------------------------------
+// mixed precision helpers
+template <int D>
+__global__ __launch_bounds__(256) void k_residual_demote(const double* __restrict__ u, const double* __restrict__ b,
+                                                         float* __restrict__ r, Grid g) {
+    const int i = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    const int n = g.n;
+    if (i > n - 1 || j > n - 1) return;
+    const int64_t P = g.pitch, S = g.plane;
+    const int64_t p = i + P * j + S * k;
+    double ku;
+    if (D == 2)
+        ku = 4.0 * u[p] - ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P]));
+    else
+        ku = g.h * (6.0 * u[p] - (((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P])) + (u[p - S] + u[p + S])));
+    r[p] = (float)(b[p] - ku);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_add_promote(double* __restrict__ u, const float* __restrict__ e, Grid g) {
+    const int i = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    const int n = g.n;
+    if (i > n - 1 || j > n - 1) return;
+    const int64_t p = i + g.pitch * j + g.plane * k;
+    u[p] += (double)e[p];
+}
+
+void launch_residual_demote(const Grid& g, const double* u, const double* b, float* r, hipStream_t s) {
+    const int n = g.n;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_residual_demote<2>, grd, blk, 0, s, u, b, r, g);
+    else
+        hipLaunchKernelGGL(k_residual_demote<3>, grd, blk, 0, s, u, b, r, g);
+}
+void launch_add_promote(const Grid& g, double* u, const float* e, hipStream_t s) {
+    const int n = g.n;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_add_promote<2>, grd, blk, 0, s, u, e, g);
+    else
+        hipLaunchKernelGGL(k_add_promote<3>, grd, blk, 0, s, u, e, g);
+}
+
+// ------------------------------------------------------------------------------------------
+// u <- c u~ + Pi x_H.  Pi x_H at a fine node is the coarsest-level P1 function evaluated
+// there: the coarse cell and the simplex inside it follow from the coarse-local
+// coordinates (2D: lower triangle when X >= Y; 3D: the Kuhn simplex of the ordering of
+// X, Y, Z), and the barycentric weights from the sorted coordinates.
+template <int D>
+__global__ __launch_bounds__(256) void k_form_u(double* __restrict__ u, const double* __restrict__ xc, Grid gf,
+                                                Grid gc, const double* __restrict__ coef) {
+    const int i = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
+    const int n = gf.n, nc = gc.n;
+    if (i > n - 1 || j > n - 1) return;
+    const int s = n / nc;
+    const double inv_s = 1.0 / s;
+    int c0[3] = {min(i / s, nc - 1), min(j / s, nc - 1), D == 3 ? min(k / s, nc - 1) : 0};
+    double t[3] = {(i - c0[0] * s) * inv_s, (j - c0[1] * s) * inv_s, D == 3 ? (k - c0[2] * s) * inv_s : 0.0};
+    // sort axes by coordinate, descending (ties: lower axis first)
+    int ax[3] = {0, 1, 2};
+    if (D == 2) {
+        if (t[1] > t[0]) { ax[0] = 1; ax[1] = 0; }
+    } else {
+        if (t[ax[1]] > t[ax[0]]) { int q = ax[0]; ax[0] = ax[1]; ax[1] = q; }
+        if (t[ax[2]] > t[ax[1]]) { int q = ax[1]; ax[1] = ax[2]; ax[2] = q; }
+        if (t[ax[1]] > t[ax[0]]) { int q = ax[0]; ax[0] = ax[1]; ax[1] = q; }
+    }
+    const int64_t Pc = gc.pitch, Sc = gc.plane;
+    int64_t q = c0[0] + Pc * c0[1] + Sc * c0[2];
+    double val = (1.0 - t[ax[0]]) * xc[q];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        q += (ax[r] == 0) ? 1 : (ax[r] == 1 ? Pc : Sc);
+        double wgt = (r + 1 < D) ? t[ax[r]] - t[ax[r + 1]] : t[ax[r]];
+        val += wgt * xc[q];
+    }
+    const int64_t p = i + gf.pitch * j + gf.plane * k;
+    u[p] = coef[0] * u[p] + val;
+}
+
+void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_level, const double* coef,
+                   hipStream_t s) {
+    const int n = gf.n;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), gf.dim == 3 ? n - 1 : 1);
+    if (gf.dim == 2)
+        hipLaunchKernelGGL(k_form_u<2>, grd, blk, 0, s, u, xc_level, gf, gc, coef);
+    else
+        hipLaunchKernelGGL(k_form_u<3>, grd, blk, 0, s, u, xc_level, gf, gc, coef);
+}
+
+// ------------------------------------------------------------------------------------------
+// Rayleigh-quotient pieces: (u^T K u, u^T M_W u, u^T M u, int u^4 = u^T N(u)), block sums
+// in a fixed grid, then one block adds the partials in index order (deterministic).
+template <int D>
+__global__ __launch_bounds__(256) void k_forms(const double* __restrict__ u, Grid g, Phys ph,
+                                               double* __restrict__ partial) {
+    const int n = g.n, m = n - 1;
+    const int64_t total = (D == 2) ? (int64_t)m * m : (int64_t)m * m * m;
+    double a[4] = {0, 0, 0, 0};
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(t % m) + 1;
+        int64_t r = t / m;
+        int j = (int)(r % m) + 1, k = (D == 3) ? (int)(r / m) + 1 : 0;
+        double Mu, MWu, Nu, Ku;
+        node_forms<D>(u, g, ph, i, j, k, Mu, MWu, Nu, Ku);
+        double u0 = u[i + g.pitch * j + g.plane * k];
+        a[0] += u0 * Ku;
+        a[1] += u0 * MWu;
+        a[2] += u0 * Mu;
+        a[3] += u0 * Nu;
+    }
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double v = wave_sum(a[q]);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int w = 0; w < 4; ++w) v += red[w][threadIdx.x];
+        partial[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int nblk, int width, double* __restrict__ out) {
+    // one block; thread q sums column q in index order
+    for (int q = threadIdx.x; q < width; q += blockDim.x) {
+        double v = 0.0;
+        for (int b = 0; b < nblk; ++b) v += partial[b * width + q];
+        out[q] = v;
+    }
+}
+
+void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s) {
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_forms<2>, dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, partial);
+    else
+        hipLaunchKernelGGL(k_forms<3>, dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partial, kReduceBlocks, 4, out);
+}
+
+}  // namespace fmg

@@ -1,0 +1,75 @@
+// Host-side launchers of the HIP kernels (one translation unit per kernel family).
+#pragma once
+
+#include "common.h"
+
+namespace fmg {
+
+// ---- grid.hip ---------------------------------------------------------------------------
+template <typename T> void launch_fill(T* p, int64_t count, T v, hipStream_t s);
+void launch_pack(const Grid& g, const double* compact, double* level, hipStream_t s);
+void launch_unpack(const Grid& g, const double* level, double* compact, hipStream_t s);
+// one red-black half sweep of Gauss-Seidel on K x = f for the nodes of `color`
+template <typename T> void launch_smooth_half(const Grid& g, T* x, const T* f, int color, hipStream_t s);
+// `half_sweeps` alternating half sweeps starting with colour `first` (temporal blocking
+// inside one kernel where the level is small enough; identical arithmetic)
+template <typename T> void launch_smooth(const Grid& g, T* x, const T* f, int half_sweeps, int first,
+                                         hipStream_t s);
+template <typename T> void launch_resid_restrict(const Grid& gf, const Grid& gc, const T* x, const T* f,
+                                                 T* rc, hipStream_t s);
+template <typename T> void launch_prolong(const Grid& gc, const Grid& gf, const T* xc, T* xf, int accumulate,
+                                          hipStream_t s);
+template <typename T> void launch_coarse_solve(const Grid& g, const T* f, T* x, hipStream_t s);
+// b = lambda M u - M_W u - zeta N(u); lambda = *lam_dev if lam_dev else lam_host
+void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev,
+                double lam_host, hipStream_t s);
+// mixed precision: r32 = (float)(b - K u); u += (double)e32
+void launch_residual_demote(const Grid& g, const double* u, const double* b, float* r, hipStream_t s);
+void launch_add_promote(const Grid& g, double* u, const float* e, hipStream_t s);
+// u <- c * ut + Pi x_H   (Pi: P1 interpolation from the coarsest level); c = coef[0]
+void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_level, const double* coef,
+                   hipStream_t s);
+// out[0..3] = (u^T K u, u^T M_W u, u^T M u, int u^4): two-stage fixed-order reduction,
+// partial must hold kReduceBlocks*4 doubles
+constexpr int kReduceBlocks = 512;
+void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s);
+
+// ---- moments.hip ------------------------------------------------------------------------
+int moments_per_element(int dim);            // doubles per coarse element in the output
+size_t moments_scratch_bytes(int dim, int nc, int n);
+void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double* ut, double* scratch,
+                    double* out, hipStream_t s);
+
+// ---- small.hip --------------------------------------------------------------------------
+struct SmallState {
+    double lambda;        // current eigenvalue estimate
+    double lambda_prev;
+    double dlambda;       // |lambda - lambda_prev| / lambda of the last augmented solve
+    double c;             // coefficient of u~ of the last augmented solve
+    double tol_lambda;    // tolerance-loop threshold (0: inactive)
+    int32_t status;       // 0, or FMG_E* of the first failure
+    int32_t newton_total;
+    int32_t hist_len;
+    int32_t done;         // tolerance loop satisfied: later steps become no-ops
+    int32_t steps;
+    int32_t certify_fail;
+    int32_t fail_reason;  // first failure: 1 zero pivot, 2 no convergence, 3 non-finite,
+                          // 4 singular border system, 5 not the ground state
+    int32_t fail_step;    // history index of the first failure
+    double fail_residual; // relative Newton residual at the first failure
+    double hist[512];
+};
+size_t small_arena_bytes(int dim, int nc);
+// Coarse nonlinear eigenproblem (Algorithm 3.2 step 1) -> x_H written into the coarsest
+// padded level array xc_level, lambda into state.
+int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, double* arena,
+                         double* xc_level, SmallState* state, hipStream_t s);
+// Augmented nonlinear eigenproblem (3.6) from the moments of u~ -> x_H into xc_level,
+// c into state->c, lambda into state (history appended, tolerance flag updated).
+int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments,
+                      double* arena, double* xc_level, SmallState* state, int final_level, hipStream_t s);
+// Dense augmented matrices A, B, S(x) (row-major (N+1)^2 each) for tests.
+int launch_aug_dump(int dim, int nc, const Phys& ph, const double* moments, const double* x, double* arena,
+                    double* A, double* B, double* S, hipStream_t s);
+
+}  // namespace fmg

@@ -1,0 +1,79 @@
+"""Writes the stored expected values of the GPU tests and the benchmark.  Calls only the
+oracle (oracle/), never the HIP library.
+
+    python tests/golden/make_golden.py small     # seconds: fixed-schedule and converged
+                                                  # results of the small workloads
+    python tests/golden/make_golden.py large_2d   # long (tens of minutes): converged
+                                                  # lambda of the 2D 4.2M-dof workload
+
+Each JSON file holds, per workload: the problem, the oracle's fixed-schedule lambda history
+(Algorithm 3.2 with m = 1, p = 2, SGS(2,2)), the converged discrete eigenvalue lambda_ref
+of (2.4) on the finest level, its eigenvector at seeded sample nodes, and ||u||_M
+(= 1) with int u^4 for cross-checks.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import fem, fmg  # noqa: E402
+
+SMALL = {
+    "small_2d": W.SMALL_2D,
+    "small_2d_z100": W.Problem(2, 16, 2, (1.0, 1.0, 0.0), 0.0, 100.0),
+    "small_2d_z1000": W.Problem(2, 16, 2, (0.7, 1.6, 0.0), 0.0, 1000.0),
+    "small_3d": W.Problem(3, 4, 2, (1.0, 1.0, 1.0), 0.0, 10.0),
+}
+
+
+def run(name, prob, fixed=True, samples=64):
+    t0 = time.time()
+    opts = W.Options()
+    h = fmg.Hierarchy(prob)
+    out = {"problem": dataclasses.asdict(prob), "options": dataclasses.asdict(opts)}
+    if fixed:
+        r = fmg.fmg(prob, opts, h)
+        out["fixed_history"] = [float(x[2]) for x in r.history]
+        out["fixed_lambda"] = float(r.lam)
+        out["fixed_u"] = r.u.tolist() if r.u.size <= 20000 else None
+    rc = fmg.converged(prob, opts, h)
+    l = h.L - 1
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(rc.u.size, size=min(samples, rc.u.size), replace=False))
+    out["lambda_ref"] = float(rc.lam)
+    out["converged_steps"] = int(rc.steps_total)
+    out["sample_index"] = idx.tolist()
+    out["sample_u"] = rc.u[idx].tolist()
+    out["norm_M"] = float(rc.u @ (h.M[l] @ rc.u))
+    out["int_u4"] = float(fem.integral_of(h.meshes[l], rc.u, 4))
+    out["u_ref"] = rc.u.tolist() if rc.u.size <= 20000 else None
+    out["oracle_seconds"] = time.time() - t0
+    print(f"{name}: lambda_ref={rc.lam:.15f} steps={rc.steps_total} ({out['oracle_seconds']:.1f}s)", flush=True)
+    return out
+
+
+def main(which):
+    if which == "small":
+        res = {k: run(k, p) for k, p in SMALL.items()}
+        path = os.path.join(HERE, "small.json")
+    elif which == "large_2d":
+        res = {"large_2d": run("large_2d", W.LARGE_2D, fixed=False, samples=256)}
+        path = os.path.join(HERE, "large_2d.json")
+    else:
+        raise SystemExit(f"unknown set {which}")
+    with open(path, "w") as f:
+        json.dump(res, f)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "small")

@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every function include/fmgeig.h declares (no GPU
+needed: nothing here launches a kernel), and the pure host-side entry points behave."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fmgeig.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(fmg_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1502_04657_amd import _ffi
+    return _ffi.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fmg_solve", "fmg_workspace_bytes", "fmg_op_rhs", "fmg_op_smooth", "fmg_op_moments",
+                 "fmg_op_augmented_solve", "fmg_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1502_04657_amd import _ffi
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _ffi.SIGNATURES, f"binding lacks {name}"
+
+
+def test_workspace_bytes_and_validation(lib):
+    from paper_1502_04657_amd import to_c_options, to_c_problem
+    n = C.c_size_t()
+    p, o = to_c_problem(W.LARGE_2D), to_c_options(W.Options())
+    assert lib.fmg_workspace_bytes(C.byref(p), C.byref(o), C.byref(n)) == 0
+    # u and b on every level plus the V-cycle arrays below the top: about 27 bytes/dof
+    assert 20 * W.LARGE_2D.dofs() < n.value < 60 * W.LARGE_2D.dofs()
+    o_mixed = to_c_options(W.Options(precision="mixed"))
+    m = C.c_size_t()
+    assert lib.fmg_workspace_bytes(C.byref(p), C.byref(o_mixed), C.byref(m)) == 0
+    bad = to_c_problem(W.Problem(4, 8, 2))
+    assert lib.fmg_workspace_bytes(C.byref(bad), C.byref(o), C.byref(n)) == -1
+    assert b"dim" in lib.fmg_last_error()
+    bad = to_c_problem(W.Problem(2, 8, 2, zeta=-1.0))
+    assert lib.fmg_workspace_bytes(C.byref(bad), C.byref(o), C.byref(n)) == -1
+    bad = to_c_problem(W.Problem(2, 8, 2, zeta=float("nan")))
+    assert lib.fmg_workspace_bytes(C.byref(bad), C.byref(o), C.byref(n)) == -1
+    bad_o = to_c_options(W.Options(m=0))
+    assert lib.fmg_workspace_bytes(C.byref(p), C.byref(bad_o), C.byref(n)) == -1
+
+
+def test_level_layout(lib):
+    assert lib.fmg_level_pitch(2, 8) == 16
+    assert lib.fmg_level_pitch(2, 2048) == 2064
+    assert lib.fmg_level_elems(2, 8) == 9 * 16
+    assert lib.fmg_level_elems(3, 8) == 9 * 9 * 16
+    assert lib.fmg_level_elems(5, 8) == -1
+
+
+def test_solve_rejects_bad_sizes_before_touching_the_device(lib):
+    from paper_1502_04657_amd import _ffi, to_c_options, to_c_problem
+    p, o = to_c_problem(W.SMALL_2D), to_c_options(W.Options())
+    res = _ffi.fmg_result()
+    # wrong u_len is rejected on the host
+    rc = lib.fmg_solve(C.byref(p), C.byref(o), C.c_void_p(256), C.c_size_t(1 << 30), None, C.c_void_p(256),
+                       C.c_int64(5), C.byref(res))
+    assert rc == -1 and b"u_len" in lib.fmg_last_error()
+    # too small a workspace
+    rc = lib.fmg_solve(C.byref(p), C.byref(o), C.c_void_p(256), C.c_size_t(16), None, C.c_void_p(256),
+                       C.c_int64(127 * 127), C.byref(res))
+    assert rc == -2

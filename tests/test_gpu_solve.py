@@ -1,0 +1,95 @@
+"""GPU parity of whole FMG eigensolves (Algorithm 3.2) through fmg_solve against the
+oracle's stored results (tests/golden/small.json, written by make_golden.py from oracle/
+only):
+  * fixed schedule, FP64: the lambda after every correction step equals the oracle's
+    (same algorithm, only rounding differs) and so does u;
+  * converged (tolerance mode), FP64 and mixed precision: lambda within 1e-10 relative and
+    u within 1e-8 in the M-norm of the converged discrete solution of (2.4);
+  * identities on every result: b(u,u) = 1, lambda = a(u,u)/b(u,u), int u > 0."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import oracle_hierarchy
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "small.json")))
+
+
+def _problem(rec):
+    p = rec["problem"]
+    return W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"])
+
+
+def _solve(prob, opts):
+    from paper_1502_04657_amd import Solver
+    return Solver(prob, opts).solve()
+
+
+@pytest.mark.parametrize("name", ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000"])
+def test_fixed_schedule_matches_oracle_step_by_step(name):
+    rec = GOLD[name]
+    prob = _problem(rec)
+    res, u = _solve(prob, W.Options())
+    hist = rec["fixed_history"]
+    assert len(res.history) == len(hist)
+    for a, b in zip(res.history, hist):
+        assert a == pytest.approx(b, rel=1e-11)
+    h = oracle_hierarchy(prob)
+    M = h.M[h.L - 1]
+    d = u.cpu().numpy() - np.asarray(rec["fixed_u"])
+    assert math.sqrt(d @ (M @ d)) < 1e-9
+    assert res.norm == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("name", ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_matches_discrete_solution(name, precision):
+    rec = GOLD[name]
+    prob = _problem(rec)
+    opts = W.Options(tol_lambda=1e-13, max_final_steps=200, precision=precision)
+    res, u = _solve(prob, opts)
+    assert res.status == 0
+    assert res.lam == pytest.approx(rec["lambda_ref"], rel=1e-10)
+    h = oracle_hierarchy(prob)
+    M = h.M[h.L - 1]
+    d = u.cpu().numpy() - np.asarray(rec["u_ref"])
+    assert math.sqrt(d @ (M @ d)) < 1e-8
+    assert res.norm == pytest.approx(1.0, abs=1e-12)
+    assert res.lambda_rq == pytest.approx(res.lam, rel=1e-11)
+    assert float(h.hat(h.L - 1) @ u.cpu().numpy()) > 0
+
+
+def test_tolerance_mode_reaches_1e8_error():
+    rec = GOLD["small_2d_z100"]
+    prob = _problem(rec)
+    for precision in ("fp64", "mixed"):
+        res, _ = _solve(prob, W.Options(tol_lambda=1e-9, precision=precision))
+        assert res.status == 0
+        assert abs(res.lam - rec["lambda_ref"]) <= 1e-8 * rec["lambda_ref"]
+
+
+def test_repeat_solves_are_bitwise_identical():
+    from paper_1502_04657_amd import Solver
+    prob = _problem(GOLD["small_2d"])
+    s = Solver(prob, W.Options(tol_lambda=1e-12))
+    r1, u1 = s.solve()
+    r2, u2 = s.solve()
+    assert r1.lam == r2.lam
+    assert torch.equal(u1, u2)
+    assert r1.history == r2.history
+
+
+def test_solve_reports_nonconvergence_cap():
+    from paper_1502_04657_amd import FmgError, Solver
+    prob = _problem(GOLD["small_2d_z1000"])
+    s = Solver(prob, W.Options(tol_lambda=1e-15, max_final_steps=1))
+    with pytest.raises(FmgError) as e:
+        s.solve()
+    assert e.value.code == -3
