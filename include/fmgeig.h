@@ -100,6 +100,11 @@ typedef struct {
 const char* fmg_last_error(void);
 const char* fmg_version(void);
 
+/* Select the 2D V-cycle implementation for later calls in this process: 1 (default) fused
+ * temporally blocked level passes, 0 the unfused kernel sequence.  Both execute the same
+ * floating-point operations and give identical results.  Not thread-safe.                */
+int fmg_set_fused_vcycle(int32_t enable);
+
 /* ---- whole solve (Algorithm 3.2) ---------------------------------------------------- */
 
 /* Bytes of device workspace fmg_solve needs for this problem and options.  Pure function.

@@ -236,3 +236,70 @@ def prolongation(fine: Mesh, coarse: Mesh) -> sp.csr_matrix:
     P = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(fine.ndof, coarse.ndof)).tocsr()
     return P
+
+
+def coarse_simplex_moments(coarse: Mesh, fine: Mesh, ut: np.ndarray, W=None):
+    """Per coarse simplex E (in the coarse element order of mesh.simplices), the integrals
+    of powers of the fine P1 function u~ against products of the barycentric coordinates
+    l_p of E, all exact (products of P1 functions on each fine simplex):
+        T3[pqr] = int_E u~ l_p l_q l_r,  T2[pq] = int_E u~^2 l_p l_q,  T1[p] = int_E u~^3 l_p,
+        T0 = int_E u~^4,  B1[p] = int_E u~ l_p,  B2 = int_E u~^2,
+        AW1[p] = int_E W u~ l_p, AW2 = int_E W u~^2 (when W is given),
+        KG[p] = int_E grad u~ . grad l_p,  Q = int_E |grad u~|^2.
+    Returns a dict of arrays indexed [E, ...].  Plain loops over fine simplices."""
+    d = coarse.dim
+    nv = d + 1
+    I4 = bary_tensor(d, 4)
+    uf = _full(fine, ut)
+    cx = coarse.coords[coarse.elems]                        # (Ec, nv, d)
+    Tc = np.concatenate([np.ones(cx.shape[:2] + (1,)), cx], axis=2)
+    Cc = np.linalg.inv(np.transpose(Tc, (0, 2, 1)))          # lambda = Cc @ [1, x]
+    fx = fine.coords[fine.elems]                             # (Ef, nv, d)
+    cent = fx.mean(axis=1)
+    # locate the coarse simplex of every fine simplex by its centroid
+    lam_c = np.einsum("eij,fj->fei", Cc, np.concatenate([np.ones((len(cent), 1)), cent], 1))
+    owner = np.argmax(np.all(lam_c >= -1e-12, axis=2), axis=1)
+    assert np.all(np.all(lam_c[np.arange(len(cent)), owner] >= -1e-12, axis=1))
+    vol, grads = element_geometry(fine.coords, fine.elems)
+    out = {k: np.zeros((coarse.n_elements,) + sh) for k, sh in
+           [("T3", (nv, nv, nv)), ("T2", (nv, nv)), ("T1", (nv,)), ("T0", ()), ("B1", (nv,)), ("B2", ()),
+            ("AW1", (nv,)), ("AW2", ()), ("KG", (nv,)), ("Q", ())]}
+    for f in range(fine.n_elements):
+        E = owner[f]
+        u = uf[fine.elems[f]]                                # values of u~ at the fine vertices
+        pts = np.concatenate([np.ones((nv, 1)), fx[f]], 1)
+        L = (Cc[E] @ pts.T).T                                # L[j, p] = l_p at fine vertex j
+        v = vol[f]
+        # int_e prod of four linear functions = v * I4 contracted with their vertex values
+        one = np.ones(nv)
+        out["T3"][E] += v * np.einsum("ijkl,i,jp,kq,lr->pqr", I4, u, L, L, L)
+        out["T2"][E] += v * np.einsum("ijkl,i,j,kp,lq->pq", I4, u, u, L, L)
+        out["T1"][E] += v * np.einsum("ijkl,i,j,k,lp->p", I4, u, u, u, L)
+        out["T0"][E] += v * np.einsum("ijkl,i,j,k,l->", I4, u, u, u, u)
+        out["B1"][E] += v * np.einsum("ijkl,i,jp,k,l->p", I4, u, L, one, one)
+        out["B2"][E] += v * np.einsum("ijkl,i,j,k,l->", I4, u, u, one, one)
+        gu = grads[f].T @ u                                   # gradient of u~ on e
+        gl = np.linalg.inv(np.transpose(Tc[E]))[:, 1:]        # gradients of l_p
+        out["KG"][E] += v * (gl @ gu)
+        out["Q"][E] += v * (gu @ gu)
+        if W is not None:
+            # W is quadratic: exact through its P2 interpolant on e (as potential_mass)
+            wv = W(fx[f])
+            wm = W(0.5 * (fx[f][:, None, :] + fx[f][None, :, :]))
+            I5 = bary_tensor(d, 5)
+            I3 = bary_tensor(d, 3)
+            # W u~ l_p and W u~^2 are degree <= 4; expand W = sum_c W_c l_c(2 l_c - 1) + sum 4 W_ce l_c l_e
+            aw1 = np.zeros(nv)
+            aw2 = 0.0
+            for c in range(nv):
+                e4 = 2.0 * np.einsum("ijkl,i,j,k,lp->p", I4, np.eye(nv)[c], np.eye(nv)[c], u, L) - \
+                    np.einsum("ijk,i,j,kp->p", I3, np.eye(nv)[c], u, L)
+                aw1 += wv[c] * e4
+                aw2 += wv[c] * (2.0 * np.einsum("ijkl,i,j,k,l->", I4, np.eye(nv)[c], np.eye(nv)[c], u, u) -
+                                np.einsum("ijk,i,j,k->", I3, np.eye(nv)[c], u, u))
+                for e in range(c + 1, nv):
+                    aw1 += 4.0 * wm[c, e] * np.einsum("ijkl,i,j,k,lp->p", I4, np.eye(nv)[c], np.eye(nv)[e], u, L)
+                    aw2 += 4.0 * wm[c, e] * np.einsum("ijkl,i,j,k,l->", I4, np.eye(nv)[c], np.eye(nv)[e], u, u)
+            out["AW1"][E] += v * aw1
+            out["AW2"][E] += v * aw2
+    return out

@@ -41,6 +41,7 @@ D = C.c_double
 SIGNATURES = {
     "fmg_last_error": (C.c_char_p, []),
     "fmg_version": (C.c_char_p, []),
+    "fmg_set_fused_vcycle": (C.c_int, [I32]),
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),
     "fmg_solve": (C.c_int, [P, P, P, SZ, P, P, I64, P]),
     "fmg_level_pitch": (I64, [I32, I32]),

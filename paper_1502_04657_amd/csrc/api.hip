@@ -15,6 +15,8 @@
 namespace fmg {
 
 static thread_local char g_err[512] = "";
+// fused 2D V-cycle passes (1) or the unfused kernel sequence (0); both give identical bits
+static int g_fused = 1;
 
 int set_error(int code, const char* fmt, ...) {
     va_list ap;
@@ -108,17 +110,26 @@ template <typename T>
 static T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
 
 // ----------------------------------------------------------------------------------------
-// V-cycle: x_l (+)= MG step for K_l x = f_l; levels below l use the workspace arrays
+// V-cycle: x_l (+)= MG step for K_l x = f_l; levels below l use the workspace arrays.
+// zero_x: x enters as zero (it is not read).  2D uses the fused level passes.
 template <typename T>
-static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_pre, int nu_post, hipStream_t s) {
+static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_pre, int nu_post, hipStream_t s,
+                   bool zero_x = false) {
     const Grid& g = lo.g[l];
     if (l == 0) {
         launch_coarse_solve<T>(g, f, x, s);
         return;
     }
-    if (nu_pre > 0) launch_smooth<T>(g, x, f, 2 * nu_pre + 1, 0, s);
     T* xc = at<T>(ws, lo.xv[l - 1]);
     T* fc = at<T>(ws, lo.fv[l - 1]);
+    if (lo.dim == 2 && nu_pre <= 2 && nu_post <= 2 && g_fused) {
+        launch_vpre2d<T>(g, lo.g[l - 1], x, f, fc, nu_pre, zero_x ? 1 : 0, s);
+        vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
+        launch_vpost2d<T>(g, lo.g[l - 1], x, f, xc, nu_post, s);
+        return;
+    }
+    if (zero_x) launch_fill<T>(x, g.elems, T(0), s);
+    if (nu_pre > 0) launch_smooth<T>(g, x, f, 2 * nu_pre + 1, 0, s);
     launch_resid_restrict<T>(g, lo.g[l - 1], x, f, fc, s);
     launch_fill<T>(xc, lo.g[l - 1].elems, T(0), s);
     vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s);
@@ -142,8 +153,7 @@ static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, 
             float* r = at<float>(ws, lo.fv[k]);
             float* e = at<float>(ws, lo.xv[k]);
             launch_residual_demote(g, u, b, r, s);
-            launch_fill<float>(e, g.elems, 0.0f, s);
-            vcycle<float>(lo, ws, k, e, r, opt->nu_pre, opt->nu_post, s);
+            vcycle<float>(lo, ws, k, e, r, opt->nu_pre, opt->nu_post, s, true);
             launch_add_promote(g, u, e, s);
         } else {
             vcycle<double>(lo, ws, k, u, b, opt->nu_pre, opt->nu_post, s);
@@ -166,6 +176,11 @@ using namespace fmg;
 extern "C" {
 
 const char* fmg_last_error(void) { return g_err; }
+
+int fmg_set_fused_vcycle(int32_t enable) {
+    g_fused = enable ? 1 : 0;
+    return 0;
+}
 const char* fmg_version(void) { return "fmgeig 0.1 (gfx950)"; }
 
 int64_t fmg_level_pitch(int32_t dim, int32_t n) {

@@ -34,6 +34,15 @@ void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_l
 constexpr int kReduceBlocks = 512;
 void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s);
 
+// ---- vcycle2d.hip ----------------------------------------------------------------------
+// fused 2D V-cycle level passes (nu symmetric sweeps = 2 nu + 1 half sweeps, nu <= 2);
+// return false when nu is not supported (the caller then uses the unfused kernels).
+// zero_x: treat the incoming x as zero (coarse-level corrections) without reading it.
+template <typename T> bool launch_vpre2d(const Grid& g, const Grid& gc, T* x, const T* f, T* rc, int nu,
+                                         int zero_x, hipStream_t s);
+template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, T* x, const T* f, const T* xc, int nu,
+                                          hipStream_t s);
+
 // ---- moments.hip ------------------------------------------------------------------------
 int moments_per_element(int dim);            // doubles per coarse element in the output
 size_t moments_scratch_bytes(int dim, int nc, int n);

@@ -31,31 +31,25 @@ struct MomLayout {
     static constexpr int NE = (D == 2) ? 2 : 6;  // simplices per cell
 };
 
-// index of a multiset {p,q[,r]} among the sorted tuples in lexicographic order
-template <int V>
-struct SymIdx {
-    int i2[V][V];
-    int i3[V][V][V];
-    constexpr SymIdx() : i2{}, i3{} {
-        int c = 0;
-        for (int p = 0; p < V; ++p)
-            for (int q = p; q < V; ++q) {
-                i2[p][q] = c;
-                i2[q][p] = c;
-                ++c;
-            }
-        c = 0;
-        for (int p = 0; p < V; ++p)
-            for (int q = p; q < V; ++q)
-                for (int r = q; r < V; ++r) {
-                    i3[p][q][r] = c; i3[p][r][q] = c; i3[q][p][r] = c;
-                    i3[q][r][p] = c; i3[r][p][q] = c; i3[r][q][p] = c;
-                    ++c;
-                }
-    }
-};
-static constexpr SymIdx<3> kSym2{};
-static constexpr SymIdx<4> kSym3{};
+// index of a multiset {p,q[,r]} (entries in [0,V)) among the sorted tuples in
+// lexicographic order: closed form, so no lookup table is indexed at run time
+__host__ __device__ constexpr int sym2(int p, int q, int V) {
+    const int a = p < q ? p : q, b = p < q ? q : p;
+    return a * V - a * (a - 1) / 2 + (b - a);
+}
+__host__ __device__ constexpr int sym3(int p, int q, int r, int V) {
+    int a = p, b = q, c = r, t = 0;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+    int idx = 0;
+    for (int k = 0; k < a; ++k) idx += (V - k) * (V - k + 1) / 2;   // tuples starting below a
+    return idx + sym2(b - a, c - a, V - a);
+}
+static_assert(sym2(1, 1, 3) == 3 && sym2(2, 0, 3) == 2 && sym2(2, 2, 3) == 5, "sym2");
+static_assert(sym3(0, 1, 1, 3) == 3 && sym3(1, 1, 1, 3) == 6 && sym3(2, 1, 2, 3) == 8 && sym3(2, 2, 2, 3) == 9,
+              "sym3");
+static_assert(sym3(3, 3, 3, 4) == 19 && sym3(1, 1, 1, 4) == 10 && sym2(3, 3, 4) == 9, "sym3 (4)");
 
 // monomials X^a (|a| <= 3) of the coarse-local coordinates, ordered by degree
 static constexpr int kMon2[10][2] = {{0, 0}, {1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}, {3, 0}, {2, 1}, {1, 2}, {0, 3}};

@@ -259,12 +259,12 @@ __global__ void k_moments_final(const double* __restrict__ partial, int nc, int6
             poly_mul<D>(lam[p], lam[q], t1);
             double s2 = 0.0;
             for (int m = 0; m < R::M2; ++m) s2 += t1[m] * raw[R::P2 + m];
-            o[L::T2 + (D == 2 ? kSym2.i2[p][q] : kSym3.i2[p][q])] = s2;
+            o[L::T2 + sym2(p, q, D + 1)] = s2;
             for (int r = q; r < V; ++r) {
                 poly_mul<D>(t1, lam[r], t2);
                 double s3 = 0.0;
                 for (int m = 0; m < NM; ++m) s3 += t2[m] * raw[R::P1 + m];
-                o[L::T3 + (D == 2 ? kSym2.i3[p][q][r] : kSym3.i3[p][q][r])] = s3;
+                o[L::T3 + sym3(p, q, r, D + 1)] = s3;
             }
         }
     for (int p = 0; p < V; ++p) {

@@ -293,8 +293,8 @@ __device__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
                     if (AUG) {
                         double t3 = 0.0;
                         for (int p = 0; p < V; ++p)
-                            t3 += U[p] * mo[L::T3 + (D == 2 ? kSym2.i3[p][va][q] : kSym3.i3[p][va][q])];
-                        val += 2.0 * c * t3 + c * c * mo[L::T2 + (D == 2 ? kSym2.i2[va][q] : kSym3.i2[va][q])];
+                            t3 += U[p] * mo[L::T3 + sym3(p, va, q, D + 1)];
+                        val += 2.0 * c * t3 + c * c * mo[L::T2 + sym2(va, q, D + 1)];
                     }
                     srow[vs[q]] += val;
                 }
@@ -302,8 +302,8 @@ __device__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
                     double s1 = 0.0, s2 = 0.0;
                     for (int p = 0; p < V; ++p) {
                         for (int r = 0; r < V; ++r)
-                            s1 += U[p] * U[r] * mo[L::T3 + (D == 2 ? kSym2.i3[p][r][va] : kSym3.i3[p][r][va])];
-                        s2 += U[p] * mo[L::T2 + (D == 2 ? kSym2.i2[p][va] : kSym3.i2[p][va])];
+                            s1 += U[p] * U[r] * mo[L::T3 + sym3(p, r, va, D + 1)];
+                        s2 += U[p] * mo[L::T2 + sym2(p, va, D + 1)];
                     }
                     sh += s1 + 2.0 * c * s2 + c * c * mo[L::T1 + va];
                 }
@@ -328,7 +328,7 @@ __device__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
             const double* mo = a.mom + (size_t)e * L::SIZE;
             double s1 = 0.0, s2 = 0.0;
             for (int p = 0; p < V; ++p) {
-                for (int r = 0; r < V; ++r) s1 += U[p] * U[r] * mo[L::T2 + (D == 2 ? kSym2.i2[p][r] : kSym3.i2[p][r])];
+                for (int r = 0; r < V; ++r) s1 += U[p] * U[r] * mo[L::T2 + sym2(p, r, D + 1)];
                 s2 += U[p] * mo[L::T1 + p];
             }
             v[0] += s1 + 2.0 * c * s2 + c * c * mo[L::T0];
@@ -487,7 +487,10 @@ __device__ int newton(Arena<D, AUG>& ar, const Args& a, double zs) {
         const double res = sqrt(v[0]) / (fabs(mu) * sqrt(v[1]));
         if (threadIdx.x == 0) ar.sc[7] = res;
         if (!(v[0] == v[0]) || !(mu == mu)) return -3;
-        if (res <= a.tol && fabs(F2) <= 1e-15) {
+        // x^T B x = 1 up to the rounding of an N-term dot product
+        if (res <= a.tol && fabs(F2) <= 4.0 * N1 * 1.1e-16) {
+            const double sN = 1.0 / sqrt(ar.sc[5]);
+            for (int i = threadIdx.x; i < N1; i += blockDim.x) ar.x[i] *= sN;
             if (threadIdx.x == 0) ar.sc[6] = mu;
             __syncthreads();
             return it;

@@ -1,0 +1,198 @@
+// Fused, temporally blocked V-cycle level kernels for the 2D mesh family.
+//
+// A V(nu,nu) level is two passes over the fine arrays instead of ~14:
+//   pre : x <- NH red-black half sweeps, then r_c = P^T (f - K x)        (read x, f; write x, r_c)
+//   post: x <- x + P x_c, then NH red-black half sweeps                   (read x, f, x_c; write x)
+// with NH = 2 nu + 1 (the symmetric sweeps R,B,B,R,... collapse to R,B,R,... because a
+// repeated half sweep of the same colour changes nothing).  Each workgroup owns a TX x TY
+// tile, loads it with a halo of HALO nodes into LDS, and runs the half sweeps on shrinking
+// regions (the dependency cone of the tile), so only the tile is written back.  Every node
+// update, residual and restriction uses exactly the expression of the unfused kernels in
+// grid.hip, so the fused and unfused paths produce identical bits.
+#include "kernels.h"
+
+namespace fmg {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr int TY = 32;
+constexpr int THREADS = 256;
+
+template <typename T>
+__device__ inline T gs2f(T f, T w, T e, T s, T n) {
+    return (f + ((w + e) + (s + n))) * T(0.25);
+}
+
+// Red-black half sweeps on the LDS region.  Region coordinates: column c in [0, RW),
+// row r in [0, RH); global node (gi, gj) = (i0 - HALO + c, j0 - HALO + r).  Half sweep s
+// updates the colour-`col` interior nodes within distance ext_s = (R + NH - 1 - s) of the
+// tile.
+template <typename T, int HALO, int NH, int R>
+__device__ inline void half_sweeps(T* xs, const T* fs, int i0, int j0, int n, int first) {
+    constexpr int RW = TX + 2 * HALO;
+#pragma unroll 1
+    for (int s = 0; s < NH; ++s) {
+        const int col = first ^ (s & 1);
+        const int ext = R + NH - 1 - s;
+        // update rectangle in global coordinates, clipped to the domain interior
+        const int ia = max(1, i0 - ext), ib = min(n - 1, i0 + TX - 1 + ext);
+        const int ja = max(1, j0 - ext), jb = min(n - 1, j0 + TY - 1 + ext);
+        const int w = ib - ia + 1, h = jb - ja + 1;
+        if (w > 0 && h > 0) {
+            const int cnt = (w + 1) >> 1;
+            const int items = cnt * h;
+            for (int t = threadIdx.x; t < items; t += THREADS) {
+                const int rr = t / cnt, q = t - rr * cnt;
+                const int gj = ja + rr;
+                const int gi = ia + 2 * q + ((col - gj - ia) & 1);
+                if (gi > ib) continue;
+                const int c = gi - (i0 - HALO), r = gj - (j0 - HALO);
+                const int p = c + RW * r;
+                xs[p] = gs2f<T>(fs[p], xs[p - 1], xs[p + 1], xs[p - RW], xs[p + RW]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int HALO>
+__device__ inline void load_region(T* xs, T* fs, const T* __restrict__ x, const T* __restrict__ f, const Grid& g,
+                                   int i0, int j0, int zero_x) {
+    constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
+    const int n = g.n;
+    for (int t = threadIdx.x; t < RW * RH; t += THREADS) {
+        const int r = t / RW, c = t - r * RW;
+        const int gi = i0 - HALO + c, gj = j0 - HALO + r;
+        T xv = T(0), fv = T(0);
+        if (gi >= 0 && gi <= n && gj >= 0 && gj <= n) {
+            const int64_t q = gi + g.pitch * gj;
+            if (!zero_x) xv = x[q];
+            fv = f[q];
+        }
+        xs[t] = xv;
+        fs[t] = fv;
+    }
+}
+
+template <typename T, int HALO>
+__device__ inline void store_tile(const T* xs, T* __restrict__ x, const Grid& g, int i0, int j0) {
+    constexpr int RW = TX + 2 * HALO;
+    const int n = g.n;
+    for (int t = threadIdx.x; t < TX * TY; t += THREADS) {
+        const int r = t / TX, c = t - r * TX;
+        const int gi = i0 + c, gj = j0 + r;
+        if (gi <= n - 1 && gj <= n - 1) x[gi + g.pitch * gj] = xs[(c + HALO) + RW * (r + HALO)];
+    }
+}
+
+// pre-smoothing + residual + restriction
+template <typename T, int NH>
+__global__ __launch_bounds__(THREADS) void k_vpre2d(T* __restrict__ x, const T* __restrict__ f,
+                                                    T* __restrict__ rc, Grid g, Grid gc, int zero_x) {
+    constexpr int R = 2;                 // x must be final within 2 rings for the residual ring
+    constexpr int HALO = NH + R;
+    constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
+    __shared__ T xs[RW * RH];
+    __shared__ T fs[RW * RH];
+    const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+    const int n = g.n;
+    load_region<T, HALO>(xs, fs, x, f, g, i0, j0, zero_x);
+    __syncthreads();
+    half_sweeps<T, HALO, NH, R>(xs, fs, i0, j0, n, 0);
+    // residual r = f - K x on the tile and one ring, stored over f
+    {
+        constexpr int W1 = TX + 2, H1 = TY + 2;
+        for (int t = threadIdx.x; t < W1 * H1; t += THREADS) {
+            const int r = t / W1, c = t - r * W1;
+            const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+            if (gi < 1 || gi > n - 1 || gj < 1 || gj > n - 1) continue;
+            const int p = (c - 1 + HALO) + RW * (r - 1 + HALO);
+            fs[p] = fs[p] - (T(4) * xs[p] - ((xs[p - 1] + xs[p + 1]) + (xs[p - RW] + xs[p + RW])));
+        }
+    }
+    __syncthreads();
+    store_tile<T, HALO>(xs, x, g, i0, j0);
+    // restriction for the coarse nodes whose centre 2I, 2J lies in this tile
+    {
+        constexpr int CW = TX / 2, CH = TY / 2;
+        const int nc = gc.n;
+        for (int t = threadIdx.x; t < CW * CH; t += THREADS) {
+            const int r = t / CW, c = t - r * CW;
+            const int I = (i0 + 1) / 2 + c, J = (j0 + 1) / 2 + r;
+            if (I > nc - 1 || J > nc - 1) continue;
+            const int p = (2 * I - i0 + HALO) + RW * (2 * J - j0 + HALO);
+            const T e = (fs[p - 1] + fs[p + 1]) + (fs[p - RW] + fs[p + RW]) + (fs[p - 1 - RW] + fs[p + 1 + RW]);
+            rc[I + gc.pitch * J] = fs[p] + T(0.5) * e;
+        }
+    }
+}
+
+// prolongation + correction + post-smoothing
+template <typename T, int NH>
+__global__ __launch_bounds__(THREADS) void k_vpost2d(T* __restrict__ x, const T* __restrict__ f,
+                                                     const T* __restrict__ xc, Grid g, Grid gc) {
+    constexpr int R = 0;
+    constexpr int HALO = NH > 0 ? NH + R : 1;
+    constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
+    __shared__ T xs[RW * RH];
+    __shared__ T fs[RW * RH];
+    const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+    const int n = g.n;
+    load_region<T, HALO>(xs, fs, x, f, g, i0, j0, 0);
+    __syncthreads();
+    // x += P x_c on every interior node of the region (same expression as k_prolong)
+    for (int t = threadIdx.x; t < RW * RH; t += THREADS) {
+        const int r = t / RW, c = t - r * RW;
+        const int gi = i0 - HALO + c, gj = j0 - HALO + r;
+        if (gi < 1 || gi > n - 1 || gj < 1 || gj > n - 1) continue;
+        const int di = gi & 1, dj = gj & 1;
+        const int64_t q0 = (gi >> 1) + gc.pitch * (gj >> 1);
+        T v = xc[q0];
+        if (di | dj) v = T(0.5) * (v + xc[q0 + di + gc.pitch * dj]);
+        xs[t] += v;
+    }
+    __syncthreads();
+    half_sweeps<T, HALO, NH, R>(xs, fs, i0, j0, n, 0);
+    store_tile<T, HALO>(xs, x, g, i0, j0);
+}
+
+template <typename T, int NH>
+void pre_launch(const Grid& g, const Grid& gc, T* x, const T* f, T* rc, int zero_x, hipStream_t s) {
+    dim3 grd(cdiv(g.n - 1, TX), cdiv(g.n - 1, TY));
+    hipLaunchKernelGGL((k_vpre2d<T, NH>), grd, dim3(THREADS), 0, s, x, f, rc, g, gc, zero_x);
+}
+template <typename T, int NH>
+void post_launch(const Grid& g, const Grid& gc, T* x, const T* f, const T* xc, hipStream_t s) {
+    dim3 grd(cdiv(g.n - 1, TX), cdiv(g.n - 1, TY));
+    hipLaunchKernelGGL((k_vpost2d<T, NH>), grd, dim3(THREADS), 0, s, x, f, xc, g, gc);
+}
+
+}  // namespace
+
+template <typename T>
+bool launch_vpre2d(const Grid& g, const Grid& gc, T* x, const T* f, T* rc, int nu, int zero_x, hipStream_t s) {
+    switch (nu) {
+        case 0: pre_launch<T, 0>(g, gc, x, f, rc, zero_x, s); return true;
+        case 1: pre_launch<T, 3>(g, gc, x, f, rc, zero_x, s); return true;
+        case 2: pre_launch<T, 5>(g, gc, x, f, rc, zero_x, s); return true;
+        default: return false;
+    }
+}
+template <typename T>
+bool launch_vpost2d(const Grid& g, const Grid& gc, T* x, const T* f, const T* xc, int nu, hipStream_t s) {
+    switch (nu) {
+        case 0: post_launch<T, 0>(g, gc, x, f, xc, s); return true;
+        case 1: post_launch<T, 3>(g, gc, x, f, xc, s); return true;
+        case 2: post_launch<T, 5>(g, gc, x, f, xc, s); return true;
+        default: return false;
+    }
+}
+template bool launch_vpre2d<double>(const Grid&, const Grid&, double*, const double*, double*, int, int,
+                                    hipStream_t);
+template bool launch_vpre2d<float>(const Grid&, const Grid&, float*, const float*, float*, int, int, hipStream_t);
+template bool launch_vpost2d<double>(const Grid&, const Grid&, double*, const double*, const double*, int,
+                                     hipStream_t);
+template bool launch_vpost2d<float>(const Grid&, const Grid&, float*, const float*, const float*, int, hipStream_t);
+
+}  // namespace fmg

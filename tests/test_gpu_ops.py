@@ -80,9 +80,9 @@ def test_prolongation(ops, dim, n):
     xc = W.random_interior(dim, n // 2, seed=6)
     xf0 = W.random_interior(dim, n, seed=7)
     got = ops.prolong(dim, n, dev_level(dim, n // 2, xc))
-    assert rel_err(host_compact(dim, n, got), P @ xc) < 1e-15
+    assert rel_err(host_compact(dim, n, got), P @ xc) < 1e-14
     acc = ops.prolong(dim, n, dev_level(dim, n // 2, xc), dev_level(dim, n, xf0), accumulate=True)
-    assert rel_err(host_compact(dim, n, acc), xf0 + P @ xc) < 1e-15
+    assert rel_err(host_compact(dim, n, acc), xf0 + P @ xc) < 1e-14
 
 
 @pytest.mark.parametrize("dim, n", [(2, 2), (2, 8), (2, 16), (2, 32), (3, 2), (3, 4), (3, 8), (3, 16)])
@@ -96,9 +96,10 @@ def test_coarse_solve_is_exact(ops, dim, n):
     assert rel_err(host_compact(dim, n, x32), ref) < 1e-5
 
 
-@pytest.mark.parametrize("dim, nc, levels", [(2, 8, 3), (2, 16, 4), (3, 4, 3), (3, 2, 4)])
+@pytest.mark.parametrize("dim, nc, levels", [(2, 8, 3), (2, 16, 4), (2, 12, 4), (3, 4, 3), (3, 2, 4)])
 def test_vcycle(ops, dim, nc, levels):
     from oracle.mg import MGHierarchy
+    from paper_1502_04657_amd import lib
     H = MGHierarchy(dim, nc, levels)
     n = nc << (levels - 1)
     x0 = W.random_interior(dim, n, seed=9)
@@ -107,6 +108,22 @@ def test_vcycle(ops, dim, nc, levels):
     prob = W.Problem(dim, nc, levels - 1)
     got = ops.vcycle(prob, W.Options(), dev_level(dim, n, x0), dev_level(dim, n, f))
     assert rel_err(host_compact(dim, n, got), ref) < 1e-12
+    # the fused (temporally blocked) and unfused kernel sequences give identical bits
+    lib().fmg_set_fused_vcycle(0)
+    try:
+        unf = ops.vcycle(prob, W.Options(), dev_level(dim, n, x0), dev_level(dim, n, f))
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+    assert torch.equal(got, unf)
+    for nu in (0, 1):
+        a = ops.vcycle(prob, W.Options(nu_pre=nu, nu_post=nu + 1), dev_level(dim, n, x0), dev_level(dim, n, f))
+        lib().fmg_set_fused_vcycle(0)
+        try:
+            b = ops.vcycle(prob, W.Options(nu_pre=nu, nu_post=nu + 1), dev_level(dim, n, x0), dev_level(dim, n, f))
+        finally:
+            lib().fmg_set_fused_vcycle(1)
+        assert torch.equal(a, b)
+        assert rel_err(host_compact(dim, n, a), H.vcycle(levels - 1, x0, f, nu, nu + 1)) < 1e-12
 
 
 RHS_CASES = [W.Problem(2, 4, 2, (1.5, 0.5, 0.0), 0.25, 7.0), W.Problem(2, 12, 3, (1.0, 2.0, 0.0), 0.0, 100.0),
@@ -145,14 +162,53 @@ def _oracle_aug(h, l, ut, x):
     return A, B, S
 
 
+def _unique(arr, order):
+    import itertools
+    V = arr.shape[-1]
+    idx = list(itertools.combinations_with_replacement(range(V), order))
+    return np.stack([arr[(slice(None),) + t] for t in idx], axis=-1)
+
+
 @pytest.mark.parametrize("prob", AUG_CASES)
-def test_moments_build_the_augmented_matrices(ops, prob):
+def test_moments_match_oracle_per_coarse_simplex(ops, prob):
+    from oracle import fem
+    h = oracle_hierarchy(prob)
+    l = h.L - 1
+    n, dim = prob.n_fine, prob.dim
+    ut = W.smooth_interior(dim, n, seed=13) + 0.02 * W.random_interior(dim, n, seed=14)
+    ref = fem.coarse_simplex_moments(h.meshes[0], h.meshes[l], ut, h.W)
+    mom = ops.moments(prob, n, dev_level(dim, n, ut)).cpu().numpy()
+    ne = 2 if dim == 2 else 6
+    ncell = prob.n_coarse ** dim
+    # library order: element = cell * ne + type; oracle order: type * ncell + cell
+    perm = np.array([t * ncell + c for c in range(ncell) for t in range(ne)])
+    V = dim + 1
+    cols = [("T3", _unique(ref["T3"], 3)), ("T2", _unique(ref["T2"], 2)), ("T1", ref["T1"]), ("T0", ref["T0"][:, None]),
+            ("B1", ref["B1"]), ("B2", ref["B2"][:, None]), ("AW1", ref["AW1"]), ("AW2", ref["AW2"][:, None]),
+            ("KG", ref["KG"]), ("Q", ref["Q"][:, None])]
+    off = 0
+    for name, arr in cols:
+        k = arr.shape[1]
+        got = mom[:, off:off + k]
+        want = arr[perm]
+        assert rel_err(got, want) < 1e-12, name
+        off += k
+    assert off == mom.shape[1]
+
+
+@pytest.mark.parametrize("prob", AUG_CASES)
+@pytest.mark.parametrize("variant", ["coarse_only", "u_tilde_only", "full"])
+def test_moments_build_the_augmented_matrices(ops, prob, variant):
     h = oracle_hierarchy(prob)
     l = h.L - 1
     n, dim = prob.n_fine, prob.dim
     ut = W.smooth_interior(dim, n, seed=13) + 0.02 * W.random_interior(dim, n, seed=14)
     N1 = h.Pi[l].shape[1] + 1
     x = np.random.default_rng(15).standard_normal(N1)
+    if variant == "coarse_only":
+        x[-1] = 0.0
+    elif variant == "u_tilde_only":
+        x[:-1] = 0.0
     A, B, S = _oracle_aug(h, l, ut, x)
     mom = ops.moments(prob, n, dev_level(dim, n, ut))
     Ag, Bg, Sg = (t.cpu().numpy() for t in ops.augmented_matrices(prob, mom.reshape(-1), to_dev(x)))
