@@ -135,7 +135,7 @@ def main():
                       "precision": "fp64", "global_batch": 1},
            "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
            "lambda": res.lam, "lambda_rq": res.lambda_rq, "steps_total": res.steps_total,
-           "newton_total": res.newton_total,
+           "newton_total": res.newton_total, "factorizations": res.factor_total,
            "lambda_rel_err_vs_oracle": (abs(res.lam - lam_ref) / lam_ref) if lam_ref else None}
     if not args.no_mixed:
         print("bench: mixed precision", file=sys.stderr, flush=True)

@@ -92,7 +92,7 @@ typedef struct {
     int32_t newton_total; /* Newton iterations (coarse step + every augmented solve)      */
     double  seconds;      /* host wall time of the call                                   */
     int32_t history_len;  /* entries in history[]                                         */
-    int32_t reserved;
+    int32_t factor_total; /* banded LDL^T factorisations of the small solves (incl. checks)  */
     double  history[FMG_HISTORY_MAX]; /* lambda after the coarse step and after every      */
                                       /* correction step, in execution order              */
 } fmg_result;

@@ -82,6 +82,7 @@ class Result:
     newton_total: int
     seconds: float
     history: list
+    factor_total: int = 0
 
 
 class Solver:
@@ -108,7 +109,7 @@ class Solver:
         if check:
             _check(rc)
         out = Result(res.lambda_, res.lambda_rq, res.norm, res.dlambda, res.status, res.levels, res.steps_total,
-                     res.newton_total, res.seconds, list(res.history[: res.history_len]))
+                     res.newton_total, res.seconds, list(res.history[: res.history_len]), res.factor_total)
         return out, u_out
 
 

@@ -28,7 +28,7 @@ class fmg_result(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("lambda_rq", C.c_double), ("norm", C.c_double), ("dlambda", C.c_double),
                 ("status", C.c_int32), ("levels", C.c_int32), ("steps_total", C.c_int32),
                 ("newton_total", C.c_int32), ("seconds", C.c_double), ("history_len", C.c_int32),
-                ("reserved", C.c_int32), ("history", C.c_double * HISTORY_MAX)]
+                ("factor_total", C.c_int32), ("history", C.c_double * HISTORY_MAX)]
 
 
 P = C.c_void_p

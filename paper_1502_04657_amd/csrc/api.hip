@@ -69,7 +69,7 @@ static int check_options(const fmg_options* o) {
 struct Layout {
     int dim, nc, L, mixed;
     std::vector<Grid> g;
-    size_t state, xc, mom, momscr, arena, forms;
+    size_t state, xc, mom, momscr, arena, fac, forms;
     std::vector<size_t> u, b, xv, fv;   // per level (u[0] = xc)
     size_t total;
 };
@@ -101,6 +101,7 @@ static Layout make_layout(int dim, int nc, int levels, int mixed) {
     for (int l = 1; l < levels; ++l) ms = std::max(ms, moments_scratch_bytes(dim, nc, nc << l));
     lo.momscr = take(std::max<size_t>(ms, 256));
     lo.arena = take(small_arena_bytes(dim, nc));
+    lo.fac = take(small_factor_bytes(dim, nc));
     lo.forms = take(sizeof(double) * (kReduceBlocks * 4 + 8));
     lo.total = off;
     return lo;
@@ -139,7 +140,7 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
 
 // one correction step (Algorithm 3.1) on level k
 static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, const fmg_options* opt, int k,
-                           int final_flag, hipStream_t s) {
+                           int final_flag, int certify, hipStream_t s) {
     const Grid& g = lo.g[k];
     const Phys ph = make_phys(prob);
     SmallState* st = at<SmallState>(ws, lo.state);
@@ -163,7 +164,7 @@ static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, 
     double* mom = at<double>(ws, lo.mom);
     launch_moments(lo.dim, lo.nc, g, ph, u, at<double>(ws, lo.momscr), mom, s);
     int rc = launch_aug_newton(lo.dim, lo.nc, ph, opt->newton_max_iter, opt->newton_tol, mom, at<double>(ws, lo.arena),
-                               at<double>(ws, lo.xc), st, final_flag, s);
+                               at<double>(ws, lo.fac), at<double>(ws, lo.xc), st, final_flag, certify, 1, s);
     if (rc) return set_error(rc, "augmented solve launch failed");
     launch_form_u(g, lo.g[0], u, at<double>(ws, lo.xc), &st->c, s);
     return 0;
@@ -231,7 +232,7 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     }
     // Algorithm 3.2 step 1
     int rc = launch_coarse_newton(prob->dim, prob->n_coarse, ph, opt->newton_max_iter, opt->newton_tol,
-                                  at<double>(ws, lo.arena), at<double>(ws, lo.xc), st, s);
+                                  at<double>(ws, lo.arena), at<double>(ws, lo.fac), at<double>(ws, lo.xc), st, s);
     if (rc) return set_error(rc, "coarse solve launch failed");
     // Algorithm 3.2 step 2
     for (int k = 1; k < L; ++k) {
@@ -240,7 +241,9 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
         const bool tol_mode = finest && opt->tol_lambda > 0.0;
         for (int step = 0; step < opt->p; ++step) {
             int flag = tol_mode && step >= std::max(1, opt->p - 1);
-            if ((rc = correction_step(lo, ws, prob, opt, k, flag, s))) return rc;
+            // ground-state check: every finest-level step and the last step of each level
+            int cert = finest || step == opt->p - 1;
+            if ((rc = correction_step(lo, ws, prob, opt, k, flag, cert, s))) return rc;
         }
         if (tol_mode) {
             SmallState h;
@@ -248,7 +251,7 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
                 FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
                 FMG_HIP_CHECK(hipStreamSynchronize(s));
                 if (h.done || h.status != 0 || extra >= opt->max_final_steps) break;
-                if ((rc = correction_step(lo, ws, prob, opt, k, 1, s))) return rc;
+                if ((rc = correction_step(lo, ws, prob, opt, k, 1, 1, s))) return rc;
             }
         }
     }
@@ -270,6 +273,7 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     out->levels = L;
     out->steps_total = h.steps;
     out->newton_total = h.newton_total;
+    out->factor_total = h.fact_total;
     out->history_len = std::min(h.hist_len, FMG_HISTORY_MAX);
     for (int i = 0; i < out->history_len; ++i) out->history[i] = h.hist[i];
     int status = h.status;
@@ -395,7 +399,9 @@ int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* ut, double*
     return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "moments launch failed");
 }
 
-static size_t small_scratch(int dim, int nc) { return align256(sizeof(SmallState)) + align256(small_arena_bytes(dim, nc)); }
+static size_t small_scratch(int dim, int nc) {
+    return align256(sizeof(SmallState)) + align256(small_arena_bytes(dim, nc)) + small_factor_bytes(dim, nc);
+}
 
 int fmg_small_scratch_bytes(int32_t dim, int32_t n_coarse, size_t* bytes) {
     if ((dim != 2 && dim != 3) || n_coarse < 2 || !bytes) return set_error(FMG_EINVAL, "bad arguments");
@@ -425,11 +431,12 @@ static int small_common(const fmg_problem* prob, const fmg_options* opt, double*
     std::memset(&init, 0, sizeof(init));
     SmallState* st = at<SmallState>(scratch, 0);
     double* arena = at<double>(scratch, align256(sizeof(SmallState)));
+    double* fac = at<double>(scratch, align256(sizeof(SmallState)) + align256(small_arena_bytes(prob->dim, prob->n_coarse)));
     FMG_HIP_CHECK(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
     int rc = aug ? launch_aug_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter, opt->newton_tol,
-                                     mom, arena, xc, st, 0, s)
+                                     mom, arena, fac, xc, st, 0, 1, 0, s)
                  : launch_coarse_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter,
-                                        opt->newton_tol, arena, xc, st, s);
+                                        opt->newton_tol, arena, fac, xc, st, s);
     if (rc) return set_error(rc, "small solve launch failed");
     SmallState h;
     FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -66,17 +66,22 @@ struct SmallState {
                           // 4 singular border system, 5 not the ground state
     int32_t fail_step;    // history index of the first failure
     double fail_residual; // relative Newton residual at the first failure
+    int32_t fac_valid;    // the persistent Jacobian factor holds a usable factor
+    int32_t fact_total;   // LDL^T factorisations (Newton, chord refreshes, inertia checks)
     double hist[512];
 };
 size_t small_arena_bytes(int dim, int nc);
+size_t small_factor_bytes(int dim, int nc);   // persistent Jacobian factor
 // Coarse nonlinear eigenproblem (Algorithm 3.2 step 1) -> x_H written into the coarsest
-// padded level array xc_level, lambda into state.
-int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, double* arena,
+// padded level array xc_level, lambda into state.  Ground-state check always on.
+int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, double* arena, double* fac,
                          double* xc_level, SmallState* state, hipStream_t s);
 // Augmented nonlinear eigenproblem (3.6) from the moments of u~ -> x_H into xc_level,
 // c into state->c, lambda into state (history appended, tolerance flag updated).
+// certify: run the ground-state inertia check; reuse: start from the stored factor.
 int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments,
-                      double* arena, double* xc_level, SmallState* state, int final_level, hipStream_t s);
+                      double* arena, double* fac, double* xc_level, SmallState* state, int final_level,
+                      int certify, int reuse, hipStream_t s);
 // Dense augmented matrices A, B, S(x) (row-major (N+1)^2 each) for tests.
 int launch_aug_dump(int dim, int nc, const Phys& ph, const double* moments, const double* x, double* arena,
                     double* A, double* B, double* S, hipStream_t s);
