@@ -120,6 +120,9 @@ int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t*
  *   d_u_out     : device, compact layout, u_len = (n-1)^dim; receives u_h with
  *                 b(u,u) = 1 and int u_h > 0.
  *   out         : host struct, filled on return (also on FMG_ENOCONV).
+ * The coarsest solution and the returned state (last step of a fixed schedule, or the step
+ * that meets tol_lambda) are checked to be the ground state by an inertia count; a failed
+ * check returns FMG_ENOCONV.
  * Errors: FMG_EINVAL (dim not 2/3, n_coarse < 2, n_refine < 0 or > 12, zeta < 0 or
  * non-finite inputs, m/p < 1, nu_pre + nu_post < 1, u_len mismatch), FMG_ENOMEM
  * (workspace too small), FMG_ENOCONV, FMG_ENONFINITE, FMG_EHIP.                            */

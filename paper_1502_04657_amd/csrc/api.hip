@@ -241,8 +241,9 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
         const bool tol_mode = finest && opt->tol_lambda > 0.0;
         for (int step = 0; step < opt->p; ++step) {
             int flag = tol_mode && step >= std::max(1, opt->p - 1);
-            // ground-state check: every finest-level step and the last step of each level
-            int cert = finest || step == opt->p - 1;
+            // ground-state check of the returned state only: the last step of a fixed
+            // schedule, or the step that meets the lambda tolerance
+            int cert = !finest ? 0 : (tol_mode ? (flag ? 2 : 0) : (step == opt->p - 1 ? 1 : 0));
             if ((rc = correction_step(lo, ws, prob, opt, k, flag, cert, s))) return rc;
         }
         if (tol_mode) {
@@ -251,7 +252,7 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
                 FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
                 FMG_HIP_CHECK(hipStreamSynchronize(s));
                 if (h.done || h.status != 0 || extra >= opt->max_final_steps) break;
-                if ((rc = correction_step(lo, ws, prob, opt, k, 1, 1, s))) return rc;
+                if ((rc = correction_step(lo, ws, prob, opt, k, 1, 2, s))) return rc;
             }
         }
     }

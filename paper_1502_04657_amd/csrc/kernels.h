@@ -78,7 +78,8 @@ int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double t
                          double* xc_level, SmallState* state, hipStream_t s);
 // Augmented nonlinear eigenproblem (3.6) from the moments of u~ -> x_H into xc_level,
 // c into state->c, lambda into state (history appended, tolerance flag updated).
-// certify: run the ground-state inertia check; reuse: start from the stored factor.
+// certify: ground-state inertia check (0 never, 1 always, 2 only when the step meets the
+// lambda tolerance); reuse: start from the stored factor.
 int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments,
                       double* arena, double* fac, double* xc_level, SmallState* state, int final_level,
                       int certify, int reuse, hipStream_t s);

@@ -21,6 +21,8 @@
 // geometric stages (factor 8 from a first stage <= 1, the step halved on failure).  When
 // requested, the final state is checked to be the ground state by the inertia of
 // A + zeta S(x) - (mu - eps) B (no negative pivot).
+#include <utility>
+
 #include "kernels.h"
 #include "layout.h"
 
@@ -53,6 +55,62 @@ __device__ inline int cell_vert(int t, int v, int d) {
     return D == 2 ? kCellElemVert2D[t][v][d] : kCellElemVert3D[t][v][d];
 }
 
+// stencil slot of vertex b seen from vertex a in simplex t of a cell (compile time)
+template <int D>
+__host__ __device__ constexpr int qslot_ce(int t, int a, int b) {
+    for (int s = 0; s < Geo<D>::NS; ++s) {
+        bool eq = true;
+        for (int d = 0; d < D; ++d) {
+            const int o = (D == 2) ? kCellElemVert2D[t % 2][b][d] - kCellElemVert2D[t % 2][a][d]
+                                   : kCellElemVert3D[t][b][d] - kCellElemVert3D[t][a][d];
+            eq = eq && (o == ((D == 2) ? kOff2D[s][d] : kOff3D[s][d]));
+        }
+        if (eq) return s;
+    }
+    return -1;
+}
+template <int D, int T, int A, int B>
+struct QSlot {
+    static constexpr int value = qslot_ce<D>(T, A, B);
+    static_assert(value >= 0, "simplex edge outside the stencil");
+};
+template <int D, int T, int V, int Dim>
+struct CellVert {
+    static constexpr int value = (D == 2) ? kCellElemVert2D[T % 2][V % 3][Dim % 2] : kCellElemVert3D[T][V][Dim];
+};
+
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled at compile time
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// f(integral_constant<int, t>) for t = 0 .. N-1 in a loop that is not unrolled (one
+// instance of f per t, selected at run time), which keeps register pressure to one body
+template <int N, typename F>
+__device__ __forceinline__ void rolled_for(F&& f) {
+#pragma unroll 1
+    for (int t = 0; t < N; ++t) {
+        static_for<N>([&](auto tc) {
+            if (decltype(tc)::value == t) f(tc);
+        });
+    }
+}
+// simplices of a cell: unrolled in 2D, rolled in 3D
+template <int D, typename F>
+__device__ __forceinline__ void for_simplices(F&& f) {
+#ifdef FMG_EXP_UNROLL3D
+    static_for<Geo<D>::NE>(f);
+#else
+    if constexpr (D == 2) static_for<Geo<D>::NE>(f);
+    else rolled_for<Geo<D>::NE>(f);
+#endif
+}
+
 struct Args {
     int nc;
     Phys ph;
@@ -65,7 +123,7 @@ struct Args {
     Grid gc;
     SmallState* st;
     int final_level;     // tolerance checks enabled for this step
-    int certify;         // run the ground-state inertia check
+    int certify;         // ground-state inertia check: 0 never, 1 always, 2 when the step meets tol_lambda
     double* fac;         // persistent band factor (N*(w+1) doubles), may be null
     int reuse;           // start from the stored factor when it exists
     // dump mode
@@ -78,6 +136,19 @@ struct Args {
 struct Sizes {
     int m, N, w, N1, np, nel;
 };
+
+// Optional phase timers of the small solves (wall clock, 100 MHz ticks); compiled only
+// with -DFMG_SMALL_TIMING, read back with fmg_debug_small_timers().
+#ifdef FMG_SMALL_TIMING
+__device__ unsigned long long g_small_t[32];
+#define FMG_T0(v) const unsigned long long v = wall_clock64()
+#define FMG_TACC(k, v) do { if (threadIdx.x == 0) atomicAdd(&g_small_t[(AUG ? 0 : 16) + (k)], wall_clock64() - (v)); } while (0)
+#define FMG_TCNT(k) do { if (threadIdx.x == 0) atomicAdd(&g_small_t[(AUG ? 0 : 16) + (k)], 1ull); } while (0)
+#else
+#define FMG_T0(v) do { } while (0)
+#define FMG_TACC(k, v) do { } while (0)
+#define FMG_TCNT(k) do { } while (0)
+#endif
 
 template <int D, bool AUG>
 __host__ __device__ inline Sizes sizes(int nc) {
@@ -95,21 +166,21 @@ __host__ __device__ inline Sizes sizes(int nc) {
 template <int D, bool AUG>
 struct Arena {
     Sizes z;
-    double* Ast; double* Bst; double* Sst; double* band;
+    double* Ast; double* Bst; double* Sst; double* band; double* bandT;
     double* x; double* xs; double* xk; double* y; double* z2; double* F; double* rhs;
-    double* aH; double* bH; double* sH; double* sc; double* I4t;
-    int* nb; int* star; int* enode; int* qslot; int* pairs;
+    double* aH; double* bH; double* sH; double* sc;
+    int* nb; int* pairs;
 
     __device__ void carve(double* base, int nc) {
         z = sizes<D, AUG>(nc);
         constexpr int NS = Geo<D>::NS;
-        constexpr int V = D + 1;
         const int N = z.N;
         double* p = base;
         Ast = p; p += (size_t)N * NS;
         Bst = p; p += (size_t)N * NS;
         Sst = p; p += (size_t)N * NS;
         band = p; p += (size_t)N * (z.w + 1);
+        bandT = p; p += (size_t)N * (z.w + 1);
         x = p; p += N + 2;
         xs = p; p += N + 2;
         xk = p; p += N + 2;
@@ -121,12 +192,8 @@ struct Arena {
         bH = p; p += N;
         sH = p; p += N;
         sc = p; p += 32;
-        I4t = p; p += V * V * V * V;
         int* q = reinterpret_cast<int*>(p);
         nb = q; q += N * NS;
-        star = q; q += N * Geo<D>::NSTAR;
-        enode = q; q += z.nel * V;
-        qslot = q; q += Geo<D>::NE * V * V;
         pairs = q;
     }
 };
@@ -135,10 +202,9 @@ template <int D, bool AUG>
 __host__ __device__ inline size_t arena_bytes_t(int nc) {
     Sizes z = sizes<D, AUG>(nc);
     constexpr int NS = Geo<D>::NS;
-    constexpr int V = D + 1;
     size_t N = z.N;
-    size_t dbl = 3 * N * NS + N * (z.w + 1) + 6 * (N + 2) + 3 * N + 3 * N + 32 + V * V * V * V;
-    size_t ints = N * NS + N * Geo<D>::NSTAR + (size_t)z.nel * V + Geo<D>::NE * V * V + z.np;
+    size_t dbl = 3 * N * NS + 2 * N * (z.w + 1) + 6 * (N + 2) + 3 * N + 3 * N + 32;
+    size_t ints = N * NS + z.np;
     return dbl * sizeof(double) + ints * sizeof(int) + 64;
 }
 
@@ -158,36 +224,47 @@ __device__ inline int node_id(const int* P, int m) {
     return (D == 2) ? (P[0] - 1) + m * (P[1] - 1) : (P[0] - 1) + m * ((P[1] - 1) + m * (P[2] - 1));
 }
 
+// Cells of the coarse mesh in 2^D colour classes (parity of the cell index in every
+// direction): cells of one class share no vertex, so one lane per cell may scatter into
+// the rows of its vertices without atomics, and the summation order is fixed.
+// f(C0, C1, C2, cell) is called for every cell; one barrier after each class.
+template <int D, typename F>
+__device__ __forceinline__ void for_cells_colored(int nc, F&& f) {
+    for (int color = 0; color < (1 << D); ++color) {
+        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
+        const int hx = (nc - px + 1) >> 1, hy = (nc - py + 1) >> 1, hz = (D == 3) ? (nc - pz + 1) >> 1 : 1;
+        const int ncol = hx * hy * hz;
+        for (int q = threadIdx.x; q < ncol; q += kThreads) {
+            const int C0 = px + 2 * (q % hx);
+            const int C1 = py + 2 * ((q / hx) % hy);
+            const int C2 = (D == 3) ? pz + 2 * (q / (hx * hy)) : 0;
+            const int cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
+            f(C0, C1, C2, cl);
+        }
+        __syncthreads();
+    }
+}
+
+// interior node index of vertex V of simplex T in cell (C0, C1, C2), or -1 on the boundary
+template <int D, int T, int V>
+__device__ __forceinline__ int vert_node(int C0, int C1, int C2, int m) {
+    int P[3] = {C0 + CellVert<D, T, V, 0>::value, C1 + CellVert<D, T, V, 1>::value,
+                (D == 3) ? C2 + CellVert<D, T, V, 2>::value : 0};
+    return node_id<D>(P, m);
+}
+
 // ---------------------------------------------------------------------------------------
 // setup: tables, coarse stencils of K + M_W and M, and the u~ border
 template <int D, bool AUG>
-__device__ void setup(Arena<D, AUG>& ar, const Args& a) {
+__device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
     constexpr int NS = Geo<D>::NS;
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
-    constexpr int NSTAR = Geo<D>::NSTAR;
     using L = MomLayout<D>;
     const int N = ar.z.N, m = ar.z.m, nc = a.nc;
     const double H = 1.0 / nc;
     const double Hd = (D == 2) ? H * H : H * H * H;
     const int lane = threadIdx.x;
-    // element vertex -> node table
-    for (int e = lane; e < ar.z.nel; e += kThreads) {
-        const int cl = e / NE, t = e % NE;
-        int C[3] = {cl % nc, (cl / nc) % nc, D == 3 ? cl / (nc * nc) : 0};
-        for (int v = 0; v < V; ++v) {
-            int Q[3] = {0, 0, 0};
-            for (int d = 0; d < D; ++d) Q[d] = C[d] + cell_vert<D>(t, v, d);
-            ar.enode[e * V + v] = node_id<D>(Q, m);
-        }
-    }
-    // stencil slot of vertex q seen from vertex va of a simplex of type t
-    for (int k = lane; k < NE * V * V; k += kThreads) {
-        const int t = k / (V * V), va = (k / V) % V, q = k % V;
-        int o[3] = {0, 0, 0};
-        for (int d = 0; d < D; ++d) o[d] = cell_vert<D>(t, q, d) - cell_vert<D>(t, va, d);
-        ar.qslot[k] = slot_of<D>(o);
-    }
     // LDL^T update pairs (ii >= jj) of the trailing window, ordered by ii
     for (int p = lane; p < ar.z.np; p += kThreads) {
         int ii = 0;
@@ -224,41 +301,32 @@ __device__ void setup(Arena<D, AUG>& ar, const Args& a) {
             ar.Ast[i * NS + s] = (j >= 0) ? kk + Hd * cw : 0.0;
             ar.Bst[i * NS + s] = (j >= 0) ? Hd * m0 : 0.0;
         }
-        // the simplices around node i
-        int cnt = 0;
-        for (int cc = 0; cc < (1 << D); ++cc) {
-            int C[3] = {P[0] - ((cc >> 0) & 1), P[1] - ((cc >> 1) & 1), D == 3 ? P[2] - ((cc >> 2) & 1) : 0};
-            int cl = (D == 2) ? C[0] + nc * C[1] : C[0] + nc * (C[1] + nc * C[2]);
-            for (int t = 0; t < NE; ++t)
-                for (int v = 0; v < V; ++v) {
-                    bool hit = true;
-                    for (int d = 0; d < D; ++d) hit = hit && (C[d] + cell_vert<D>(t, v, d) == P[d]);
-                    if (hit && cnt < NSTAR) ar.star[i * NSTAR + cnt++] = (cl * NE + t) * V + v;
-                }
-        }
         if (AUG) {
-            double ah = 0.0, bh = 0.0;
-            for (int s = 0; s < NSTAR; ++s) {
-                const int pk = ar.star[i * NSTAR + s];
-                const int e = pk / V, va = pk % V;
-                const double* mo = a.mom + (size_t)e * L::SIZE;
-                ah += mo[L::KG + va] + mo[L::AW1 + va];
-                bh += mo[L::B1 + va];
-            }
-            ar.aH[i] = ah;
-            ar.bH[i] = bh;
+            ar.aH[i] = 0.0;
+            ar.bH[i] = 0.0;
         }
     }
     if (AUG) {
+        __syncthreads();
+        // a(u~, phi_i), b(u~, phi_i) by simplex; a(u~,u~), b(u~,u~), int u~ as sums
         double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        for (int e = lane; e < ar.z.nel; e += kThreads) {
-            const double* mo = a.mom + (size_t)e * L::SIZE;
-            v0 += mo[L::Q] + mo[L::AW2];
-            v1 += mo[L::B2];
-            double s = 0.0;
-            for (int p = 0; p < V; ++p) s += mo[L::B1 + p];
-            v2 += s;
-        }
+        for_cells_colored<D>(nc, [&](int C0, int C1, int C2, int cl) {
+            for_simplices<D>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
+                static_for<V>([&](auto vc) {
+                    constexpr int v = decltype(vc)::value;
+                    const int nd = vert_node<D, t, v>(C0, C1, C2, m);
+                    if (nd >= 0) {
+                        ar.aH[nd] += mo[L::KG + v] + mo[L::AW1 + v];
+                        ar.bH[nd] += mo[L::B1 + v];
+                    }
+                    v2 += mo[L::B1 + v];
+                });
+                v0 += mo[L::Q] + mo[L::AW2];
+                v1 += mo[L::B2];
+            });
+        });
         v0 = wsum(v0); v1 = wsum(v1); v2 = wsum(v2);
         if (lane == 0) {
             ar.sc[0] = v0;  // aU
@@ -282,109 +350,124 @@ __host__ __device__ constexpr double i4e(int p, int r, int a, int b, int D) {
     return num / ((D == 2) ? 720.0 : 5040.0);
 }
 
-// contributions of one simplex to row `va` of S(x) and to the border entry
-template <int D, bool AUG, int VA>
-__device__ inline void elem_row(const double* U, const double* mo, double c, double vol, const int* qs, double* srow,
-                                double& sh) {
+// S(x) on one simplex, row AA: Sr[b] = int u^2 l_AA l_b (u = sum_p U_p l_p + c u~) and,
+// with AUG, the border entry sh = int u^2 u~ l_AA.  UU[sym2(p,r)] = U_p U_r (doubled off
+// the diagonal).
+template <int D, bool AUG, int AA>
+__device__ __forceinline__ void elem_row(const double* U, const double* UU, const double* mo, double c, double vol,
+                                         double* Sr, double& sh) {
     constexpr int V = D + 1;
     using L = MomLayout<D>;
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-        double val = 0.0;
+    for (int bb = 0; bb < V; ++bb) {
+        double v = 0.0;
 #pragma unroll
         for (int p = 0; p < V; ++p)
 #pragma unroll
-            for (int r = 0; r < V; ++r) val += U[p] * U[r] * i4e(p, r, VA, q, D);
-        val *= vol;
+            for (int r = p; r < V; ++r) v += UU[sym2(p, r, V)] * i4e(p, r, AA, bb, D);
+        v *= vol;
         if (AUG) {
             double t3 = 0.0;
 #pragma unroll
-            for (int p = 0; p < V; ++p) t3 += U[p] * mo[L::T3 + sym3(p, VA, q, V)];
-            val += 2.0 * c * t3 + c * c * mo[L::T2 + sym2(VA, q, V)];
+            for (int p = 0; p < V; ++p) t3 += U[p] * mo[L::T3 + sym3(p, AA, bb, V)];
+            v += 2.0 * c * t3 + c * c * mo[L::T2 + sym2(AA, bb, V)];
         }
-        srow[qs[q]] += val;
+        Sr[bb] = v;
     }
     if (AUG) {
         double s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int p = 0; p < V; ++p) {
 #pragma unroll
-            for (int r = 0; r < V; ++r) s1 += U[p] * U[r] * mo[L::T3 + sym3(p, r, VA, V)];
-            s2 += U[p] * mo[L::T2 + sym2(p, VA, V)];
+            for (int r = p; r < V; ++r) s1 += UU[sym2(p, r, V)] * mo[L::T3 + sym3(p, r, AA, V)];
+            s2 += U[p] * mo[L::T2 + sym2(p, AA, V)];
         }
-        sh += s1 + 2.0 * c * s2 + c * c * mo[L::T1 + VA];
+        sh = s1 + 2.0 * c * s2 + c * c * mo[L::T1 + AA];
     }
 }
 
-// S(x): coarse stencil Sst, border sH, corner sc[3]
+// int u^2 u~^2 on one simplex (the corner of S with AUG)
+template <int D>
+__device__ __forceinline__ double elem_corner(const double* U, const double* UU, const double* mo, double c) {
+    constexpr int V = D + 1;
+    using L = MomLayout<D>;
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int p = 0; p < V; ++p) {
+#pragma unroll
+        for (int r = p; r < V; ++r) s1 += UU[sym2(p, r, V)] * mo[L::T2 + sym2(p, r, V)];
+        s2 += U[p] * mo[L::T1 + p];
+    }
+    return s1 + 2.0 * c * s2 + c * c * mo[L::T0];
+}
+
+// vertex rows of a simplex: unrolled in 2D, rolled in 3D (register pressure)
+template <int D, typename F>
+__device__ __forceinline__ void for_vertices(F&& f) {
+    if constexpr (D == 2) static_for<D + 1>(f);
+    else rolled_for<D + 1>(f);
+}
+
+// S(x): coarse stencil Sst, border sH, corner sc[3]; simplex by simplex, cells in colour
+// classes so that the scatter into the vertex rows needs no atomics
 template <int D, bool AUG>
-__device__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
+__device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
     constexpr int NS = Geo<D>::NS;
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
-    constexpr int NSTAR = Geo<D>::NSTAR;
     using L = MomLayout<D>;
-    const int N = ar.z.N, nc = a.nc;
+    const int N = ar.z.N, nc = a.nc, m = ar.z.m;
     const double H = 1.0 / nc;
     const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
     const double c = AUG ? x[N] : 0.0;
     const int lane = threadIdx.x;
-    for (int i = lane; i < N; i += kThreads) {
-        double srow[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) srow[s] = 0.0;
-        double sh = 0.0;
-        for (int s = 0; s < NSTAR; ++s) {
-            const int pk = ar.star[i * NSTAR + s];
-            const int e = pk / V, va = pk % V, t = e % NE;
-            double U[V];
-            int qs[V];
-#pragma unroll
-            for (int p = 0; p < V; ++p) {
-                const int j = ar.enode[e * V + p];
-                U[p] = (j >= 0) ? x[j] : 0.0;
-                qs[p] = ar.qslot[(t * V + va) * V + p];
-            }
-            const double* mo = AUG ? a.mom + (size_t)e * L::SIZE : nullptr;
-            switch (va) {
-                case 0: elem_row<D, AUG, 0>(U, mo, c, vol, qs, srow, sh); break;
-                case 1: elem_row<D, AUG, 1>(U, mo, c, vol, qs, srow, sh); break;
-                case 2: elem_row<D, AUG, 2>(U, mo, c, vol, qs, srow, sh); break;
-                default: if (D == 3) elem_row<D, AUG, (D == 3 ? 3 : 2)>(U, mo, c, vol, qs, srow, sh); break;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < NS; ++s) ar.Sst[(size_t)i * NS + s] = (ar.nb[i * NS + s] >= 0) ? srow[s] : 0.0;
-        if (AUG) ar.sH[i] = sh;
-    }
-    if (AUG) {
-        double v = 0.0;
-        for (int e = lane; e < ar.z.nel; e += kThreads) {
-            double U[V];
-#pragma unroll
-            for (int p = 0; p < V; ++p) {
-                const int j = ar.enode[e * V + p];
-                U[p] = (j >= 0) ? x[j] : 0.0;
-            }
-            const double* mo = a.mom + (size_t)e * L::SIZE;
-            double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-            for (int p = 0; p < V; ++p) {
-#pragma unroll
-                for (int r = 0; r < V; ++r) s1 += U[p] * U[r] * mo[L::T2 + sym2(p, r, V)];
-                s2 += U[p] * mo[L::T1 + p];
-            }
-            v += s1 + 2.0 * c * s2 + c * c * mo[L::T0];
-        }
-        v = wsum(v);
-        if (lane == 0) ar.sc[3] = v;  // sU
-    }
+    for (int t = lane; t < N * NS; t += kThreads) ar.Sst[t] = 0.0;
+    if (AUG)
+        for (int i = lane; i < N; i += kThreads) ar.sH[i] = 0.0;
     __syncthreads();
+    double sU = 0.0;
+    for_cells_colored<D>(nc, [&](int C0, int C1, int C2, int cl) {
+        for_simplices<D>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            int nd[V];
+            double U[V];
+            static_for<V>([&](auto vc) {
+                constexpr int v = decltype(vc)::value;
+                nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
+                U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
+            });
+            double UU[V * (V + 1) / 2];
+#pragma unroll
+            for (int p = 0; p < V; ++p)
+#pragma unroll
+                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+            const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
+            for_vertices<D>([&](auto ac) {
+                constexpr int aa = decltype(ac)::value;
+                if (nd[aa] >= 0) {
+                    double Sr[V], sh = 0.0;
+                    elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
+                    double* row = ar.Sst + (size_t)nd[aa] * NS;
+                    static_for<V>([&](auto bc) {
+                        constexpr int bb = decltype(bc)::value;
+                        if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
+                    });
+                    if (AUG) ar.sH[nd[aa]] += sh;
+                }
+            });
+            if (AUG) sU += elem_corner<D>(U, UU, mo, c);
+        });
+    });
+    if (AUG) {
+        sU = wsum(sU);
+        if (lane == 0) ar.sc[3] = sU;
+        __syncthreads();
+    }
 }
 
 // y = (A + zs S) x, z = B x (with borders); sc[4] = x^T y, sc[5] = x^T z
 template <int D, bool AUG>
-__device__ void apply(Arena<D, AUG>& ar, double zs, const double* x, double* y, double* z) {
+__device__ __forceinline__ void apply(Arena<D, AUG>& ar, double zs, const double* x, double* y, double* z) {
     constexpr int NS = Geo<D>::NS;
     const int N = ar.z.N;
     const double c = AUG ? x[N] : 0.0;
@@ -428,7 +511,7 @@ __device__ void apply(Arena<D, AUG>& ar, double zs, const double* x, double* y, 
 
 // band <- Ast + alpha Sst - sigma Bst   (lower band, row-major, band[i*(w+1)+k] = J(i,i-k))
 template <int D, bool AUG>
-__device__ void fill_band(Arena<D, AUG>& ar, double alpha, double sigma) {
+__device__ __forceinline__ void fill_band(Arena<D, AUG>& ar, double alpha, double sigma) {
     constexpr int NS = Geo<D>::NS;
     const int N = ar.z.N, W1 = ar.z.w + 1;
     for (int t = threadIdx.x; t < N * W1; t += kThreads) ar.band[t] = 0.0;
@@ -443,10 +526,21 @@ __device__ void fill_band(Arena<D, AUG>& ar, double alpha, double sigma) {
     __syncthreads();
 }
 
+// column copy of the factor: bandT[k*(w+1) + t] = band[(k+t)*(w+1) + t] (t > 0), d_k at t = 0
+template <int D, bool AUG>
+__device__ __forceinline__ void transpose_band(Arena<D, AUG>& ar) {
+    const int N = ar.z.N, W1 = ar.z.w + 1;
+    for (int t = threadIdx.x; t < N * W1; t += kThreads) {
+        const int i = t / W1, q = t - i * W1;
+        if (i - q >= 0) ar.bandT[(size_t)(i - q) * W1 + q] = ar.band[t];
+    }
+    __syncthreads();
+}
+
 // In-place banded LDL^T without pivoting; afterwards band[i][0] = d_i and band[i][t] =
 // l_{i,i-t}.  Returns the number of negative pivots, or -1 for a (numerically) zero pivot.
 template <int D, bool AUG>
-__device__ int ldlt(Arena<D, AUG>& ar) {
+__device__ __forceinline__ int ldlt(Arena<D, AUG>& ar) {
     const int N = ar.z.N, w = ar.z.w, W1 = w + 1;
     double* b = ar.band;
     double scale = 0.0;
@@ -475,6 +569,7 @@ __device__ int ldlt(Arena<D, AUG>& ar) {
         if (q > 0 && i - q >= 0) b[t] /= b[(size_t)(i - q) * W1];
     }
     __syncthreads();
+    transpose_band<D, AUG>(ar);
     return neg;
 }
 
@@ -485,13 +580,14 @@ __device__ inline double readlane_d(double v, int lane) {
 }
 
 // Solve (L D L^T) X = R for R right-hand sides stored as rhs[q*N + i].  Row i lives in
-// lane i % 64, register slot i / 64; the value of the eliminated row is broadcast with
-// readlane, so the dependency chain never goes through memory.  Needs N <= 64*SMAX and a
-// band half-width w <= 128 (otherwise the LDS variant below is used).
-constexpr int SMAX = 16;
-
-template <int R>
-__device__ void band_solve_reg(const double* __restrict__ b, int N, int w, double* rhs) {
+// lane i % 64, register slot i / 64; the eliminated value is broadcast with readlane, so
+// the dependency chain never goes through memory.  With a half-width w < 64 every lane
+// owns at most one of the rows an elimination step touches, so a step is one coefficient
+// load (issued a step ahead), 2R readlanes and 2R FMAs.  Needs N <= 64*SMAX.  The forward
+// sweep reads the column copy cT (cT[k*(w+1)+t] = l_{k+t,k}), the backward sweep the rows.
+template <int R, int SMAX>
+__device__ __forceinline__ void band_solve_reg(const double* __restrict__ b, const double* __restrict__ cT, int N,
+                                               int w, double* rhs) {
     const int W1 = w + 1;
     const int lane = threadIdx.x;
     const int S = (N + 63) >> 6;
@@ -502,26 +598,38 @@ __device__ void band_solve_reg(const double* __restrict__ b, int N, int w, doubl
 #pragma unroll
         for (int q = 0; q < R; ++q) y[q][s] = (s < S && i < N) ? rhs[q * N + i] : 0.0;
     }
+    // coefficient of this lane's row for forward step k: l_{i,k}, i = k + t
+    auto fcoef = [&](int k) -> double {
+        const int kk = k & 63, s = k >> 6;
+        const int i = (lane > kk) ? 64 * s + lane : 64 * (s + 1) + lane;
+        const int t = i - k;
+        return (t <= w && i < N) ? cT[(size_t)k * W1 + t] : 0.0;
+    };
+    // coefficient of this lane's row for backward step k: l_{k,j}, j = k - t
+    auto bcoef = [&](int k) -> double {
+        const int kk = k & 63, s = k >> 6;
+        const int j = (lane < kk) ? 64 * s + lane : 64 * (s - 1) + lane;
+        const int t = k - j;
+        return (t <= w && j >= 0) ? b[(size_t)k * W1 + t] : 0.0;
+    };
     // forward: unit lower L
+    double lnext = fcoef(0);
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
         if (s < S) {
             for (int kk = 0; kk < 64; ++kk) {
                 const int k = 64 * s + kk;
                 if (k >= N) break;
-                double yk[R];
+                const double l = lnext;
+                if (k + 1 < N) lnext = fcoef(k + 1);
+                const bool here = lane > kk;
+                const double l0 = here ? l : 0.0;
+                const double l1 = here ? 0.0 : l;
 #pragma unroll
-                for (int q = 0; q < R; ++q) yk[q] = readlane_d(y[q][s], kk);
-#pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    if (s + o < SMAX) {
-                        const int i = 64 * (s + o) + lane;
-                        if (i > k && i <= k + w && i < N) {
-                            const double l = b[(size_t)i * W1 + (i - k)];
-#pragma unroll
-                            for (int q = 0; q < R; ++q) y[q][s + o] -= l * yk[q];
-                        }
-                    }
+                for (int q = 0; q < R; ++q) {
+                    const double yk = readlane_d(y[q][s], kk);
+                    y[q][s] = fma(-l0, yk, y[q][s]);
+                    if (s + 1 < SMAX) y[q][s + 1] = fma(-l1, yk, y[q][s + 1]);
                 }
             }
         }
@@ -537,25 +645,23 @@ __device__ void band_solve_reg(const double* __restrict__ b, int N, int w, doubl
         }
     }
     // backward: unit upper L^T
+    lnext = bcoef(N - 1);
 #pragma unroll
     for (int s = SMAX - 1; s >= 0; --s) {
         if (s < S) {
             for (int kk = 63; kk >= 0; --kk) {
                 const int k = 64 * s + kk;
                 if (k >= N) continue;
-                double xk[R];
+                const double l = lnext;
+                if (k > 0) lnext = bcoef(k - 1);
+                const bool here = lane < kk;
+                const double l0 = here ? l : 0.0;
+                const double l1 = here ? 0.0 : l;
 #pragma unroll
-                for (int q = 0; q < R; ++q) xk[q] = readlane_d(y[q][s], kk);
-#pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    if (s - o >= 0) {
-                        const int j = 64 * (s - o) + lane;
-                        if (j < k && j >= k - w) {
-                            const double l = b[(size_t)k * W1 + (k - j)];
-#pragma unroll
-                            for (int q = 0; q < R; ++q) y[q][s - o] -= l * xk[q];
-                        }
-                    }
+                for (int q = 0; q < R; ++q) {
+                    const double xk = readlane_d(y[q][s], kk);
+                    y[q][s] = fma(-l0, xk, y[q][s]);
+                    if (s >= 1) y[q][s - 1] = fma(-l1, xk, y[q][s - 1]);
                 }
             }
         }
@@ -573,7 +679,7 @@ __device__ void band_solve_reg(const double* __restrict__ b, int N, int w, doubl
 
 // LDS variant for large problems (one barrier per elimination step)
 template <int D, bool AUG>
-__device__ void ldlt_solve_lds(Arena<D, AUG>& ar, double* rhs, int R) {
+__device__ __forceinline__ void ldlt_solve_lds(Arena<D, AUG>& ar, double* rhs, int R) {
     const int N = ar.z.N, w = ar.z.w, W1 = w + 1;
     const double* b = ar.band;
     for (int k = 0; k < N; ++k) {
@@ -601,26 +707,39 @@ __device__ void ldlt_solve_lds(Arena<D, AUG>& ar, double* rhs, int R) {
     }
 }
 
-template <int D, bool AUG>
-__device__ void ldlt_solve(Arena<D, AUG>& ar, double* rhs, int R) {
+template <int D, bool AUG, int R>
+__device__ __forceinline__ void ldlt_solve(Arena<D, AUG>& ar, double* rhs) {
     const int N = ar.z.N, w = ar.z.w;
     __syncthreads();
-    if (N <= 64 * SMAX && w <= 128) {
-        if (R == 1) band_solve_reg<1>(ar.band, N, w, rhs);
-        else if (R == 2) band_solve_reg<2>(ar.band, N, w, rhs);
-        else band_solve_reg<3>(ar.band, N, w, rhs);
-    } else {
-        ldlt_solve_lds<D, AUG>(ar, rhs, R);
-    }
+    // the register sweeps only for an LDS-resident arena (the test folds at compile time);
+    // the global-memory variant serves large problems and keeps its register budget
+#if defined(__HIP_DEVICE_COMPILE__)
+    const bool lds = __builtin_amdgcn_is_shared(reinterpret_cast<const void*>(ar.band));
+#else
+    const bool lds = false;   // host pass: device code is not generated
+#endif
+    if (lds && N <= 256 && w < 64) band_solve_reg<R, 4>(ar.band, ar.bandT, N, w, rhs);
+    else ldlt_solve_lds<D, AUG>(ar, rhs, R);
 }
 
 // One Newton solve at coupling zs from the iterate in ar.x, using (and refreshing) the
 // factor in ar.band.  `have` says whether band already holds a usable factor.  Returns
 // iterations >= 0 on convergence, or -reason.  mu in sc[6], factorisations added to sc[8].
+//
+// Steps are chord steps with a frozen bordered Jacobian
+//     M = [ J   C ]     J = A + 3 zs S - mu B (coarse block, factored),
+//         [ C^T E ]     C = border columns (d/dc and d/dmu), E = 2x2 (or 1x1) corner,
+// all taken at the last refresh.  With V = J^{-1} C (kept in rhs[N..]) and the Schur
+// complement G = E - C^T V, a step is
+//     y0 = J^{-1}(-F_H),  G dbeta = r_beta - C^T y0,  dx_H = y0 - V dbeta,
+// and because J is symmetric C^T y0 = -V^T F_H, so one right-hand side per step suffices.
+// A refresh (new factor, or first step of a call with a stored factor) freezes the
+// current border columns again.
 template <int D, bool AUG>
-__device__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
+__device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
     const int N = ar.z.N, N1 = ar.z.N1;
     const int lane = threadIdx.x;
+    FMG_TCNT(9);
     {
         // x <- x / ||x||_B  (B needs no assembly)
         constexpr int NS = Geo<D>::NS;
@@ -644,9 +763,14 @@ __device__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
         __syncthreads();
     }
     double mu = 0.0, mus = 0.0, res_prev = 1e300;
-    bool last_fresh = false, need_fresh = !have;
+    bool last_fresh = false, need_fresh = !have, frozen = false;
+    double g11 = 0.0, g12 = 0.0, g21 = 0.0, g22 = 1.0;   // frozen Schur complement G
     for (int it = 0; it <= a.max_iter; ++it) {
+        FMG_TCNT(8);
+        FMG_T0(t_as);
         assemble_S<D, AUG>(ar, a, ar.x);
+        FMG_TACC(1, t_as);
+        FMG_T0(t_ap);
         apply<D, AUG>(ar, zs, ar.x, ar.y, ar.z2);
         if (it == 0) mu = ar.sc[4] / ar.sc[5];
         const double F2 = 0.5 * (1.0 - ar.sc[5]);
@@ -670,9 +794,10 @@ __device__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
             __syncthreads();
             return it;
         }
+        FMG_TACC(2, t_ap);
         if (it == a.max_iter) return -2;
         if (it > 0 && !last_fresh && res > 0.25 * res_prev) {
-            // the stale Jacobian stopped contracting: back to the previous iterate, refactor
+            // the frozen Jacobian stopped contracting: back to the previous iterate, refactor
             for (int i = lane; i < N1; i += kThreads) ar.x[i] = ar.xs[i];
             mu = mus;
             need_fresh = true;
@@ -681,10 +806,13 @@ __device__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
             continue;
         }
         if (need_fresh) {
+            FMG_T0(t_f);
             fill_band<D, AUG>(ar, 3.0 * zs, mu);
             if (ldlt<D, AUG>(ar) < 0) return -1;
+            FMG_TACC(3, t_f);
             need_fresh = false;
             last_fresh = true;
+            frozen = false;
             have = true;
             if (lane == 0) ar.sc[8] += 1.0;
         } else {
@@ -693,65 +821,85 @@ __device__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
         for (int i = lane; i < N1; i += kThreads) ar.xs[i] = ar.x[i];
         mus = mu;
         res_prev = res;
-        const int R = AUG ? 3 : 2;
-        for (int i = lane; i < N; i += kThreads) {
-            ar.rhs[i] = -ar.F[i];
-            if (AUG) {
-                ar.rhs[N + i] = ar.aH[i] + 3.0 * zs * ar.sH[i] - mu * ar.bH[i];
-                ar.rhs[2 * N + i] = -ar.z2[i];
-            } else {
-                ar.rhs[N + i] = -ar.z2[i];
+        FMG_T0(t_s);
+        if (!frozen) {
+            // freeze the border columns at this iterate: V = J^{-1} C
+            for (int i = lane; i < N; i += kThreads) {
+                ar.rhs[i] = -ar.F[i];
+                if (AUG) {
+                    ar.rhs[N + i] = ar.aH[i] + 3.0 * zs * ar.sH[i] - mu * ar.bH[i];
+                    ar.rhs[2 * N + i] = -ar.z2[i];
+                } else {
+                    ar.rhs[N + i] = -ar.z2[i];
+                }
             }
+            ldlt_solve<D, AUG, AUG ? 3 : 2>(ar, ar.rhs);
+            if (AUG) {
+                double s1 = 0.0, s2 = 0.0, s4 = 0.0, s5 = 0.0;
+                for (int i = lane; i < N; i += kThreads) {
+                    const double jh = ar.aH[i] + 3.0 * zs * ar.sH[i] - mu * ar.bH[i];
+                    const double zh = ar.z2[i];
+                    s1 += jh * ar.rhs[N + i];
+                    s2 += jh * ar.rhs[2 * N + i];
+                    s4 += zh * ar.rhs[N + i];
+                    s5 += zh * ar.rhs[2 * N + i];
+                }
+                s1 = wsum(s1); s2 = wsum(s2); s4 = wsum(s4); s5 = wsum(s5);
+                const double jU = ar.sc[0] + 3.0 * zs * ar.sc[3] - mu * ar.sc[1];
+                const double zU = ar.z2[N];
+                g11 = jU - s1;
+                g12 = -s2 - zU;
+                g21 = s4 - zU;
+                g22 = s5;
+            } else {
+                double s1 = 0.0;
+                for (int i = lane; i < N; i += kThreads) s1 += ar.z2[i] * ar.rhs[N + i];
+                g22 = wsum(s1);
+            }
+            frozen = true;
+        } else {
+            for (int i = lane; i < N; i += kThreads) ar.rhs[i] = -ar.F[i];
+            ldlt_solve<D, AUG, 1>(ar, ar.rhs);
         }
-        __syncthreads();
-        ldlt_solve<D, AUG>(ar, ar.rhs, R);
+        FMG_TACC(4, t_s);
+        FMG_T0(t_u);
+        // C^T y0 = -V^T F_H
         double dmu, dc = 0.0;
         if (AUG) {
-            double s[6] = {0, 0, 0, 0, 0, 0};
+            double p1 = 0.0, p2 = 0.0;
             for (int i = lane; i < N; i += kThreads) {
-                const double jh = ar.aH[i] + 3.0 * zs * ar.sH[i] - mu * ar.bH[i];
-                const double zh = ar.z2[i];
-                s[0] += jh * ar.rhs[i];
-                s[1] += jh * ar.rhs[N + i];
-                s[2] += jh * ar.rhs[2 * N + i];
-                s[3] += zh * ar.rhs[i];
-                s[4] += zh * ar.rhs[N + i];
-                s[5] += zh * ar.rhs[2 * N + i];
+                p1 += ar.rhs[N + i] * ar.F[i];
+                p2 += ar.rhs[2 * N + i] * ar.F[i];
             }
-#pragma unroll
-            for (int q = 0; q < 6; ++q) s[q] = wsum(s[q]);
-            const double jU = ar.sc[0] + 3.0 * zs * ar.sc[3] - mu * ar.sc[1];
-            const double zU = ar.z2[N];
-            const double a11 = jU - s[1], a12 = -s[2] - zU, r1 = -ar.F[N] - s[0];
-            const double a21 = s[4] - zU, a22 = s[5], r2 = -F2 + s[3];
-            const double det = a11 * a22 - a12 * a21;
+            p1 = wsum(p1);
+            p2 = wsum(p2);
+            // C = [j_H, -z_H]: C^T y0 = -V^T F_H = (-p1, -p2), so j_H.y0 = -p1, z_H.y0 = p2
+            const double r1 = -ar.F[N] + p1, r2 = -F2 + p2;
+            const double det = g11 * g22 - g12 * g21;
             if (!(fabs(det) > 0.0)) return -4;
-            dc = (r1 * a22 - a12 * r2) / det;
-            dmu = (a11 * r2 - a21 * r1) / det;
+            dc = (r1 * g22 - g12 * r2) / det;
+            dmu = (g11 * r2 - g21 * r1) / det;
             for (int i = lane; i < N; i += kThreads)
                 ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dc - ar.rhs[2 * N + i] * dmu;
             if (lane == 0) ar.x[N] += dc;
         } else {
-            double s0 = 0.0, s1 = 0.0;
-            for (int i = lane; i < N; i += kThreads) {
-                s0 += ar.z2[i] * ar.rhs[i];
-                s1 += ar.z2[i] * ar.rhs[N + i];
-            }
-            s0 = wsum(s0);
-            s1 = wsum(s1);
-            if (!(fabs(s1) > 0.0)) return -4;
-            dmu = (-F2 + s0) / s1;
+            double p1 = 0.0;
+            for (int i = lane; i < N; i += kThreads) p1 += ar.rhs[N + i] * ar.F[i];
+            p1 = wsum(p1);
+            if (!(fabs(g22) > 0.0)) return -4;
+            dmu = (-F2 + p1) / g22;   // z.y0 = p1 with V = J^{-1}(-z)
             for (int i = lane; i < N; i += kThreads) ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dmu;
         }
         mu += dmu;
         __syncthreads();
+        FMG_TACC(5, t_u);
     }
     return -2;
 }
 
 // inertia check: number of eigenvalues of (A + zs S(x), B) below sigma (0: ground state)
 template <int D, bool AUG>
-__device__ int count_below(Arena<D, AUG>& ar, double zs, double sigma) {
+__device__ __forceinline__ int count_below(Arena<D, AUG>& ar, double zs, double sigma) {
     const int N = ar.z.N;
     fill_band<D, AUG>(ar, zs, sigma);
     int neg = ldlt<D, AUG>(ar);
@@ -759,7 +907,7 @@ __device__ int count_below(Arena<D, AUG>& ar, double zs, double sigma) {
     if (AUG) {
         for (int i = threadIdx.x; i < N; i += kThreads) ar.rhs[i] = ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i];
         __syncthreads();
-        ldlt_solve<D, AUG>(ar, ar.rhs, 1);
+        ldlt_solve<D, AUG, 1>(ar, ar.rhs);
         double s = 0.0;
         for (int i = threadIdx.x; i < N; i += kThreads) s += (ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i]) * ar.rhs[i];
         s = wsum(s);
@@ -770,7 +918,7 @@ __device__ int count_below(Arena<D, AUG>& ar, double zs, double sigma) {
 }
 
 template <int D, bool AUG>
-__device__ void store_factor(Arena<D, AUG>& ar, const Args& a) {
+__device__ __forceinline__ void store_factor(Arena<D, AUG>& ar, const Args& a) {
     if (!a.fac) return;
     const int n = ar.z.N * (ar.z.w + 1);
     for (int t = threadIdx.x; t < n; t += kThreads) a.fac[t] = ar.band[t];
@@ -778,14 +926,21 @@ __device__ void store_factor(Arena<D, AUG>& ar, const Args& a) {
 }
 
 template <int D, bool AUG>
-__device__ void finish(Arena<D, AUG>& ar, const Args& a, int iters, bool ok, int reason) {
+__device__ __forceinline__ void finish(Arena<D, AUG>& ar, const Args& a, int iters, bool ok, int reason) {
     const int N = ar.z.N, m = ar.z.m;
     const double H = 1.0 / a.nc;
     const double Hd = (D == 2) ? H * H : H * H * H;
     if (ok) {
         const double mu = ar.sc[6];
+        // certify 1: always; 2: only when this step meets the lambda tolerance
+        const double prev = a.st->lambda;
+        const bool meets = AUG && a.final_level && a.st->tol_lambda > 0.0 &&
+                           fabs(mu - prev) / fabs(mu) <= a.st->tol_lambda;
+        const bool cert = a.certify == 1 || (a.certify == 2 && meets);
         int below = 0;
-        if (a.certify) below = count_below<D, AUG>(ar, a.ph.zeta, mu - 1e-9 * fabs(mu));
+        FMG_T0(t_cb);
+        if (cert) below = count_below<D, AUG>(ar, a.ph.zeta, mu - 1e-9 * fabs(mu));
+        FMG_TACC(7, t_cb);
         // sign: int u_h > 0
         double v = 0.0;
         for (int i = threadIdx.x; i < N; i += kThreads) v += ar.x[i];
@@ -797,15 +952,15 @@ __device__ void finish(Arena<D, AUG>& ar, const Args& a, int iters, bool ok, int
             node_pos<D>(i, m, P);
             a.xc[P[0] + a.gc.pitch * P[1] + a.gc.plane * P[2]] = sgn * ar.x[i];
         }
+        __syncthreads();
         if (threadIdx.x == 0) {
             SmallState* st = a.st;
-            const double prev = st->lambda;
             st->lambda_prev = prev;
             st->lambda = mu;
             st->dlambda = fabs(mu - prev) / fabs(mu);
             st->c = AUG ? sgn * ar.x[N] : 0.0;
             st->newton_total += iters;
-            st->fact_total += (int)ar.sc[8] + (a.certify ? 1 : 0);
+            st->fact_total += (int)ar.sc[8] + (cert ? 1 : 0);
             if (st->hist_len < 512) st->hist[st->hist_len] = mu;
             st->hist_len += 1;
             st->steps += AUG ? 1 : 0;
@@ -817,7 +972,7 @@ __device__ void finish(Arena<D, AUG>& ar, const Args& a, int iters, bool ok, int
                     st->fail_residual = ar.sc[7];
                 }
             }
-            if (AUG && a.final_level && st->tol_lambda > 0.0 && st->dlambda <= st->tol_lambda) st->done = 1;
+            if (meets) st->done = 1;
         }
     } else {
         // keep u = u~ (c = 1, x_H = 0) so later kernels stay finite; report the failure
@@ -839,13 +994,17 @@ __device__ void finish(Arena<D, AUG>& ar, const Args& a, int iters, bool ok, int
     }
 }
 
-template <int D, bool AUG>
+template <int D, bool AUG, bool LDS>
 __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     extern __shared__ double lds[];
     Arena<D, AUG> ar;
-    ar.carve(a.use_lds ? lds : a.arena, a.nc);
+    if constexpr (LDS) ar.carve(lds, a.nc);
+    else ar.carve(a.arena, a.nc);
     if (AUG && a.st->done) return;   // tolerance loop already satisfied
+    FMG_T0(t_all);
+    FMG_T0(t_setup);
     setup<D, AUG>(ar, a);
+    FMG_TACC(0, t_setup);
     const int N = ar.z.N, m = ar.z.m;
     const int lane = threadIdx.x;
     if (lane == 0) ar.sc[8] = 0.0;
@@ -855,6 +1014,8 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         const int n = N * (ar.z.w + 1);
         for (int t = lane; t < n; t += kThreads) ar.band[t] = a.fac[t];
         have = true;
+        __syncthreads();
+        transpose_band<D, AUG>(ar);
     }
     __syncthreads();
     int iters = 0;
@@ -870,7 +1031,8 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         iters = ok ? r : 0;
         reason = ok ? 0 : -r;
     } else {
-        // discrete sine mode, then zeta stages (first stage <= 1, factor 8)
+        // discrete sine mode, then zeta stages (first stage <= 1, factor 8); a failed stage
+        // goes back to the last converged iterate and retries with half the step
         const double H = 1.0 / a.nc;
         for (int i = lane; i < N; i += kThreads) {
             int P[3];
@@ -881,59 +1043,66 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         }
         __syncthreads();
         const double zeta = a.ph.zeta;
-        if (zeta <= 1.0) {
-            int r = newton<D, AUG>(ar, a, zeta, have);
-            ok = r >= 0;
-            iters = ok ? r : 0;
-            reason = ok ? 0 : -r;
-        } else {
-            const double lf = log(8.0);
-            const double lt = log(zeta);
-            int J = (int)ceil(lt / lf - 1e-12);
-            double lnext = lt - J * lf, step = lf, lcur = 0.0;
-            bool have_cur = false;
-            int first_tries = 0;
-            for (int guard = 0; guard < 200; ++guard) {
-                const bool last = !(lnext < lt);
-                const double z = last ? zeta : exp(lnext);
-                for (int i = lane; i < N; i += kThreads) ar.xk[i] = ar.x[i];   // committed iterate
+        const bool direct = !(zeta > 1.0);
+        const double lf = log(8.0);
+        const double lt = direct ? 0.0 : log(zeta);
+        const int J = direct ? 0 : (int)ceil(lt / lf - 1e-12);
+        double lnext = lt - J * lf, step = lf, lcur = 0.0;
+        bool have_cur = false;
+        int first_tries = 0;
+        for (int guard = 0; guard < 200; ++guard) {
+            const bool last = direct || !(lnext < lt);
+            const double z = last ? zeta : exp(lnext);
+            for (int i = lane; i < N; i += kThreads) ar.xk[i] = ar.x[i];   // committed iterate
+            __syncthreads();
+            const int rr = newton<D, AUG>(ar, a, z, have);
+            if (rr < 0) {
+                for (int i = lane; i < N; i += kThreads) ar.x[i] = ar.xk[i];
+                have = false;
                 __syncthreads();
-                int rr = newton<D, AUG>(ar, a, z, have);
-                if (rr < 0) {
-                    for (int i = lane; i < N; i += kThreads) ar.x[i] = ar.xk[i];
-                    have = false;
-                    __syncthreads();
-                    if (!have_cur) {
-                        // first stage failed from the sine mode: start lower
-                        if (++first_tries > 4) { ok = false; reason = -rr; break; }
-                        lnext -= lf;
-                        continue;
-                    }
-                    step *= 0.5;
-                    if (step < 1e-3) { ok = false; reason = -rr; break; }
-                    lnext = lcur + step;
+                if (direct) { ok = false; reason = -rr; break; }
+                if (!have_cur) {
+                    // first stage failed from the sine mode: start lower
+                    if (++first_tries > 4) { ok = false; reason = -rr; break; }
+                    lnext -= lf;
                     continue;
                 }
-                iters += rr;
-                if (last) break;
-                lcur = lnext;
-                have_cur = true;
-                lnext = fmin(lt, lcur + step);
+                step *= 0.5;
+                if (step < 1e-3) { ok = false; reason = -rr; break; }
+                lnext = lcur + step;
+                continue;
             }
+            iters += rr;
+            if (last) break;
+            lcur = lnext;
+            have_cur = true;
+            lnext = fmin(lt, lcur + step);
         }
     }
     __syncthreads();
+    FMG_T0(t_fin);
     if (ok && ar.sc[8] > 0.0) store_factor<D, AUG>(ar, a);
     __syncthreads();
     finish<D, AUG>(ar, a, iters, ok, reason);
+    FMG_TACC(6, t_fin);
+    FMG_TACC(10, t_all);
+    FMG_TCNT(11);
+#ifdef FMG_EXP_DUMPARENA
+    if constexpr (LDS) {
+        __syncthreads();
+        const int nd = (int)(arena_bytes_t<D, AUG>(a.nc) / sizeof(double));
+        for (int t = threadIdx.x; t < nd; t += kThreads) a.arena[t] = lds[t];
+    }
+#endif
 }
 
 // dense A, B, S(x) of the augmented problem (tests)
-template <int D>
+template <int D, bool LDS>
 __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     extern __shared__ double lds[];
     Arena<D, true> ar;
-    ar.carve(a.use_lds ? lds : a.arena, a.nc);
+    if constexpr (LDS) ar.carve(lds, a.nc);
+    else ar.carve(a.arena, a.nc);
     setup<D, true>(ar, a);
     constexpr int NS = Geo<D>::NS;
     const int N = ar.z.N, N1 = N + 1;
@@ -965,12 +1134,17 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     }
 }
 
+#ifdef FMG_EXP_NOLDS
+constexpr size_t kLdsLimit = 0;
+#else
 constexpr size_t kLdsLimit = 150 * 1024;
+#endif
 
 template <typename K>
-int launch_small(K kern, size_t bytes, Args& a, hipStream_t s) {
+int launch_small(K kern_lds, K kern_glb, size_t bytes, Args& a, hipStream_t s) {
     a.use_lds = bytes <= kLdsLimit;
     size_t shm = a.use_lds ? bytes : 0;
+    K kern = a.use_lds ? kern_lds : kern_glb;
     if (shm > 64 * 1024) {
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm) != hipSuccess)
@@ -981,6 +1155,19 @@ int launch_small(K kern, size_t bytes, Args& a, hipStream_t s) {
 }
 
 }  // namespace
+
+#ifdef FMG_SMALL_TIMING
+extern "C" int fmg_debug_small_timers(double* out, int reset) {
+    unsigned long long h[32];
+    if (hipMemcpyFromSymbol(h, HIP_SYMBOL(g_small_t), sizeof(h)) != hipSuccess) return -5;
+    for (int k = 0; k < 32; ++k) out[k] = (double)h[k];
+    if (reset) {
+        unsigned long long z[32] = {};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_small_t), z, sizeof(z)) != hipSuccess) return -5;
+    }
+    return 0;
+}
+#endif
 
 size_t small_arena_bytes(int dim, int nc) {
     size_t a = dim == 2 ? std::max(arena_bytes_t<2, true>(nc), arena_bytes_t<2, false>(nc))
@@ -999,8 +1186,8 @@ int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double t
     a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.tol = tol; a.mom = nullptr; a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = 0; a.certify = 1;
     a.fac = fac; a.reuse = 0;
-    return dim == 2 ? launch_small(k_newton<2, false>, arena_bytes_t<2, false>(nc), a, s)
-                    : launch_small(k_newton<3, false>, arena_bytes_t<3, false>(nc), a, s);
+    return dim == 2 ? launch_small(k_newton<2, false, true>, k_newton<2, false, false>, arena_bytes_t<2, false>(nc), a, s)
+                    : launch_small(k_newton<3, false, true>, k_newton<3, false, false>, arena_bytes_t<3, false>(nc), a, s);
 }
 
 int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments, double* arena,
@@ -1010,8 +1197,8 @@ int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol,
     a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.tol = tol; a.mom = moments; a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = final_level;
     a.certify = certify; a.fac = fac; a.reuse = reuse;
-    return dim == 2 ? launch_small(k_newton<2, true>, arena_bytes_t<2, true>(nc), a, s)
-                    : launch_small(k_newton<3, true>, arena_bytes_t<3, true>(nc), a, s);
+    return dim == 2 ? launch_small(k_newton<2, true, true>, k_newton<2, true, false>, arena_bytes_t<2, true>(nc), a, s)
+                    : launch_small(k_newton<3, true, true>, k_newton<3, true, false>, arena_bytes_t<3, true>(nc), a, s);
 }
 
 int launch_aug_dump(int dim, int nc, const Phys& ph, const double* moments, const double* x, double* arena, double* A,
@@ -1019,8 +1206,8 @@ int launch_aug_dump(int dim, int nc, const Phys& ph, const double* moments, cons
     Args a{};
     a.nc = nc; a.ph = ph; a.mom = moments; a.arena = arena; a.xin = x; a.Aout = A; a.Bout = B; a.Sout = S;
     a.gc = make_grid(dim, nc);
-    return dim == 2 ? launch_small(k_aug_dump<2>, arena_bytes_t<2, true>(nc), a, s)
-                    : launch_small(k_aug_dump<3>, arena_bytes_t<3, true>(nc), a, s);
+    return dim == 2 ? launch_small(k_aug_dump<2, true>, k_aug_dump<2, false>, arena_bytes_t<2, true>(nc), a, s)
+                    : launch_small(k_aug_dump<3, true>, k_aug_dump<3, false>, arena_bytes_t<3, true>(nc), a, s);
 }
 
 }  // namespace fmg
