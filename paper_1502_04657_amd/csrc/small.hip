@@ -1,4 +1,4 @@
-// The small nonlinear eigenproblems of the method, solved on the device by one wavefront:
+// The small nonlinear eigenproblems of the method, solved on the device by one workgroup:
 //   * Algorithm 3.2 step 1: the ground state on the coarsest space V_{h_1};
 //   * Algorithm 3.1 step 2: the augmented problem (3.6) on V_H + span{u~}.
 // With u = Z x, Z = [coarse hats, u~] (or the coarse hats alone),
@@ -6,21 +6,27 @@
 // A = Z^T (K + M_W) Z, B = Z^T M Z, S(x) = Z^T M_{(Zx)^2} Z, is solved by Newton's method
 // (the paper allows a self-consistent or a Newton-type iteration) with the Jacobian
 //     [ A + 3 zeta S(x) - mu B , -B x ; -(B x)^T , 0 ].
-// The coarse block of the Jacobian is banded (coarse stencils, lexicographic order); it is
-// factored by a banded LDL^T without pivoting and the one or two border rows are
-// eliminated through a small Schur complement.  The coarse-coarse blocks of A and B are
-// the coarse stencils themselves (Galerkin identities of nested P1 spaces); everything
-// involving u~ comes from the fine-grid moments (layout.h).
+// The coarse-coarse blocks of A and B are the coarse stencils themselves (Galerkin
+// identities of nested P1 spaces), evaluated on the fly; everything involving u~ comes
+// from the fine-grid moments (layout.h).
 //
-// The factorisation is the sequential part, so it is reused: a factor is kept in device
-// memory between calls and Newton steps use the latest factor (chord steps) for as long as
-// the residual contracts by at least a factor 4 per step; otherwise the iterate goes back
-// one step and the Jacobian is refactored there.  The fixed point is unchanged.
+// Linear algebra.  In lexicographic order the coarse block J of the Jacobian is block
+// tridiagonal: blocks are grid rows (2D) or grid planes (3D).  It is factored by block
+// cyclic reduction: at each level the odd blocks of the remaining chain are eliminated in
+// parallel (explicit inverse of each pivot block, Schur updates of the neighbours), so the
+// dependency chain has log2(rows) levels of dense block products instead of one step per
+// unknown.  A solve is one sweep down and one sweep up the levels.  The border rows of the
+// Newton system are eliminated through a 2x2 (or 1x1) Schur complement.  The numbers of
+// negative pivots of the block inverses give the inertia of J (Sylvester), which is the
+// ground-state check.
+//
+// The factorisation is reused: it is kept in device memory between calls, and Newton
+// steps use the latest factor and the border columns frozen with it (chord steps) for as
+// long as the residual contracts by at least a factor 4 per step; otherwise the iterate
+// goes back one step and the Jacobian is refactored there.  The fixed point is unchanged.
 //
 // On the coarsest space the iteration starts from the discrete sine mode and raises zeta in
-// geometric stages (factor 8 from a first stage <= 1, the step halved on failure).  When
-// requested, the final state is checked to be the ground state by the inertia of
-// A + zeta S(x) - (mu - eps) B (no negative pivot).
+// geometric stages (factor 8 from a first stage <= 1, the step halved on failure).
 #include <utility>
 
 #include "kernels.h"
@@ -30,30 +36,15 @@ namespace fmg {
 
 namespace {
 
-constexpr int kThreads = 64;   // one wavefront: barriers are cheap, reductions are shuffles
+constexpr int kThreads = 256;               // four wavefronts
+constexpr int kWaves = kThreads / 64;
 
 template <int D>
 struct Geo {
     static constexpr int V = D + 1;
     static constexpr int NE = (D == 2) ? 2 : 6;
     static constexpr int NS = (D == 2) ? kStencil2D : kStencil3D;
-    static constexpr int NSTAR = (D == 2) ? 6 : 24;
 };
-
-template <int D>
-__device__ inline int slot_of(const int* o) {
-    for (int s = 0; s < Geo<D>::NS; ++s) {
-        bool eq = true;
-        for (int d = 0; d < D; ++d) eq = eq && ((D == 2 ? kOff2D[s][d] : kOff3D[s][d]) == o[d]);
-        if (eq) return s;
-    }
-    return -1;
-}
-
-template <int D>
-__device__ inline int cell_vert(int t, int v, int d) {
-    return D == 2 ? kCellElemVert2D[t][v][d] : kCellElemVert3D[t][v][d];
-}
 
 // stencil slot of vertex b seen from vertex a in simplex t of a cell (compile time)
 template <int D>
@@ -78,6 +69,10 @@ template <int D, int T, int V, int Dim>
 struct CellVert {
     static constexpr int value = (D == 2) ? kCellElemVert2D[T % 2][V % 3][Dim % 2] : kCellElemVert3D[T][V][Dim];
 };
+template <int D, int S, int Dim>
+struct Off {
+    static constexpr int value = (D == 2) ? kOff2D[S % 7][Dim % 2] : kOff3D[S][Dim];
+};
 
 // f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled at compile time
 template <typename F, int... I>
@@ -88,7 +83,6 @@ template <int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
-
 // f(integral_constant<int, t>) for t = 0 .. N-1 in a loop that is not unrolled (one
 // instance of f per t, selected at run time), which keeps register pressure to one body
 template <int N, typename F>
@@ -103,12 +97,15 @@ __device__ __forceinline__ void rolled_for(F&& f) {
 // simplices of a cell: unrolled in 2D, rolled in 3D
 template <int D, typename F>
 __device__ __forceinline__ void for_simplices(F&& f) {
-#ifdef FMG_EXP_UNROLL3D
-    static_for<Geo<D>::NE>(f);
-#else
     if constexpr (D == 2) static_for<Geo<D>::NE>(f);
     else rolled_for<Geo<D>::NE>(f);
-#endif
+}
+// f(integral_constant<int, v>) for the run-time value v in [0, N) (uniform per wavefront)
+template <int N, typename F>
+__device__ __forceinline__ void dispatch(int v, F&& f) {
+    static_for<N>([&](auto vc) {
+        if (decltype(vc)::value == v) f(vc);
+    });
 }
 
 struct Args {
@@ -124,17 +121,13 @@ struct Args {
     SmallState* st;
     int final_level;     // tolerance checks enabled for this step
     int certify;         // ground-state inertia check: 0 never, 1 always, 2 when the step meets tol_lambda
-    double* fac;         // persistent band factor (N*(w+1) doubles), may be null
+    double* fac;         // persistent block factor, may be null
     int reuse;           // start from the stored factor when it exists
     // dump mode
     const double* xin;
     double* Aout;
     double* Bout;
     double* Sout;
-};
-
-struct Sizes {
-    int m, N, w, N1, np, nel;
 };
 
 // Optional phase timers of the small solves (wall clock, 100 MHz ticks); compiled only
@@ -150,37 +143,48 @@ __device__ unsigned long long g_small_t[32];
 #define FMG_TCNT(k) do { } while (0)
 #endif
 
+struct Sizes {
+    int m, N, N1, nel;
+    int nb, bs, B2;   // block rows, block size, bs^2
+    int h;            // most blocks eliminated on one level
+    int sz1;          // scratch doubles (products, solve temporaries)
+};
+
 template <int D, bool AUG>
 __host__ __device__ inline Sizes sizes(int nc) {
     Sizes z;
     z.m = nc - 1;
     z.N = (D == 2) ? z.m * z.m : z.m * z.m * z.m;
-    z.w = (D == 2) ? z.m + 1 : z.m * z.m + z.m + 1;
-    if (z.w > z.N - 1) z.w = z.N > 1 ? z.N - 1 : 1;
     z.N1 = AUG ? z.N + 1 : z.N;
-    z.np = z.w * (z.w + 1) / 2;
     z.nel = ((D == 2) ? nc * nc : nc * nc * nc) * Geo<D>::NE;
+    z.nb = z.m;
+    z.bs = (D == 2) ? z.m : z.m * z.m;
+    z.B2 = z.bs * z.bs;
+    z.h = z.nb / 2 > 0 ? z.nb / 2 : 1;
+    z.sz1 = z.h * z.B2 > 3 * z.N ? z.h * z.B2 : 3 * z.N;
     return z;
 }
 
 template <int D, bool AUG>
 struct Arena {
     Sizes z;
-    double* Ast; double* Bst; double* Sst; double* band; double* bandT;
+    double* Sst;                                   // S(x) stencil, N x NS
     double* x; double* xs; double* xk; double* y; double* z2; double* F; double* rhs;
-    double* aH; double* bH; double* sH; double* sc;
-    int* nb; int* pairs;
+    double* aH; double* bH; double* sH; double* sc; double* red;
+    double* Dm; double* Fm; double* Rm;            // block factor (nb blocks each)
+    double* S1; double* S2;                        // scratch
 
     __device__ void carve(double* base, int nc) {
         z = sizes<D, AUG>(nc);
         constexpr int NS = Geo<D>::NS;
         const int N = z.N;
         double* p = base;
-        Ast = p; p += (size_t)N * NS;
-        Bst = p; p += (size_t)N * NS;
+        Dm = p; p += (size_t)z.nb * z.B2;
+        Fm = p; p += (size_t)z.nb * z.B2;
+        Rm = p; p += (size_t)z.nb * z.B2;
+        S1 = p; p += z.sz1;
+        S2 = p; p += (size_t)z.h * z.B2;
         Sst = p; p += (size_t)N * NS;
-        band = p; p += (size_t)N * (z.w + 1);
-        bandT = p; p += (size_t)N * (z.w + 1);
         x = p; p += N + 2;
         xs = p; p += N + 2;
         xk = p; p += N + 2;
@@ -192,9 +196,7 @@ struct Arena {
         bH = p; p += N;
         sH = p; p += N;
         sc = p; p += 32;
-        int* q = reinterpret_cast<int*>(p);
-        nb = q; q += N * NS;
-        pairs = q;
+        red = p;
     }
 };
 
@@ -203,12 +205,56 @@ __host__ __device__ inline size_t arena_bytes_t(int nc) {
     Sizes z = sizes<D, AUG>(nc);
     constexpr int NS = Geo<D>::NS;
     size_t N = z.N;
-    size_t dbl = 3 * N * NS + 2 * N * (z.w + 1) + 6 * (N + 2) + 3 * N + 3 * N + 32;
-    size_t ints = N * NS + z.np;
-    return dbl * sizeof(double) + ints * sizeof(int) + 64;
+    size_t dbl = 3 * (size_t)z.nb * z.B2 + z.sz1 + (size_t)z.h * z.B2 + N * NS + 6 * (N + 2) + 3 * N + 3 * N + 32 +
+                 8 * kWaves;
+    return dbl * sizeof(double) + 64;
 }
 
-__device__ inline double wsum(double v) { return wave_sum(v); }
+// factor = Dm, Fm, Rm (contiguous at the start of the arena)
+template <int D>
+__host__ __device__ inline size_t factor_doubles(int nc) {
+    Sizes z = sizes<D, true>(nc);
+    return 3 * (size_t)z.nb * z.B2;
+}
+
+// ---- workgroup reductions (fixed order: every thread gets the same bits) ------------------
+template <int K>
+__device__ __forceinline__ void bsum(double* red, double (&v)[K]) {
+    static_assert(K <= 8, "at most 8 values per reduction");
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wid * 8 + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = red[k];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) s += red[w * 8 + k];
+        v[k] = s;
+    }
+}
+__device__ __forceinline__ double bsum1(double* red, double v) {
+    double a[1] = {v};
+    bsum<1>(red, a);
+    return a[0];
+}
+__device__ __forceinline__ double bmax1(double* red, double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[wid * 8] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s = fmax(s, red[w * 8]);
+    return s;
+}
 
 template <int D>
 __device__ inline void node_pos(int a, int m, int* P) {
@@ -224,25 +270,61 @@ __device__ inline int node_id(const int* P, int m) {
     return (D == 2) ? (P[0] - 1) + m * (P[1] - 1) : (P[0] - 1) + m * ((P[1] - 1) + m * (P[2] - 1));
 }
 
-// Cells of the coarse mesh in 2^D colour classes (parity of the cell index in every
-// direction): cells of one class share no vertex, so one lane per cell may scatter into
-// the rows of its vertices without atomics, and the summation order is fixed.
-// f(C0, C1, C2, cell) is called for every cell; one barrier after each class.
-template <int D, typename F>
-__device__ __forceinline__ void for_cells_colored(int nc, F&& f) {
-    for (int color = 0; color < (1 << D); ++color) {
-        const int px = color & 1, py = (color >> 1) & 1, pz = (color >> 2) & 1;
-        const int hx = (nc - px + 1) >> 1, hy = (nc - py + 1) >> 1, hz = (D == 3) ? (nc - pz + 1) >> 1 : 1;
-        const int ncol = hx * hy * hz;
-        for (int q = threadIdx.x; q < ncol; q += kThreads) {
-            const int C0 = px + 2 * (q % hx);
-            const int C1 = py + 2 * ((q / hx) % hy);
-            const int C2 = (D == 3) ? pz + 2 * (q / (hx * hy)) : 0;
-            const int cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
-            f(C0, C1, C2, cl);
-        }
-        __syncthreads();
+// neighbour of node P in stencil slot S, or -1 on the boundary
+template <int D, int S>
+__device__ __forceinline__ int nbr(const int* P, int m) {
+    int Q[3] = {P[0] + Off<D, S, 0>::value, P[1] + Off<D, S, 1>::value, (D == 3) ? P[2] + Off<D, S, 2>::value : 0};
+    return node_id<D>(Q, m);
+}
+
+// coarse stencils at node X (coordinates), slot S: a = (K + M_W)_S, b = M_S
+template <int D, int S>
+__device__ __forceinline__ void stencil_ab(const double* X, double H, double Hd, const Phys& ph, double& a, double& b) {
+    constexpr double m0 = (D == 2) ? kM0_2D[S % 7] : kM0_3D[S];
+    double cw = ph.wc * m0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double m1 = (D == 2) ? kM1_2D[k % 2][S % 7] : kM1_3D[k][S];
+        const double m2 = (D == 2) ? kM2_2D[k % 2][S % 7] : kM2_3D[k][S];
+        cw += ph.w[k] * (X[k] * X[k] * m0 + 2.0 * X[k] * H * m1 + H * H * m2);
     }
+    constexpr int o1 = (Off<D, S, 0>::value < 0 ? -Off<D, S, 0>::value : Off<D, S, 0>::value) +
+                       (Off<D, S, 1>::value < 0 ? -Off<D, S, 1>::value : Off<D, S, 1>::value) +
+                       (D == 3 ? (Off<D, S, 2>::value < 0 ? -Off<D, S, 2>::value : Off<D, S, 2>::value) : 0);
+    double kk;
+    if (D == 2)
+        kk = (o1 == 0) ? 4.0 : (o1 == 1 ? -1.0 : 0.0);
+    else
+        kk = (o1 == 0) ? 6.0 * H : (o1 == 1 ? -H : 0.0);
+    a = kk + Hd * cw;
+    b = Hd * m0;
+}
+
+// Cells of the coarse mesh in 2^D colour classes (parity of the cell index in every
+// direction): cells of one class share no vertex, so one thread per cell and vertex may
+// scatter into the vertex rows without atomics, and the summation order is fixed.
+struct ColorClass {
+    int px, py, pz, hx, hy, hz, ncol, ncolp;
+};
+template <int D>
+__device__ __forceinline__ ColorClass color_class(int nc, int color) {
+    ColorClass c;
+    c.px = color & 1;
+    c.py = (color >> 1) & 1;
+    c.pz = (color >> 2) & 1;
+    c.hx = (nc - c.px + 1) >> 1;
+    c.hy = (nc - c.py + 1) >> 1;
+    c.hz = (D == 3) ? (nc - c.pz + 1) >> 1 : 1;
+    c.ncol = c.hx * c.hy * c.hz;
+    c.ncolp = (c.ncol + 63) & ~63;   // a multiple of the wavefront: vertex index uniform per wave
+    return c;
+}
+template <int D>
+__device__ __forceinline__ void cell_of(const ColorClass& c, int q, int nc, int& C0, int& C1, int& C2, int& cl) {
+    C0 = c.px + 2 * (q % c.hx);
+    C1 = c.py + 2 * ((q / c.hx) % c.hy);
+    C2 = (D == 3) ? c.pz + 2 * (q / (c.hx * c.hy)) : 0;
+    cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
 }
 
 // interior node index of vertex V of simplex T in cell (C0, C1, C2), or -1 on the boundary
@@ -254,63 +336,25 @@ __device__ __forceinline__ int vert_node(int C0, int C1, int C2, int m) {
 }
 
 // ---------------------------------------------------------------------------------------
-// setup: tables, coarse stencils of K + M_W and M, and the u~ border
+// setup: the u~ border a(u~, phi_i), b(u~, phi_i) and the scalars a(u~,u~), b(u~,u~), int u~
 template <int D, bool AUG>
 __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
-    constexpr int NS = Geo<D>::NS;
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
     using L = MomLayout<D>;
     const int N = ar.z.N, m = ar.z.m, nc = a.nc;
-    const double H = 1.0 / nc;
-    const double Hd = (D == 2) ? H * H : H * H * H;
-    const int lane = threadIdx.x;
-    // LDL^T update pairs (ii >= jj) of the trailing window, ordered by ii
-    for (int p = lane; p < ar.z.np; p += kThreads) {
-        int ii = 0;
-        while ((ii + 1) * (ii + 2) / 2 <= p) ++ii;
-        const int jj = p - ii * (ii + 1) / 2;
-        ar.pairs[p] = (ii << 16) | jj;
+    if (!AUG) return;
+    for (int i = threadIdx.x; i < N; i += kThreads) {
+        ar.aH[i] = 0.0;
+        ar.bH[i] = 0.0;
     }
-    for (int i = lane; i < N; i += kThreads) {
-        int P[3];
-        node_pos<D>(i, m, P);
-        double X[3] = {P[0] * H, P[1] * H, P[2] * H};
-        for (int s = 0; s < NS; ++s) {
-            int Q[3], o1 = 0;
-            for (int d = 0; d < 3; ++d) Q[d] = P[d];
-            for (int d = 0; d < D; ++d) {
-                int od = (D == 2 ? kOff2D[s][d] : kOff3D[s][d]);
-                Q[d] += od;
-                o1 += od < 0 ? -od : od;
-            }
-            int j = node_id<D>(Q, m);
-            ar.nb[i * NS + s] = j;
-            double m0 = (D == 2) ? kM0_2D[s] : kM0_3D[s];
-            double cw = a.ph.wc * m0;
-            for (int k = 0; k < D; ++k) {
-                double m1 = (D == 2) ? kM1_2D[k][s] : kM1_3D[k][s];
-                double m2 = (D == 2) ? kM2_2D[k][s] : kM2_3D[k][s];
-                cw += a.ph.w[k] * (X[k] * X[k] * m0 + 2.0 * X[k] * H * m1 + H * H * m2);
-            }
-            double kk;
-            if (D == 2)
-                kk = (o1 == 0) ? 4.0 : (o1 == 1 ? -1.0 : 0.0);
-            else
-                kk = (o1 == 0) ? 6.0 * H : (o1 == 1 ? -H : 0.0);
-            ar.Ast[i * NS + s] = (j >= 0) ? kk + Hd * cw : 0.0;
-            ar.Bst[i * NS + s] = (j >= 0) ? Hd * m0 : 0.0;
-        }
-        if (AUG) {
-            ar.aH[i] = 0.0;
-            ar.bH[i] = 0.0;
-        }
-    }
-    if (AUG) {
-        __syncthreads();
-        // a(u~, phi_i), b(u~, phi_i) by simplex; a(u~,u~), b(u~,u~), int u~ as sums
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        for_cells_colored<D>(nc, [&](int C0, int C1, int C2, int cl) {
+    __syncthreads();
+    double v3[3] = {0.0, 0.0, 0.0};
+    for (int color = 0; color < (1 << D); ++color) {
+        const ColorClass cc = color_class<D>(nc, color);
+        for (int q = threadIdx.x; q < cc.ncol; q += kThreads) {
+            int C0, C1, C2, cl;
+            cell_of<D>(cc, q, nc, C0, C1, C2, cl);
             for_simplices<D>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
@@ -321,18 +365,19 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
                         ar.aH[nd] += mo[L::KG + v] + mo[L::AW1 + v];
                         ar.bH[nd] += mo[L::B1 + v];
                     }
-                    v2 += mo[L::B1 + v];
+                    v3[2] += mo[L::B1 + v];
                 });
-                v0 += mo[L::Q] + mo[L::AW2];
-                v1 += mo[L::B2];
+                v3[0] += mo[L::Q] + mo[L::AW2];
+                v3[1] += mo[L::B2];
             });
-        });
-        v0 = wsum(v0); v1 = wsum(v1); v2 = wsum(v2);
-        if (lane == 0) {
-            ar.sc[0] = v0;  // aU
-            ar.sc[1] = v1;  // bU
-            ar.sc[2] = v2;  // int u~
         }
+        __syncthreads();
+    }
+    bsum<3>(ar.red, v3);
+    if (threadIdx.x == 0) {
+        ar.sc[0] = v3[0];  // aU
+        ar.sc[1] = v3[1];  // bU
+        ar.sc[2] = v3[2];  // int u~
     }
     __syncthreads();
 }
@@ -401,15 +446,8 @@ __device__ __forceinline__ double elem_corner(const double* U, const double* UU,
     return s1 + 2.0 * c * s2 + c * c * mo[L::T0];
 }
 
-// vertex rows of a simplex: unrolled in 2D, rolled in 3D (register pressure)
-template <int D, typename F>
-__device__ __forceinline__ void for_vertices(F&& f) {
-    if constexpr (D == 2) static_for<D + 1>(f);
-    else rolled_for<D + 1>(f);
-}
-
-// S(x): coarse stencil Sst, border sH, corner sc[3]; simplex by simplex, cells in colour
-// classes so that the scatter into the vertex rows needs no atomics
+// S(x): coarse stencil Sst, border sH, corner sc[3].  One pass per (colour class, simplex
+// type); within a pass one thread per (cell, vertex row), the vertex uniform per wavefront.
 template <int D, bool AUG>
 __device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
     constexpr int NS = Geo<D>::NS;
@@ -420,310 +458,368 @@ __device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, con
     const double H = 1.0 / nc;
     const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
     const double c = AUG ? x[N] : 0.0;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < N * NS; t += kThreads) ar.Sst[t] = 0.0;
+    for (int t = threadIdx.x; t < N * NS; t += kThreads) ar.Sst[t] = 0.0;
     if (AUG)
-        for (int i = lane; i < N; i += kThreads) ar.sH[i] = 0.0;
+        for (int i = threadIdx.x; i < N; i += kThreads) ar.sH[i] = 0.0;
     __syncthreads();
     double sU = 0.0;
-    for_cells_colored<D>(nc, [&](int C0, int C1, int C2, int cl) {
+    for (int color = 0; color < (1 << D); ++color) {
+        const ColorClass cc = color_class<D>(nc, color);
         for_simplices<D>([&](auto tc) {
             constexpr int t = decltype(tc)::value;
-            int nd[V];
-            double U[V];
-            static_for<V>([&](auto vc) {
-                constexpr int v = decltype(vc)::value;
-                nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
-                U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
-            });
-            double UU[V * (V + 1) / 2];
-#pragma unroll
-            for (int p = 0; p < V; ++p)
-#pragma unroll
-                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-            const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
-            for_vertices<D>([&](auto ac) {
-                constexpr int aa = decltype(ac)::value;
-                if (nd[aa] >= 0) {
-                    double Sr[V], sh = 0.0;
-                    elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
-                    double* row = ar.Sst + (size_t)nd[aa] * NS;
-                    static_for<V>([&](auto bc) {
-                        constexpr int bb = decltype(bc)::value;
-                        if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
+            for (int task = threadIdx.x; task < V * cc.ncolp; task += kThreads) {
+                const int aav = task / cc.ncolp, q = task - aav * cc.ncolp;
+                if (q < cc.ncol) {
+                    int C0, C1, C2, cl;
+                    cell_of<D>(cc, q, nc, C0, C1, C2, cl);
+                    int nd[V];
+                    double U[V];
+                    static_for<V>([&](auto vc) {
+                        constexpr int v = decltype(vc)::value;
+                        nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
+                        U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
                     });
-                    if (AUG) ar.sH[nd[aa]] += sh;
+                    double UU[V * (V + 1) / 2];
+#pragma unroll
+                    for (int p = 0; p < V; ++p)
+#pragma unroll
+                        for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+                    const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
+                    dispatch<V>(aav, [&](auto ac) {
+                        constexpr int aa = decltype(ac)::value;
+                        if (nd[aa] >= 0) {
+                            double Sr[V], sh = 0.0;
+                            elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
+                            double* row = ar.Sst + (size_t)nd[aa] * NS;
+                            static_for<V>([&](auto bc) {
+                                constexpr int bb = decltype(bc)::value;
+                                if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
+                            });
+                            if (AUG) ar.sH[nd[aa]] += sh;
+                        }
+                        if (AUG && aa == 0) sU += elem_corner<D>(U, UU, mo, c);
+                    });
                 }
-            });
-            if (AUG) sU += elem_corner<D>(U, UU, mo, c);
+            }
+            __syncthreads();
         });
-    });
+    }
     if (AUG) {
-        sU = wsum(sU);
-        if (lane == 0) ar.sc[3] = sU;
+        sU = bsum1(ar.red, sU);
+        if (threadIdx.x == 0) ar.sc[3] = sU;
         __syncthreads();
     }
 }
 
 // y = (A + zs S) x, z = B x (with borders); sc[4] = x^T y, sc[5] = x^T z
 template <int D, bool AUG>
-__device__ __forceinline__ void apply(Arena<D, AUG>& ar, double zs, const double* x, double* y, double* z) {
+__device__ __forceinline__ void apply(Arena<D, AUG>& ar, const Args& a, double zs, const double* x, double* y,
+                                      double* z) {
     constexpr int NS = Geo<D>::NS;
-    const int N = ar.z.N;
+    const int N = ar.z.N, m = ar.z.m;
+    const double H = 1.0 / a.nc;
+    const double Hd = (D == 2) ? H * H : H * H * H;
     const double c = AUG ? x[N] : 0.0;
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < N; i += kThreads) {
+        int P[3];
+        node_pos<D>(i, m, P);
+        const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
         double yi = 0.0, zi = 0.0;
-        for (int s = 0; s < NS; ++s) {
-            int j = ar.nb[i * NS + s];
-            if (j < 0) continue;
-            yi += (ar.Ast[i * NS + s] + zs * ar.Sst[i * NS + s]) * x[j];
-            zi += ar.Bst[i * NS + s] * x[j];
-        }
+        static_for<NS>([&](auto sc_) {
+            constexpr int s = decltype(sc_)::value;
+            const int j = nbr<D, s>(P, m);
+            if (j >= 0) {
+                double as, bs;
+                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+                yi += (as + zs * ar.Sst[(size_t)i * NS + s]) * x[j];
+                zi += bs * x[j];
+            }
+        });
         if (AUG) {
             const double g = ar.aH[i] + zs * ar.sH[i];
             yi += g * c;
             zi += ar.bH[i] * c;
-            v2 += g * x[i];
-            v3 += ar.bH[i] * x[i];
+            v[2] += g * x[i];
+            v[3] += ar.bH[i] * x[i];
         }
         y[i] = yi;
         z[i] = zi;
-        v0 += x[i] * yi;
-        v1 += x[i] * zi;
+        v[0] += x[i] * yi;
+        v[1] += x[i] * zi;
     }
-    v0 = wsum(v0); v1 = wsum(v1);
-    if (AUG) { v2 = wsum(v2); v3 = wsum(v3); }
+    bsum<4>(ar.red, v);
     if (threadIdx.x == 0) {
         if (AUG) {
-            const double yU = v2 + (ar.sc[0] + zs * ar.sc[3]) * c;
-            const double zU = v3 + ar.sc[1] * c;
+            const double yU = v[2] + (ar.sc[0] + zs * ar.sc[3]) * c;
+            const double zU = v[3] + ar.sc[1] * c;
             y[N] = yU;
             z[N] = zU;
-            v0 += c * yU;
-            v1 += c * zU;
+            v[0] += c * yU;
+            v[1] += c * zU;
         }
-        ar.sc[4] = v0;
-        ar.sc[5] = v1;
+        ar.sc[4] = v[0];
+        ar.sc[5] = v[1];
     }
     __syncthreads();
 }
 
-// band <- Ast + alpha Sst - sigma Bst   (lower band, row-major, band[i*(w+1)+k] = J(i,i-k))
-template <int D, bool AUG>
-__device__ __forceinline__ void fill_band(Arena<D, AUG>& ar, double alpha, double sigma) {
-    constexpr int NS = Geo<D>::NS;
-    const int N = ar.z.N, W1 = ar.z.w + 1;
-    for (int t = threadIdx.x; t < N * W1; t += kThreads) ar.band[t] = 0.0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < N; i += kThreads)
-        for (int s = 0; s < NS; ++s) {
-            int j = ar.nb[i * NS + s];
-            if (j < 0 || j > i) continue;
-            ar.band[(size_t)i * W1 + (i - j)] =
-                ar.Ast[i * NS + s] + alpha * ar.Sst[i * NS + s] - sigma * ar.Bst[i * NS + s];
-        }
-    __syncthreads();
-}
+// ---------------------------------------------------------------------------------------
+// Block cyclic reduction of J = A + alpha S - sigma B (coarse block).  Blocks j = 0..nb-1
+// hold rows j*bs .. j*bs+bs-1.  At level st (1, 2, 4, ...) the blocks e = st*(2i+1) are
+// eliminated; their neighbours are l = e - st and r = e + st.  Afterwards
+//     Dm[e] = P_e = (pivot block)^{-1},  Fm[e] = G_l = P_e J_{e,l},  Rm[e] = G_r = P_e J_{r,e}^T,
+// and Dm[0] is the inverse of the last pivot block.  Fm[j] holds the coupling J_{j, left}
+// of block j while j is still in the chain.
 
-// column copy of the factor: bandT[k*(w+1) + t] = band[(k+t)*(w+1) + t] (t > 0), d_k at t = 0
-template <int D, bool AUG>
-__device__ __forceinline__ void transpose_band(Arena<D, AUG>& ar) {
-    const int N = ar.z.N, W1 = ar.z.w + 1;
-    for (int t = threadIdx.x; t < N * W1; t += kThreads) {
-        const int i = t / W1, q = t - i * W1;
-        if (i - q >= 0) ar.bandT[(size_t)(i - q) * W1 + q] = ar.band[t];
+// Thread layout for block-vector work: this thread serves rows p = p0, p0 + pstep, ... of
+// the blocks g, g + G, ... (one division per thread, none in the loops).
+struct VecMap {
+    int p0, pstep, g, G;
+};
+__device__ __forceinline__ VecMap vec_map(int bs) {
+    VecMap v;
+    if (bs <= kThreads) {
+        v.G = kThreads / bs;
+        v.g = threadIdx.x / bs;
+        v.p0 = threadIdx.x - v.g * bs;
+        v.pstep = bs;
+        if (v.g >= v.G) v.g = 1 << 30;   // idle thread
+    } else {
+        v.G = 1;
+        v.g = 0;
+        v.p0 = threadIdx.x;
+        v.pstep = kThreads;
     }
-    __syncthreads();
+    return v;
 }
 
-// In-place banded LDL^T without pivoting; afterwards band[i][0] = d_i and band[i][t] =
-// l_{i,i-t}.  Returns the number of negative pivots, or -1 for a (numerically) zero pivot.
+// Batched in-place Gauss-Jordan inversion of the pivot blocks Dm[first + step*i], i < cnt.
+// Pivots are those of an LDL^T of each block; returns the number of negative pivots, or
+// -1 if one is zero relative to `scale`.
 template <int D, bool AUG>
-__device__ __forceinline__ int ldlt(Arena<D, AUG>& ar) {
-    const int N = ar.z.N, w = ar.z.w, W1 = w + 1;
-    double* b = ar.band;
-    double scale = 0.0;
-    for (int i = threadIdx.x; i < N; i += kThreads) scale = fmax(scale, fabs(b[(size_t)i * W1]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) scale = fmax(scale, __shfl_xor(scale, off, 64));
+__device__ __forceinline__ int block_invert(Arena<D, AUG>& ar, int first, int step, int cnt, double scale) {
+    const int bs = ar.z.bs, B2 = ar.z.B2;
     int neg = 0;
-    for (int k = 0; k < N; ++k) {
-        const double d = b[(size_t)k * W1];
-        if (!(fabs(d) > 1e-15 * scale)) return -1;
-        if (d < 0.0) ++neg;
-        const double inv = 1.0 / d;
-        const int r = min(w, N - 1 - k);
-        const int np = r * (r + 1) / 2;   // the pairs with ii < r come first
-        for (int p = threadIdx.x; p < np; p += kThreads) {
-            const int pk = ar.pairs[p];
-            const int ii = pk >> 16, jj = pk & 0xffff;
-            const int i = k + 1 + ii, j = k + 1 + jj;
-            b[(size_t)i * W1 + (ii - jj)] -= b[(size_t)i * W1 + (ii + 1)] * b[(size_t)j * W1 + (jj + 1)] * inv;
+    for (int k = 0; k < bs; ++k) {
+        for (int i = 0; i < cnt; ++i) {
+            const double piv = ar.Dm[(size_t)(first + step * i) * B2 + k * bs + k];
+            if (!(fabs(piv) > 1e-15 * scale)) return -1;
+            if (piv < 0.0) ++neg;
+        }
+        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
+            const int r = e2 / bs, c = e2 - r * bs;
+            for (int i = 0; i < cnt; ++i) {
+                const double* M = ar.Dm + (size_t)(first + step * i) * B2;
+                const double inv = 1.0 / M[k * bs + k];
+                double v;
+                if (r == k) v = (c == k) ? inv : M[k * bs + c] * inv;
+                else v = (c == k) ? -M[r * bs + k] * inv : M[r * bs + c] - M[r * bs + k] * (M[k * bs + c] * inv);
+                ar.S1[(size_t)i * B2 + e2] = v;
+            }
         }
         __syncthreads();
+        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads)
+            for (int i = 0; i < cnt; ++i) ar.Dm[(size_t)(first + step * i) * B2 + e2] = ar.S1[(size_t)i * B2 + e2];
+        __syncthreads();
     }
-    // scale the columns: l_{i,k} = a_{i,k} / d_k
-    for (int t = threadIdx.x; t < N * W1; t += kThreads) {
-        const int i = t / W1, q = t - i * W1;
-        if (q > 0 && i - q >= 0) b[t] /= b[(size_t)(i - q) * W1];
-    }
-    __syncthreads();
-    transpose_band<D, AUG>(ar);
     return neg;
 }
 
-__device__ inline double readlane_d(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// Solve (L D L^T) X = R for R right-hand sides stored as rhs[q*N + i].  Row i lives in
-// lane i % 64, register slot i / 64; the eliminated value is broadcast with readlane, so
-// the dependency chain never goes through memory.  With a half-width w < 64 every lane
-// owns at most one of the rows an elimination step touches, so a step is one coefficient
-// load (issued a step ahead), 2R readlanes and 2R FMAs.  Needs N <= 64*SMAX.  The forward
-// sweep reads the column copy cT (cT[k*(w+1)+t] = l_{k+t,k}), the backward sweep the rows.
-template <int R, int SMAX>
-__device__ __forceinline__ void band_solve_reg(const double* __restrict__ b, const double* __restrict__ cT, int N,
-                                               int w, double* rhs) {
-    const int W1 = w + 1;
-    const int lane = threadIdx.x;
-    const int S = (N + 63) >> 6;
-    double y[R][SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        const int i = 64 * s + lane;
-#pragma unroll
-        for (int q = 0; q < R; ++q) y[q][s] = (s < S && i < N) ? rhs[q * N + i] : 0.0;
-    }
-    // coefficient of this lane's row for forward step k: l_{i,k}, i = k + t
-    auto fcoef = [&](int k) -> double {
-        const int kk = k & 63, s = k >> 6;
-        const int i = (lane > kk) ? 64 * s + lane : 64 * (s + 1) + lane;
-        const int t = i - k;
-        return (t <= w && i < N) ? cT[(size_t)k * W1 + t] : 0.0;
-    };
-    // coefficient of this lane's row for backward step k: l_{k,j}, j = k - t
-    auto bcoef = [&](int k) -> double {
-        const int kk = k & 63, s = k >> 6;
-        const int j = (lane < kk) ? 64 * s + lane : 64 * (s - 1) + lane;
-        const int t = k - j;
-        return (t <= w && j >= 0) ? b[(size_t)k * W1 + t] : 0.0;
-    };
-    // forward: unit lower L
-    double lnext = fcoef(0);
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        if (s < S) {
-            for (int kk = 0; kk < 64; ++kk) {
-                const int k = 64 * s + kk;
-                if (k >= N) break;
-                const double l = lnext;
-                if (k + 1 < N) lnext = fcoef(k + 1);
-                const bool here = lane > kk;
-                const double l0 = here ? l : 0.0;
-                const double l1 = here ? 0.0 : l;
-#pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const double yk = readlane_d(y[q][s], kk);
-                    y[q][s] = fma(-l0, yk, y[q][s]);
-                    if (s + 1 < SMAX) y[q][s + 1] = fma(-l1, yk, y[q][s + 1]);
-                }
-            }
-        }
-    }
-    // diagonal
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        const int i = 64 * s + lane;
-        if (s < S && i < N) {
-            const double inv = 1.0 / b[(size_t)i * W1];
-#pragma unroll
-            for (int q = 0; q < R; ++q) y[q][s] *= inv;
-        }
-    }
-    // backward: unit upper L^T
-    lnext = bcoef(N - 1);
-#pragma unroll
-    for (int s = SMAX - 1; s >= 0; --s) {
-        if (s < S) {
-            for (int kk = 63; kk >= 0; --kk) {
-                const int k = 64 * s + kk;
-                if (k >= N) continue;
-                const double l = lnext;
-                if (k > 0) lnext = bcoef(k - 1);
-                const bool here = lane < kk;
-                const double l0 = here ? l : 0.0;
-                const double l1 = here ? 0.0 : l;
-#pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const double xk = readlane_d(y[q][s], kk);
-                    y[q][s] = fma(-l0, xk, y[q][s]);
-                    if (s >= 1) y[q][s - 1] = fma(-l1, xk, y[q][s - 1]);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        const int i = 64 * s + lane;
-        if (s < S && i < N) {
-#pragma unroll
-            for (int q = 0; q < R; ++q) rhs[q * N + i] = y[q][s];
-        }
-    }
-    __syncthreads();
-}
-
-// LDS variant for large problems (one barrier per elimination step)
 template <int D, bool AUG>
-__device__ __forceinline__ void ldlt_solve_lds(Arena<D, AUG>& ar, double* rhs, int R) {
-    const int N = ar.z.N, w = ar.z.w, W1 = w + 1;
-    const double* b = ar.band;
-    for (int k = 0; k < N; ++k) {
-        const int r = min(w, N - 1 - k);
-        for (int t = threadIdx.x; t < r * R; t += kThreads) {
-            const int q = t / r, ii = t - q * r;
-            const int i = k + 1 + ii;
-            rhs[q * N + i] -= b[(size_t)i * W1 + (ii + 1)] * rhs[q * N + k];
-        }
-        __syncthreads();
-    }
-    for (int t = threadIdx.x; t < N * R; t += kThreads) {
-        const int i = t % N;
-        rhs[t] /= b[(size_t)i * W1];
+__device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, double alpha, double sigma) {
+    constexpr int NS = Geo<D>::NS;
+    const int N = ar.z.N, m = ar.z.m, nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
+    const double H = 1.0 / a.nc;
+    const double Hd = (D == 2) ? H * H : H * H * H;
+    for (int t = threadIdx.x; t < nb * B2; t += kThreads) {
+        ar.Dm[t] = 0.0;
+        ar.Fm[t] = 0.0;
     }
     __syncthreads();
-    for (int k = N - 1; k >= 0; --k) {
-        const int r = min(w, k);
-        for (int t = threadIdx.x; t < r * R; t += kThreads) {
-            const int q = t / r, ii = t - q * r;
-            const int i = k - 1 - ii;
-            rhs[q * N + i] -= b[(size_t)k * W1 + (ii + 1)] * rhs[q * N + k];
+    double dmax = 0.0;
+    for (int i = threadIdx.x; i < N; i += kThreads) {
+        int P[3];
+        node_pos<D>(i, m, P);
+        const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
+        const int blk = i / bs, r = i - blk * bs;
+        static_for<NS>([&](auto sc_) {
+            constexpr int s = decltype(sc_)::value;
+            const int j = nbr<D, s>(P, m);
+            if (j >= 0) {
+                double as, bs_;
+                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs_);
+                const double v = as + alpha * ar.Sst[(size_t)i * NS + s] - sigma * bs_;
+                // neighbours lie in the same block row, the previous one or the next one
+                const int jb = j < blk * bs ? blk - 1 : (j >= (blk + 1) * bs ? blk + 1 : blk);
+                if (jb == blk) ar.Dm[(size_t)blk * B2 + r * bs + (j - jb * bs)] = v;
+                else if (jb == blk - 1) ar.Fm[(size_t)blk * B2 + r * bs + (j - jb * bs)] = v;
+                if (s == 0) dmax = fmax(dmax, fabs(v));
+            }
+        });
+    }
+    const double scale = bmax1(ar.red, dmax);   // (its barriers also publish the blocks)
+    int neg = 0;
+    for (int st = 1; st < nb; st *= 2) {
+        int ne = 0;
+        while (st * (2 * ne + 1) < nb) ++ne;
+        const int r0 = block_invert<D, AUG>(ar, st, 2 * st, ne, scale);
+        if (r0 < 0) return -1;
+        neg += r0;
+        // G_l = P_e J_{e,l} -> S1,  G_r = P_e J_{r,e}^T -> Rm[e]
+        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
+            const int p = e2 / bs, q = e2 - p * bs;
+            for (int i = 0; i < ne; ++i) {
+                const int e = st * (2 * i + 1), rr = e + st;
+                const double* P = ar.Dm + (size_t)e * B2 + p * bs;
+                const double* Fl = ar.Fm + (size_t)e * B2 + q;
+                double vl = 0.0, vr = 0.0;
+                for (int k = 0; k < bs; ++k) vl += P[k] * Fl[k * bs];
+                if (rr < nb) {
+                    const double* Fr = ar.Fm + (size_t)rr * B2 + q * bs;
+                    for (int k = 0; k < bs; ++k) vr += P[k] * Fr[k];
+                }
+                ar.S1[(size_t)i * B2 + e2] = vl;
+                ar.Rm[(size_t)e * B2 + e2] = vr;
+            }
+        }
+        __syncthreads();
+        // Schur updates of the blocks that stay (a = 2k st), and the new couplings r <- l
+        const int na = (nb - 1) / (2 * st) + 1;
+        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
+            const int p = e2 / bs, q = e2 - p * bs;
+            for (int ka = 0; ka < na; ++ka) {
+                const int aa = 2 * st * ka;
+                const int e1 = aa + st, e0 = aa - st;
+                double v = 0.0;
+                if (e1 < nb) {   // D_a -= J_{e1,a}^T G_l(e1)
+                    const double* Fl = ar.Fm + (size_t)e1 * B2 + p;
+                    const double* G = ar.S1 + (size_t)ka * B2 + q;   // e1 = st (2 ka + 1)
+                    for (int k = 0; k < bs; ++k) v += Fl[k * bs] * G[k * bs];
+                }
+                if (e0 >= 0) {   // D_a -= J_{a,e0} G_r(e0)
+                    const double* Fr = ar.Fm + (size_t)aa * B2 + p * bs;
+                    const double* G = ar.Rm + (size_t)e0 * B2 + q;
+                    for (int k = 0; k < bs; ++k) v += Fr[k] * G[k * bs];
+                }
+                ar.Dm[(size_t)aa * B2 + e2] -= v;
+            }
+            for (int i = 0; i < ne; ++i) {
+                const int e = st * (2 * i + 1), rr = e + st;
+                if (rr < nb) {   // J_{r,l} = -J_{r,e} G_l(e)
+                    const double* Fr = ar.Fm + (size_t)rr * B2 + p * bs;
+                    const double* G = ar.S1 + (size_t)i * B2 + q;
+                    double v = 0.0;
+                    for (int k = 0; k < bs; ++k) v += Fr[k] * G[k * bs];
+                    ar.S2[(size_t)i * B2 + e2] = -v;
+                }
+            }
+        }
+        __syncthreads();
+        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
+            for (int i = 0; i < ne; ++i) {
+                const int e = st * (2 * i + 1), rr = e + st;
+                ar.Fm[(size_t)e * B2 + e2] = ar.S1[(size_t)i * B2 + e2];
+                if (rr < nb) ar.Fm[(size_t)rr * B2 + e2] = ar.S2[(size_t)i * B2 + e2];
+            }
         }
         __syncthreads();
     }
+    const int r0 = block_invert<D, AUG>(ar, 0, 1, 1, scale);
+    if (r0 < 0) return -1;
+    return neg + r0;
 }
 
+// Solve J X = R for R right-hand sides stored as rhs[q*N + i] with the factor of bcr_factor.
 template <int D, bool AUG, int R>
-__device__ __forceinline__ void ldlt_solve(Arena<D, AUG>& ar, double* rhs) {
-    const int N = ar.z.N, w = ar.z.w;
+__device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
+    const int N = ar.z.N, nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
+    double* tmp = ar.S1;
+    const VecMap vm = vec_map(bs);
     __syncthreads();
-    // the register sweeps only for an LDS-resident arena (the test folds at compile time);
-    // the global-memory variant serves large problems and keeps its register budget
-#if defined(__HIP_DEVICE_COMPILE__)
-    const bool lds = __builtin_amdgcn_is_shared(reinterpret_cast<const void*>(ar.band));
-#else
-    const bool lds = false;   // host pass: device code is not generated
-#endif
-    if (lds && N <= 256 && w < 64) band_solve_reg<R, 4>(ar.band, ar.bandT, N, w, rhs);
-    else ldlt_solve_lds<D, AUG>(ar, rhs, R);
+    int top = 1;
+    while (2 * top < nb) top *= 2;
+    // down: b_l -= G_l(e)^T b_e, b_r -= G_r(e)^T b_e
+    for (int st = 1; st < nb; st *= 2) {
+        const int na = (nb - 1) / (2 * st) + 1;
+        for (int ka = vm.g; ka < na; ka += vm.G) {
+            const int aa = 2 * st * ka, e1 = aa + st, e0 = aa - st;
+            for (int p = vm.p0; p < bs; p += vm.pstep) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const double* b = rhs + (size_t)q * N;
+                    double v = 0.0;
+                    if (e1 < nb) {
+                        const double* G = ar.Fm + (size_t)e1 * B2 + p;
+                        for (int k = 0; k < bs; ++k) v += G[k * bs] * b[e1 * bs + k];
+                    }
+                    if (e0 >= 0) {
+                        const double* G = ar.Rm + (size_t)e0 * B2 + p;
+                        for (int k = 0; k < bs; ++k) v += G[k * bs] * b[e0 * bs + k];
+                    }
+                    rhs[(size_t)q * N + aa * bs + p] -= v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // last block
+    if (vm.g == 0) {
+        for (int p = vm.p0; p < bs; p += vm.pstep) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const double* b = rhs + (size_t)q * N;
+                double v = 0.0;
+                for (int k = 0; k < bs; ++k) v += ar.Dm[p * bs + k] * b[k];
+                tmp[q * bs + p] = v;
+            }
+        }
+    }
+    __syncthreads();
+    if (vm.g == 0) {
+        for (int p = vm.p0; p < bs; p += vm.pstep) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) rhs[(size_t)q * N + p] = tmp[q * bs + p];
+        }
+    }
+    __syncthreads();
+    // up: x_e = P_e b_e - G_l(e) x_l - G_r(e) x_r
+    if (nb > 1) {
+        for (int st = top; st >= 1; st /= 2) {
+            int ne = 0;
+            while (st * (2 * ne + 1) < nb) ++ne;
+            for (int i = vm.g; i < ne; i += vm.G) {
+                const int e = st * (2 * i + 1), l = e - st, rr = e + st;
+                for (int p = vm.p0; p < bs; p += vm.pstep) {
+                    const double* P = ar.Dm + (size_t)e * B2 + p * bs;
+                    const double* Gl = ar.Fm + (size_t)e * B2 + p * bs;
+                    const double* Gr = ar.Rm + (size_t)e * B2 + p * bs;
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const double* b = rhs + (size_t)q * N;
+                        double v = 0.0;
+                        for (int k = 0; k < bs; ++k) v += P[k] * b[e * bs + k] - Gl[k] * b[l * bs + k];
+                        if (rr < nb)
+                            for (int k = 0; k < bs; ++k) v -= Gr[k] * b[rr * bs + k];
+                        tmp[((size_t)q * ne + i) * bs + p] = v;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int i = vm.g; i < ne; i += vm.G) {
+                const int e = st * (2 * i + 1);
+                for (int p = vm.p0; p < bs; p += vm.pstep) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) rhs[(size_t)q * N + e * bs + p] = tmp[((size_t)q * ne + i) * bs + p];
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // One Newton solve at coupling zs from the iterate in ar.x, using (and refreshing) the
-// factor in ar.band.  `have` says whether band already holds a usable factor.  Returns
+// factor.  `have` says whether the arena already holds a usable factor.  Returns
 // iterations >= 0 on convergence, or -reason.  mu in sc[6], factorisations added to sc[8].
 //
 // Steps are chord steps with a frozen bordered Jacobian
@@ -737,29 +833,37 @@ __device__ __forceinline__ void ldlt_solve(Arena<D, AUG>& ar, double* rhs) {
 // current border columns again.
 template <int D, bool AUG>
 __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
-    const int N = ar.z.N, N1 = ar.z.N1;
-    const int lane = threadIdx.x;
+    const int N = ar.z.N, N1 = ar.z.N1, m = ar.z.m;
+    const int tid = threadIdx.x;
     FMG_TCNT(9);
     {
         // x <- x / ||x||_B  (B needs no assembly)
         constexpr int NS = Geo<D>::NS;
-        double v = 0.0, vb = 0.0;
+        const double H = 1.0 / a.nc;
+        const double Hd = (D == 2) ? H * H : H * H * H;
+        double v[2] = {0.0, 0.0};
         const double c = AUG ? ar.x[N] : 0.0;
-        for (int i = lane; i < N; i += kThreads) {
+        for (int i = tid; i < N; i += kThreads) {
+            int P[3];
+            node_pos<D>(i, m, P);
+            const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
             double zi = 0.0;
-            for (int s = 0; s < NS; ++s) {
-                const int j = ar.nb[i * NS + s];
-                if (j >= 0) zi += ar.Bst[i * NS + s] * ar.x[j];
-            }
-            v += ar.x[i] * zi;
-            if (AUG) vb += ar.bH[i] * ar.x[i];
+            static_for<NS>([&](auto sc_) {
+                constexpr int s = decltype(sc_)::value;
+                const int j = nbr<D, s>(P, m);
+                if (j >= 0) {
+                    double as, bs;
+                    stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+                    zi += bs * ar.x[j];
+                }
+            });
+            v[0] += ar.x[i] * zi;
+            if (AUG) v[1] += ar.bH[i] * ar.x[i];
         }
-        v = wsum(v);
-        if (AUG) vb = wsum(vb);
-        const double xbx = v + (AUG ? c * (2.0 * vb + ar.sc[1] * c) : 0.0);
+        bsum<2>(ar.red, v);
+        const double xbx = v[0] + (AUG ? c * (2.0 * v[1] + ar.sc[1] * c) : 0.0);
         const double sN = 1.0 / sqrt(xbx);
-        __syncthreads();
-        for (int i = lane; i < N1; i += kThreads) ar.x[i] *= sN;
+        for (int i = tid; i < N1; i += kThreads) ar.x[i] *= sN;
         __syncthreads();
     }
     double mu = 0.0, mus = 0.0, res_prev = 1e300;
@@ -771,26 +875,25 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         assemble_S<D, AUG>(ar, a, ar.x);
         FMG_TACC(1, t_as);
         FMG_T0(t_ap);
-        apply<D, AUG>(ar, zs, ar.x, ar.y, ar.z2);
+        apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
         if (it == 0) mu = ar.sc[4] / ar.sc[5];
         const double F2 = 0.5 * (1.0 - ar.sc[5]);
-        double f2 = 0.0, zz = 0.0;
-        for (int i = lane; i < N1; i += kThreads) {
+        double fz[2] = {0.0, 0.0};
+        for (int i = tid; i < N1; i += kThreads) {
             const double f = ar.y[i] - mu * ar.z2[i];
             ar.F[i] = f;
-            f2 += f * f;
-            zz += ar.z2[i] * ar.z2[i];
+            fz[0] += f * f;
+            fz[1] += ar.z2[i] * ar.z2[i];
         }
-        f2 = wsum(f2);
-        zz = wsum(zz);
-        const double res = sqrt(f2) / (fabs(mu) * sqrt(zz));
-        if (lane == 0) ar.sc[7] = res;
+        bsum<2>(ar.red, fz);
+        const double res = sqrt(fz[0]) / (fabs(mu) * sqrt(fz[1]));
+        if (tid == 0) ar.sc[7] = res;
         if (!(res == res) || !(mu == mu)) return -3;
         // x^T B x = 1 up to the rounding of an N-term dot product
         if (res <= a.tol && fabs(F2) <= 4.0 * N1 * 1.1e-16) {
             const double sN = 1.0 / sqrt(ar.sc[5]);
-            for (int i = lane; i < N1; i += kThreads) ar.x[i] *= sN;
-            if (lane == 0) ar.sc[6] = mu;
+            for (int i = tid; i < N1; i += kThreads) ar.x[i] *= sN;
+            if (tid == 0) ar.sc[6] = mu;
             __syncthreads();
             return it;
         }
@@ -798,7 +901,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         if (it == a.max_iter) return -2;
         if (it > 0 && !last_fresh && res > 0.25 * res_prev) {
             // the frozen Jacobian stopped contracting: back to the previous iterate, refactor
-            for (int i = lane; i < N1; i += kThreads) ar.x[i] = ar.xs[i];
+            for (int i = tid; i < N1; i += kThreads) ar.x[i] = ar.xs[i];
             mu = mus;
             need_fresh = true;
             res_prev = 1e300;
@@ -807,24 +910,23 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         }
         if (need_fresh) {
             FMG_T0(t_f);
-            fill_band<D, AUG>(ar, 3.0 * zs, mu);
-            if (ldlt<D, AUG>(ar) < 0) return -1;
+            if (bcr_factor<D, AUG>(ar, a, 3.0 * zs, mu) < 0) return -1;
             FMG_TACC(3, t_f);
             need_fresh = false;
             last_fresh = true;
             frozen = false;
             have = true;
-            if (lane == 0) ar.sc[8] += 1.0;
+            if (tid == 0) ar.sc[8] += 1.0;
         } else {
             last_fresh = false;
         }
-        for (int i = lane; i < N1; i += kThreads) ar.xs[i] = ar.x[i];
+        for (int i = tid; i < N1; i += kThreads) ar.xs[i] = ar.x[i];
         mus = mu;
         res_prev = res;
         FMG_T0(t_s);
         if (!frozen) {
             // freeze the border columns at this iterate: V = J^{-1} C
-            for (int i = lane; i < N; i += kThreads) {
+            for (int i = tid; i < N; i += kThreads) {
                 ar.rhs[i] = -ar.F[i];
                 if (AUG) {
                     ar.rhs[N + i] = ar.aH[i] + 3.0 * zs * ar.sH[i] - mu * ar.bH[i];
@@ -833,62 +935,61 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
                     ar.rhs[N + i] = -ar.z2[i];
                 }
             }
-            ldlt_solve<D, AUG, AUG ? 3 : 2>(ar, ar.rhs);
+            bcr_solve<D, AUG, AUG ? 3 : 2>(ar, ar.rhs);
             if (AUG) {
-                double s1 = 0.0, s2 = 0.0, s4 = 0.0, s5 = 0.0;
-                for (int i = lane; i < N; i += kThreads) {
+                double s[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int i = tid; i < N; i += kThreads) {
                     const double jh = ar.aH[i] + 3.0 * zs * ar.sH[i] - mu * ar.bH[i];
                     const double zh = ar.z2[i];
-                    s1 += jh * ar.rhs[N + i];
-                    s2 += jh * ar.rhs[2 * N + i];
-                    s4 += zh * ar.rhs[N + i];
-                    s5 += zh * ar.rhs[2 * N + i];
+                    s[0] += jh * ar.rhs[N + i];
+                    s[1] += jh * ar.rhs[2 * N + i];
+                    s[2] += zh * ar.rhs[N + i];
+                    s[3] += zh * ar.rhs[2 * N + i];
                 }
-                s1 = wsum(s1); s2 = wsum(s2); s4 = wsum(s4); s5 = wsum(s5);
+                bsum<4>(ar.red, s);
                 const double jU = ar.sc[0] + 3.0 * zs * ar.sc[3] - mu * ar.sc[1];
                 const double zU = ar.z2[N];
-                g11 = jU - s1;
-                g12 = -s2 - zU;
-                g21 = s4 - zU;
-                g22 = s5;
+                g11 = jU - s[0];
+                g12 = -s[1] - zU;
+                g21 = s[2] - zU;
+                g22 = s[3];
             } else {
                 double s1 = 0.0;
-                for (int i = lane; i < N; i += kThreads) s1 += ar.z2[i] * ar.rhs[N + i];
-                g22 = wsum(s1);
+                for (int i = tid; i < N; i += kThreads) s1 += ar.z2[i] * ar.rhs[N + i];
+                g22 = bsum1(ar.red, s1);
             }
             frozen = true;
         } else {
-            for (int i = lane; i < N; i += kThreads) ar.rhs[i] = -ar.F[i];
-            ldlt_solve<D, AUG, 1>(ar, ar.rhs);
+            for (int i = tid; i < N; i += kThreads) ar.rhs[i] = -ar.F[i];
+            bcr_solve<D, AUG, 1>(ar, ar.rhs);
         }
         FMG_TACC(4, t_s);
         FMG_T0(t_u);
         // C^T y0 = -V^T F_H
         double dmu, dc = 0.0;
         if (AUG) {
-            double p1 = 0.0, p2 = 0.0;
-            for (int i = lane; i < N; i += kThreads) {
-                p1 += ar.rhs[N + i] * ar.F[i];
-                p2 += ar.rhs[2 * N + i] * ar.F[i];
+            double p[2] = {0.0, 0.0};
+            for (int i = tid; i < N; i += kThreads) {
+                p[0] += ar.rhs[N + i] * ar.F[i];
+                p[1] += ar.rhs[2 * N + i] * ar.F[i];
             }
-            p1 = wsum(p1);
-            p2 = wsum(p2);
+            bsum<2>(ar.red, p);
             // C = [j_H, -z_H]: C^T y0 = -V^T F_H = (-p1, -p2), so j_H.y0 = -p1, z_H.y0 = p2
-            const double r1 = -ar.F[N] + p1, r2 = -F2 + p2;
+            const double r1 = -ar.F[N] + p[0], r2 = -F2 + p[1];
             const double det = g11 * g22 - g12 * g21;
             if (!(fabs(det) > 0.0)) return -4;
             dc = (r1 * g22 - g12 * r2) / det;
             dmu = (g11 * r2 - g21 * r1) / det;
-            for (int i = lane; i < N; i += kThreads)
+            for (int i = tid; i < N; i += kThreads)
                 ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dc - ar.rhs[2 * N + i] * dmu;
-            if (lane == 0) ar.x[N] += dc;
+            if (tid == 0) ar.x[N] += dc;
         } else {
             double p1 = 0.0;
-            for (int i = lane; i < N; i += kThreads) p1 += ar.rhs[N + i] * ar.F[i];
-            p1 = wsum(p1);
+            for (int i = tid; i < N; i += kThreads) p1 += ar.rhs[N + i] * ar.F[i];
+            p1 = bsum1(ar.red, p1);
             if (!(fabs(g22) > 0.0)) return -4;
             dmu = (-F2 + p1) / g22;   // z.y0 = p1 with V = J^{-1}(-z)
-            for (int i = lane; i < N; i += kThreads) ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dmu;
+            for (int i = tid; i < N; i += kThreads) ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dmu;
         }
         mu += dmu;
         __syncthreads();
@@ -899,18 +1000,17 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
 
 // inertia check: number of eigenvalues of (A + zs S(x), B) below sigma (0: ground state)
 template <int D, bool AUG>
-__device__ __forceinline__ int count_below(Arena<D, AUG>& ar, double zs, double sigma) {
+__device__ __forceinline__ int count_below(Arena<D, AUG>& ar, const Args& a, double zs, double sigma) {
     const int N = ar.z.N;
-    fill_band<D, AUG>(ar, zs, sigma);
-    int neg = ldlt<D, AUG>(ar);
+    int neg = bcr_factor<D, AUG>(ar, a, zs, sigma);
     if (neg < 0) return 1;
     if (AUG) {
         for (int i = threadIdx.x; i < N; i += kThreads) ar.rhs[i] = ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i];
-        __syncthreads();
-        ldlt_solve<D, AUG, 1>(ar, ar.rhs);
+        bcr_solve<D, AUG, 1>(ar, ar.rhs);
         double s = 0.0;
-        for (int i = threadIdx.x; i < N; i += kThreads) s += (ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i]) * ar.rhs[i];
-        s = wsum(s);
+        for (int i = threadIdx.x; i < N; i += kThreads)
+            s += (ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i]) * ar.rhs[i];
+        s = bsum1(ar.red, s);
         const double schur = (ar.sc[0] + zs * ar.sc[3] - sigma * ar.sc[1]) - s;
         if (!(schur > 0.0)) ++neg;
     }
@@ -920,8 +1020,8 @@ __device__ __forceinline__ int count_below(Arena<D, AUG>& ar, double zs, double 
 template <int D, bool AUG>
 __device__ __forceinline__ void store_factor(Arena<D, AUG>& ar, const Args& a) {
     if (!a.fac) return;
-    const int n = ar.z.N * (ar.z.w + 1);
-    for (int t = threadIdx.x; t < n; t += kThreads) a.fac[t] = ar.band[t];
+    const int n = 3 * ar.z.nb * ar.z.B2;
+    for (int t = threadIdx.x; t < n; t += kThreads) a.fac[t] = ar.Dm[t];
     if (threadIdx.x == 0) a.st->fac_valid = 1;
 }
 
@@ -939,12 +1039,12 @@ __device__ __forceinline__ void finish(Arena<D, AUG>& ar, const Args& a, int ite
         const bool cert = a.certify == 1 || (a.certify == 2 && meets);
         int below = 0;
         FMG_T0(t_cb);
-        if (cert) below = count_below<D, AUG>(ar, a.ph.zeta, mu - 1e-9 * fabs(mu));
+        if (cert) below = count_below<D, AUG>(ar, a, a.ph.zeta, mu - 1e-9 * fabs(mu));
         FMG_TACC(7, t_cb);
         // sign: int u_h > 0
         double v = 0.0;
         for (int i = threadIdx.x; i < N; i += kThreads) v += ar.x[i];
-        v = wsum(v);
+        v = bsum1(ar.red, v);
         const double integ = Hd * v + (AUG ? ar.x[N] * ar.sc[2] : 0.0);
         const double sgn = integ < 0.0 ? -1.0 : 1.0;
         for (int i = threadIdx.x; i < N; i += kThreads) {
@@ -1006,16 +1106,14 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     setup<D, AUG>(ar, a);
     FMG_TACC(0, t_setup);
     const int N = ar.z.N, m = ar.z.m;
-    const int lane = threadIdx.x;
-    if (lane == 0) ar.sc[8] = 0.0;
+    const int tid = threadIdx.x;
+    if (tid == 0) ar.sc[8] = 0.0;
     // a stored factor of the coarse Jacobian block (previous call) seeds chord steps
     bool have = false;
     if (a.reuse && a.fac && a.st->fac_valid) {
-        const int n = N * (ar.z.w + 1);
-        for (int t = lane; t < n; t += kThreads) ar.band[t] = a.fac[t];
+        const int n = 3 * ar.z.nb * ar.z.B2;
+        for (int t = tid; t < n; t += kThreads) ar.Dm[t] = a.fac[t];
         have = true;
-        __syncthreads();
-        transpose_band<D, AUG>(ar);
     }
     __syncthreads();
     int iters = 0;
@@ -1023,8 +1121,8 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     int reason = 0;
     if (AUG) {
         // start from u = u~ / ||u~||_M
-        for (int i = lane; i < N; i += kThreads) ar.x[i] = 0.0;
-        if (lane == 0) ar.x[N] = 1.0;
+        for (int i = tid; i < N; i += kThreads) ar.x[i] = 0.0;
+        if (tid == 0) ar.x[N] = 1.0;
         __syncthreads();
         int r = newton<D, AUG>(ar, a, a.ph.zeta, have);
         ok = r >= 0;
@@ -1034,7 +1132,7 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         // discrete sine mode, then zeta stages (first stage <= 1, factor 8); a failed stage
         // goes back to the last converged iterate and retries with half the step
         const double H = 1.0 / a.nc;
-        for (int i = lane; i < N; i += kThreads) {
+        for (int i = tid; i < N; i += kThreads) {
             int P[3];
             node_pos<D>(i, m, P);
             double v = sinpi(P[0] * H) * sinpi(P[1] * H);
@@ -1053,11 +1151,11 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         for (int guard = 0; guard < 200; ++guard) {
             const bool last = direct || !(lnext < lt);
             const double z = last ? zeta : exp(lnext);
-            for (int i = lane; i < N; i += kThreads) ar.xk[i] = ar.x[i];   // committed iterate
+            for (int i = tid; i < N; i += kThreads) ar.xk[i] = ar.x[i];   // committed iterate
             __syncthreads();
             const int rr = newton<D, AUG>(ar, a, z, have);
             if (rr < 0) {
-                for (int i = lane; i < N; i += kThreads) ar.x[i] = ar.xk[i];
+                for (int i = tid; i < N; i += kThreads) ar.x[i] = ar.xk[i];
                 have = false;
                 __syncthreads();
                 if (direct) { ok = false; reason = -rr; break; }
@@ -1087,13 +1185,6 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     FMG_TACC(6, t_fin);
     FMG_TACC(10, t_all);
     FMG_TCNT(11);
-#ifdef FMG_EXP_DUMPARENA
-    if constexpr (LDS) {
-        __syncthreads();
-        const int nd = (int)(arena_bytes_t<D, AUG>(a.nc) / sizeof(double));
-        for (int t = threadIdx.x; t < nd; t += kThreads) a.arena[t] = lds[t];
-    }
-#endif
 }
 
 // dense A, B, S(x) of the augmented problem (tests)
@@ -1105,7 +1196,9 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     else ar.carve(a.arena, a.nc);
     setup<D, true>(ar, a);
     constexpr int NS = Geo<D>::NS;
-    const int N = ar.z.N, N1 = N + 1;
+    const int N = ar.z.N, N1 = N + 1, m = ar.z.m;
+    const double H = 1.0 / a.nc;
+    const double Hd = (D == 2) ? H * H : H * H * H;
     for (int i = threadIdx.x; i < N1; i += kThreads) ar.x[i] = a.xin[i];
     __syncthreads();
     assemble_S<D, true>(ar, a, ar.x);
@@ -1116,13 +1209,20 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < N; i += kThreads) {
-        for (int s = 0; s < NS; ++s) {
-            int j = ar.nb[i * NS + s];
-            if (j < 0) continue;
-            a.Aout[(size_t)i * N1 + j] = ar.Ast[i * NS + s];
-            a.Bout[(size_t)i * N1 + j] = ar.Bst[i * NS + s];
-            a.Sout[(size_t)i * N1 + j] = ar.Sst[i * NS + s];
-        }
+        int P[3];
+        node_pos<D>(i, m, P);
+        const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
+        static_for<NS>([&](auto sc_) {
+            constexpr int s = decltype(sc_)::value;
+            const int j = nbr<D, s>(P, m);
+            if (j >= 0) {
+                double as, bs;
+                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+                a.Aout[(size_t)i * N1 + j] = as;
+                a.Bout[(size_t)i * N1 + j] = bs;
+                a.Sout[(size_t)i * N1 + j] = ar.Sst[(size_t)i * NS + s];
+            }
+        });
         a.Aout[(size_t)i * N1 + N] = a.Aout[(size_t)N * N1 + i] = ar.aH[i];
         a.Bout[(size_t)i * N1 + N] = a.Bout[(size_t)N * N1 + i] = ar.bH[i];
         a.Sout[(size_t)i * N1 + N] = a.Sout[(size_t)N * N1 + i] = ar.sH[i];
@@ -1134,11 +1234,8 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     }
 }
 
-#ifdef FMG_EXP_NOLDS
-constexpr size_t kLdsLimit = 0;
-#else
-constexpr size_t kLdsLimit = 150 * 1024;
-#endif
+// the whole arena in LDS when it fits (gfx950: 160 KiB per workgroup)
+constexpr size_t kLdsLimit = 156 * 1024;
 
 template <typename K>
 int launch_small(K kern_lds, K kern_glb, size_t bytes, Args& a, hipStream_t s) {
@@ -1176,8 +1273,8 @@ size_t small_arena_bytes(int dim, int nc) {
 }
 
 size_t small_factor_bytes(int dim, int nc) {
-    Sizes z = dim == 2 ? sizes<2, true>(nc) : sizes<3, true>(nc);
-    return ((size_t)z.N * (z.w + 1) * sizeof(double) + 255) / 256 * 256;
+    const size_t n = dim == 2 ? factor_doubles<2>(nc) : factor_doubles<3>(nc);
+    return (n * sizeof(double) + 255) / 256 * 256;
 }
 
 int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, double* arena, double* fac,
