@@ -594,33 +594,74 @@ __device__ __forceinline__ VecMap vec_map(int bs) {
     return v;
 }
 
-// Batched in-place Gauss-Jordan inversion of the pivot blocks Dm[first + step*i], i < cnt.
-// Pivots are those of an LDL^T of each block; returns the number of negative pivots, or
-// -1 if one is zero relative to `scale`.
+// sum_k a[k*sa] * b[k*sb] for k = 0..n-1 in order; the loads of 16 terms are issued
+// together (indices clamped in bounds), so a short dot costs one memory latency
+__device__ __forceinline__ double dotn(const double* a, int sa, const double* b, int sb, int n) {
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        double x[16], y[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = min(k0 + j, n - 1);
+            x[j] = a[k * sa];
+            y[j] = b[k * sb];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (k0 + j < n) acc = fma(x[j], y[j], acc);
+    }
+    return acc;
+}
+
+// Batched Gauss-Jordan inversion of the pivot blocks Dm[first + step*i], i < cnt, in place.
+// Steps alternate between the blocks and the scratch S1 (one barrier per step).  Pivots
+// are those of an LDL^T of each block; returns the number of negative pivots, or -1 if one
+// is zero relative to `scale`.
 template <int D, bool AUG>
 __device__ __forceinline__ int block_invert(Arena<D, AUG>& ar, int first, int step, int cnt, double scale) {
     const int bs = ar.z.bs, B2 = ar.z.B2;
     int neg = 0;
+    double* bufA = ar.Dm + (size_t)first * B2;
+    const size_t strideA = (size_t)step * B2;
+    double* bufB = ar.S1;
+    const size_t strideB = B2;
     for (int k = 0; k < bs; ++k) {
-        for (int i = 0; i < cnt; ++i) {
-            const double piv = ar.Dm[(size_t)(first + step * i) * B2 + k * bs + k];
-            if (!(fabs(piv) > 1e-15 * scale)) return -1;
-            if (piv < 0.0) ++neg;
-        }
-        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
-            const int r = e2 / bs, c = e2 - r * bs;
-            for (int i = 0; i < cnt; ++i) {
-                const double* M = ar.Dm + (size_t)(first + step * i) * B2;
-                const double inv = 1.0 / M[k * bs + k];
-                double v;
-                if (r == k) v = (c == k) ? inv : M[k * bs + c] * inv;
-                else v = (c == k) ? -M[r * bs + k] * inv : M[r * bs + c] - M[r * bs + k] * (M[k * bs + c] * inv);
-                ar.S1[(size_t)i * B2 + e2] = v;
+        const bool fromA = (k & 1) == 0;
+        const double* src = fromA ? bufA : bufB;
+        double* dst = fromA ? bufB : bufA;
+        const size_t ss = fromA ? strideA : strideB, ds = fromA ? strideB : strideA;
+        for (int i0 = 0; i0 < cnt; i0 += 8) {
+            double inv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = min(i0 + j, cnt - 1);
+                const double piv = src[(size_t)i * ss + k * bs + k];
+                if (i0 + j < cnt) {
+                    if (!(fabs(piv) > 1e-15 * scale)) return -1;
+                    if (piv < 0.0) ++neg;
+                }
+                inv[j] = 1.0 / piv;
+            }
+            for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
+                const int r = e2 / bs, c = e2 - r * bs;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (i0 + j < cnt) {
+                        const double* M = src + (size_t)(i0 + j) * ss;
+                        const double mkc = M[k * bs + c], mrk = M[r * bs + k], mrc = M[r * bs + c];
+                        double v;
+                        if (r == k) v = (c == k) ? inv[j] : mkc * inv[j];
+                        else v = (c == k) ? -mrk * inv[j] : mrc - mrk * (mkc * inv[j]);
+                        dst[(size_t)(i0 + j) * ds + e2] = v;
+                    }
+                }
             }
         }
         __syncthreads();
+    }
+    if (bs & 1) {   // the result sits in the scratch after an odd number of steps
         for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads)
-            for (int i = 0; i < cnt; ++i) ar.Dm[(size_t)(first + step * i) * B2 + e2] = ar.S1[(size_t)i * B2 + e2];
+            for (int i = 0; i < cnt; ++i) bufA[(size_t)i * strideA + e2] = bufB[(size_t)i * strideB + e2];
         __syncthreads();
     }
     return neg;
@@ -663,7 +704,9 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
     for (int st = 1; st < nb; st *= 2) {
         int ne = 0;
         while (st * (2 * ne + 1) < nb) ++ne;
+        FMG_T0(t_inv);
         const int r0 = block_invert<D, AUG>(ar, st, 2 * st, ne, scale);
+        FMG_TACC(15, t_inv);
         if (r0 < 0) return -1;
         neg += r0;
         // G_l = P_e J_{e,l} -> S1,  G_r = P_e J_{r,e}^T -> Rm[e]
@@ -672,13 +715,8 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
             for (int i = 0; i < ne; ++i) {
                 const int e = st * (2 * i + 1), rr = e + st;
                 const double* P = ar.Dm + (size_t)e * B2 + p * bs;
-                const double* Fl = ar.Fm + (size_t)e * B2 + q;
-                double vl = 0.0, vr = 0.0;
-                for (int k = 0; k < bs; ++k) vl += P[k] * Fl[k * bs];
-                if (rr < nb) {
-                    const double* Fr = ar.Fm + (size_t)rr * B2 + q * bs;
-                    for (int k = 0; k < bs; ++k) vr += P[k] * Fr[k];
-                }
+                const double vl = dotn(P, 1, ar.Fm + (size_t)e * B2 + q, bs, bs);
+                const double vr = rr < nb ? dotn(P, 1, ar.Fm + (size_t)rr * B2 + q * bs, 1, bs) : 0.0;
                 ar.S1[(size_t)i * B2 + e2] = vl;
                 ar.Rm[(size_t)e * B2 + e2] = vr;
             }
@@ -692,27 +730,17 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
                 const int aa = 2 * st * ka;
                 const int e1 = aa + st, e0 = aa - st;
                 double v = 0.0;
-                if (e1 < nb) {   // D_a -= J_{e1,a}^T G_l(e1)
-                    const double* Fl = ar.Fm + (size_t)e1 * B2 + p;
-                    const double* G = ar.S1 + (size_t)ka * B2 + q;   // e1 = st (2 ka + 1)
-                    for (int k = 0; k < bs; ++k) v += Fl[k * bs] * G[k * bs];
-                }
-                if (e0 >= 0) {   // D_a -= J_{a,e0} G_r(e0)
-                    const double* Fr = ar.Fm + (size_t)aa * B2 + p * bs;
-                    const double* G = ar.Rm + (size_t)e0 * B2 + q;
-                    for (int k = 0; k < bs; ++k) v += Fr[k] * G[k * bs];
-                }
+                if (e1 < nb)   // D_a -= J_{e1,a}^T G_l(e1), e1 = st (2 ka + 1)
+                    v += dotn(ar.Fm + (size_t)e1 * B2 + p, bs, ar.S1 + (size_t)ka * B2 + q, bs, bs);
+                if (e0 >= 0)   // D_a -= J_{a,e0} G_r(e0)
+                    v += dotn(ar.Fm + (size_t)aa * B2 + p * bs, 1, ar.Rm + (size_t)e0 * B2 + q, bs, bs);
                 ar.Dm[(size_t)aa * B2 + e2] -= v;
             }
             for (int i = 0; i < ne; ++i) {
                 const int e = st * (2 * i + 1), rr = e + st;
-                if (rr < nb) {   // J_{r,l} = -J_{r,e} G_l(e)
-                    const double* Fr = ar.Fm + (size_t)rr * B2 + p * bs;
-                    const double* G = ar.S1 + (size_t)i * B2 + q;
-                    double v = 0.0;
-                    for (int k = 0; k < bs; ++k) v += Fr[k] * G[k * bs];
-                    ar.S2[(size_t)i * B2 + e2] = -v;
-                }
+                if (rr < nb)   // J_{r,l} = -J_{r,e} G_l(e)
+                    ar.S2[(size_t)i * B2 + e2] =
+                        -dotn(ar.Fm + (size_t)rr * B2 + p * bs, 1, ar.S1 + (size_t)i * B2 + q, bs, bs);
             }
         }
         __syncthreads();
@@ -739,6 +767,7 @@ __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
     __syncthreads();
     int top = 1;
     while (2 * top < nb) top *= 2;
+    FMG_T0(t_dn);
     // down: b_l -= G_l(e)^T b_e, b_r -= G_r(e)^T b_e
     for (int st = 1; st < nb; st *= 2) {
         const int na = (nb - 1) / (2 * st) + 1;
@@ -749,29 +778,22 @@ __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
                 for (int q = 0; q < R; ++q) {
                     const double* b = rhs + (size_t)q * N;
                     double v = 0.0;
-                    if (e1 < nb) {
-                        const double* G = ar.Fm + (size_t)e1 * B2 + p;
-                        for (int k = 0; k < bs; ++k) v += G[k * bs] * b[e1 * bs + k];
-                    }
-                    if (e0 >= 0) {
-                        const double* G = ar.Rm + (size_t)e0 * B2 + p;
-                        for (int k = 0; k < bs; ++k) v += G[k * bs] * b[e0 * bs + k];
-                    }
+                    if (e1 < nb) v += dotn(ar.Fm + (size_t)e1 * B2 + p, bs, b + e1 * bs, 1, bs);
+                    if (e0 >= 0) v += dotn(ar.Rm + (size_t)e0 * B2 + p, bs, b + e0 * bs, 1, bs);
                     rhs[(size_t)q * N + aa * bs + p] -= v;
                 }
             }
         }
         __syncthreads();
     }
+    FMG_TACC(12, t_dn);
+    FMG_T0(t_tp);
     // last block
     if (vm.g == 0) {
         for (int p = vm.p0; p < bs; p += vm.pstep) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const double* b = rhs + (size_t)q * N;
-                double v = 0.0;
-                for (int k = 0; k < bs; ++k) v += ar.Dm[p * bs + k] * b[k];
-                tmp[q * bs + p] = v;
+                tmp[q * bs + p] = dotn(ar.Dm + p * bs, 1, rhs + (size_t)q * N, 1, bs);
             }
         }
     }
@@ -783,6 +805,8 @@ __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
         }
     }
     __syncthreads();
+    FMG_TACC(13, t_tp);
+    FMG_T0(t_upp);
     // up: x_e = P_e b_e - G_l(e) x_l - G_r(e) x_r
     if (nb > 1) {
         for (int st = top; st >= 1; st /= 2) {
@@ -797,10 +821,8 @@ __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
 #pragma unroll
                     for (int q = 0; q < R; ++q) {
                         const double* b = rhs + (size_t)q * N;
-                        double v = 0.0;
-                        for (int k = 0; k < bs; ++k) v += P[k] * b[e * bs + k] - Gl[k] * b[l * bs + k];
-                        if (rr < nb)
-                            for (int k = 0; k < bs; ++k) v -= Gr[k] * b[rr * bs + k];
+                        double v = dotn(P, 1, b + e * bs, 1, bs) - dotn(Gl, 1, b + l * bs, 1, bs);
+                        if (rr < nb) v -= dotn(Gr, 1, b + rr * bs, 1, bs);
                         tmp[((size_t)q * ne + i) * bs + p] = v;
                     }
                 }
@@ -816,6 +838,7 @@ __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
             __syncthreads();
         }
     }
+    FMG_TACC(14, t_upp);
 }
 
 // One Newton solve at coupling zs from the iterate in ar.x, using (and refreshing) the
