@@ -55,33 +55,72 @@ def time_solves(prob, opts, steps, warmup):
     return res, u, total, lat
 
 
-def smoother_roofline(prob, reps=20):
-    """Average duration of the finest-level red-black half sweep (the V-cycle's dominant
-    kernel) measured with HIP events on the stream it is launched on; algorithmic bytes
-    per half sweep: read the other colour of x and f of this colour, write this colour
-    of x = 1.5 * N * 8 bytes."""
+VPOST_KERNEL = "k_vpost2d<double, 5>"
+PMC_FILE = os.path.join(ROOT, "profiles", "k_vpost2d_f64_pmc.md")
+VPOST_SRC = os.path.join(ROOT, "paper_1502_04657_amd", "csrc", "vcycle2d.hip")
+
+
+def _pmc_traffic():
+    """HBM bytes per launch of the fused post pass from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on the finest-level
+    unpack copy of known size), or None when the kernel source changed since."""
+    import hashlib
+    import re
+    if not os.path.exists(PMC_FILE):
+        return None
+    txt = open(PMC_FILE).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"vcycle2d_sha256:\s*([0-9a-f]{64})", txt)
+    if not m or not h:
+        return None
+    cur = hashlib.sha256(open(VPOST_SRC, "rb").read()).hexdigest()
+    return float(m.group(1)) if cur == h.group(1) else None
+
+
+def vpost_roofline(prob, steps):
+    """Roofline of the fused FP64 post-smoothing level pass (prolongation-add + 5 red-black
+    half sweeps), the largest HBM-bound kernel of the solve: HIP events recorded by the
+    library on the launch stream around every launch of that kernel during `steps` solves
+    of the benchmark workload; algorithmic bytes per launch = 8 (3 N_l + N_{l-1})."""
+    import ctypes as C
+    import torch
+    from paper_1502_04657_amd import Solver, _ffi, lib
+    s = Solver(prob, W.Options(tol_lambda=TOL))
+    u = torch.empty(s.ndof, dtype=torch.float64, device="cuda")
+    s.solve(u)
+    torch.cuda.synchronize()
+    L = lib()
+    if L.fmg_profile_begin(_ffi.FMG_PROF_VPOST2D_F64, 64 * (steps + 1)) != 0:
+        raise RuntimeError(L.fmg_last_error().decode())
+    for _ in range(steps):
+        s.solve(u)
+    prof = _ffi.fmg_kernel_profile()
+    if L.fmg_profile_end(C.byref(prof)) != 0:
+        raise RuntimeError(L.fmg_last_error().decode())
+    achieved = prof.bytes / prof.seconds / 1e9
+    return {"kernel": VPOST_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": _pmc_traffic(),
+            "avg_launch_us": prof.seconds / prof.launches * 1e6,
+            "algorithmic_bytes_per_launch": prof.bytes / prof.launches, "launches": prof.launches}
+
+
+def copy_calibration():
+    """A plain copy of known size for scaling memory counters: the unpack of a cold padded
+    n = 8192 level array (8191^2 interior doubles read, the same number written), after a
+    1 GiB fill has pushed it out of the caches."""
     import torch
     from paper_1502_04657_amd import ops
-    n, dim = prob.n_fine, prob.dim
-    N = (n - 1) ** dim
-    g = torch.Generator(device="cuda").manual_seed(0)
-    x = ops.pack(dim, n, torch.randn(N, dtype=torch.float64, device="cuda", generator=g))
-    f = ops.pack(dim, n, torch.randn(N, dtype=torch.float64, device="cuda", generator=g))
-    ops.smooth(dim, n, x, f, 2)
+    n = 8192
+    N = (n - 1) ** 2
+    lv = ops.new_level(2, n, device="cuda")
+    lv.fill_(1.0)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    flush.fill_(2.0)
     torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        ops.smooth(dim, n, x, f, 2)    # 5 half sweeps per call
-    e1.record(st)
+    out = ops.unpack(2, n, lv)
     torch.cuda.synchronize()
-    dt = e0.elapsed_time(e1) / 1e3 / (5 * reps)
-    algo = 1.5 * N * 8
-    achieved = algo / dt / 1e9
-    return {"kernel": "k_smooth_half<2,double> (finest level)", "bound": "hbm", "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_us": dt * 1e6, "algorithmic_bytes_per_launch": algo}
+    print(json.dumps({"copy_calibration": {"kernel": "k_unpack", "read_bytes": 8 * N, "write_bytes": 8 * N,
+                                           "check": float(out[:4].sum().item())}}))
 
 
 def cpu_baseline():
@@ -109,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a cold plain copy of known size (memory-counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; instances shard across GPUs with no communication "
@@ -116,6 +157,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration()
+        return
     prob = W.LARGE_2D
     N = prob.dofs()
     lam_ref = None
@@ -145,7 +189,7 @@ def main():
                         "lambda": rm.lam, "steps_total": rm.steps_total,
                         "lambda_rel_err_vs_oracle": (abs(rm.lam - lam_ref) / lam_ref) if lam_ref else None}
     print("bench: roofline", file=sys.stderr, flush=True)
-    out["roofline"] = smoother_roofline(prob)
+    out["roofline"] = vpost_roofline(prob, args.steps)
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -105,6 +105,22 @@ const char* fmg_version(void);
  * floating-point operations and give identical results.  Not thread-safe.                */
 int fmg_set_fused_vcycle(int32_t enable);
 
+/* ---- measurement hooks ------------------------------------------------------------------ */
+/* Per-launch timing of one kernel inside later solves: HIP events are recorded on the
+ * launch stream around each launch (up to max_launches), with the algorithmic bytes of
+ * each launch.  FMG_PROF_VPOST2D_F64 is the fused 2D FP64 post-smoothing level pass
+ * (prolongation-add plus the post half-sweeps; bytes = 8 * (3 N_l + N_{l-1}), reading x,
+ * f and the coarse correction and writing x).  Not thread-safe; one profile at a time.
+ * fmg_profile_end synchronises on the last recorded event and fills *out.                */
+enum { FMG_PROF_VPOST2D_F64 = 1 };
+typedef struct {
+    int64_t launches;   /* launches recorded                                               */
+    double seconds;     /* sum of the per-launch event intervals                           */
+    double bytes;       /* sum of the algorithmic bytes of those launches                  */
+} fmg_kernel_profile;
+int fmg_profile_begin(int32_t kernel, int32_t max_launches);
+int fmg_profile_end(fmg_kernel_profile* out);
+
 /* ---- whole solve (Algorithm 3.2) ---------------------------------------------------- */
 
 /* Bytes of device workspace fmg_solve needs for this problem and options.  Pure function.

@@ -24,6 +24,13 @@ class fmg_options(C.Structure):
                 ("newton_tol", C.c_double), ("precision", C.c_int32), ("reserved", C.c_int32)]
 
 
+class fmg_kernel_profile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double)]
+
+
+FMG_PROF_VPOST2D_F64 = 1
+
+
 class fmg_result(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("lambda_rq", C.c_double), ("norm", C.c_double), ("dlambda", C.c_double),
                 ("status", C.c_int32), ("levels", C.c_int32), ("steps_total", C.c_int32),
@@ -42,6 +49,8 @@ SIGNATURES = {
     "fmg_last_error": (C.c_char_p, []),
     "fmg_version": (C.c_char_p, []),
     "fmg_set_fused_vcycle": (C.c_int, [I32]),
+    "fmg_profile_begin": (C.c_int, [I32, I32]),
+    "fmg_profile_end": (C.c_int, [P]),
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),
     "fmg_solve": (C.c_int, [P, P, P, SZ, P, P, I64, P]),
     "fmg_level_pitch": (I64, [I32, I32]),

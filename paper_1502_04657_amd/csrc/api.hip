@@ -18,6 +18,17 @@ static thread_local char g_err[512] = "";
 // fused 2D V-cycle passes (1) or the unfused kernel sequence (0); both give identical bits
 static int g_fused = 1;
 
+// Optional per-launch timing of one kernel (instrumentation for measurements): HIP events
+// recorded around each launch on the stream it runs on, plus the algorithmic bytes of
+// each launch.  Not thread-safe.
+struct KernelProfiler {
+    int kernel = 0;                  // FMG_PROF_* being recorded, 0: off
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;      // 2 per launch
+    double bytes = 0.0;
+};
+static KernelProfiler g_prof;
+
 int set_error(int code, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -71,6 +82,7 @@ struct Layout {
     std::vector<Grid> g;
     size_t state, xc, mom, momscr, arena, fac, forms;
     std::vector<size_t> u, b, xv, fv;   // per level (u[0] = xc)
+    std::vector<size_t> tv;             // per level: target of the fused 2D pre pass
     size_t total;
 };
 
@@ -85,7 +97,7 @@ static Layout make_layout(int dim, int nc, int levels, int mixed) {
     lo.state = take(sizeof(SmallState));
     lo.xc = take(sizeof(double) * lo.g[0].elems);
     const size_t ts = mixed ? sizeof(float) : sizeof(double);
-    lo.u.resize(levels); lo.b.resize(levels); lo.xv.resize(levels); lo.fv.resize(levels);
+    lo.u.resize(levels); lo.b.resize(levels); lo.xv.resize(levels); lo.fv.resize(levels); lo.tv.resize(levels);
     for (int l = 0; l < levels; ++l) {
         lo.u[l] = (l == 0) ? lo.xc : take(sizeof(double) * lo.g[l].elems);
         lo.b[l] = take(sizeof(double) * lo.g[l].elems);
@@ -93,6 +105,8 @@ static Layout make_layout(int dim, int nc, int levels, int mixed) {
         bool top_only = !mixed && l == levels - 1;
         lo.xv[l] = top_only ? 0 : take(ts * lo.g[l].elems);
         lo.fv[l] = top_only ? 0 : take(ts * lo.g[l].elems);
+        // the fused passes run in the V-cycle precision; the coarsest level needs none
+        lo.tv[l] = (dim == 2 && l > 0) ? take(ts * lo.g[l].elems) : 0;
     }
     const int64_t ncell = dim == 2 ? (int64_t)nc * nc : (int64_t)nc * nc * nc;
     const int ne = dim == 2 ? 2 : 6;
@@ -124,9 +138,19 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
     T* xc = at<T>(ws, lo.xv[l - 1]);
     T* fc = at<T>(ws, lo.fv[l - 1]);
     if (lo.dim == 2 && nu_pre <= 2 && nu_post <= 2 && g_fused) {
-        launch_vpre2d<T>(g, lo.g[l - 1], x, f, fc, nu_pre, zero_x ? 1 : 0, s);
+        T* y = at<T>(ws, lo.tv[l]);
+        launch_vpre2d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
         vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
-        launch_vpost2d<T>(g, lo.g[l - 1], x, f, xc, nu_post, s);
+        const bool rec = g_prof.kernel == FMG_PROF_VPOST2D_F64 && sizeof(T) == 8 && g_prof.used < g_prof.cap;
+        if (rec) hipEventRecord(g_prof.ev[2 * g_prof.used], s);
+        launch_vpost2d<T>(g, lo.g[l - 1], y, x, f, xc, nu_post, s);
+        if (rec) {
+            hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s);
+            // read x, f and the coarse correction, write x (interior values)
+            const double nf = std::pow((double)(g.n - 1), 2), ncs = std::pow((double)(lo.g[l - 1].n - 1), 2);
+            g_prof.bytes += (3.0 * nf + ncs) * sizeof(double);
+            ++g_prof.used;
+        }
         return;
     }
     if (zero_x) launch_fill<T>(x, g.elems, T(0), s);
@@ -182,6 +206,41 @@ int fmg_set_fused_vcycle(int32_t enable) {
     g_fused = enable ? 1 : 0;
     return 0;
 }
+int fmg_profile_begin(int32_t kernel, int32_t max_launches) {
+    if (kernel != FMG_PROF_VPOST2D_F64 || max_launches < 1 || max_launches > (1 << 20))
+        return set_error(FMG_EINVAL, "bad profile request");
+    if (g_prof.kernel) return set_error(FMG_EINVAL, "a profile is already running");
+    g_prof.ev.resize(2 * (size_t)max_launches);
+    for (auto& e : g_prof.ev) FMG_HIP_CHECK(hipEventCreate(&e));
+    g_prof.cap = max_launches;
+    g_prof.used = 0;
+    g_prof.bytes = 0.0;
+    g_prof.kernel = kernel;
+    return 0;
+}
+
+int fmg_profile_end(fmg_kernel_profile* out) {
+    if (!g_prof.kernel) return set_error(FMG_EINVAL, "no profile is running");
+    g_prof.kernel = 0;
+    double ms_total = 0.0;
+    int rc = 0;
+    if (g_prof.used > 0 && hipEventSynchronize(g_prof.ev[2 * g_prof.used - 1]) != hipSuccess) rc = FMG_EHIP;
+    for (int i = 0; i < g_prof.used && !rc; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) rc = FMG_EHIP;
+        ms_total += ms;
+    }
+    for (auto& e : g_prof.ev) hipEventDestroy(e);
+    g_prof.ev.clear();
+    if (rc) return set_error(rc, "profile events failed");
+    if (out) {
+        out->launches = g_prof.used;
+        out->seconds = ms_total * 1e-3;
+        out->bytes = g_prof.bytes;
+    }
+    return 0;
+}
+
 const char* fmg_version(void) { return "fmgeig 0.1 (gfx950)"; }
 
 int64_t fmg_level_pitch(int32_t dim, int32_t n) {
@@ -373,9 +432,12 @@ int fmg_op_vcycle(int32_t dim, int32_t n_coarse, int32_t levels, int32_t nu_pre,
     Layout lo = make_layout(dim, n_coarse, levels, 0);
     if (ws_bytes < lo.total) return set_error(FMG_ENOMEM, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int l = 0; l + 1 < levels; ++l) {
-        launch_fill<double>(at<double>(ws, lo.xv[l]), lo.g[l].elems, 0.0, s);
-        launch_fill<double>(at<double>(ws, lo.fv[l]), lo.g[l].elems, 0.0, s);
+    for (int l = 0; l < levels; ++l) {
+        if (l + 1 < levels) {
+            launch_fill<double>(at<double>(ws, lo.xv[l]), lo.g[l].elems, 0.0, s);
+            launch_fill<double>(at<double>(ws, lo.fv[l]), lo.g[l].elems, 0.0, s);
+        }
+        if (lo.tv[l]) launch_fill<double>(at<double>(ws, lo.tv[l]), lo.g[l].elems, 0.0, s);
     }
     vcycle<double>(lo, ws, levels - 1, x, f, nu_pre, nu_post, s);
     return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "vcycle launch failed");

@@ -38,10 +38,12 @@ void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partia
 // fused 2D V-cycle level passes (nu symmetric sweeps = 2 nu + 1 half sweeps, nu <= 2);
 // return false when nu is not supported (the caller then uses the unfused kernels).
 // zero_x: treat the incoming x as zero (coarse-level corrections) without reading it.
-template <typename T> bool launch_vpre2d(const Grid& g, const Grid& gc, T* x, const T* f, T* rc, int nu,
-                                         int zero_x, hipStream_t s);
-template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, T* x, const T* f, const T* xc, int nu,
-                                          hipStream_t s);
+// pre reads x and writes the smoothed values to y; post reads y and writes x (out of place:
+// the passes read halos across tiles).  Boundary rings of x and y must be zero.
+template <typename T> bool launch_vpre2d(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc,
+                                         int nu, int zero_x, hipStream_t s);
+template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc,
+                                          int nu, hipStream_t s);
 
 // ---- moments.hip ------------------------------------------------------------------------
 int moments_per_element(int dim);            // doubles per coarse element in the output

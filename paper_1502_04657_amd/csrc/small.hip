@@ -69,6 +69,24 @@ template <int D, int T, int V, int Dim>
 struct CellVert {
     static constexpr int value = (D == 2) ? kCellElemVert2D[T % 2][V % 3][Dim % 2] : kCellElemVert3D[T][V][Dim];
 };
+// local index in simplex T of the cell vertex with offsets (CV & 1, CV >> 1 & 1, CV >> 2 & 1),
+// or -1 if T does not contain it
+template <int D>
+__host__ __device__ constexpr int vert_of(int t, int cv) {
+    for (int v = 0; v < D + 1; ++v) {
+        bool eq = true;
+        for (int d = 0; d < D; ++d) {
+            const int o = (D == 2) ? kCellElemVert2D[t % 2][v % 3][d % 2] : kCellElemVert3D[t][v][d];
+            eq = eq && (o == ((cv >> d) & 1));
+        }
+        if (eq) return v;
+    }
+    return -1;
+}
+template <int D, int T, int CV>
+struct VertOf {
+    static constexpr int value = vert_of<D>(T, CV);
+};
 template <int D, int S, int Dim>
 struct Off {
     static constexpr int value = (D == 2) ? kOff2D[S % 7][Dim % 2] : kOff3D[S][Dim];
@@ -446,13 +464,16 @@ __device__ __forceinline__ double elem_corner(const double* U, const double* UU,
     return s1 + 2.0 * c * s2 + c * c * mo[L::T0];
 }
 
-// S(x): coarse stencil Sst, border sH, corner sc[3].  One pass per (colour class, simplex
-// type); within a pass one thread per (cell, vertex row), the vertex uniform per wavefront.
+// S(x): coarse stencil Sst, border sH, corner sc[3].  One pass per colour class; within a
+// pass one thread per (cell, cell vertex) adds the rows of that vertex from every simplex
+// of the cell that contains it (the cell vertex is uniform per wavefront).  The corner
+// term of each simplex is added by the thread of its vertex 0 (the cell origin).
 template <int D, bool AUG>
 __device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
     constexpr int NS = Geo<D>::NS;
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
+    constexpr int NCV = 1 << D;
     using L = MomLayout<D>;
     const int N = ar.z.N, nc = a.nc, m = ar.z.m;
     const double H = 1.0 / nc;
@@ -463,46 +484,49 @@ __device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, con
         for (int i = threadIdx.x; i < N; i += kThreads) ar.sH[i] = 0.0;
     __syncthreads();
     double sU = 0.0;
-    for (int color = 0; color < (1 << D); ++color) {
+    for (int color = 0; color < NCV; ++color) {
         const ColorClass cc = color_class<D>(nc, color);
-        for_simplices<D>([&](auto tc) {
-            constexpr int t = decltype(tc)::value;
-            for (int task = threadIdx.x; task < V * cc.ncolp; task += kThreads) {
-                const int aav = task / cc.ncolp, q = task - aav * cc.ncolp;
-                if (q < cc.ncol) {
-                    int C0, C1, C2, cl;
-                    cell_of<D>(cc, q, nc, C0, C1, C2, cl);
-                    int nd[V];
-                    double U[V];
-                    static_for<V>([&](auto vc) {
-                        constexpr int v = decltype(vc)::value;
-                        nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
-                        U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
-                    });
-                    double UU[V * (V + 1) / 2];
-#pragma unroll
-                    for (int p = 0; p < V; ++p)
-#pragma unroll
-                        for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-                    const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
-                    dispatch<V>(aav, [&](auto ac) {
-                        constexpr int aa = decltype(ac)::value;
-                        if (nd[aa] >= 0) {
-                            double Sr[V], sh = 0.0;
-                            elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
-                            double* row = ar.Sst + (size_t)nd[aa] * NS;
-                            static_for<V>([&](auto bc) {
-                                constexpr int bb = decltype(bc)::value;
-                                if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
+        for (int task = threadIdx.x; task < NCV * cc.ncolp; task += kThreads) {
+            const int cvv = task / cc.ncolp, q = task - cvv * cc.ncolp;
+            if (q < cc.ncol) {
+                int C0, C1, C2, cl;
+                cell_of<D>(cc, q, nc, C0, C1, C2, cl);
+                dispatch<NCV>(cvv, [&](auto cvc) {
+                    constexpr int cv = decltype(cvc)::value;
+                    for_simplices<D>([&](auto tc) {
+                        constexpr int t = decltype(tc)::value;
+                        constexpr int aa = VertOf<D, t, cv>::value;
+                        if constexpr (aa >= 0) {
+                            int nd[V];
+                            double U[V];
+                            static_for<V>([&](auto vc) {
+                                constexpr int v = decltype(vc)::value;
+                                nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
+                                U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
                             });
-                            if (AUG) ar.sH[nd[aa]] += sh;
+                            double UU[V * (V + 1) / 2];
+#pragma unroll
+                            for (int p = 0; p < V; ++p)
+#pragma unroll
+                                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+                            const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
+                            if (nd[aa] >= 0) {
+                                double Sr[V], sh = 0.0;
+                                elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
+                                double* row = ar.Sst + (size_t)nd[aa] * NS;
+                                static_for<V>([&](auto bc) {
+                                    constexpr int bb = decltype(bc)::value;
+                                    if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
+                                });
+                                if (AUG) ar.sH[nd[aa]] += sh;
+                            }
+                            if (AUG && aa == 0) sU += elem_corner<D>(U, UU, mo, c);
                         }
-                        if (AUG && aa == 0) sU += elem_corner<D>(U, UU, mo, c);
                     });
-                }
+                });
             }
-            __syncthreads();
-        });
+        }
+        __syncthreads();
     }
     if (AUG) {
         sU = bsum1(ar.red, sU);

@@ -1,8 +1,11 @@
 // Fused, temporally blocked V-cycle level kernels for the 2D mesh family.
 //
 // A V(nu,nu) level is two passes over the fine arrays instead of ~14:
-//   pre : x <- NH red-black half sweeps, then r_c = P^T (f - K x)        (read x, f; write x, r_c)
-//   post: x <- x + P x_c, then NH red-black half sweeps                   (read x, f, x_c; write x)
+//   pre : y <- NH red-black half sweeps on x, then r_c = P^T (f - K y)   (read x, f; write y, r_c)
+//   post: x <- y + P x_c, then NH red-black half sweeps                   (read y, f, x_c; write x)
+// Each pass reads one array and writes another (y is a scratch level array): a workgroup
+// reads a halo around its tile, so an in-place pass would let it read nodes that a
+// neighbouring workgroup has already overwritten.
 // with NH = 2 nu + 1 (the symmetric sweeps R,B,B,R,... collapse to R,B,R,... because a
 // repeated half sweep of the same colour changes nothing).  Each workgroup owns a TX x TY
 // tile, loads it with a halo of HALO nodes into LDS, and runs the half sweeps on shrinking
@@ -15,9 +18,9 @@ namespace fmg {
 
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 32;
 constexpr int THREADS = 256;
+constexpr int ROWLANES = 32;                      // threads per region row in the sweeps
+constexpr int ROWGROUPS = THREADS / ROWLANES;     // rows processed at once
 
 template <typename T>
 __device__ inline T gs2f(T f, T w, T e, T s, T n) {
@@ -27,10 +30,11 @@ __device__ inline T gs2f(T f, T w, T e, T s, T n) {
 // Red-black half sweeps on the LDS region.  Region coordinates: column c in [0, RW),
 // row r in [0, RH); global node (gi, gj) = (i0 - HALO + c, j0 - HALO + r).  Half sweep s
 // updates the colour-`col` interior nodes within distance ext_s = (R + NH - 1 - s) of the
-// tile.
-template <typename T, int HALO, int NH, int R>
+// tile.  Threads take rows in groups of ROWLANES (no run-time divisions).
+template <typename T, int TX, int TY, int HALO, int NH, int R>
 __device__ inline void half_sweeps(T* xs, const T* fs, int i0, int j0, int n, int first) {
     constexpr int RW = TX + 2 * HALO;
+    const int lane = threadIdx.x % ROWLANES, grp = threadIdx.x / ROWLANES;
 #pragma unroll 1
     for (int s = 0; s < NH; ++s) {
         const int col = first ^ (s & 1);
@@ -38,17 +42,11 @@ __device__ inline void half_sweeps(T* xs, const T* fs, int i0, int j0, int n, in
         // update rectangle in global coordinates, clipped to the domain interior
         const int ia = max(1, i0 - ext), ib = min(n - 1, i0 + TX - 1 + ext);
         const int ja = max(1, j0 - ext), jb = min(n - 1, j0 + TY - 1 + ext);
-        const int w = ib - ia + 1, h = jb - ja + 1;
-        if (w > 0 && h > 0) {
-            const int cnt = (w + 1) >> 1;
-            const int items = cnt * h;
-            for (int t = threadIdx.x; t < items; t += THREADS) {
-                const int rr = t / cnt, q = t - rr * cnt;
-                const int gj = ja + rr;
-                const int gi = ia + 2 * q + ((col - gj - ia) & 1);
-                if (gi > ib) continue;
-                const int c = gi - (i0 - HALO), r = gj - (j0 - HALO);
-                const int p = c + RW * r;
+        for (int gj = ja + grp; gj <= jb; gj += ROWGROUPS) {
+            const int gi0 = ia + ((col - gj - ia) & 1);   // first node of this colour in the row
+            const int r = gj - (j0 - HALO);
+            for (int gi = gi0 + 2 * lane; gi <= ib; gi += 2 * ROWLANES) {
+                const int p = (gi - (i0 - HALO)) + RW * r;
                 xs[p] = gs2f<T>(fs[p], xs[p - 1], xs[p + 1], xs[p - RW], xs[p + RW]);
             }
         }
@@ -56,7 +54,7 @@ __device__ inline void half_sweeps(T* xs, const T* fs, int i0, int j0, int n, in
     }
 }
 
-template <typename T, int HALO>
+template <typename T, int TX, int TY, int HALO>
 __device__ inline void load_region(T* xs, T* fs, const T* __restrict__ x, const T* __restrict__ f, const Grid& g,
                                    int i0, int j0, int zero_x) {
     constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
@@ -75,7 +73,7 @@ __device__ inline void load_region(T* xs, T* fs, const T* __restrict__ x, const 
     }
 }
 
-template <typename T, int HALO>
+template <typename T, int TX, int TY, int HALO>
 __device__ inline void store_tile(const T* xs, T* __restrict__ x, const Grid& g, int i0, int j0) {
     constexpr int RW = TX + 2 * HALO;
     const int n = g.n;
@@ -87,9 +85,10 @@ __device__ inline void store_tile(const T* xs, T* __restrict__ x, const Grid& g,
 }
 
 // pre-smoothing + residual + restriction
-template <typename T, int NH>
-__global__ __launch_bounds__(THREADS) void k_vpre2d(T* __restrict__ x, const T* __restrict__ f,
-                                                    T* __restrict__ rc, Grid g, Grid gc, int zero_x) {
+template <typename T, int NH, int TX, int TY>
+__global__ __launch_bounds__(THREADS) void k_vpre2d(const T* __restrict__ x, T* __restrict__ y,
+                                                    const T* __restrict__ f, T* __restrict__ rc, Grid g, Grid gc,
+                                                    int zero_x) {
     constexpr int R = 2;                 // x must be final within 2 rings for the residual ring
     constexpr int HALO = NH + R;
     constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
@@ -97,9 +96,9 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(T* __restrict__ x, const T* 
     __shared__ T fs[RW * RH];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n;
-    load_region<T, HALO>(xs, fs, x, f, g, i0, j0, zero_x);
+    load_region<T, TX, TY, HALO>(xs, fs, x, f, g, i0, j0, zero_x);
     __syncthreads();
-    half_sweeps<T, HALO, NH, R>(xs, fs, i0, j0, n, 0);
+    half_sweeps<T, TX, TY, HALO, NH, R>(xs, fs, i0, j0, n, 0);
     // residual r = f - K x on the tile and one ring, stored over f
     {
         constexpr int W1 = TX + 2, H1 = TY + 2;
@@ -112,7 +111,7 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(T* __restrict__ x, const T* 
         }
     }
     __syncthreads();
-    store_tile<T, HALO>(xs, x, g, i0, j0);
+    store_tile<T, TX, TY, HALO>(xs, y, g, i0, j0);
     // restriction for the coarse nodes whose centre 2I, 2J lies in this tile
     {
         constexpr int CW = TX / 2, CH = TY / 2;
@@ -129,9 +128,10 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(T* __restrict__ x, const T* 
 }
 
 // prolongation + correction + post-smoothing
-template <typename T, int NH>
-__global__ __launch_bounds__(THREADS) void k_vpost2d(T* __restrict__ x, const T* __restrict__ f,
-                                                     const T* __restrict__ xc, Grid g, Grid gc) {
+template <typename T, int NH, int TX, int TY>
+__global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T* __restrict__ x,
+                                                     const T* __restrict__ f, const T* __restrict__ xc, Grid g,
+                                                     Grid gc) {
     constexpr int R = 0;
     constexpr int HALO = NH > 0 ? NH + R : 1;
     constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(T* __restrict__ x, const T*
     __shared__ T fs[RW * RH];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n;
-    load_region<T, HALO>(xs, fs, x, f, g, i0, j0, 0);
+    load_region<T, TX, TY, HALO>(xs, fs, y, f, g, i0, j0, 0);
     __syncthreads();
     // x += P x_c on every interior node of the region (same expression as k_prolong)
     for (int t = threadIdx.x; t < RW * RH; t += THREADS) {
@@ -153,46 +153,64 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(T* __restrict__ x, const T*
         xs[t] += v;
     }
     __syncthreads();
-    half_sweeps<T, HALO, NH, R>(xs, fs, i0, j0, n, 0);
-    store_tile<T, HALO>(xs, x, g, i0, j0);
+    half_sweeps<T, TX, TY, HALO, NH, R>(xs, fs, i0, j0, n, 0);
+    store_tile<T, TX, TY, HALO>(xs, x, g, i0, j0);
 }
 
+// Tile shape by level: 64 x 32 where the level has many tiles, 16 x 16 on coarse levels
+// (more workgroups, shorter sweeps; the halo overhead is irrelevant there).
+constexpr int kSmallLevel = 256;
+
 template <typename T, int NH>
-void pre_launch(const Grid& g, const Grid& gc, T* x, const T* f, T* rc, int zero_x, hipStream_t s) {
-    dim3 grd(cdiv(g.n - 1, TX), cdiv(g.n - 1, TY));
-    hipLaunchKernelGGL((k_vpre2d<T, NH>), grd, dim3(THREADS), 0, s, x, f, rc, g, gc, zero_x);
+void pre_launch(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc, int zero_x, hipStream_t s) {
+    if (g.n <= kSmallLevel) {
+        dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
+        hipLaunchKernelGGL((k_vpre2d<T, NH, 16, 16>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
+    } else {
+        dim3 grd(cdiv(g.n - 1, 64), cdiv(g.n - 1, 32));
+        hipLaunchKernelGGL((k_vpre2d<T, NH, 64, 32>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
+    }
 }
 template <typename T, int NH>
-void post_launch(const Grid& g, const Grid& gc, T* x, const T* f, const T* xc, hipStream_t s) {
-    dim3 grd(cdiv(g.n - 1, TX), cdiv(g.n - 1, TY));
-    hipLaunchKernelGGL((k_vpost2d<T, NH>), grd, dim3(THREADS), 0, s, x, f, xc, g, gc);
+void post_launch(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc, hipStream_t s) {
+    if (g.n <= kSmallLevel) {
+        dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
+        hipLaunchKernelGGL((k_vpost2d<T, NH, 16, 16>), grd, dim3(THREADS), 0, s, y, x, f, xc, g, gc);
+    } else {
+        dim3 grd(cdiv(g.n - 1, 64), cdiv(g.n - 1, 32));
+        hipLaunchKernelGGL((k_vpost2d<T, NH, 64, 32>), grd, dim3(THREADS), 0, s, y, x, f, xc, g, gc);
+    }
 }
 
 }  // namespace
 
 template <typename T>
-bool launch_vpre2d(const Grid& g, const Grid& gc, T* x, const T* f, T* rc, int nu, int zero_x, hipStream_t s) {
+bool launch_vpre2d(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc, int nu, int zero_x,
+                   hipStream_t s) {
     switch (nu) {
-        case 0: pre_launch<T, 0>(g, gc, x, f, rc, zero_x, s); return true;
-        case 1: pre_launch<T, 3>(g, gc, x, f, rc, zero_x, s); return true;
-        case 2: pre_launch<T, 5>(g, gc, x, f, rc, zero_x, s); return true;
+        case 0: pre_launch<T, 0>(g, gc, x, y, f, rc, zero_x, s); return true;
+        case 1: pre_launch<T, 3>(g, gc, x, y, f, rc, zero_x, s); return true;
+        case 2: pre_launch<T, 5>(g, gc, x, y, f, rc, zero_x, s); return true;
         default: return false;
     }
 }
 template <typename T>
-bool launch_vpost2d(const Grid& g, const Grid& gc, T* x, const T* f, const T* xc, int nu, hipStream_t s) {
+bool launch_vpost2d(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc, int nu,
+                    hipStream_t s) {
     switch (nu) {
-        case 0: post_launch<T, 0>(g, gc, x, f, xc, s); return true;
-        case 1: post_launch<T, 3>(g, gc, x, f, xc, s); return true;
-        case 2: post_launch<T, 5>(g, gc, x, f, xc, s); return true;
+        case 0: post_launch<T, 0>(g, gc, y, x, f, xc, s); return true;
+        case 1: post_launch<T, 3>(g, gc, y, x, f, xc, s); return true;
+        case 2: post_launch<T, 5>(g, gc, y, x, f, xc, s); return true;
         default: return false;
     }
 }
-template bool launch_vpre2d<double>(const Grid&, const Grid&, double*, const double*, double*, int, int,
+template bool launch_vpre2d<double>(const Grid&, const Grid&, const double*, double*, const double*, double*, int,
+                                    int, hipStream_t);
+template bool launch_vpre2d<float>(const Grid&, const Grid&, const float*, float*, const float*, float*, int, int,
+                                   hipStream_t);
+template bool launch_vpost2d<double>(const Grid&, const Grid&, const double*, double*, const double*,
+                                     const double*, int, hipStream_t);
+template bool launch_vpost2d<float>(const Grid&, const Grid&, const float*, float*, const float*, const float*, int,
                                     hipStream_t);
-template bool launch_vpre2d<float>(const Grid&, const Grid&, float*, const float*, float*, int, int, hipStream_t);
-template bool launch_vpost2d<double>(const Grid&, const Grid&, double*, const double*, const double*, int,
-                                     hipStream_t);
-template bool launch_vpost2d<float>(const Grid&, const Grid&, float*, const float*, const float*, int, hipStream_t);
 
 }  // namespace fmg

@@ -96,7 +96,7 @@ def test_coarse_solve_is_exact(ops, dim, n):
     assert rel_err(host_compact(dim, n, x32), ref) < 1e-5
 
 
-@pytest.mark.parametrize("dim, nc, levels", [(2, 8, 3), (2, 16, 4), (2, 12, 4), (3, 4, 3), (3, 2, 4)])
+@pytest.mark.parametrize("dim, nc, levels", [(2, 8, 3), (2, 16, 4), (2, 12, 4), (2, 6, 7), (3, 4, 3), (3, 2, 4)])
 def test_vcycle(ops, dim, nc, levels):
     from oracle.mg import MGHierarchy
     from paper_1502_04657_amd import lib
@@ -124,6 +124,25 @@ def test_vcycle(ops, dim, nc, levels):
             lib().fmg_set_fused_vcycle(1)
         assert torch.equal(a, b)
         assert rel_err(host_compact(dim, n, a), H.vcycle(levels - 1, x0, f, nu, nu + 1)) < 1e-12
+
+
+@pytest.mark.parametrize("nc, levels", [(12, 8), (10, 7), (16, 8)])
+def test_fused_vcycle_large_levels_bitwise(ops, nc, levels):
+    """Levels above the small-tile threshold (64 x 32 tiles, ragged last tiles) give the
+    same bits as the unfused kernel sequence."""
+    from paper_1502_04657_amd import lib
+    n = nc << (levels - 1)
+    x0 = W.random_interior(2, n, seed=21)
+    f = W.random_interior(2, n, seed=22)
+    prob = W.Problem(2, nc, levels - 1)
+    got = ops.vcycle(prob, W.Options(), dev_level(2, n, x0), dev_level(2, n, f))
+    lib().fmg_set_fused_vcycle(0)
+    try:
+        unf = ops.vcycle(prob, W.Options(), dev_level(2, n, x0), dev_level(2, n, f))
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+    assert torch.equal(got, unf)
+    assert bool(torch.isfinite(got).all())
 
 
 RHS_CASES = [W.Problem(2, 4, 2, (1.5, 0.5, 0.0), 0.25, 7.0), W.Problem(2, 12, 3, (1.0, 2.0, 0.0), 0.0, 100.0),
