@@ -26,7 +26,8 @@
 // goes back one step and the Jacobian is refactored there.  The fixed point is unchanged.
 //
 // On the coarsest space the iteration starts from the discrete sine mode and raises zeta in
-// geometric stages (factor 8 from a first stage <= 1, the step halved on failure).
+// geometric stages (factor 8 from a first stage <= 1, the step halved on failure); stages
+// before the last stop at a relative residual of 1e-8.
 #include <utility>
 
 #include "kernels.h"
@@ -37,6 +38,7 @@ namespace fmg {
 namespace {
 
 constexpr int kThreads = 256;               // four wavefronts
+constexpr double kStageTol = 1e-8;          // residual for intermediate continuation stages
 constexpr int kWaves = kThreads / 64;
 
 template <int D>
@@ -118,6 +120,12 @@ __device__ __forceinline__ void for_simplices(F&& f) {
     if constexpr (D == 2) static_for<Geo<D>::NE>(f);
     else rolled_for<Geo<D>::NE>(f);
 }
+// stencil slots of a node: unrolled in 2D (7), rolled in 3D (15)
+template <int D, typename F>
+__device__ __forceinline__ void for_slots(F&& f) {
+    if constexpr (D == 2) static_for<Geo<D>::NS>(f);
+    else rolled_for<Geo<D>::NS>(f);
+}
 // f(integral_constant<int, v>) for the run-time value v in [0, N) (uniform per wavefront)
 template <int N, typename F>
 __device__ __forceinline__ void dispatch(int v, F&& f) {
@@ -150,8 +158,10 @@ struct Args {
 
 // Optional phase timers of the small solves (wall clock, 100 MHz ticks); compiled only
 // with -DFMG_SMALL_TIMING, read back with fmg_debug_small_timers().
-#ifdef FMG_SMALL_TIMING
+#if defined(FMG_SMALL_TIMING) || defined(FMG_SMALL_MICRO)
 __device__ unsigned long long g_small_t[32];
+#endif
+#ifdef FMG_SMALL_TIMING
 #define FMG_T0(v) const unsigned long long v = wall_clock64()
 #define FMG_TACC(k, v) do { if (threadIdx.x == 0) atomicAdd(&g_small_t[(AUG ? 0 : 16) + (k)], wall_clock64() - (v)); } while (0)
 #define FMG_TCNT(k) do { if (threadIdx.x == 0) atomicAdd(&g_small_t[(AUG ? 0 : 16) + (k)], 1ull); } while (0)
@@ -550,7 +560,7 @@ __device__ __forceinline__ void apply(Arena<D, AUG>& ar, const Args& a, double z
         node_pos<D>(i, m, P);
         const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
         double yi = 0.0, zi = 0.0;
-        static_for<NS>([&](auto sc_) {
+        for_slots<D>([&](auto sc_) {
             constexpr int s = decltype(sc_)::value;
             const int j = nbr<D, s>(P, m);
             if (j >= 0) {
@@ -618,23 +628,309 @@ __device__ __forceinline__ VecMap vec_map(int bs) {
     return v;
 }
 
-// sum_k a[k*sa] * b[k*sb] for k = 0..n-1 in order; the loads of 16 terms are issued
-// together (indices clamped in bounds), so a short dot costs one memory latency
+// sum_k a[k*sa] * b[k*sb] for k = 0..n-1 in order; the loads of 8 terms are issued
+// together (indices clamped in bounds)
 __device__ __forceinline__ double dotn(const double* a, int sa, const double* b, int sb, int n) {
     double acc = 0.0;
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        double x[16], y[16];
+    for (int k0 = 0; k0 < n; k0 += 8) {
+        double x[8], y[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < 8; ++j) {
             const int k = min(k0 + j, n - 1);
             x[j] = a[k * sa];
             y[j] = b[k * sb];
         }
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < 8; ++j)
             if (k0 + j < n) acc = fma(x[j], y[j], acc);
     }
     return acc;
+}
+
+// ---- blocks of at most 16 x 16: one wavefront per block product on the FP64 matrix
+// cores (v_mfma_f64_16x16x4).  Lane l supplies A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16]; the 16 x 16 result sits in lane l, register r at
+// (row l / 16 + 4 r, column l % 16).  Blocks are stored row-major with leading dimension
+// bs and padded with zeros to 16 inside the product.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+struct Tile {
+    int i;    // lane % 16: row of A, column of B and of the result
+    int kq;   // lane / 16: k within a chunk of 4, row group of the result
+};
+__device__ __forceinline__ Tile tile_lane() {
+    const int l = threadIdx.x & 63;
+    return Tile{l & 15, l >> 4};
+}
+
+// Operands of one 16 x 16 x 16 product in this lane: av[j] = s * op(A)[i][4j + kq],
+// bv[j] = op(B)[4j + kq][i] (zero outside the bs x bs block).  All loads are issued before
+// the matrix instructions that consume them.
+struct Ops16 {
+    double av[4], bv[4];
+};
+__device__ __forceinline__ Ops16 ops_mm(const Tile& t, const double* A, bool ta, const double* B, bool tb, int bs,
+                                        double s) {
+    Ops16 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * j + t.kq;
+        const bool ok = t.i < bs && k < bs;
+        const int ia = ok ? (ta ? k * bs + t.i : t.i * bs + k) : 0;
+        const int ib = ok ? (tb ? t.i * bs + k : k * bs + t.i) : 0;
+        const double a = A[ia], b = B[ib];
+        o.av[j] = ok ? s * a : 0.0;
+        o.bv[j] = ok ? b : 0.0;
+    }
+    return o;
+}
+// op(A) times R right-hand sides X (column q = x[q*N + k])
+__device__ __forceinline__ Ops16 ops_mv(const Tile& t, const double* A, bool ta, const double* x, int N, int R,
+                                        int bs, double s) {
+    Ops16 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * j + t.kq;
+        const bool oka = t.i < bs && k < bs, okb = k < bs && t.i < R;
+        const double a = A[oka ? (ta ? k * bs + t.i : t.i * bs + k) : 0];
+        const double b = x[okb ? (size_t)t.i * N + k : 0];
+        o.av[j] = oka ? s * a : 0.0;
+        o.bv[j] = okb ? b : 0.0;
+    }
+    return o;
+}
+__device__ __forceinline__ d4_t mfma16(const Ops16& o, d4_t c) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(o.av[j], o.bv[j], c, 0, 0, 0);
+    return c;
+}
+// c += s * op(A) op(B) for bs x bs blocks (op = transpose when the flag is set)
+__device__ __forceinline__ d4_t mm16(const Tile& t, const double* A, bool ta, const double* B, bool tb, int bs,
+                                     double s, d4_t c) {
+    return mfma16(ops_mm(t, A, ta, B, tb, bs, s), c);
+}
+// c += s * op(A) X for a bs x bs block A and R right-hand sides X
+__device__ __forceinline__ d4_t mv16(const Tile& t, const double* A, bool ta, const double* x, int N, int R, int bs,
+                                     double s, d4_t c) {
+    return mfma16(ops_mv(t, A, ta, x, N, R, bs, s), c);
+}
+__device__ __forceinline__ d4_t load16(const Tile& t, const double* M, int bs) {
+    d4_t c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = t.kq + 4 * r;
+        c[r] = (row < bs && t.i < bs) ? M[row * bs + t.i] : 0.0;
+    }
+    return c;
+}
+__device__ __forceinline__ void store16(const Tile& t, double* M, int bs, d4_t c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = t.kq + 4 * r;
+        if (row < bs && t.i < bs) M[row * bs + t.i] = c[r];
+    }
+}
+
+// 1/p: hardware estimate refined by two Newton-Raphson steps (r <- r + r (1 - p r))
+__device__ __forceinline__ double recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double sel4(const d4_t& v, int r) {
+    return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
+}
+
+// Gauss-Jordan inversion of the pivot blocks Dm[first + step*i], i < cnt, one wavefront per
+// block with the block in registers (result layout of mm16); pivot rows and columns move
+// between lanes with shuffles.  Returns the number of negative pivots (LDL^T pivots of the
+// blocks), or -1 if one is zero relative to `scale`.
+template <int D, bool AUG>
+__device__ __forceinline__ int block_invert16(Arena<D, AUG>& ar, int first, int step, int cnt, double scale) {
+    const int bs = ar.z.bs, B2 = ar.z.B2;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const Tile t = tile_lane();
+    int neg = 0, bad = 0;
+    #pragma unroll 1
+    for (int task = wid; task < cnt; task += kWaves) {
+        double* M = ar.Dm + (size_t)(first + step * task) * B2;
+        d4_t m = load16(t, M, bs);
+#pragma unroll 1
+        for (int k = 0; k < bs; ++k) {
+            const int kr = k >> 2, kl = (k & 3) * 16;
+            const double piv = __shfl(sel4(m, kr), kl + k, 64);
+            if (!(fabs(piv) > 1e-15 * scale)) bad = 1;
+            if (piv < 0.0) ++neg;
+            const double inv = recip(piv);
+            const double pr = __shfl(sel4(m, kr), kl + t.i, 64);   // A[k][col]
+            d4_t pc;                                                 // A[row][k] of my rows
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pc[r] = __shfl(m[r], t.kq * 16 + k, 64);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = t.kq + 4 * r;
+                double v;
+                if (row == k) v = (t.i == k) ? inv : pr * inv;
+                else v = (t.i == k) ? -pc[r] * inv : m[r] - pc[r] * (pr * inv);
+                m[r] = v;
+            }
+        }
+        store16(t, M, bs, m);
+    }
+    // combine the per-wavefront counts
+    __syncthreads();
+    if (lane == 0) {
+        ar.red[wid * 8 + 6] = (double)neg;
+        ar.red[wid * 8 + 7] = (double)bad;
+    }
+    __syncthreads();
+    int tn = 0, tb = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        tn += (int)ar.red[w * 8 + 6];
+        tb += (int)ar.red[w * 8 + 7];
+    }
+    __syncthreads();
+    return tb ? -1 : tn;
+}
+
+// the levels of the block cyclic reduction for bs <= 16 (blocks already built)
+template <int D, bool AUG>
+__device__ __forceinline__ int bcr_levels16(Arena<D, AUG>& ar, double scale) {
+    const int nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
+    const int wid = threadIdx.x >> 6;
+    const Tile t = tile_lane();
+    int neg = 0;
+    for (int st = 1; st < nb; st *= 2) {
+        int ne = 0;
+        while (st * (2 * ne + 1) < nb) ++ne;
+        const int r0 = block_invert16<D, AUG>(ar, st, 2 * st, ne, scale);
+        if (r0 < 0) return -1;
+        neg += r0;
+        // G_l = P_e J_{e,l} -> S1[i],  G_r = P_e J_{r,e}^T -> Rm[e]
+        #pragma unroll 1
+        for (int task = wid; task < 2 * ne; task += kWaves) {
+            const int i = task >> 1, e = st * (2 * i + 1), rr = e + st;
+            const double* P = ar.Dm + (size_t)e * B2;
+            d4_t c = {0.0, 0.0, 0.0, 0.0};
+            if ((task & 1) == 0) {
+                c = mm16(t, P, false, ar.Fm + (size_t)e * B2, false, bs, 1.0, c);
+                store16(t, ar.S1 + (size_t)i * B2, bs, c);
+            } else {
+                if (rr < nb) c = mm16(t, P, false, ar.Fm + (size_t)rr * B2, true, bs, 1.0, c);
+                store16(t, ar.Rm + (size_t)e * B2, bs, c);
+            }
+        }
+        __syncthreads();
+        // Schur updates of the blocks that stay, and the new couplings r <- l
+        const int na = (nb - 1) / (2 * st) + 1;
+        #pragma unroll 1
+        for (int task = wid; task < na + ne; task += kWaves) {
+            if (task < na) {
+                const int aa = 2 * st * task, e1 = aa + st, e0 = aa - st;
+                // D_a -= J_{e1,a}^T G_l(e1) + J_{a,e0} G_r(e0)  (missing neighbours: zero operands)
+                const Ops16 o1 = ops_mm(t, ar.Fm + (size_t)(e1 < nb ? e1 : aa) * B2, true,
+                                        ar.S1 + (size_t)(e1 < nb ? task : 0) * B2, false, bs, e1 < nb ? -1.0 : 0.0);
+                const Ops16 o0 = ops_mm(t, ar.Fm + (size_t)aa * B2, false, ar.Rm + (size_t)(e0 >= 0 ? e0 : aa) * B2,
+                                        false, bs, e0 >= 0 ? -1.0 : 0.0);
+                d4_t c = load16(t, ar.Dm + (size_t)aa * B2, bs);
+                c = mfma16(o1, c);
+                c = mfma16(o0, c);
+                store16(t, ar.Dm + (size_t)aa * B2, bs, c);
+            } else {
+                const int i = task - na, e = st * (2 * i + 1), rr = e + st;
+                if (rr < nb) {   // J_{r,l} = -J_{r,e} G_l(e)
+                    d4_t c = {0.0, 0.0, 0.0, 0.0};
+                    c = mm16(t, ar.Fm + (size_t)rr * B2, false, ar.S1 + (size_t)i * B2, false, bs, -1.0, c);
+                    store16(t, ar.S2 + (size_t)i * B2, bs, c);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) {
+            for (int i = 0; i < ne; ++i) {
+                const int e = st * (2 * i + 1), rr = e + st;
+                ar.Fm[(size_t)e * B2 + e2] = ar.S1[(size_t)i * B2 + e2];
+                if (rr < nb) ar.Fm[(size_t)rr * B2 + e2] = ar.S2[(size_t)i * B2 + e2];
+            }
+        }
+        __syncthreads();
+    }
+    const int r0 = block_invert16<D, AUG>(ar, 0, 1, 1, scale);
+    if (r0 < 0) return -1;
+    return neg + r0;
+}
+
+// block solve for bs <= 16: one wavefront per block, all R right-hand sides in one product
+template <int D, bool AUG, int R>
+__device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
+    const int N = ar.z.N, nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
+    const int wid = threadIdx.x >> 6;
+    const Tile t = tile_lane();
+    __syncthreads();
+    int top = 1;
+    while (2 * top < nb) top *= 2;
+    // down: b_a -= G_l(e1)^T b_e1 + G_r(e0)^T b_e0
+    for (int st = 1; st < nb; st *= 2) {
+        const int na = (nb - 1) / (2 * st) + 1;
+        #pragma unroll 1
+        for (int ka = wid; ka < na; ka += kWaves) {
+            const int aa = 2 * st * ka, e1 = aa + st, e0 = aa - st;
+            // (a missing neighbour contributes a zero operand set)
+            const Ops16 o1 = ops_mv(t, ar.Fm + (size_t)(e1 < nb ? e1 : aa) * B2, true, rhs + (e1 < nb ? e1 : aa) * bs,
+                                    N, R, bs, e1 < nb ? 1.0 : 0.0);
+            const Ops16 o0 = ops_mv(t, ar.Rm + (size_t)(e0 >= 0 ? e0 : aa) * B2, true, rhs + (e0 >= 0 ? e0 : aa) * bs,
+                                    N, R, bs, e0 >= 0 ? 1.0 : 0.0);
+            d4_t c = {0.0, 0.0, 0.0, 0.0};
+            c = mfma16(o1, c);
+            c = mfma16(o0, c);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = t.kq + 4 * r;
+                if (row < bs && t.i < R) rhs[(size_t)t.i * N + aa * bs + row] -= c[r];
+            }
+        }
+        __syncthreads();
+    }
+    // last block, then up: x_e = P_e b_e - G_l(e) x_l - G_r(e) x_r (in place: only this
+    // wavefront reads b_e, and it has read it before writing)
+    if (wid == 0) {
+        d4_t c = {0.0, 0.0, 0.0, 0.0};
+        c = mv16(t, ar.Dm, false, rhs, N, R, bs, 1.0, c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = t.kq + 4 * r;
+            if (row < bs && t.i < R) rhs[(size_t)t.i * N + row] = c[r];
+        }
+    }
+    __syncthreads();
+    if (nb > 1) {
+        for (int st = top; st >= 1; st /= 2) {
+            int ne = 0;
+            while (st * (2 * ne + 1) < nb) ++ne;
+            #pragma unroll 1
+            for (int i = wid; i < ne; i += kWaves) {
+                const int e = st * (2 * i + 1), l = e - st, rr = e + st;
+                const Ops16 op = ops_mv(t, ar.Dm + (size_t)e * B2, false, rhs + e * bs, N, R, bs, 1.0);
+                const Ops16 ol = ops_mv(t, ar.Fm + (size_t)e * B2, false, rhs + l * bs, N, R, bs, -1.0);
+                const Ops16 orr = ops_mv(t, ar.Rm + (size_t)e * B2, false, rhs + (rr < nb ? rr : l) * bs, N, R, bs,
+                                         rr < nb ? -1.0 : 0.0);
+                d4_t c = {0.0, 0.0, 0.0, 0.0};
+                c = mfma16(op, c);
+                c = mfma16(ol, c);
+                c = mfma16(orr, c);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = t.kq + 4 * r;
+                    if (row < bs && t.i < R) rhs[(size_t)t.i * N + e * bs + row] = c[r];
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // Batched Gauss-Jordan inversion of the pivot blocks Dm[first + step*i], i < cnt, in place.
@@ -691,7 +987,7 @@ __device__ __forceinline__ int block_invert(Arena<D, AUG>& ar, int first, int st
     return neg;
 }
 
-template <int D, bool AUG>
+template <int D, bool AUG, bool MF>
 __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, double alpha, double sigma) {
     constexpr int NS = Geo<D>::NS;
     const int N = ar.z.N, m = ar.z.m, nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
@@ -708,7 +1004,7 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
         node_pos<D>(i, m, P);
         const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
         const int blk = i / bs, r = i - blk * bs;
-        static_for<NS>([&](auto sc_) {
+        for_slots<D>([&](auto sc_) {
             constexpr int s = decltype(sc_)::value;
             const int j = nbr<D, s>(P, m);
             if (j >= 0) {
@@ -724,6 +1020,7 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
         });
     }
     const double scale = bmax1(ar.red, dmax);   // (its barriers also publish the blocks)
+    if constexpr (MF) return bcr_levels16<D, AUG>(ar, scale);
     int neg = 0;
     for (int st = 1; st < nb; st *= 2) {
         int ne = 0;
@@ -783,8 +1080,12 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
 }
 
 // Solve J X = R for R right-hand sides stored as rhs[q*N + i] with the factor of bcr_factor.
-template <int D, bool AUG, int R>
+template <int D, bool AUG, int R, bool MF>
 __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
+    if constexpr (MF) {
+        bcr_solve16<D, AUG, R>(ar, rhs);
+        return;
+    }
     const int N = ar.z.N, nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
     double* tmp = ar.S1;
     const VecMap vm = vec_map(bs);
@@ -878,14 +1179,13 @@ __device__ __forceinline__ void bcr_solve(Arena<D, AUG>& ar, double* rhs) {
 // and because J is symmetric C^T y0 = -V^T F_H, so one right-hand side per step suffices.
 // A refresh (new factor, or first step of a call with a stored factor) freezes the
 // current border columns again.
-template <int D, bool AUG>
-__device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, bool& have) {
+template <int D, bool AUG, bool MF>
+__device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double zs, double tol, bool& have) {
     const int N = ar.z.N, N1 = ar.z.N1, m = ar.z.m;
     const int tid = threadIdx.x;
     FMG_TCNT(9);
     {
         // x <- x / ||x||_B  (B needs no assembly)
-        constexpr int NS = Geo<D>::NS;
         const double H = 1.0 / a.nc;
         const double Hd = (D == 2) ? H * H : H * H * H;
         double v[2] = {0.0, 0.0};
@@ -895,7 +1195,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             node_pos<D>(i, m, P);
             const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
             double zi = 0.0;
-            static_for<NS>([&](auto sc_) {
+            for_slots<D>([&](auto sc_) {
                 constexpr int s = decltype(sc_)::value;
                 const int j = nbr<D, s>(P, m);
                 if (j >= 0) {
@@ -937,7 +1237,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         if (tid == 0) ar.sc[7] = res;
         if (!(res == res) || !(mu == mu)) return -3;
         // x^T B x = 1 up to the rounding of an N-term dot product
-        if (res <= a.tol && fabs(F2) <= 4.0 * N1 * 1.1e-16) {
+        if (res <= tol && fabs(F2) <= 4.0 * N1 * 1.1e-16) {
             const double sN = 1.0 / sqrt(ar.sc[5]);
             for (int i = tid; i < N1; i += kThreads) ar.x[i] *= sN;
             if (tid == 0) ar.sc[6] = mu;
@@ -957,7 +1257,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         }
         if (need_fresh) {
             FMG_T0(t_f);
-            if (bcr_factor<D, AUG>(ar, a, 3.0 * zs, mu) < 0) return -1;
+            if (bcr_factor<D, AUG, MF>(ar, a, 3.0 * zs, mu) < 0) return -1;
             FMG_TACC(3, t_f);
             need_fresh = false;
             last_fresh = true;
@@ -982,7 +1282,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
                     ar.rhs[N + i] = -ar.z2[i];
                 }
             }
-            bcr_solve<D, AUG, AUG ? 3 : 2>(ar, ar.rhs);
+            bcr_solve<D, AUG, AUG ? 3 : 2, MF>(ar, ar.rhs);
             if (AUG) {
                 double s[4] = {0.0, 0.0, 0.0, 0.0};
                 for (int i = tid; i < N; i += kThreads) {
@@ -1008,7 +1308,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             frozen = true;
         } else {
             for (int i = tid; i < N; i += kThreads) ar.rhs[i] = -ar.F[i];
-            bcr_solve<D, AUG, 1>(ar, ar.rhs);
+            bcr_solve<D, AUG, 1, MF>(ar, ar.rhs);
         }
         FMG_TACC(4, t_s);
         FMG_T0(t_u);
@@ -1046,14 +1346,14 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
 }
 
 // inertia check: number of eigenvalues of (A + zs S(x), B) below sigma (0: ground state)
-template <int D, bool AUG>
+template <int D, bool AUG, bool MF>
 __device__ __forceinline__ int count_below(Arena<D, AUG>& ar, const Args& a, double zs, double sigma) {
     const int N = ar.z.N;
-    int neg = bcr_factor<D, AUG>(ar, a, zs, sigma);
+    int neg = bcr_factor<D, AUG, MF>(ar, a, zs, sigma);
     if (neg < 0) return 1;
     if (AUG) {
         for (int i = threadIdx.x; i < N; i += kThreads) ar.rhs[i] = ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i];
-        bcr_solve<D, AUG, 1>(ar, ar.rhs);
+        bcr_solve<D, AUG, 1, MF>(ar, ar.rhs);
         double s = 0.0;
         for (int i = threadIdx.x; i < N; i += kThreads)
             s += (ar.aH[i] + zs * ar.sH[i] - sigma * ar.bH[i]) * ar.rhs[i];
@@ -1072,7 +1372,7 @@ __device__ __forceinline__ void store_factor(Arena<D, AUG>& ar, const Args& a) {
     if (threadIdx.x == 0) a.st->fac_valid = 1;
 }
 
-template <int D, bool AUG>
+template <int D, bool AUG, bool MF>
 __device__ __forceinline__ void finish(Arena<D, AUG>& ar, const Args& a, int iters, bool ok, int reason) {
     const int N = ar.z.N, m = ar.z.m;
     const double H = 1.0 / a.nc;
@@ -1086,7 +1386,7 @@ __device__ __forceinline__ void finish(Arena<D, AUG>& ar, const Args& a, int ite
         const bool cert = a.certify == 1 || (a.certify == 2 && meets);
         int below = 0;
         FMG_T0(t_cb);
-        if (cert) below = count_below<D, AUG>(ar, a, a.ph.zeta, mu - 1e-9 * fabs(mu));
+        if (cert) below = count_below<D, AUG, MF>(ar, a, a.ph.zeta, mu - 1e-9 * fabs(mu));
         FMG_TACC(7, t_cb);
         // sign: int u_h > 0
         double v = 0.0;
@@ -1141,7 +1441,7 @@ __device__ __forceinline__ void finish(Arena<D, AUG>& ar, const Args& a, int ite
     }
 }
 
-template <int D, bool AUG, bool LDS>
+template <int D, bool AUG, bool LDS, bool MF>
 __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     extern __shared__ double lds[];
     Arena<D, AUG> ar;
@@ -1171,7 +1471,7 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         for (int i = tid; i < N; i += kThreads) ar.x[i] = 0.0;
         if (tid == 0) ar.x[N] = 1.0;
         __syncthreads();
-        int r = newton<D, AUG>(ar, a, a.ph.zeta, have);
+        int r = newton<D, AUG, MF>(ar, a, a.ph.zeta, a.tol, have);
         ok = r >= 0;
         iters = ok ? r : 0;
         reason = ok ? 0 : -r;
@@ -1200,7 +1500,10 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
             const double z = last ? zeta : exp(lnext);
             for (int i = tid; i < N; i += kThreads) ar.xk[i] = ar.x[i];   // committed iterate
             __syncthreads();
-            const int rr = newton<D, AUG>(ar, a, z, have);
+            // a new coupling changes the 3 zeta S term of the Jacobian by up to a factor 8:
+            // factor afresh; intermediate stages only seed the next one (looser residual)
+            have = false;
+            const int rr = newton<D, AUG, MF>(ar, a, z, last ? a.tol : fmax(a.tol, kStageTol), have);
             if (rr < 0) {
                 for (int i = tid; i < N; i += kThreads) ar.x[i] = ar.xk[i];
                 have = false;
@@ -1225,10 +1528,45 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         }
     }
     __syncthreads();
+#ifdef FMG_SMALL_MICRO
+    // measurement build only: repeat phases on the converged state (results are discarded)
+    if (AUG && ok) {
+        unsigned long long tt[8];
+        const int reps = 50;
+        __syncthreads();
+        tt[0] = wall_clock64();
+        for (int r = 0; r < reps; ++r) assemble_S<D, AUG>(ar, a, ar.x);
+        __syncthreads();
+        tt[1] = wall_clock64();
+        for (int r = 0; r < reps; ++r) apply<D, AUG>(ar, a, a.ph.zeta, ar.x, ar.y, ar.z2);
+        __syncthreads();
+        tt[2] = wall_clock64();
+        for (int r = 0; r < reps; ++r) bcr_solve<D, AUG, 1, MF>(ar, ar.rhs);
+        __syncthreads();
+        tt[3] = wall_clock64();
+        for (int r = 0; r < reps; ++r) bcr_solve<D, AUG, 3, MF>(ar, ar.rhs);
+        __syncthreads();
+        tt[4] = wall_clock64();
+        for (int r = 0; r < 10; ++r) bcr_factor<D, AUG, MF>(ar, a, 3.0 * a.ph.zeta, ar.sc[6]);
+        __syncthreads();
+        tt[5] = wall_clock64();
+        double acc = 0.0;
+        for (int r = 0; r < reps; ++r) acc += bsum1(ar.red, (double)r);
+        __syncthreads();
+        tt[6] = wall_clock64();
+        for (int r = 0; r < reps; ++r) __syncthreads();
+        tt[7] = wall_clock64();
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 7; ++k) atomicAdd(&g_small_t[k], tt[k + 1] - tt[k]);
+            atomicAdd(&g_small_t[7], 1ull);
+            atomicAdd(&g_small_t[8], acc < 0.0 ? 1ull : 0ull);
+        }
+    }
+#endif
     FMG_T0(t_fin);
     if (ok && ar.sc[8] > 0.0) store_factor<D, AUG>(ar, a);
     __syncthreads();
-    finish<D, AUG>(ar, a, iters, ok, reason);
+    finish<D, AUG, MF>(ar, a, iters, ok, reason);
     FMG_TACC(6, t_fin);
     FMG_TACC(10, t_all);
     FMG_TCNT(11);
@@ -1259,7 +1597,7 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
         int P[3];
         node_pos<D>(i, m, P);
         const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
-        static_for<NS>([&](auto sc_) {
+        for_slots<D>([&](auto sc_) {
             constexpr int s = decltype(sc_)::value;
             const int j = nbr<D, s>(P, m);
             if (j >= 0) {
@@ -1281,8 +1619,19 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     }
 }
 
-// the whole arena in LDS when it fits (gfx950: 160 KiB per workgroup)
-constexpr size_t kLdsLimit = 156 * 1024;
+// the whole arena in LDS when it fits (gfx950: 160 KiB per workgroup); a build may lower the
+// limit (FMG_SMALL_LDS_LIMIT) to exercise the global-memory arena on small problems
+#ifndef FMG_SMALL_LDS_LIMIT
+#define FMG_SMALL_LDS_LIMIT (156 * 1024)
+#endif
+constexpr size_t kLdsLimit = FMG_SMALL_LDS_LIMIT;
+
+// blocks of the coarse Jacobian: grid rows (2D) or planes (3D); up to 16 x 16, with the arena
+// in LDS, they go to the matrix cores (the global-arena build of that path would spill)
+inline bool small_blocks(int dim, int nc, size_t bytes) {
+    const int m = nc - 1;
+    return (dim == 2 ? m : m * m) <= 16 && bytes <= kLdsLimit;
+}
 
 template <typename K>
 int launch_small(K kern_lds, K kern_glb, size_t bytes, Args& a, hipStream_t s) {
@@ -1300,7 +1649,7 @@ int launch_small(K kern_lds, K kern_glb, size_t bytes, Args& a, hipStream_t s) {
 
 }  // namespace
 
-#ifdef FMG_SMALL_TIMING
+#if defined(FMG_SMALL_TIMING) || defined(FMG_SMALL_MICRO)
 extern "C" int fmg_debug_small_timers(double* out, int reset) {
     unsigned long long h[32];
     if (hipMemcpyFromSymbol(h, HIP_SYMBOL(g_small_t), sizeof(h)) != hipSuccess) return -5;
@@ -1330,8 +1679,14 @@ int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double t
     a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.tol = tol; a.mom = nullptr; a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = 0; a.certify = 1;
     a.fac = fac; a.reuse = 0;
-    return dim == 2 ? launch_small(k_newton<2, false, true>, k_newton<2, false, false>, arena_bytes_t<2, false>(nc), a, s)
-                    : launch_small(k_newton<3, false, true>, k_newton<3, false, false>, arena_bytes_t<3, false>(nc), a, s);
+    if (dim == 2) {
+        const size_t b = arena_bytes_t<2, false>(nc);
+        return small_blocks(2, nc, b) ? launch_small(k_newton<2, false, true, true>, k_newton<2, false, true, true>, b, a, s)
+                                      : launch_small(k_newton<2, false, true, false>, k_newton<2, false, false, false>, b, a, s);
+    }
+    const size_t b = arena_bytes_t<3, false>(nc);
+    return small_blocks(3, nc, b) ? launch_small(k_newton<3, false, true, true>, k_newton<3, false, true, true>, b, a, s)
+                                  : launch_small(k_newton<3, false, true, false>, k_newton<3, false, false, false>, b, a, s);
 }
 
 int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments, double* arena,
@@ -1341,8 +1696,14 @@ int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol,
     a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.tol = tol; a.mom = moments; a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = final_level;
     a.certify = certify; a.fac = fac; a.reuse = reuse;
-    return dim == 2 ? launch_small(k_newton<2, true, true>, k_newton<2, true, false>, arena_bytes_t<2, true>(nc), a, s)
-                    : launch_small(k_newton<3, true, true>, k_newton<3, true, false>, arena_bytes_t<3, true>(nc), a, s);
+    if (dim == 2) {
+        const size_t b = arena_bytes_t<2, true>(nc);
+        return small_blocks(2, nc, b) ? launch_small(k_newton<2, true, true, true>, k_newton<2, true, true, true>, b, a, s)
+                                      : launch_small(k_newton<2, true, true, false>, k_newton<2, true, false, false>, b, a, s);
+    }
+    const size_t b = arena_bytes_t<3, true>(nc);
+    return small_blocks(3, nc, b) ? launch_small(k_newton<3, true, true, true>, k_newton<3, true, true, true>, b, a, s)
+                                  : launch_small(k_newton<3, true, true, false>, k_newton<3, true, false, false>, b, a, s);
 }
 
 int launch_aug_dump(int dim, int nc, const Phys& ph, const double* moments, const double* x, double* arena, double* A,
