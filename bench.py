@@ -55,7 +55,7 @@ def time_solves(prob, opts, steps, warmup):
     return res, u, total, lat
 
 
-VPOST_KERNEL = "k_vpost2d<double, 5>"
+VPOST_KERNEL = "k_vpost2d<double, 5, 64, 32>"
 PMC_FILE = os.path.join(ROOT, "profiles", "k_vpost2d_f64_pmc.md")
 VPOST_SRC = os.path.join(ROOT, "paper_1502_04657_amd", "csrc", "vcycle2d.hip")
 
@@ -79,9 +79,11 @@ def _pmc_traffic():
 
 def vpost_roofline(prob, steps):
     """Roofline of the fused FP64 post-smoothing level pass (prolongation-add + 5 red-black
-    half sweeps), the largest HBM-bound kernel of the solve: HIP events recorded by the
-    library on the launch stream around every launch of that kernel during `steps` solves
-    of the benchmark workload; algorithmic bytes per launch = 8 (3 N_l + N_{l-1})."""
+    half sweeps; 64 x 32-tile build) on the finest level n = 2048, the largest HBM-bound
+    kernel of the solve: start/stop HIP events stamped by each launch's own dispatch on its
+    stream (hipExtLaunchKernel) for every finest-level launch during `steps` solves of the
+    benchmark workload; algorithmic bytes per launch = 8 (3 N_l + N_{l-1}), N_l = 2047^2
+    fine and N_{l-1} = 1023^2 coarse interior nodes."""
     import ctypes as C
     import torch
     from paper_1502_04657_amd import Solver, _ffi, lib
@@ -90,7 +92,7 @@ def vpost_roofline(prob, steps):
     s.solve(u)
     torch.cuda.synchronize()
     L = lib()
-    if L.fmg_profile_begin(_ffi.FMG_PROF_VPOST2D_F64, 64 * (steps + 1)) != 0:
+    if L.fmg_profile_begin(_ffi.FMG_PROF_VPOST2D_F64, 16 * (steps + 1)) != 0:
         raise RuntimeError(L.fmg_last_error().decode())
     for _ in range(steps):
         s.solve(u)

@@ -106,11 +106,13 @@ const char* fmg_version(void);
 int fmg_set_fused_vcycle(int32_t enable);
 
 /* ---- measurement hooks ------------------------------------------------------------------ */
-/* Per-launch timing of one kernel inside later solves: HIP events are recorded on the
- * launch stream around each launch (up to max_launches), with the algorithmic bytes of
- * each launch.  FMG_PROF_VPOST2D_F64 is the fused 2D FP64 post-smoothing level pass
+/* Per-launch timing of one kernel inside later solves: a pair of HIP events is stamped by
+ * each launch's own dispatch on its stream (hipExtLaunchKernel start/stop events, so the
+ * interval is the kernel's execution without launch gaps; up to max_launches), with the
+ * algorithmic bytes of each launch.  FMG_PROF_VPOST2D_F64 is the fused 2D FP64 post-smoothing level pass
  * (prolongation-add plus the post half-sweeps; bytes = 8 * (3 N_l + N_{l-1}), reading x,
- * f and the coarse correction and writing x).  Not thread-safe; one profile at a time.
+ * f and the coarse correction and writing x) on the finest level of each solve, when that
+ * level has more than 256 cells per side (the 64 x 32-tile build of the kernel).  Not thread-safe; one profile at a time.
  * fmg_profile_end synchronises on the last recorded event and fills *out.                */
 enum { FMG_PROF_VPOST2D_F64 = 1 };
 typedef struct {

@@ -141,11 +141,11 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
         T* y = at<T>(ws, lo.tv[l]);
         launch_vpre2d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
         vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
-        const bool rec = g_prof.kernel == FMG_PROF_VPOST2D_F64 && sizeof(T) == 8 && g_prof.used < g_prof.cap;
-        if (rec) hipEventRecord(g_prof.ev[2 * g_prof.used], s);
-        launch_vpost2d<T>(g, lo.g[l - 1], y, x, f, xc, nu_post, s);
+        const bool rec = g_prof.kernel == FMG_PROF_VPOST2D_F64 && sizeof(T) == 8 && l == lo.L - 1 &&
+                         vpass2d_wide_tiles(g) && g_prof.used < g_prof.cap;
+        launch_vpost2d<T>(g, lo.g[l - 1], y, x, f, xc, nu_post, s, rec ? g_prof.ev[2 * g_prof.used] : nullptr,
+                          rec ? g_prof.ev[2 * g_prof.used + 1] : nullptr);
         if (rec) {
-            hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s);
             // read x, f and the coarse correction, write x (interior values)
             const double nf = std::pow((double)(g.n - 1), 2), ncs = std::pow((double)(lo.g[l - 1].n - 1), 2);
             g_prof.bytes += (3.0 * nf + ncs) * sizeof(double);

@@ -40,10 +40,15 @@ void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partia
 // zero_x: treat the incoming x as zero (coarse-level corrections) without reading it.
 // pre reads x and writes the smoothed values to y; post reads y and writes x (out of place:
 // the passes read halos across tiles).  Boundary rings of x and y must be zero.
+// ev0/ev1 (optional): events stamped by the dispatch itself at the start and end of the
+// post kernel (per-launch timing without the launch gaps of stream-recorded events).
 template <typename T> bool launch_vpre2d(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc,
                                          int nu, int zero_x, hipStream_t s);
+// levels above 256 cells per side use 64 x 32 tiles, smaller ones 16 x 16
+bool vpass2d_wide_tiles(const Grid& g);
 template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc,
-                                          int nu, hipStream_t s);
+                                          int nu, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                          hipEvent_t ev1 = nullptr);
 
 // ---- moments.hip ------------------------------------------------------------------------
 int moments_per_element(int dim);            // doubles per coarse element in the output
