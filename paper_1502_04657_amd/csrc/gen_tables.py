@@ -12,7 +12,10 @@ for every neighbour offset o.  On a mesh of spacing h, with the node at X, a qua
 potential W = sum_k w_k x_k^2 + c gives the exact potential-mass row
     int W phi_i phi_j = h^d [ sum_k w_k (X_k^2 m0 + 2 X_k h m1[k] + h^2 m2[k]) + c m0 ],
 and m0 h^d is the consistent mass stencil.  It also emits the exact degree-4 quadrature
-rules (rational points and weights) used for the fine-grid moment integrals.
+rules used for the fine-grid moment integrals: on triangles two symmetric orbits
+(a, a, 1-2a), (b, b, 1-2b) of 3 points each, whose parameters and weights are the root of the
+four moment equations of the symmetric polynomials up to degree 4 (solved to 40 digits
+and checked on every monomial); on tetrahedra orbits with rational points.
 """
 from __future__ import annotations
 
@@ -81,12 +84,42 @@ def stencil(dim):
     return offs, acc
 
 
+def exact_simplex(f, lam, dim):
+    """int over the unit simplex of the polynomial f(lambda) / volume (monomial identity)."""
+    poly = sp.Poly(sp.expand(f), *lam)
+    tot = 0
+    for mon, cf in poly.terms():
+        num = sp.factorial(dim)
+        for a in mon:
+            num *= sp.factorial(a)
+        tot += cf * num / sp.factorial(sum(mon) + dim)
+    return tot
+
+
 def rule_2d():
-    l0, l1 = sp.symbols("l0 l1")
-    h = sp.Rational(1, 2); q = sp.Rational(1, 4); th = sp.Rational(1, 3)
-    pts = ([(1, 0, 0), (0, 1, 0), (0, 0, 1)], [(h, h, 0), (h, 0, h), (0, h, h)], [(th, th, th)],
-           [(h, q, q), (q, h, q), (q, q, h)])
-    return pts
+    """6-point degree-4 rule on triangles: two orbits (t, t, 1-2t) with weights w (per
+    point, relative to the area).  The four unknowns solve the moment equations of
+    1, e2, e3, e2^2 (e_k: elementary symmetric polynomials of the barycentrics)."""
+    lam = sp.symbols("l0:3")
+    a, b, wa, wb = sp.symbols("a b wa wb")
+    el = lambda k: sum(sp.Mul(*c) for c in itertools.combinations(lam, k))
+    orbit = lambda t: [(t, t, 1 - 2 * t), (t, 1 - 2 * t, t), (1 - 2 * t, t, t)]
+    eqs = []
+    for f in (sp.Integer(1), el(2), el(3), el(2) ** 2):
+        s = sum(wa * f.subs(dict(zip(lam, p))) for p in orbit(a)) + \
+            sum(wb * f.subs(dict(zip(lam, p))) for p in orbit(b))
+        eqs.append(sp.expand(s - exact_simplex(f, lam, 2)))
+    ra, rb, rwa, rwb = sp.nsolve(eqs, [a, b, wa, wb], [0.4, 0.1, 1 / 6, 1 / 6], prec=40)
+    assert 0 < rb < ra < 0.5 and rwa > 0 and rwb > 0
+    pts = orbit(ra) + orbit(rb)
+    wts = [rwa] * 3 + [rwb] * 3
+    for mon in itertools.product(range(5), repeat=3):
+        if sum(mon) > 4:
+            continue
+        f = sp.Mul(*[lam[i] ** mon[i] for i in range(3)])
+        q = sum(w * f.subs(dict(zip(lam, p))) for w, p in zip(wts, pts))
+        assert abs(q - exact_simplex(f, lam, 2)) < sp.Float(1e-30)
+    return pts, wts
 
 
 def solve_rule(dim, orbits):
@@ -99,15 +132,7 @@ def solve_rule(dim, orbits):
     w = sp.symbols(f"w0:{len(orbits)}")
 
     def exact(f):
-        # int over the unit simplex of f(lambda) / volume, via the monomial identity
-        poly = sp.Poly(sp.expand(f), *lam)
-        tot = 0
-        for mon, cf in poly.terms():
-            num = sp.factorial(dim)
-            for a in mon:
-                num *= sp.factorial(a)
-            tot += cf * num / sp.factorial(sum(mon) + dim)
-        return tot
+        return exact_simplex(f, lam, dim)
     eqs = []
     for f in conds:
         s = 0
@@ -167,7 +192,8 @@ def fmt(v):
 
 
 def main():
-    out = ["// Generated by gen_tables.py -- exact rational values printed to 17 significant digits.",
+    out = ["// Generated by gen_tables.py -- exact values (the triangle rule: 40-digit roots) printed",
+           "// to 17 significant digits.",
            "#pragma once", ""]
     for dim in (2, 3):
         offs, acc = stencil(dim)
@@ -207,12 +233,7 @@ def main():
                    ", ".join("{" + ", ".join("{" + ", ".join(str(c) for c in v) + "}" for v in e) + "}" for e in st) + "};")
         out.append("")
     # quadrature rules
-    orb2 = rule_2d()
-    w2 = solve_rule(2, orb2)
-    pts, wts = [], []
-    for wi, orb in zip(w2, orb2):
-        for p in orb:
-            pts.append(p); wts.append(wi)
+    pts, wts = rule_2d()
     out.append(f"// exact degree-4 rule on triangles: barycentric points, weights / area (sum 1)")
     out.append(f"constexpr int kQuad2D = {len(pts)};")
     out.append("static constexpr double kQuadPt2D[%d][3] = {%s};" % (
@@ -235,7 +256,6 @@ def main():
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     print("wrote", path)
-    print("2D weights", w2, "3D weights", w3)
 
 
 if __name__ == "__main__":

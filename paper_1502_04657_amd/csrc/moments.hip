@@ -10,9 +10,13 @@
 //
 // Pass 1 (k_moments_raw): block (coarse cell, chunk, coarse simplex type) integrates
 // u~^a X^b over the fine simplices of that coarse simplex with an exact degree-4 rule
-// (tables.h) and writes one partial sum per block.  Pass 2 (k_moments_final): one thread
+// (tables.h) and writes one partial sum per block.  In 2D a block walks only the fine
+// cells of its coarse triangle (a triangular index set, folded into full rows); in 3D it
+// walks the fine cells of the coarse cell and skips those of other coarse tetrahedra.  Pass 2 (k_moments_final): one thread
 // per coarse simplex adds the partials in chunk order and converts the X-monomial moments
 // to the barycentric form.  Both passes are deterministic.
+#include <utility>
+
 #include "kernels.h"
 #include "layout.h"
 
@@ -28,10 +32,13 @@ static int64_t ipow(int64_t b, int e) {
     return r;
 }
 
+// cells_per: fine cells one block list covers.  2D: the fine cells (a0, a1) of one coarse
+// triangle, a0 >= a1 or a0 <= a1 (diagonal cells included, s (s + 1) / 2 of them), as s / 2
+// rows of s + 1 cells (s = n / nc is even on every level that has moments).
 static void chunk_shape(int dim, int nc, int n, int64_t& ncell, int64_t& cells_per, int64_t& nchunk) {
     const int s = n / nc;
     ncell = ipow(nc, dim);
-    cells_per = ipow(s, dim);
+    cells_per = dim == 2 ? (int64_t)(s / 2) * (s + 1) : ipow(s, dim);
     nchunk = (cells_per + kChunkCells - 1) / kChunkCells;
 }
 
@@ -85,11 +92,27 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
     for (int q = 0; q < R::SIZE; ++q) acc[q] = 0.0;
 
     for (int64_t idx = start + threadIdx.x; idx < end; idx += blockDim.x) {
-        int a[3] = {(int)(idx % s), (int)((idx / s) % s), D == 3 ? (int)(idx / ((int64_t)s * s)) : 0};
-        // quick reject: fine cells whose simplices all map to other coarse types
+        int a[3];
         if (D == 2) {
-            if (a[0] != a[1] && ((a[0] > a[1]) ? 0 : 1) != type) continue;
+            // row pair (r, s-1-r) of the triangular set: s - r cells of row r, then r + 1 of
+            // row s-1-r; (lo, hi) = (row, column) with hi >= lo
+            const int t = (int)idx, r = t / (s + 1), x = t - r * (s + 1);
+            int lo, hi;
+            if (x < s - r) {
+                lo = r;
+                hi = r + x;
+            } else {
+                lo = s - 1 - r;
+                hi = lo + (x - (s - r));
+            }
+            a[0] = type == 0 ? hi : lo;
+            a[1] = type == 0 ? lo : hi;
+            a[2] = 0;
         } else {
+            a[0] = (int)(idx % s);
+            a[1] = (int)((idx / s) % s);
+            a[2] = (int)(idx / ((int64_t)s * s));
+            // quick reject: fine cells whose simplices all map to other coarse types
             if (a[0] != a[1] && a[1] != a[2] && a[0] != a[2] && coarse_type<D>(a, 0) != type) continue;
         }
         const int i = C[0] * s + a[0], j = C[1] * s + a[1], k = D == 3 ? C[2] * s + a[2] : 0;
@@ -183,110 +206,133 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
     }
 }
 
-// polynomial helpers over the monomial lists of layout.h (degree <= 3)
-template <int D>
-__device__ inline int mon_index(const int* e) {
-    constexpr int NM = (D == 2) ? 10 : 20;
-    for (int q = 0; q < NM; ++q) {
-        bool ok = true;
-        for (int d = 0; d < D; ++d) ok = ok && ((D == 2 ? kMon2[q][d] : kMon3[q][d]) == e[d]);
-        if (ok) return q;
-    }
-    return -1;
+// ---- pass 2 ------------------------------------------------------------------------------
+// Polynomials of the coarse-local coordinates are coefficient arrays over the graded
+// monomial lists of layout.h (degree <= 3).  All loops below have compile-time bounds and
+// indices, so the products are straight-line register code.
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
 template <int D>
-__device__ inline void poly_mul(const double* A, const double* B, double* out) {
-    constexpr int NM = (D == 2) ? 10 : 20;
-    for (int q = 0; q < NM; ++q) out[q] = 0.0;
-    for (int p = 0; p < NM; ++p) {
-        if (A[p] == 0.0) continue;
-        for (int q = 0; q < NM; ++q) {
-            if (B[q] == 0.0) continue;
-            int e[3], deg = 0;
-            for (int d = 0; d < D; ++d) {
-                e[d] = (D == 2 ? kMon2[p][d] + kMon2[q][d] : kMon3[p][d] + kMon3[q][d]);
-                deg += e[d];
-            }
-            if (deg > 3) continue;  // never reached for the products used here
-            out[mon_index<D>(e)] += A[p] * B[q];
+struct Mono {
+    static constexpr int NM = (D == 2) ? 10 : 20;        // degree <= 3
+    static constexpr int N2 = (D == 2) ? 6 : 10;         // degree <= 2
+    static constexpr int exp(int q, int k) { return D == 2 ? kMon2[q][k] : kMon3[q][k]; }
+    // index of monomial q times x_d, -1 above degree 3
+    static constexpr int times_x(int q, int d) {
+        for (int r = 0; r < NM; ++r) {
+            bool ok = true;
+            for (int k = 0; k < D; ++k) ok = ok && exp(r, k) == exp(q, k) + (k == d ? 1 : 0);
+            if (ok) return r;
         }
+        return -1;
     }
+    static constexpr int square(int d) { return times_x(times_x(0, d), d); }   // x_d^2
+};
+
+// out = A * (l[0] + sum_d l[1+d] x_d) for A of degree <= 2 (its first N2 coefficients)
+template <int D>
+__device__ __forceinline__ void mul_affine(const double* A, const double* l, double* out) {
+    using M = Mono<D>;
+    static_for<M::NM>([&](auto q) { out[q] = 0.0; });
+    static_for<M::N2>([&](auto q_) {
+        constexpr int q = decltype(q_)::value;
+        out[q] += A[q] * l[0];
+        static_for<D>([&](auto d_) {
+            constexpr int d = decltype(d_)::value;
+            constexpr int j = M::times_x(q, d);
+            if constexpr (j >= 0) out[j] += A[q] * l[1 + d];
+        });
+    });
 }
 
 template <int D>
-__global__ void k_moments_final(const double* __restrict__ partial, int nc, int64_t nchunk, Phys ph,
+__global__ __launch_bounds__(64) void k_moments_final(const double* __restrict__ partial, int nc, int64_t nchunk, Phys ph,
                                 double* __restrict__ out) {
     using R = RawLayout<D>;
     using L = MomLayout<D>;
+    using M = Mono<D>;
     constexpr int V = D + 1;
-    constexpr int NM = (D == 2) ? 10 : 20;
+    constexpr int NM = M::NM;
     const int64_t ncell = (D == 2) ? (int64_t)nc * nc : (int64_t)nc * nc * nc;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncell * L::NE) return;
     const int64_t cell = e / L::NE;
     const int type = (int)(e % L::NE);
     double raw[R::SIZE];
-    for (int q = 0; q < R::SIZE; ++q) raw[q] = 0.0;
-    for (int64_t c = 0; c < nchunk; ++c)
-        for (int q = 0; q < R::SIZE; ++q) raw[q] += partial[(((int64_t)type * ncell + cell) * nchunk + c) * R::SIZE + q];
-
-    // barycentric coordinates as polynomials of the coarse-local coordinates
-    double lam[V][NM];
-    for (int p = 0; p < V; ++p) {
-        for (int q = 0; q < NM; ++q) lam[p][q] = 0.0;
-        lam[p][0] = (D == 2) ? kCellElemBary2D[type][p][0] : kCellElemBary3D[type][p][0];
-        for (int d = 0; d < D; ++d) lam[p][1 + d] = (D == 2) ? kCellElemBary2D[type][p][1 + d] : kCellElemBary3D[type][p][1 + d];
+    static_for<R::SIZE>([&](auto q) { raw[q] = 0.0; });
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const double* pp = partial + (((int64_t)type * ncell + cell) * nchunk + c) * R::SIZE;
+        static_for<R::SIZE>([&](auto q) { raw[q] += pp[q]; });
     }
+
+    // barycentric coordinates of the coarse simplex as affine functions of X
+    double lam[V][4], lamp[V][NM];
+    static_for<V>([&](auto p) {
+        static_for<D + 1>([&](auto k) {
+            lam[p][k] = (D == 2) ? kCellElemBary2D[type][p][k] : kCellElemBary3D[type][p][k];
+        });
+        static_for<NM>([&](auto q) { lamp[p][q] = 0.0; });
+        static_for<D + 1>([&](auto k) { lamp[p][k] = lam[p][k]; });   // 1, x_0, .. are monomials 0..D
+    });
     // W in coarse-local coordinates: x_k = (C_k + X_k) H
     const double H = 1.0 / nc;
-    int C[3] = {(int)(cell % nc), (int)((cell / nc) % nc), D == 3 ? (int)(cell / ((int64_t)nc * nc)) : 0};
+    const int C[3] = {(int)(cell % nc), (int)((cell / nc) % nc), D == 3 ? (int)(cell / ((int64_t)nc * nc)) : 0};
     double Wp[NM];
-    for (int q = 0; q < NM; ++q) Wp[q] = 0.0;
+    static_for<NM>([&](auto q) { Wp[q] = 0.0; });
     Wp[0] = ph.wc;
-    for (int d = 0; d < D; ++d) {
+    static_for<D>([&](auto d_) {
+        constexpr int d = decltype(d_)::value;
         const double wk = ph.w[d] * H * H;
         Wp[0] += wk * C[d] * C[d];
         Wp[1 + d] += 2.0 * wk * C[d];
-        int ee[3] = {0, 0, 0};
-        ee[d] = 2;
-        Wp[mon_index<D>(ee)] += wk;
-    }
+        Wp[M::square(d)] += wk;
+    });
     double* o = out + e * L::SIZE;
     double t1[NM], t2[NM];
-    for (int p = 0; p < V; ++p)
-        for (int q = p; q < V; ++q) {
-            poly_mul<D>(lam[p], lam[q], t1);
+    static_for<V>([&](auto p_) {
+        constexpr int p = decltype(p_)::value;
+        static_for<V - p>([&](auto qq) {
+            constexpr int q = p + decltype(qq)::value;
+            mul_affine<D>(lamp[p], lam[q], t1);
             double s2 = 0.0;
-            for (int m = 0; m < R::M2; ++m) s2 += t1[m] * raw[R::P2 + m];
+            static_for<R::M2>([&](auto m) { s2 += t1[m] * raw[R::P2 + m]; });
             o[L::T2 + sym2(p, q, D + 1)] = s2;
-            for (int r = q; r < V; ++r) {
-                poly_mul<D>(t1, lam[r], t2);
+            static_for<V - q>([&](auto rr) {
+                constexpr int r = q + decltype(rr)::value;
+                mul_affine<D>(t1, lam[r], t2);
                 double s3 = 0.0;
-                for (int m = 0; m < NM; ++m) s3 += t2[m] * raw[R::P1 + m];
+                static_for<NM>([&](auto m) { s3 += t2[m] * raw[R::P1 + m]; });
                 o[L::T3 + sym3(p, q, r, D + 1)] = s3;
-            }
-        }
-    for (int p = 0; p < V; ++p) {
+            });
+        });
+    });
+    static_for<V>([&](auto p) {
         double s1 = 0.0, sb = 0.0;
-        for (int m = 0; m < R::M1; ++m) {
-            s1 += lam[p][m] * raw[R::P3 + m];
-            sb += lam[p][m] * raw[R::P1 + m];
-        }
+        static_for<R::M1>([&](auto m) {
+            s1 += lamp[p][m] * raw[R::P3 + m];
+            sb += lamp[p][m] * raw[R::P1 + m];
+        });
         o[L::T1 + p] = s1;
         o[L::B1 + p] = sb;
-        poly_mul<D>(Wp, lam[p], t1);
+        mul_affine<D>(Wp, lam[p], t1);
         double sw = 0.0;
-        for (int m = 0; m < NM; ++m) sw += t1[m] * raw[R::P1 + m];
+        static_for<NM>([&](auto m) { sw += t1[m] * raw[R::P1 + m]; });
         o[L::AW1 + p] = sw;
         double kg = 0.0;
-        for (int d = 0; d < D; ++d) kg += lam[p][1 + d] / H * raw[R::G + d];
+        static_for<D>([&](auto d) { kg += lam[p][1 + d] / H * raw[R::G + d]; });
         o[L::KG + p] = kg;
-    }
+    });
     o[L::T0] = raw[R::P4];
     o[L::B2] = raw[R::P2];
     double aw2 = 0.0;
-    for (int m = 0; m < R::M2; ++m) aw2 += Wp[m] * raw[R::P2 + m];
+    static_for<R::M2>([&](auto m) { aw2 += Wp[m] * raw[R::P2 + m]; });
     o[L::AW2] = aw2;
     o[L::Q] = raw[R::Q];
 }
