@@ -90,7 +90,9 @@ typedef struct {
     int32_t levels;
     int32_t steps_total;  /* correction steps executed (all levels)                       */
     int32_t newton_total; /* Newton iterations (coarse step + every augmented solve)      */
-    double  seconds;      /* host wall time of the call                                   */
+    double  seconds;      /* host wall time: of the call (fmg_solve); from the batch call  */
+                          /* or the submission to completion (batch, server)              */
+    double  wait_seconds; /* batch / server: time queued before admission (0 otherwise)   */
     int32_t history_len;  /* entries in history[]                                         */
     int32_t factor_total; /* banded LDL^T factorisations of the small solves (incl. checks)  */
     double  history[FMG_HISTORY_MAX]; /* lambda after the coarse step and after every      */
@@ -148,6 +150,57 @@ int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t*
 int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* d_workspace,
               size_t workspace_bytes, void* stream, double* d_u_out, int64_t u_len,
               fmg_result* out);
+
+/* ---- many solves: footprint, allocator, batch, serving -------------------------------- */
+/* Every instance below is the problem and method of fmg_solve (Section 2 problem, the
+ * mesh sequence of (3.1)-(3.2), Algorithm 3.2 with the tolerance loop); results are bitwise
+ * those of fmg_solve on the same problem and options, alone or in any mix.               */
+
+/* Device bytes one solve holds while it runs (its workspace, rounded to 256 B): the
+ * admission footprint of the batch and serving calls.  Pure; 0 for an invalid problem
+ * or options.                                                                            */
+size_t fmg_footprint_bytes(const fmg_problem* prob, const fmg_options* opt);
+
+/* Device allocator for the memory pools of fmg_batch_solve and fmg_server_create (e.g.
+ * torch's caching allocator).  alloc(bytes, ctx) must return 256-B aligned device memory
+ * or NULL; free(ptr, ctx) releases it.  Both NULL restores hipMalloc / hipFree.  A pool
+ * is freed with the allocator that created it.  Applies to pools created afterwards.      */
+int fmg_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx),
+                      void* ctx);
+
+/* Solve `count` independent instances (probs[i], opts[i]) together: one pool holding every
+ * workspace is allocated for the call, up to 8 instances run at once on streams of their
+ * own (their kernels overlap on the device), and each u is written to d_u_out[i] (device,
+ * compact layout, u_len[i] = (n_i - 1)^dim_i).  Work already enqueued on `stream` runs
+ * first.  Returns after every instance is done; out[i] is filled for each (seconds: from
+ * the call to that instance's completion, wait_seconds: until its admission).  Returns 0,
+ * or the status of the first failed instance (the others still complete), or FMG_EINVAL /
+ * FMG_ENOMEM before any work for bad arguments or a failed pool allocation.              */
+int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* opts, void* stream,
+                    double* const* d_u_out, const int64_t* u_len, fmg_result* out);
+
+/* Serving: continuous batching of requests of different sizes.  The server owns a pool of
+ * hbm_budget bytes (0: half of the free device memory) and up to max_slots (1..64)
+ * streams, and a worker thread that admits queued requests in FIFO order whenever a
+ * stream and fmg_footprint_bytes() of pool memory are free, and advances running ones.
+ * A finished request keeps its workspace until it is polled.  Work of the caller on
+ * `stream` before a request's admission runs first; poll copies u on `stream`.
+ * create returns NULL on failure (fmg_last_error says why).                              */
+typedef struct fmg_server fmg_server;
+fmg_server* fmg_server_create(size_t hbm_budget, int32_t max_slots, void* stream);
+/* Queue one request.  FMG_EINVAL for invalid problems/options, FMG_ENOMEM when its
+ * footprint exceeds the whole budget (it could never be admitted).  Thread-safe.         */
+int fmg_server_submit(fmg_server* server, const fmg_problem* prob, const fmg_options* opt,
+                      uint64_t* ticket);
+/* FMG_PENDING (1) while the request is queued or running.  Once done: fills *out (seconds:
+ * submission to completion, wait_seconds: submission to admission), copies u into d_u_out
+ * (device, compact, u_len = (n-1)^dim; NULL to skip) and synchronises `stream`, releases
+ * the request's memory and forgets the ticket; returns the solve's status.  FMG_EINVAL for
+ * an unknown ticket or a wrong u_len (the request stays pollable).  Thread-safe.          */
+int fmg_server_poll(fmg_server* server, uint64_t ticket, fmg_result* out, double* d_u_out, int64_t u_len);
+/* Stops admissions, waits for running requests to finish, frees everything (requests not
+ * yet polled are dropped).                                                               */
+void fmg_server_destroy(fmg_server* server);
 
 /* ---- level layout -------------------------------------------------------------------- */
 int64_t fmg_level_pitch(int32_t dim, int32_t n);   /* row pitch in elements, or -1          */

@@ -14,7 +14,8 @@ import torch
 from . import _ffi
 from ._ffi import FMG_FP64, FMG_MIXED, fmg_options, fmg_problem, fmg_result
 
-__all__ = ["solve", "workspace_bytes", "Solver", "FmgError", "ops", "lib", "to_c_problem", "to_c_options"]
+__all__ = ["solve", "workspace_bytes", "footprint_bytes", "Solver", "batch_solve", "Server", "FmgError", "ops", "lib",
+           "to_c_problem", "to_c_options"]
 
 
 class FmgError(RuntimeError):
@@ -83,6 +84,26 @@ class Result:
     seconds: float
     history: list
     factor_total: int = 0
+    wait_seconds: float = 0.0
+
+
+def _result(res: fmg_result) -> "Result":
+    return Result(res.lambda_, res.lambda_rq, res.norm, res.dlambda, res.status, res.levels, res.steps_total,
+                  res.newton_total, res.seconds, list(res.history[: res.history_len]), res.factor_total,
+                  res.wait_seconds)
+
+
+def footprint_bytes(problem, options) -> int:
+    """Device bytes one solve holds (admission footprint); raises for invalid input."""
+    n = lib().fmg_footprint_bytes(C.byref(to_c_problem(problem)), C.byref(to_c_options(options)))
+    if n == 0:
+        raise FmgError(_ffi.FMG_EINVAL, "invalid problem or options")
+    return n
+
+
+def _ndof(problem) -> int:
+    n = problem.n_coarse << problem.n_refine
+    return (n - 1) ** problem.dim
 
 
 class Solver:
@@ -108,13 +129,80 @@ class Solver:
                              C.c_int64(u_out.numel()), C.byref(res))
         if check:
             _check(rc)
-        out = Result(res.lambda_, res.lambda_rq, res.norm, res.dlambda, res.status, res.levels, res.steps_total,
-                     res.newton_total, res.seconds, list(res.history[: res.history_len]), res.factor_total)
-        return out, u_out
+        return _result(res), u_out
 
 
 def solve(problem, options, device="cuda", check=True):
     return Solver(problem, options, device).solve(check=check)
+
+
+def batch_solve(problems, options, device="cuda", stream=None, check=True):
+    """fmg_batch_solve over lists of problems and options (one options object is reused for
+    every problem).  Returns ([Result], [u tensors])."""
+    k = len(problems)
+    opts = options if isinstance(options, (list, tuple)) else [options] * k
+    cps = (fmg_problem * k)(*[to_c_problem(p) for p in problems])
+    cos = (fmg_options * k)(*[to_c_options(o) for o in opts])
+    us = [torch.empty(_ndof(p), dtype=torch.float64, device=device) for p in problems]
+    ptrs = (C.c_void_p * k)(*[u.data_ptr() for u in us])
+    lens = (C.c_int64 * k)(*[u.numel() for u in us])
+    res = (fmg_result * k)()
+    rc = lib().fmg_batch_solve(k, cps, cos, _stream(stream), ptrs, lens, res)
+    if check:
+        _check(rc)
+    return [_result(r) for r in res], us
+
+
+class Server:
+    """fmg_server_*: continuous batching of eigensolve requests within an HBM budget."""
+
+    def __init__(self, hbm_budget=0, max_slots=8, stream=None, device="cuda"):
+        self.device = device
+        self._stream = _stream(stream)
+        h = lib().fmg_server_create(C.c_size_t(hbm_budget), max_slots, self._stream)
+        if not h:
+            raise FmgError(_ffi.FMG_ENOMEM, lib().fmg_last_error().decode())
+        self._h = C.c_void_p(h)
+        self._problems = {}
+
+    def submit(self, problem, options) -> int:
+        t = C.c_uint64()
+        _check(lib().fmg_server_submit(self._h, C.byref(to_c_problem(problem)), C.byref(to_c_options(options)),
+                                       C.byref(t)))
+        self._problems[t.value] = problem
+        return t.value
+
+    def poll(self, ticket, want_u=True, check=True):
+        """None while pending; else (Result, u or None)."""
+        p = self._problems[ticket]
+        u = torch.empty(_ndof(p), dtype=torch.float64, device=self.device) if want_u else None
+        res = fmg_result()
+        rc = lib().fmg_server_poll(self._h, C.c_uint64(ticket), C.byref(res),
+                                   C.c_void_p(u.data_ptr()) if u is not None else None,
+                                   C.c_int64(u.numel() if u is not None else 0))
+        if rc == _ffi.FMG_PENDING:
+            return None
+        del self._problems[ticket]
+        if check:
+            _check(rc)
+        return _result(res), u
+
+    def close(self):
+        if self._h:
+            lib().fmg_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 from . import ops  # noqa: E402  (needs the helpers above)

@@ -34,7 +34,8 @@ FMG_PROF_VPOST2D_F64 = 1
 class fmg_result(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("lambda_rq", C.c_double), ("norm", C.c_double), ("dlambda", C.c_double),
                 ("status", C.c_int32), ("levels", C.c_int32), ("steps_total", C.c_int32),
-                ("newton_total", C.c_int32), ("seconds", C.c_double), ("history_len", C.c_int32),
+                ("newton_total", C.c_int32), ("seconds", C.c_double), ("wait_seconds", C.c_double),
+                ("history_len", C.c_int32),
                 ("factor_total", C.c_int32), ("history", C.c_double * HISTORY_MAX)]
 
 
@@ -53,6 +54,13 @@ SIGNATURES = {
     "fmg_profile_end": (C.c_int, [P]),
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),
     "fmg_solve": (C.c_int, [P, P, P, SZ, P, P, I64, P]),
+    "fmg_footprint_bytes": (SZ, [P, P]),
+    "fmg_set_allocator": (C.c_int, [P, P, P]),
+    "fmg_batch_solve": (C.c_int, [I32, P, P, P, P, P, P]),
+    "fmg_server_create": (P, [SZ, I32, P]),
+    "fmg_server_submit": (C.c_int, [P, P, P, C.POINTER(C.c_uint64)]),
+    "fmg_server_poll": (C.c_int, [P, C.c_uint64, P, P, I64]),
+    "fmg_server_destroy": (None, [P]),
     "fmg_level_pitch": (I64, [I32, I32]),
     "fmg_level_elems": (I64, [I32, I32]),
     "fmg_pack": (C.c_int, [I32, I32, P, P, P]),

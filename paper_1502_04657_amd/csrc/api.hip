@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/fmgeig.h"
-#include "kernels.h"
+#include "job.h"
 
 namespace fmg {
 
@@ -45,7 +45,7 @@ static Phys make_phys(const fmg_problem* p) {
     return ph;
 }
 
-static int check_problem(const fmg_problem* p) {
+int check_problem(const fmg_problem* p) {
     if (!p) return set_error(FMG_EINVAL, "problem is NULL");
     if (p->dim != 2 && p->dim != 3) return set_error(FMG_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
     if (p->n_coarse < 2) return set_error(FMG_EINVAL, "n_coarse must be >= 2 (got %d)", p->n_coarse);
@@ -62,7 +62,7 @@ static int check_problem(const fmg_problem* p) {
     return 0;
 }
 
-static int check_options(const fmg_options* o) {
+int check_options(const fmg_options* o) {
     if (!o) return set_error(FMG_EINVAL, "options is NULL");
     if (o->m < 1 || o->p < 1) return set_error(FMG_EINVAL, "m and p must be >= 1");
     if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1)
@@ -75,20 +75,9 @@ static int check_options(const fmg_options* o) {
     return 0;
 }
 
-// ----------------------------------------------------------------------------------------
-// workspace layout
-struct Layout {
-    int dim, nc, L, mixed;
-    std::vector<Grid> g;
-    size_t state, xc, mom, momscr, arena, fac, forms;
-    std::vector<size_t> u, b, xv, fv;   // per level (u[0] = xc)
-    std::vector<size_t> tv;             // per level: target of the fused 2D pre pass
-    size_t total;
-};
-
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-static Layout make_layout(int dim, int nc, int levels, int mixed) {
+Layout make_layout(int dim, int nc, int levels, int mixed) {
     Layout lo;
     lo.dim = dim; lo.nc = nc; lo.L = levels; lo.mixed = mixed;
     for (int l = 0; l < levels; ++l) lo.g.push_back(make_grid(dim, nc << l));
@@ -194,6 +183,119 @@ static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, 
     return 0;
 }
 
+// ---- whole solve as a resumable schedule --------------------------------------------------
+int64_t compact_len(const fmg_problem* p) {
+    const int64_t n = (int64_t)p->n_coarse << p->n_refine;
+    return p->dim == 2 ? (n - 1) * (n - 1) : (n - 1) * (n - 1) * (n - 1);
+}
+
+static bool tol_mode(const SolveJob& j) { return j.opt.tol_lambda > 0.0 && j.lo.L > 1; }
+
+// device state (and the Rayleigh-quotient forms after the final chunk) into the host mirror
+static int end_chunk(SolveJob& j, bool final_chunk) {
+    SmallState* st = at<SmallState>(j.ws, j.lo.state);
+    FMG_HIP_CHECK(hipMemcpyAsync(&j.host->st, st, sizeof(SmallState), hipMemcpyDeviceToHost, j.s));
+    if (final_chunk)
+        FMG_HIP_CHECK(hipMemcpyAsync(j.host->forms, at<double>(j.ws, j.lo.forms), sizeof(j.host->forms),
+                                     hipMemcpyDeviceToHost, j.s));
+    if (j.ev) FMG_HIP_CHECK(hipEventRecord(j.ev, j.s));
+    return 0;
+}
+
+// Rayleigh quotient of the finest u, and the output copy when a target is set
+static int final_chunk(SolveJob& j) {
+    const Layout& lo = j.lo;
+    const Grid& gf = lo.g[lo.L - 1];
+    double* forms = at<double>(j.ws, lo.forms);
+    launch_forms(gf, make_phys(&j.prob), at<double>(j.ws, lo.u[lo.L - 1]), forms + 8, forms, j.s);
+    if (j.u_out) launch_unpack(gf, at<double>(j.ws, lo.u[lo.L - 1]), j.u_out, j.s);
+    j.phase = 2;
+    return end_chunk(j, true);
+}
+
+int job_start(SolveJob& j) {
+    const Layout& lo = j.lo;
+    const fmg_problem* prob = &j.prob;
+    const fmg_options* opt = &j.opt;
+    hipStream_t s = j.s;
+    void* ws = j.ws;
+    const Phys ph = make_phys(prob);
+    const int L = lo.L;
+    j.phase = 0;
+    j.extra = 0;
+    // initial state and zeroed level arrays (the Dirichlet rings must be zero)
+    std::memset(&j.host->st, 0, sizeof(SmallState));
+    j.host->st.tol_lambda = opt->tol_lambda;
+    SmallState* st = at<SmallState>(ws, lo.state);
+    FMG_HIP_CHECK(hipMemcpyAsync(st, &j.host->st, sizeof(SmallState), hipMemcpyHostToDevice, s));
+    launch_fill<double>(at<double>(ws, lo.xc), (int64_t)((lo.mom - lo.xc) / sizeof(double)), 0.0, s);
+    // Algorithm 3.2 step 1
+    int rc = launch_coarse_newton(prob->dim, prob->n_coarse, ph, opt->newton_max_iter, opt->newton_tol,
+                                  at<double>(ws, lo.arena), at<double>(ws, lo.fac), at<double>(ws, lo.xc), st, s);
+    if (rc) return set_error(rc, "coarse solve launch failed");
+    // Algorithm 3.2 step 2
+    for (int k = 1; k < L; ++k) {
+        launch_prolong<double>(lo.g[k - 1], lo.g[k], at<double>(ws, lo.u[k - 1]), at<double>(ws, lo.u[k]), 0, s);
+        const bool finest = (k == L - 1);
+        const bool tm = finest && tol_mode(j);
+        for (int step = 0; step < opt->p; ++step) {
+            int flag = tm && step >= std::max(1, opt->p - 1);
+            // ground-state check of the returned state only: the last step of a fixed
+            // schedule, or the step that meets the lambda tolerance
+            int cert = !finest ? 0 : (tm ? (flag ? 2 : 0) : (step == opt->p - 1 ? 1 : 0));
+            if ((rc = correction_step(lo, ws, prob, opt, k, flag, cert, s))) return rc;
+        }
+    }
+    if (tol_mode(j)) {
+        j.phase = 1;
+        return end_chunk(j, false);
+    }
+    return final_chunk(j);
+}
+
+int job_step(SolveJob& j) {
+    if (j.phase == 1) {
+        const SmallState& h = j.host->st;
+        if (h.done || h.status != 0 || j.extra >= j.opt.max_final_steps) return final_chunk(j);
+        // one more finest-level correction step (Algorithm 3.1), then check again
+        if (int rc = correction_step(j.lo, j.ws, &j.prob, &j.opt, j.lo.L - 1, 1, 2, j.s)) return rc;
+        ++j.extra;
+        return end_chunk(j, false);
+    }
+    if (j.phase == 2) j.phase = 3;
+    return 0;
+}
+
+int job_result(const SolveJob& j, fmg_result* out) {
+    const SmallState& h = j.host->st;
+    const double* f4 = j.host->forms;
+    out->lambda = h.lambda;
+    out->norm = f4[2];
+    out->lambda_rq = (f4[0] + f4[1] + j.prob.zeta * f4[3]) / f4[2];
+    out->dlambda = h.dlambda;
+    out->levels = j.lo.L;
+    out->steps_total = h.steps;
+    out->newton_total = h.newton_total;
+    out->factor_total = h.fact_total;
+    out->history_len = std::min(h.hist_len, FMG_HISTORY_MAX);
+    for (int i = 0; i < out->history_len; ++i) out->history[i] = h.hist[i];
+    int status = h.status;
+    if (!status && !std::isfinite(h.lambda)) status = FMG_ENONFINITE;
+    if (!status && h.certify_fail) status = FMG_ENOCONV;
+    if (!status && j.opt.tol_lambda > 0.0 && !h.done) status = FMG_ENOCONV;
+    out->status = status;
+    if (status) {
+        static const char* why[] = {"", "zero pivot", "Newton did not converge", "non-finite value",
+                                    "singular border system", "not the ground state"};
+        if (h.fail_reason)
+            return set_error(status, "status %d: %s in the nonlinear solve after history entry %d (residual %.3e)",
+                             status, why[h.fail_reason > 5 ? 0 : h.fail_reason], h.fail_step, h.fail_residual);
+        return set_error(status, "status %d: tolerance %.3e not reached in %d final steps (last dlambda %.3e)",
+                         status, j.opt.tol_lambda, j.opt.max_final_steps, h.dlambda);
+    }
+    return 0;
+}
+
 }  // namespace fmg
 
 using namespace fmg;
@@ -270,90 +372,31 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     if (int rc = check_options(opt)) return rc;
     if (!out) return set_error(FMG_EINVAL, "result is NULL");
     std::memset(out, 0, sizeof(*out));
-    const int L = prob->n_refine + 1;
-    const int64_t n = (int64_t)prob->n_coarse << prob->n_refine;
-    const int64_t want = prob->dim == 2 ? (n - 1) * (n - 1) : (n - 1) * (n - 1) * (n - 1);
-    if (u_len != want) return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len, (long long)want);
+    if (u_len != compact_len(prob))
+        return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len, (long long)compact_len(prob));
     if (!ws || !u_out) return set_error(FMG_EINVAL, "workspace and u_out must be device pointers");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(FMG_EINVAL, "workspace must be 256-byte aligned");
-    Layout lo = make_layout(prob->dim, prob->n_coarse, L, opt->precision == FMG_MIXED);
-    if (ws_bytes < lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, lo.total);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Phys ph = make_phys(prob);
-
-    // initial state and zeroed level arrays (the Dirichlet rings must be zero)
-    SmallState init;
-    std::memset(&init, 0, sizeof(init));
-    init.tol_lambda = opt->tol_lambda;
-    SmallState* st = at<SmallState>(ws, lo.state);
-    FMG_HIP_CHECK(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    {
-        const size_t first = lo.xc, last = lo.mom;
-        launch_fill<double>(at<double>(ws, first), (int64_t)((last - first) / sizeof(double)), 0.0, s);
+    SolveJob j;
+    j.prob = *prob;
+    j.opt = *opt;
+    j.lo = make_layout(prob->dim, prob->n_coarse, prob->n_refine + 1, opt->precision == FMG_MIXED);
+    if (ws_bytes < j.lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, j.lo.total);
+    JobHost host;
+    j.ws = ws;
+    j.s = static_cast<hipStream_t>(stream);
+    j.u_out = u_out;
+    j.host = &host;
+    // each chunk ends with the device state copied into `host`; wait for it, then continue
+    int rc = job_start(j);
+    while (!rc && j.phase != 3) {
+        FMG_HIP_CHECK(hipStreamSynchronize(j.s));
+        rc = job_step(j);
     }
-    // Algorithm 3.2 step 1
-    int rc = launch_coarse_newton(prob->dim, prob->n_coarse, ph, opt->newton_max_iter, opt->newton_tol,
-                                  at<double>(ws, lo.arena), at<double>(ws, lo.fac), at<double>(ws, lo.xc), st, s);
-    if (rc) return set_error(rc, "coarse solve launch failed");
-    // Algorithm 3.2 step 2
-    for (int k = 1; k < L; ++k) {
-        launch_prolong<double>(lo.g[k - 1], lo.g[k], at<double>(ws, lo.u[k - 1]), at<double>(ws, lo.u[k]), 0, s);
-        const bool finest = (k == L - 1);
-        const bool tol_mode = finest && opt->tol_lambda > 0.0;
-        for (int step = 0; step < opt->p; ++step) {
-            int flag = tol_mode && step >= std::max(1, opt->p - 1);
-            // ground-state check of the returned state only: the last step of a fixed
-            // schedule, or the step that meets the lambda tolerance
-            int cert = !finest ? 0 : (tol_mode ? (flag ? 2 : 0) : (step == opt->p - 1 ? 1 : 0));
-            if ((rc = correction_step(lo, ws, prob, opt, k, flag, cert, s))) return rc;
-        }
-        if (tol_mode) {
-            SmallState h;
-            for (int extra = 0;; ++extra) {
-                FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
-                FMG_HIP_CHECK(hipStreamSynchronize(s));
-                if (h.done || h.status != 0 || extra >= opt->max_final_steps) break;
-                if ((rc = correction_step(lo, ws, prob, opt, k, 1, 2, s))) return rc;
-            }
-        }
-    }
-    // Rayleigh quotient of the returned u on the finest level, and the output copy
-    const Grid& gf = lo.g[L - 1];
-    double* forms = at<double>(ws, lo.forms);
-    launch_forms(gf, ph, at<double>(ws, lo.u[L - 1]), forms + 8, forms, s);
-    launch_unpack(gf, at<double>(ws, lo.u[L - 1]), u_out, s);
-    SmallState h;
-    double f4[4];
-    FMG_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(SmallState), hipMemcpyDeviceToHost, s));
-    FMG_HIP_CHECK(hipMemcpyAsync(f4, forms, sizeof(f4), hipMemcpyDeviceToHost, s));
-    FMG_HIP_CHECK(hipStreamSynchronize(s));
+    if (rc) return rc;
     FMG_HIP_CHECK(hipGetLastError());
-    out->lambda = h.lambda;
-    out->norm = f4[2];
-    out->lambda_rq = (f4[0] + f4[1] + prob->zeta * f4[3]) / f4[2];
-    out->dlambda = h.dlambda;
-    out->levels = L;
-    out->steps_total = h.steps;
-    out->newton_total = h.newton_total;
-    out->factor_total = h.fact_total;
-    out->history_len = std::min(h.hist_len, FMG_HISTORY_MAX);
-    for (int i = 0; i < out->history_len; ++i) out->history[i] = h.hist[i];
-    int status = h.status;
-    if (!status && !std::isfinite(h.lambda)) status = FMG_ENONFINITE;
-    if (!status && h.certify_fail) status = FMG_ENOCONV;
-    if (!status && opt->tol_lambda > 0.0 && !h.done) status = FMG_ENOCONV;
-    out->status = status;
+    const int status = job_result(j, out);
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (status) {
-        static const char* why[] = {"", "zero pivot", "Newton did not converge", "non-finite value",
-                                    "singular border system", "not the ground state"};
-        if (h.fail_reason)
-            return set_error(status, "status %d: %s in the nonlinear solve after history entry %d (residual %.3e)",
-                             status, why[h.fail_reason > 5 ? 0 : h.fail_reason], h.fail_step, h.fail_residual);
-        return set_error(status, "status %d: tolerance %.3e not reached in %d final steps (last dlambda %.3e)",
-                         status, opt->tol_lambda, opt->max_final_steps, h.dlambda);
-    }
-    return 0;
+    return status;
 }
 
 // ---- single steps ----------------------------------------------------------------------

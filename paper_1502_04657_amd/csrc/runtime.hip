@@ -1,0 +1,482 @@
+// Batched and serving runtime: many independent eigensolves in flight on one GPU.
+//
+// Each solve is a resumable schedule (job.h) on a stream of its own; a scheduler pass
+// admits queued solves while a stream slot and workspace memory are free, and advances
+// every running solve whose last chunk has completed (a HIP event query, no blocking).
+// Solves on different streams overlap on the device: the single-workgroup small solves of
+// one instance run beside the bandwidth-bound V-cycles of others.
+//
+// Workspace memory comes from a pool: one device block (the HBM budget) carved first-fit
+// into 256-B aligned regions, so admission by footprint is exact and no allocation happens
+// while solves are running.  The pool block comes from the caller's allocator when one is
+// registered (fmg_set_allocator), else from hipMalloc.
+//
+// fmg_batch_solve runs the scheduler in the calling thread until every solve of the batch
+// is done.  A server runs it in a worker thread: submit queues a request (FIFO admission),
+// poll returns FMG_PENDING until the request is done and then copies its u out and
+// releases its workspace.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "job.h"
+
+namespace fmg {
+
+namespace {
+
+// ---- device allocator hooks ----------------------------------------------------------------
+struct Allocator {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+struct DeviceBlock {
+    void* p = nullptr;
+    Allocator a;   // the allocator that produced p (frees go back to it)
+    int get(size_t bytes) {
+        {
+            std::lock_guard<std::mutex> lk(g_alloc_mu);
+            a = g_alloc;
+        }
+        if (a.alloc) {
+            p = a.alloc(bytes, a.ctx);
+            if (!p) return set_error(FMG_ENOMEM, "caller allocator returned NULL for %zu bytes", bytes);
+            if (reinterpret_cast<uintptr_t>(p) % 256)
+                return set_error(FMG_EINVAL, "caller allocator returned a pointer that is not 256-B aligned");
+            return 0;
+        }
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return set_error(FMG_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+        return 0;
+    }
+    void put() {
+        if (!p) return;
+        if (a.free) a.free(p, a.ctx);
+        else (void)hipFree(p);
+        p = nullptr;
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// First-fit sub-allocator over one device block.
+class Pool {
+  public:
+    int init(size_t bytes) {
+        size_ = align256(bytes);
+        if (int rc = blk_.get(size_)) return rc;
+        free_.clear();
+        free_[0] = size_;
+        return 0;
+    }
+    void destroy() { blk_.put(); }
+    size_t size() const { return size_; }
+    char* base() const { return static_cast<char*>(blk_.p); }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    DeviceBlock blk_;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+};
+
+// One solve as the scheduler sees it.
+struct Task {
+    uint64_t ticket = 0;
+    SolveJob job;
+    size_t bytes = 0, off = 0;
+    int slot = -1;
+    enum { QUEUED, RUNNING, DONE } state = QUEUED;
+    int rc = 0;                       // status of the solve (0 or FMG_E*)
+    std::string msg;
+    fmg_result res{};
+    std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+    bool keep_ws = false;             // server: workspace held until poll copies u out
+};
+
+// Streams, events and pinned host mirrors of the slots; the scheduling pass.
+class Scheduler {
+  public:
+    int init(int slots, hipStream_t user) {
+        user_ = user;
+        slots_ = slots;
+        str_.assign(slots, nullptr);
+        ev_.assign(slots, nullptr);
+        busy_.assign(slots, nullptr);
+        for (int i = 0; i < slots; ++i) {
+            FMG_HIP_CHECK(hipStreamCreateWithFlags(&str_[i], hipStreamNonBlocking));
+            FMG_HIP_CHECK(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
+        }
+        FMG_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&host_), sizeof(JobHost) * slots, hipHostMallocDefault));
+        FMG_HIP_CHECK(hipEventCreateWithFlags(&user_ev_, hipEventDisableTiming));
+        return 0;
+    }
+    void destroy() {
+        for (auto s : str_)
+            if (s) (void)hipStreamDestroy(s);
+        for (auto e : ev_)
+            if (e) (void)hipEventDestroy(e);
+        if (user_ev_) (void)hipEventDestroy(user_ev_);
+        if (host_) (void)hipHostFree(host_);
+        str_.clear();
+        ev_.clear();
+        host_ = nullptr;
+        user_ev_ = nullptr;
+    }
+    bool idle() const {
+        for (auto* t : busy_)
+            if (t) return false;
+        return true;
+    }
+    // Admit queued tasks (FIFO; the head blocks the queue until it fits) and advance running
+    // ones.  Returns the number of tasks that changed state; finished tasks are appended to
+    // `done`.  Launch failures end the task with that status.
+    int pump(std::deque<Task*>& queue, Pool& pool, std::vector<Task*>& done) {
+        int changes = 0;
+        for (int i = 0; i < slots_; ++i) {
+            Task* t = busy_[i];
+            if (!t) continue;
+            const hipError_t q = hipEventQuery(ev_[i]);
+            if (q == hipErrorNotReady) continue;
+            int rc = (q == hipSuccess) ? job_step(t->job) : set_error(FMG_EHIP, "event query failed");
+            if (!rc && t->job.phase != 3) continue;   // next chunk enqueued
+            finish(i, rc, pool, done);
+            ++changes;
+        }
+        while (!queue.empty()) {
+            Task* t = queue.front();
+            int slot = -1;
+            for (int i = 0; i < slots_; ++i)
+                if (!busy_[i]) { slot = i; break; }
+            if (slot < 0 || !pool.alloc(t->bytes, &t->off)) break;
+            queue.pop_front();
+            start(slot, t, pool, done);
+            ++changes;
+        }
+        return changes;
+    }
+
+  private:
+    void start(int i, Task* t, Pool& pool, std::vector<Task*>& done) {
+        t->state = Task::RUNNING;
+        t->slot = i;
+        t->t_admit = std::chrono::steady_clock::now();
+        busy_[i] = t;
+        SolveJob& j = t->job;
+        j.ws = pool.base() + t->off;
+        j.s = str_[i];
+        j.ev = ev_[i];
+        j.host = host_ + i;
+        // work the caller enqueued on its stream before the submission comes first
+        int rc = 0;
+        if (hipEventRecord(user_ev_, user_) != hipSuccess || hipStreamWaitEvent(str_[i], user_ev_, 0) != hipSuccess)
+            rc = set_error(FMG_EHIP, "ordering after the caller's stream failed");
+        if (!rc) rc = job_start(j);
+        if (rc) finish(i, rc, pool, done);
+    }
+    void finish(int i, int rc, Pool& pool, std::vector<Task*>& done) {
+        Task* t = busy_[i];
+        if (rc) {
+            // a launch failed: let what was enqueued drain before the memory is reused
+            (void)hipStreamSynchronize(str_[i]);
+            t->rc = rc;
+            t->msg = g_err_message();
+            t->res.status = rc;
+        } else {
+            t->rc = job_result(t->job, &t->res);
+            if (t->rc) t->msg = g_err_message();
+        }
+        t->t_done = std::chrono::steady_clock::now();
+        t->state = Task::DONE;
+        t->job.host = nullptr;
+        t->job.ev = nullptr;
+        if (!t->keep_ws || rc) {
+            pool.release(t->off, t->bytes);
+            t->bytes = 0;
+        }
+        busy_[i] = nullptr;
+        done.push_back(t);
+    }
+    static std::string g_err_message() { return std::string(fmg_last_error()); }
+
+    hipStream_t user_ = nullptr;
+    int slots_ = 0;
+    std::vector<hipStream_t> str_;
+    std::vector<hipEvent_t> ev_;
+    std::vector<Task*> busy_;
+    JobHost* host_ = nullptr;
+    hipEvent_t user_ev_ = nullptr;
+};
+
+int validate(const fmg_problem* p, const fmg_options* o, size_t* bytes) {
+    if (int rc = check_problem(p)) return rc;
+    if (int rc = check_options(o)) return rc;
+    *bytes = make_layout(p->dim, p->n_coarse, p->n_refine + 1, o->precision == FMG_MIXED).total;
+    return 0;
+}
+
+constexpr int kMaxSlots = 64;     // streams of a server
+constexpr int kBatchSlots = 8;    // streams of a batch call
+
+}  // namespace
+
+}  // namespace fmg
+
+// ---- serving ------------------------------------------------------------------------------
+struct fmg_server {
+    fmg::Pool pool;
+    fmg::Scheduler sched;
+    hipStream_t user = nullptr;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<fmg::Task*> queue;
+    std::map<uint64_t, std::unique_ptr<fmg::Task>> tasks;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int worker_rc = 0;
+    std::thread worker;
+
+    void run() {
+        (void)hipSetDevice(device);
+        std::vector<fmg::Task*> done;
+        for (;;) {
+            std::unique_lock<std::mutex> lk(mu);
+            if (stop) {
+                // no new admissions; let running solves finish so their memory is quiet
+                queue.clear();
+                if (sched.idle()) break;
+            }
+            const int changes = sched.pump(queue, pool, done);
+            done.clear();
+            if (changes) cv.notify_all();
+            else cv.wait_for(lk, std::chrono::microseconds(20));
+        }
+        cv.notify_all();
+    }
+};
+
+using namespace fmg;
+
+extern "C" {
+
+int fmg_set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return set_error(FMG_EINVAL, "alloc and free must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.ctx = ctx;
+    return 0;
+}
+
+size_t fmg_footprint_bytes(const fmg_problem* prob, const fmg_options* opt) {
+    size_t bytes = 0;
+    if (validate(prob, opt, &bytes)) return 0;
+    return align256(bytes);
+}
+
+int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* opts, void* stream,
+                    double* const* u_out, const int64_t* u_len, fmg_result* out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (count < 0) return set_error(FMG_EINVAL, "count must be >= 0");
+    if (count == 0) return 0;
+    if (!probs || !opts || !u_out || !u_len || !out) return set_error(FMG_EINVAL, "NULL array argument");
+    std::vector<std::unique_ptr<Task>> tasks(count);
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        auto t = std::make_unique<Task>();
+        if (int rc = validate(&probs[i], &opts[i], &t->bytes))
+            return set_error(rc, "instance %d: %s", i, std::string(fmg_last_error()).c_str());
+        if (u_len[i] != compact_len(&probs[i]))
+            return set_error(FMG_EINVAL, "instance %d: u_len %lld != (n-1)^dim = %lld", i, (long long)u_len[i],
+                             (long long)compact_len(&probs[i]));
+        if (!u_out[i]) return set_error(FMG_EINVAL, "instance %d: u_out is NULL", i);
+        t->ticket = i;
+        t->job.prob = probs[i];
+        t->job.opt = opts[i];
+        t->job.lo = make_layout(probs[i].dim, probs[i].n_coarse, probs[i].n_refine + 1,
+                                opts[i].precision == FMG_MIXED);
+        t->job.u_out = u_out[i];
+        total += align256(t->bytes);
+        tasks[i] = std::move(t);
+    }
+    Pool pool;
+    if (int rc = pool.init(total)) return rc;
+    Scheduler sched;
+    int rc = sched.init(std::min(count, kBatchSlots), static_cast<hipStream_t>(stream));
+    if (rc) {
+        sched.destroy();
+        pool.destroy();
+        return rc;
+    }
+    std::deque<Task*> queue;
+    for (auto& t : tasks) {
+        t->t_submit = t0;
+        queue.push_back(t.get());
+    }
+    std::vector<Task*> done;
+    while (done.size() < (size_t)count) {
+        if (!sched.pump(queue, pool, done)) std::this_thread::sleep_for(std::chrono::microseconds(10));
+    }
+    sched.destroy();
+    pool.destroy();
+    int first = 0;
+    for (int i = 0; i < count; ++i) {
+        Task& t = *tasks[i];
+        out[i] = t.res;
+        out[i].status = t.rc;
+        out[i].seconds = std::chrono::duration<double>(t.t_done - t0).count();
+        out[i].wait_seconds = std::chrono::duration<double>(t.t_admit - t0).count();
+        if (t.rc && !first) {
+            first = t.rc;
+            set_error(t.rc, "instance %d: %s", i, t.msg.c_str());
+        }
+    }
+    return first;
+}
+
+fmg_server* fmg_server_create(size_t hbm_budget, int32_t max_slots, void* stream) {
+    if (max_slots < 1 || max_slots > kMaxSlots) {
+        set_error(FMG_EINVAL, "max_slots must be in [1, %d]", kMaxSlots);
+        return nullptr;
+    }
+    if (hbm_budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            set_error(FMG_EHIP, "hipMemGetInfo failed");
+            return nullptr;
+        }
+        hbm_budget = fr / 2;
+    }
+    auto* sv = new fmg_server();
+    sv->user = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&sv->device) != hipSuccess) {
+        set_error(FMG_EHIP, "hipGetDevice failed");
+        delete sv;
+        return nullptr;
+    }
+    if (sv->pool.init(hbm_budget) || sv->sched.init(max_slots, sv->user)) {
+        const std::string m = fmg_last_error();
+        sv->sched.destroy();
+        sv->pool.destroy();
+        delete sv;
+        set_error(FMG_ENOMEM, "%s", m.c_str());
+        return nullptr;
+    }
+    sv->worker = std::thread([sv] { sv->run(); });
+    return sv;
+}
+
+int fmg_server_submit(fmg_server* sv, const fmg_problem* prob, const fmg_options* opt, uint64_t* ticket) {
+    if (!sv || !ticket) return set_error(FMG_EINVAL, "server and ticket must not be NULL");
+    auto t = std::make_unique<Task>();
+    if (int rc = validate(prob, opt, &t->bytes)) return rc;
+    if (align256(t->bytes) > sv->pool.size())
+        return set_error(FMG_ENOMEM, "footprint %zu bytes exceeds the server budget %zu", align256(t->bytes),
+                         sv->pool.size());
+    t->job.prob = *prob;
+    t->job.opt = *opt;
+    t->job.lo = make_layout(prob->dim, prob->n_coarse, prob->n_refine + 1, opt->precision == FMG_MIXED);
+    t->keep_ws = true;
+    t->t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return set_error(FMG_EINVAL, "server is shutting down");
+    t->ticket = sv->next_ticket++;
+    *ticket = t->ticket;
+    sv->queue.push_back(t.get());
+    sv->tasks.emplace(t->ticket, std::move(t));
+    sv->cv.notify_all();
+    return 0;
+}
+
+int fmg_server_poll(fmg_server* sv, uint64_t ticket, fmg_result* out, double* u_out, int64_t u_len) {
+    if (!sv) return set_error(FMG_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->tasks.find(ticket);
+    if (it == sv->tasks.end()) return set_error(FMG_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Task& t = *it->second;
+    if (t.state != Task::DONE) return FMG_PENDING;
+    if (u_out && u_len != compact_len(&t.job.prob)) {
+        return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len,
+                         (long long)compact_len(&t.job.prob));
+    }
+    int rc = t.rc;
+    if (u_out && t.bytes) {
+        // the solve's chunks have completed; copy u on the caller's stream, then release
+        const Layout& lo = t.job.lo;
+        launch_unpack(lo.g[lo.L - 1], reinterpret_cast<const double*>(sv->pool.base() + t.off + lo.u[lo.L - 1]), u_out,
+                      sv->user);
+        if (hipStreamSynchronize(sv->user) != hipSuccess) rc = set_error(FMG_EHIP, "copy of u failed");
+    }
+    if (out) {
+        *out = t.res;
+        out->status = t.rc;
+        out->seconds = std::chrono::duration<double>(t.t_done - t.t_submit).count();
+        out->wait_seconds = std::chrono::duration<double>(t.t_admit - t.t_submit).count();
+    }
+    if (t.bytes) sv->pool.release(t.off, t.bytes);
+    const std::string msg = t.msg;
+    const int solve_rc = t.rc;
+    sv->tasks.erase(it);   // t is gone from here on
+    sv->cv.notify_all();
+    if (rc && rc == solve_rc && !msg.empty()) return set_error(rc, "%s", msg.c_str());
+    return rc;
+}
+
+void fmg_server_destroy(fmg_server* sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->cv.notify_all();
+    }
+    if (sv->worker.joinable()) sv->worker.join();
+    sv->sched.destroy();
+    sv->pool.destroy();
+    delete sv;
+}
+
+}  // extern "C"

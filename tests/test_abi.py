@@ -79,3 +79,46 @@ def test_solve_rejects_bad_sizes_before_touching_the_device(lib):
     rc = lib.fmg_solve(C.byref(p), C.byref(o), C.c_void_p(256), C.c_size_t(16), None, C.c_void_p(256),
                        C.c_int64(127 * 127), C.byref(res))
     assert rc == -2
+
+
+def test_footprint_is_the_aligned_workspace(lib):
+    from paper_1502_04657_amd import to_c_options, to_c_problem
+    for prob, opt in ((W.LARGE_2D, W.Options()), (W.SMALL_2D, W.Options(precision="mixed")),
+                      (W.LARGE_3D, W.Options(tol_lambda=1e-9))):
+        p, o = to_c_problem(prob), to_c_options(opt)
+        n = C.c_size_t()
+        assert lib.fmg_workspace_bytes(C.byref(p), C.byref(o), C.byref(n)) == 0
+        f = lib.fmg_footprint_bytes(C.byref(p), C.byref(o))
+        assert f % 256 == 0 and n.value <= f < n.value + 256
+        assert lib.fmg_footprint_bytes(C.byref(p), C.byref(o)) == f   # pure
+    bad = to_c_problem(W.Problem(2, 1, 3))
+    assert lib.fmg_footprint_bytes(C.byref(bad), C.byref(to_c_options(W.Options()))) == 0
+
+
+def test_allocator_hooks_must_come_in_pairs(lib):
+    alloc_t = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+    fake = alloc_t(lambda n, ctx: None)
+    assert lib.fmg_set_allocator(C.cast(fake, C.c_void_p), None, None) == -1
+    assert b"both" in lib.fmg_last_error()
+    assert lib.fmg_set_allocator(None, None, None) == 0
+
+
+def test_batch_validates_every_instance_before_any_work(lib):
+    from paper_1502_04657_amd import _ffi, to_c_options, to_c_problem
+    k = 3
+    probs = (_ffi.fmg_problem * k)(to_c_problem(W.SMALL_2D), to_c_problem(W.Problem(2, 8, 2)),
+                                   to_c_problem(W.Problem(2, 8, 2, zeta=-2.0)))
+    opts = (_ffi.fmg_options * k)(*[to_c_options(W.Options())] * k)
+    ptrs = (C.c_void_p * k)(256, 256, 256)
+    res = (_ffi.fmg_result * k)()
+    # the third instance is invalid: rejected on the host, nothing allocated or launched
+    lens = (C.c_int64 * k)(127 ** 2, 31 ** 2, 31 ** 2)
+    assert lib.fmg_batch_solve(k, probs, opts, None, ptrs, lens, res) == -1
+    assert b"instance 2" in lib.fmg_last_error()
+    # a wrong length
+    probs[2] = to_c_problem(W.Problem(2, 8, 2))
+    lens[1] = 5
+    assert lib.fmg_batch_solve(k, probs, opts, None, ptrs, lens, res) == -1
+    assert b"instance 1" in lib.fmg_last_error() and b"u_len" in lib.fmg_last_error()
+    assert lib.fmg_batch_solve(0, None, None, None, None, None, None) == 0
+    assert lib.fmg_batch_solve(-1, None, None, None, None, None, None) == -1
