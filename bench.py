@@ -125,6 +125,105 @@ def copy_calibration():
                                            "check": float(out[:4].sum().item())}}))
 
 
+def bench_batch(steps, warmup, count=64):
+    """Config 4: `count` uneven 2D instances (workloads.batch_instances, seed 0) per
+    fmg_batch_solve call, mixed precision, tolerance 1e-9 on |dlambda|/lambda.  value =
+    fine DOF of the batch / seconds per call; latency = each instance's completion time
+    within its call.  The same instances solved one after another through fmg_solve are
+    timed beside it."""
+    import torch
+    from paper_1502_04657_amd import Solver, batch_solve
+    probs = W.batch_instances(count, 0)
+    opts = W.Options(tol_lambda=TOL, precision="mixed")
+    dofs = sum(p.dofs() for p in probs)
+    for _ in range(warmup):
+        batch_solve(probs, opts, check=False)
+    torch.cuda.synchronize()
+    lat, fails = [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, _ = batch_solve(probs, opts, check=False)
+        lat += [r.seconds for r in res]
+        fails += sum(r.status != 0 for r in res)
+    total = time.perf_counter() - t0
+    solvers = [Solver(p, opts) for p in probs]
+    for s in solvers:
+        s.solve(check=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in solvers:
+        s.solve(check=False)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    return {"metric": "fine DOF/s, batched FMG eigensolves (mixed precision, 1e-8 lambda)",
+            "value": dofs * steps / total, "unit": "fine DOF/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": total / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": f"{count} 2D GP instances, n in {{256,512,1024}}, zeta log-uniform [0.1,1000], "
+                                   "W=a x^2+b y^2, a,b in [0.5,2], coarsest h=1/16, seed 0", "global_batch": count},
+            "instance_latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
+            "failed_instances": fails, "sequential_fmg_solve_ms": seq * 1e3,
+            "speedup_vs_sequential": seq / (total / steps)}
+
+
+def bench_serve(count, budget_gb, rates=(0.5, 0.9, 1.25)):
+    """Config 5: a request stream (workloads.serving_requests, seed 1) through one server.
+    Saturation throughput = requests / time with all submitted at once; then Poisson
+    arrivals (seed 2) at fractions of it.  Latency = submission to completion (device
+    work observed done by the server), admission wait reported separately."""
+    import torch
+    from paper_1502_04657_amd import Server
+    reqs = W.serving_requests(count, 1)
+    opts = W.Options(tol_lambda=TOL, precision="mixed")
+    budget = int(budget_gb * (1 << 30))
+
+    def run(arrivals):
+        out = {}
+        with Server(hbm_budget=budget, max_slots=16) as sv:
+            t0 = time.perf_counter()
+            tickets, i = [], 0
+            while len(out) < len(reqs):
+                now = time.perf_counter() - t0
+                while i < len(reqs) and arrivals[i] <= now:
+                    tickets.append(sv.submit(reqs[i], opts))
+                    i += 1
+                for t in tickets:
+                    if t not in out:
+                        r = sv.poll(t, want_u=False, check=False)
+                        if r is not None:
+                            out[t] = r[0]
+                time.sleep(50e-6)
+            span = time.perf_counter() - t0
+        res = list(out.values())
+        return span, res
+
+    run([0.0] * min(8, len(reqs)) + [0.0] * (len(reqs) - min(8, len(reqs))))   # warm-up
+    span, res = run([0.0] * len(reqs))
+    sat = len(reqs) / span
+    rows = [{"rate_frac": "saturation", "solves_per_s": sat,
+             "latency_ms": {"p50": _pct([r.seconds for r in res], 50) * 1e3,
+                            "p99": _pct([r.seconds for r in res], 99) * 1e3},
+             "failed": sum(r.status != 0 for r in res)}]
+    rng = np.random.default_rng(2)
+    for f in rates:
+        gaps = rng.exponential(1.0 / (f * sat), size=len(reqs))
+        arr = np.cumsum(gaps) - gaps[0]
+        span, res = run(list(arr))
+        lat = [r.seconds for r in res]
+        wait = [r.wait_seconds for r in res]
+        rows.append({"rate_frac": f, "offered_per_s": f * sat, "solves_per_s": len(reqs) / span,
+                     "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
+                     "wait_ms": {"p50": _pct(wait, 50) * 1e3, "p99": _pct(wait, 99) * 1e3},
+                     "failed": sum(r.status != 0 for r in res)})
+    dofs = sum(p.dofs() for p in reqs)
+    return {"metric": "serving: solves/s and p50/p99 latency vs offered rate (mixed precision, 1e-8 lambda)",
+            "value": sat, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"{count} requests: 70% 2D n=2^k k in 7..11, 30% 3D n in {{64,128,192}}, "
+                                   "zeta log-uniform [0.1,1000], anisotropic harmonic W, seed 1",
+                       "hbm_budget_gb": budget_gb, "fine_dof_total": dofs},
+            "rates": rows}
+
+
 def cpu_baseline():
     """The oracle, as it stands, on a bounded sample of the same workload family: the same
     problem (zeta = 100, W = x^2 + y^2, coarsest h = 1/16, same schedule and tolerance)
@@ -152,6 +251,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a cold plain copy of known size (memory-counter scaling)")
+    ap.add_argument("--workload", choices=["fmg2d", "batch", "serve"], default="fmg2d",
+                    help="fmg2d: the default line; batch / serve: the batched and serving workloads")
+    ap.add_argument("--requests", type=int, default=60, help="serve: requests per rate")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget of the server")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; instances shard across GPUs with no communication "
@@ -161,6 +264,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args.steps, args.warmup)))
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args.requests, args.budget_gb)))
         return
     prob = W.LARGE_2D
     N = prob.dofs()

@@ -104,7 +104,7 @@ def serving_requests(count: int, seed: int = 1, frac_2d: float = 0.7,
             out.append(Problem(dim=2, n_coarse=16, n_refine=k - 4, w_quad=a, zeta=zeta))
         else:
             n = int(rng.choice(list(sizes_3d)))
-            nc = 6 if n % 8 else 8
+            nc = 8 if n % 8 == 0 and ((n // 8) & (n // 8 - 1)) == 0 else 6   # n = nc * 2^k
             a = tuple(float(v) for v in rng.uniform(0.5, 2.0, size=3))
             out.append(Problem(dim=3, n_coarse=nc, n_refine=int(round(math.log2(n // nc))),
                                w_quad=a, zeta=zeta))
