@@ -198,6 +198,7 @@ struct Arena {
     Sizes z;
     double* Sst;                                   // S(x) stencil, N x NS
     double* x; double* xs; double* xk; double* y; double* z2; double* F; double* rhs;
+    double* xp; double* fp;                        // previous iterate and chord step (acceleration)
     double* aH; double* bH; double* sH; double* sc; double* red;
     double* Dm; double* Fm; double* Rm;            // block factor (nb blocks each)
     double* S1; double* S2;                        // scratch
@@ -219,6 +220,8 @@ struct Arena {
         y = p; p += N + 2;
         z2 = p; p += N + 2;
         F = p; p += N + 2;
+        xp = p; p += N + 2;
+        fp = p; p += N + 2;
         rhs = p; p += 3 * (size_t)N;
         aH = p; p += N;
         bH = p; p += N;
@@ -233,7 +236,7 @@ __host__ __device__ inline size_t arena_bytes_t(int nc) {
     Sizes z = sizes<D, AUG>(nc);
     constexpr int NS = Geo<D>::NS;
     size_t N = z.N;
-    size_t dbl = 3 * (size_t)z.nb * z.B2 + z.sz1 + (size_t)z.h * z.B2 + N * NS + 6 * (N + 2) + 3 * N + 3 * N + 32 +
+    size_t dbl = 3 * (size_t)z.nb * z.B2 + z.sz1 + (size_t)z.h * z.B2 + N * NS + 8 * (N + 2) + 3 * N + 3 * N + 32 +
                  8 * kWaves;
     return dbl * sizeof(double) + 64;
 }
@@ -1214,6 +1217,8 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         __syncthreads();
     }
     double mu = 0.0, mus = 0.0, res_prev = 1e300;
+    double mu_prev = 0.0, fmu_prev = 0.0;   // acceleration history (mu part)
+    bool aa_have = false;
     bool last_fresh = false, need_fresh = !have, frozen = false;
     double g11 = 0.0, g12 = 0.0, g21 = 0.0, g22 = 1.0;   // frozen Schur complement G
     for (int it = 0; it <= a.max_iter; ++it) {
@@ -1252,6 +1257,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             mu = mus;
             need_fresh = true;
             res_prev = 1e300;
+            aa_have = false;
             __syncthreads();
             continue;
         }
@@ -1263,6 +1269,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             last_fresh = true;
             frozen = false;
             have = true;
+            aa_have = false;
             if (tid == 0) ar.sc[8] += 1.0;
         } else {
             last_fresh = false;
@@ -1312,8 +1319,9 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         }
         FMG_TACC(4, t_s);
         FMG_T0(t_u);
-        // C^T y0 = -V^T F_H
+        // C^T y0 = -V^T F_H; the chord step (dx, dmu) goes to y (free until the next apply)
         double dmu, dc = 0.0;
+        double* dx = ar.y;
         if (AUG) {
             double p[2] = {0.0, 0.0};
             for (int i = tid; i < N; i += kThreads) {
@@ -1327,18 +1335,49 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             if (!(fabs(det) > 0.0)) return -4;
             dc = (r1 * g22 - g12 * r2) / det;
             dmu = (g11 * r2 - g21 * r1) / det;
-            for (int i = tid; i < N; i += kThreads)
-                ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dc - ar.rhs[2 * N + i] * dmu;
-            if (tid == 0) ar.x[N] += dc;
+            for (int i = tid; i < N; i += kThreads) dx[i] = ar.rhs[i] - ar.rhs[N + i] * dc - ar.rhs[2 * N + i] * dmu;
+            if (tid == 0) dx[N] = dc;
         } else {
             double p1 = 0.0;
             for (int i = tid; i < N; i += kThreads) p1 += ar.rhs[N + i] * ar.F[i];
             p1 = bsum1(ar.red, p1);
             if (!(fabs(g22) > 0.0)) return -4;
             dmu = (-F2 + p1) / g22;   // z.y0 = p1 with V = J^{-1}(-z)
-            for (int i = tid; i < N; i += kThreads) ar.x[i] += ar.rhs[i] - ar.rhs[N + i] * dmu;
+            for (int i = tid; i < N; i += kThreads) dx[i] = ar.rhs[i] - ar.rhs[N + i] * dmu;
         }
-        mu += dmu;
+        __syncthreads();
+        // Anderson acceleration (one previous pair) of the chord map z -> z + dz, z = (x, mu):
+        // gamma minimises |dz - gamma (dz - dz_prev)|, z <- z + dz - gamma (z - z_prev + dz - dz_prev).
+        // The history restarts whenever the frozen Jacobian changes.
+        double gamma = 0.0;
+        if (aa_have) {
+            double v[2] = {0.0, 0.0};
+            for (int i = tid; i < N1; i += kThreads) {
+                const double df = dx[i] - ar.fp[i];
+                v[0] += df * dx[i];
+                v[1] += df * df;
+            }
+            if (tid == 0) {
+                const double dfm = dmu - fmu_prev;
+                v[0] += dfm * dmu;
+                v[1] += dfm * dfm;
+            }
+            bsum<2>(ar.red, v);
+            gamma = v[1] > 0.0 ? v[0] / v[1] : 0.0;
+        }
+        for (int i = tid; i < N1; i += kThreads) {
+            const double xi = ar.x[i], di = dx[i];
+            ar.x[i] = xi + di - gamma * ((xi - ar.xp[i]) + (di - ar.fp[i]));
+            ar.xp[i] = xi;
+            ar.fp[i] = di;
+        }
+        {
+            const double mnew = mu + dmu - gamma * ((mu - mu_prev) + (dmu - fmu_prev));
+            mu_prev = mu;
+            fmu_prev = dmu;
+            mu = mnew;
+        }
+        aa_have = true;
         __syncthreads();
         FMG_TACC(5, t_u);
     }
