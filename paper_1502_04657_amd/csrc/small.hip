@@ -38,7 +38,10 @@ namespace fmg {
 namespace {
 
 constexpr int kThreads = 256;               // four wavefronts
-constexpr double kStageTol = 1e-8;          // residual for intermediate continuation stages
+#ifndef FMG_SMALL_STAGE_TOL
+#define FMG_SMALL_STAGE_TOL 1e-3
+#endif
+constexpr double kStageTol = FMG_SMALL_STAGE_TOL;   // residual for intermediate continuation stages
 constexpr int kWaves = kThreads / 64;
 
 template <int D>
@@ -1241,8 +1244,10 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         const double res = sqrt(fz[0]) / (fabs(mu) * sqrt(fz[1]));
         if (tid == 0) ar.sc[7] = res;
         if (!(res == res) || !(mu == mu)) return -3;
-        // x^T B x = 1 up to the rounding of an N-term dot product
-        if (res <= tol && fabs(F2) <= 4.0 * N1 * 1.1e-16) {
+        // x^T B x = 1 up to the rounding of an N-term dot product; an intermediate stage of
+        // the coarse continuation (tol above the requested one) only needs tol
+        const double f2_tol = tol > a.tol ? tol : 4.0 * N1 * 1.1e-16;
+        if (res <= tol && fabs(F2) <= f2_tol) {
             const double sN = 1.0 / sqrt(ar.sc[5]);
             for (int i = tid; i < N1; i += kThreads) ar.x[i] *= sN;
             if (tid == 0) ar.sc[6] = mu;
