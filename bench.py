@@ -55,7 +55,7 @@ def time_solves(prob, opts, steps, warmup):
     return res, u, total, lat
 
 
-VPOST_KERNEL = "k_vpost2d<double, 5, 64, 32>"
+VPOST_KERNEL = "k_vpost2d<double, 5, 54, 22>"
 PMC_FILE = os.path.join(ROOT, "profiles", "k_vpost2d_f64_pmc.md")
 VPOST_SRC = os.path.join(ROOT, "paper_1502_04657_amd", "csrc", "vcycle2d.hip")
 
@@ -79,7 +79,7 @@ def _pmc_traffic():
 
 def vpost_roofline(prob, steps):
     """Roofline of the fused FP64 post-smoothing level pass (prolongation-add + 5 red-black
-    half sweeps; 64 x 32-tile build) on the finest level n = 2048, the largest HBM-bound
+    half sweeps; 54 x 22-tile build) on the finest level n = 2048, the largest HBM-bound
     kernel of the solve: start/stop HIP events stamped by each launch's own dispatch on its
     stream (hipExtLaunchKernel) for every finest-level launch during `steps` solves of the
     benchmark workload; algorithmic bytes per launch = 8 (3 N_l + N_{l-1}), N_l = 2047^2

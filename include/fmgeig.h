@@ -114,7 +114,7 @@ int fmg_set_fused_vcycle(int32_t enable);
  * algorithmic bytes of each launch.  FMG_PROF_VPOST2D_F64 is the fused 2D FP64 post-smoothing level pass
  * (prolongation-add plus the post half-sweeps; bytes = 8 * (3 N_l + N_{l-1}), reading x,
  * f and the coarse correction and writing x) on the finest level of each solve, when that
- * level has more than 256 cells per side (the 64 x 32-tile build of the kernel).  Not thread-safe; one profile at a time.
+ * level has more than 256 cells per side (the wide-tile build of the kernel).  Not thread-safe; one profile at a time.
  * The events are created without a system-scope fence (timing only); fmg_profile_end
  * synchronises the device and fills *out.                                               */
 enum { FMG_PROF_VPOST2D_F64 = 1 };

@@ -44,7 +44,7 @@ void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partia
 // post kernel (per-launch timing without the launch gaps of stream-recorded events).
 template <typename T> bool launch_vpre2d(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc,
                                          int nu, int zero_x, hipStream_t s);
-// levels above 256 cells per side use 64 x 32 tiles, smaller ones 16 x 16
+// levels above 256 cells per side use the wide tiles, smaller ones 16 x 16
 bool vpass2d_wide_tiles(const Grid& g);
 template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc,
                                           int nu, hipStream_t s, hipEvent_t ev0 = nullptr,

@@ -6,12 +6,13 @@
 // Each pass reads one array and writes another (y is a scratch level array): a workgroup
 // reads a halo around its tile, so an in-place pass would let it read nodes that a
 // neighbouring workgroup has already overwritten.
-// with NH = 2 nu + 1 (the symmetric sweeps R,B,B,R,... collapse to R,B,R,... because a
-// repeated half sweep of the same colour changes nothing).  Each workgroup owns a TX x TY
-// tile, loads it with a halo of HALO nodes into LDS, and runs the half sweeps on shrinking
-// regions (the dependency cone of the tile), so only the tile is written back.  Every node
-// update, residual and restriction uses exactly the expression of the unfused kernels in
-// grid.hip, so the fused and unfused paths produce identical bits.
+// NH = 2 nu + 1 (the symmetric sweeps R,B,B,R,... collapse to R,B,R,... because a repeated
+// half sweep of the same colour changes nothing).  Each workgroup owns a TX x TY tile, reads
+// it with a halo of HALO nodes, and runs the half sweeps on shrinking regions (the
+// dependency cone of the tile), so only the tile is written back.  Each thread keeps f of
+// the nodes it owns in registers; LDS holds x only.  Every node update, residual and
+// restriction uses exactly the expression of the unfused kernels in grid.hip, so the fused
+// and unfused paths produce identical bits.
 #include <hip/hip_ext.h>
 
 #include <utility>
@@ -29,101 +30,131 @@ __device__ inline T gs2f(T f, T w, T e, T s, T n) {
     return (f + ((w + e) + (s + n))) * T(0.25);
 }
 
-// Red-black half sweeps on the LDS region.  Region coordinates: column c in [0, RW),
-// row r in [0, RH); global node (gi, gj) = (i0 - HALO + c, j0 - HALO + r).  Half sweep S
-// updates the colour-`col` interior nodes within distance ext = R + NH - 1 - S of the tile:
-// a (TX + 2 ext) x (TY + 2 ext) rectangle holding (TX/2 + ext) nodes of each colour per row.
-// The nodes of one colour are independent, so the workgroup takes them as one flat list
-// (compile-time sizes, no partly idle row passes); nodes outside the domain are skipped.
+// The LDS region of a workgroup: its TX x TY tile plus HALO rings, RW x RH nodes, region
+// column c / row r <-> global node (i0 - HALO + c, j0 - HALO + r).  The region is cut into
+// horizontal node pairs (columns 2p, 2p+1 of a row; RW is even); thread t owns pairs
+// t, t + THREADS, ... for the whole pass and keeps their x and f in registers.  LDS holds
+// only x, for the neighbour reads of the sweeps.  Each half sweep updates, in every owned
+// pair, the node of the sweep's colour, so all owners of pairs inside the sweep's
+// rectangle work in every half sweep.
+template <int TX, int TY, int HALO>
+struct Region {
+    static constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
+    static constexpr int HP = RW / 2;                         // pairs per row
+    static constexpr int NP = HP * RH;                        // pairs
+    static constexpr int K = (NP + THREADS - 1) / THREADS;    // pairs per thread
+    static_assert(RW % 2 == 0, "region rows hold whole pairs");
+};
+
+// per-thread values of the owned pairs
+template <typename T, int TX, int TY, int HALO>
+using PairVals = T[Region<TX, TY, HALO>::K];
+
+template <int TX, int TY, int HALO>
+__device__ inline void pair_coords(int k, int i0, int j0, int& c, int& r, int& gi, int& gj, bool& valid) {
+    using Rg = Region<TX, TY, HALO>;
+    const int P = threadIdx.x + k * THREADS;
+    valid = P < Rg::NP;
+    r = P / Rg::HP;
+    c = 2 * (P - r * Rg::HP);
+    gi = i0 - HALO + c;
+    gj = j0 - HALO + r;
+}
+
+__device__ inline bool interior(int gi, int gj, int n) { return gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1; }
+
+// Half sweep S of NH (colour col) on the owned pairs: the colour-col node of each pair
+// within distance ext = R + NH - 1 - S of the tile, clipped to the domain interior.
 template <typename T, int TX, int TY, int HALO, int NH, int R, int S>
-__device__ inline void half_sweep(T* xs, const T* fs, int i0, int j0, int n, int col) {
-    constexpr int RW = TX + 2 * HALO;
+__device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO>& fa, const PairVals<T, TX, TY, HALO>& fb,
+                                  int i0, int j0, int n, int col) {
+    using Rg = Region<TX, TY, HALO>;
+    constexpr int RW = Rg::RW;
     constexpr int ext = R + NH - 1 - S;
-    constexpr int HW = TX / 2 + ext, NI = (TY + 2 * ext) * HW;
-    const int ia = i0 - ext, ja = j0 - ext;
-    for (int k = threadIdx.x; k < NI; k += THREADS) {
-        const int r = k / HW, m = k - r * HW;
-        const int gj = ja + r;
-        const int gi = ia + 2 * m + ((col - gj - ia) & 1);   // nodes with (gi + gj) % 2 == col
-        if (gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1) {
-            const int p = (gi - (i0 - HALO)) + RW * (r + HALO - ext);
-            xs[p] = gs2f<T>(fs[p], xs[p - 1], xs[p + 1], xs[p - RW], xs[p + RW]);
+    const int ia = max(1, i0 - ext), ib = min(n - 1, i0 + TX - 1 + ext);
+    const int ja = max(1, j0 - ext), jb = min(n - 1, j0 + TY - 1 + ext);
+#pragma unroll
+    for (int k = 0; k < Rg::K; ++k) {
+        int c, r, gi, gj;
+        bool valid;
+        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        const int sel = ((gi + gj) & 1) ^ col;   // 0: the even-column node has colour col
+        const int g = gi + sel;
+        if (valid && g >= ia && g <= ib && gj >= ja && gj <= jb) {
+            const int p = c + sel + RW * r;
+            xs[p] = gs2f<T>(sel ? fb[k] : fa[k], xs[p - 1], xs[p + 1], xs[p - RW], xs[p + RW]);
         }
     }
     __syncthreads();
 }
 
 template <typename T, int TX, int TY, int HALO, int NH, int R, int... S>
-__device__ inline void half_sweeps_seq(T* xs, const T* fs, int i0, int j0, int n, int first,
+__device__ inline void half_sweeps_seq(T* xs, const PairVals<T, TX, TY, HALO>& fa,
+                                       const PairVals<T, TX, TY, HALO>& fb, int i0, int j0, int n,
                                        std::integer_sequence<int, S...>) {
-    (half_sweep<T, TX, TY, HALO, NH, R, S>(xs, fs, i0, j0, n, first ^ (S & 1)), ...);
+    (half_sweep<T, TX, TY, HALO, NH, R, S>(xs, fa, fb, i0, j0, n, S & 1), ...);
 }
 
-template <typename T, int TX, int TY, int HALO, int NH, int R>
-__device__ inline void half_sweeps(T* xs, const T* fs, int i0, int j0, int n, int first) {
-    half_sweeps_seq<T, TX, TY, HALO, NH, R>(xs, fs, i0, j0, n, first, std::make_integer_sequence<int, NH>{});
-}
-
-// Loads the tile plus HALO rings of x (zero when zero_x) and f into LDS.  PROLONG adds the
-// coarse correction P x_c on the interior nodes of the region (the expression of k_prolong).
-// Every thread issues the loads of all its region nodes before the first LDS write, so a
-// workgroup waits for memory once instead of once per node it loads.
-template <typename T, int TX, int TY, int HALO, bool PROLONG>
-__device__ inline void load_region(T* xs, T* fs, const T* __restrict__ x, const T* __restrict__ f,
-                                   const T* __restrict__ xc, const Grid& g, const Grid& gc, int i0, int j0,
-                                   int zero_x) {
-    constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO, NR = RW * RH;
-    constexpr int NT = (NR + THREADS - 1) / THREADS;
-    const int n = g.n;
-    T xv[NT], fv[NT], c0[NT], c1[NT];
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        xv[k] = T(0); fv[k] = T(0); c0[k] = T(0); c1[k] = T(0);
-        const int t = threadIdx.x + k * THREADS;
-        if (t < NR) {
-            const int r = t / RW, c = t - r * RW;
-            const int gi = i0 - HALO + c, gj = j0 - HALO + r;
-            if (gi >= 0 && gi <= n && gj >= 0 && gj <= n) {
-                const int64_t q = gi + g.pitch * gj;
-                if (!zero_x) xv[k] = x[q];
-                fv[k] = f[q];
-            }
-            if (PROLONG && gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1) {
-                const int di = gi & 1, dj = gj & 1;
-                const int64_t q0 = (gi >> 1) + gc.pitch * (gj >> 1);
-                c0[k] = xc[q0];
-                if (di | dj) c1[k] = xc[q0 + di + gc.pitch * dj];
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        const int t = threadIdx.x + k * THREADS;
-        if (t < NR) {
-            T v = xv[k];
-            if (PROLONG) {
-                const int r = t / RW, c = t - r * RW;
-                const int gi = i0 - HALO + c, gj = j0 - HALO + r;
-                if (gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1) {
-                    T p = c0[k];
-                    if ((gi & 1) | (gj & 1)) p = T(0.5) * (p + c1[k]);
-                    v += p;
-                }
-            }
-            xs[t] = v;
-            fs[t] = fv[k];
-        }
-    }
-}
-
+// x and f of the owned pairs (zero outside the domain; x zero when zero_x).  Every load of
+// the thread is issued before the first use.
 template <typename T, int TX, int TY, int HALO>
-__device__ inline void store_tile(const T* xs, T* __restrict__ x, const Grid& g, int i0, int j0) {
-    constexpr int RW = TX + 2 * HALO;
+__device__ inline void load_pairs(PairVals<T, TX, TY, HALO>& xa, PairVals<T, TX, TY, HALO>& xb,
+                                  PairVals<T, TX, TY, HALO>& fa, PairVals<T, TX, TY, HALO>& fb,
+                                  const T* __restrict__ x, const T* __restrict__ f, const Grid& g, int i0, int j0,
+                                  int zero_x) {
+    using Rg = Region<TX, TY, HALO>;
     const int n = g.n;
-    for (int t = threadIdx.x; t < TX * TY; t += THREADS) {
-        const int r = t / TX, c = t - r * TX;
-        const int gi = i0 + c, gj = j0 + r;
-        if (gi <= n - 1 && gj <= n - 1) x[gi + g.pitch * gj] = xs[(c + HALO) + RW * (r + HALO)];
+#pragma unroll
+    for (int k = 0; k < Rg::K; ++k) {
+        int c, r, gi, gj;
+        bool valid;
+        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        xa[k] = T(0); xb[k] = T(0); fa[k] = T(0); fb[k] = T(0);
+        const bool row = valid && gj >= 0 && gj <= n;
+        const int q = gi + (int)g.pitch * gj;   // level arrays hold < 2^31 elements
+        if (row && gi >= 0 && gi <= n) {
+            if (!zero_x) xa[k] = x[q];
+            fa[k] = f[q];
+        }
+        if (row && gi + 1 >= 0 && gi + 1 <= n) {
+            if (!zero_x) xb[k] = x[q + 1];
+            fb[k] = f[q + 1];
+        }
+    }
+}
+
+// owned x into the LDS region
+template <typename T, int TX, int TY, int HALO>
+__device__ inline void put_pairs(T* xs, const PairVals<T, TX, TY, HALO>& xa,
+                                 const PairVals<T, TX, TY, HALO>& xb, int i0, int j0) {
+    using Rg = Region<TX, TY, HALO>;
+#pragma unroll
+    for (int k = 0; k < Rg::K; ++k) {
+        int c, r, gi, gj;
+        bool valid;
+        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        if (valid) {
+            xs[c + Rg::RW * r] = xa[k];
+            xs[c + 1 + Rg::RW * r] = xb[k];
+        }
+    }
+}
+
+// the tile nodes of the owned pairs, from the LDS region, to the level array
+template <typename T, int TX, int TY, int HALO>
+__device__ inline void store_pairs(T* __restrict__ out, const T* xs, const Grid& g, int i0, int j0) {
+    using Rg = Region<TX, TY, HALO>;
+    const int n = g.n;
+#pragma unroll
+    for (int k = 0; k < Rg::K; ++k) {
+        int c, r, gi, gj;
+        bool valid;
+        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        if (!valid || gj < j0 || gj > min(n - 1, j0 + TY - 1)) continue;
+        const int q = gi + (int)g.pitch * gj;
+        const int p = c + Rg::RW * r;
+        if (gi >= i0 && gi <= min(n - 1, i0 + TX - 1)) out[q] = xs[p];
+        if (gi + 1 >= i0 && gi + 1 <= min(n - 1, i0 + TX - 1)) out[q + 1] = xs[p + 1];
     }
 }
 
@@ -134,27 +165,34 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(const T* __restrict__ x, T* 
                                                     int zero_x) {
     constexpr int R = 2;                 // x must be final within 2 rings for the residual ring
     constexpr int HALO = NH + R;
-    constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
-    __shared__ T xs[RW * RH];
-    __shared__ T fs[RW * RH];
+    using Rg = Region<TX, TY, HALO>;
+    constexpr int RW = Rg::RW;
+    __shared__ T xs[RW * Rg::RH];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n;
-    load_region<T, TX, TY, HALO, false>(xs, fs, x, f, nullptr, g, gc, i0, j0, zero_x);
+    T xa[Rg::K], xb[Rg::K], fa[Rg::K], fb[Rg::K];
+    load_pairs<T, TX, TY, HALO>(xa, xb, fa, fb, x, f, g, i0, j0, zero_x);
+    put_pairs<T, TX, TY, HALO>(xs, xa, xb, i0, j0);
     __syncthreads();
-    half_sweeps<T, TX, TY, HALO, NH, R>(xs, fs, i0, j0, n, 0);
-    // residual r = f - K x on the tile and one ring, stored over f
-    {
-        constexpr int W1 = TX + 2, H1 = TY + 2;
-        for (int t = threadIdx.x; t < W1 * H1; t += THREADS) {
-            const int r = t / W1, c = t - r * W1;
-            const int gi = i0 - 1 + c, gj = j0 - 1 + r;
-            if (gi < 1 || gi > n - 1 || gj < 1 || gj > n - 1) continue;
-            const int p = (c - 1 + HALO) + RW * (r - 1 + HALO);
-            fs[p] = fs[p] - (T(4) * xs[p] - ((xs[p - 1] + xs[p + 1]) + (xs[p - RW] + xs[p + RW])));
-        }
+    half_sweeps_seq<T, TX, TY, HALO, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
+    store_pairs<T, TX, TY, HALO>(y, xs, g, i0, j0);
+    // residual r = f - K x on the tile and one ring (kept in fa/fb; f elsewhere)
+    const int ia = i0 - 1, ib = i0 + TX, ja = j0 - 1, jb = j0 + TY;
+#pragma unroll
+    for (int k = 0; k < Rg::K; ++k) {
+        int c, r, gi, gj;
+        bool valid;
+        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        if (!valid || gj < ja || gj > jb) continue;
+        const int p = c + RW * r;
+        if (gi >= ia && gi <= ib && interior(gi, gj, n))
+            fa[k] = fa[k] - (T(4) * xs[p] - ((xs[p - 1] + xs[p + 1]) + (xs[p - RW] + xs[p + RW])));
+        if (gi + 1 >= ia && gi + 1 <= ib && interior(gi + 1, gj, n))
+            fb[k] = fb[k] - (T(4) * xs[p + 1] - ((xs[p] + xs[p + 2]) + (xs[p + 1 - RW] + xs[p + 1 + RW])));
     }
     __syncthreads();
-    store_tile<T, TX, TY, HALO>(xs, y, g, i0, j0);
+    put_pairs<T, TX, TY, HALO>(xs, fa, fb, i0, j0);   // the residuals replace x in LDS
+    __syncthreads();
     // restriction for the coarse nodes whose centre 2I, 2J lies in this tile
     {
         constexpr int CW = TX / 2, CH = TY / 2;
@@ -164,8 +202,8 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(const T* __restrict__ x, T* 
             const int I = (i0 + 1) / 2 + c, J = (j0 + 1) / 2 + r;
             if (I > nc - 1 || J > nc - 1) continue;
             const int p = (2 * I - i0 + HALO) + RW * (2 * J - j0 + HALO);
-            const T e = (fs[p - 1] + fs[p + 1]) + (fs[p - RW] + fs[p + RW]) + (fs[p - 1 - RW] + fs[p + 1 + RW]);
-            rc[I + gc.pitch * J] = fs[p] + T(0.5) * e;
+            const T e = (xs[p - 1] + xs[p + 1]) + (xs[p - RW] + xs[p + RW]) + (xs[p - 1 - RW] + xs[p + 1 + RW]);
+            rc[I + gc.pitch * J] = xs[p] + T(0.5) * e;
         }
     }
 }
@@ -177,22 +215,63 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T*
                                                      Grid gc) {
     constexpr int R = 0;
     constexpr int HALO = NH > 0 ? NH + R : 1;
-    constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
-    __shared__ T xs[RW * RH];
-    __shared__ T fs[RW * RH];
+    using Rg = Region<TX, TY, HALO>;
+    constexpr int RW = Rg::RW;
+    // coarse values under the region: coarse node (I, J) for I in [(i0 - HALO) >> 1, ...]
+    constexpr int CRW = Rg::RW / 2 + 2, CRH = Rg::RH / 2 + 2;
+    __shared__ T xs[RW * Rg::RH];
+    __shared__ T cs[CRW * CRH];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
-    const int n = g.n;
-    // x = y + P x_c on every interior node of the region
-    load_region<T, TX, TY, HALO, true>(xs, fs, y, f, xc, g, gc, i0, j0, 0);
+    const int n = g.n, nc = gc.n;
+    const int I0 = (i0 - HALO) >> 1, J0 = (j0 - HALO) >> 1;
+    T xa[Rg::K], xb[Rg::K], fa[Rg::K], fb[Rg::K];
+    constexpr int KC = (CRW * CRH + THREADS - 1) / THREADS;
+    T cv[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int t = threadIdx.x + k * THREADS;
+        const int r = t / CRW, c = t - r * CRW;
+        const int I = I0 + c, J = J0 + r;
+        cv[k] = (t < CRW * CRH && I >= 0 && I <= nc && J >= 0 && J <= nc) ? xc[I + (int)gc.pitch * J] : T(0);
+    }
+    load_pairs<T, TX, TY, HALO>(xa, xb, fa, fb, y, f, g, i0, j0, 0);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int t = threadIdx.x + k * THREADS;
+        if (t < CRW * CRH) cs[t] = cv[k];
+    }
     __syncthreads();
-    half_sweeps<T, TX, TY, HALO, NH, R>(xs, fs, i0, j0, n, 0);
-    store_tile<T, TX, TY, HALO>(xs, x, g, i0, j0);
+    // x = y + P x_c on the interior nodes of the region (the expression of k_prolong)
+#pragma unroll
+    for (int k = 0; k < Rg::K; ++k) {
+        int c, r, gi, gj;
+        bool valid;
+        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        if (!valid) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gg = gi + h;
+            if (!interior(gg, gj, n)) continue;
+            const int di = gg & 1, dj = gj & 1;
+            const int q0 = ((gg >> 1) - I0) + CRW * ((gj >> 1) - J0);
+            T v = cs[q0];
+            if (di | dj) v = T(0.5) * (v + cs[q0 + di + CRW * dj]);
+            if (h) xb[k] += v;
+            else xa[k] += v;
+        }
+    }
+    put_pairs<T, TX, TY, HALO>(xs, xa, xb, i0, j0);
+    __syncthreads();
+    half_sweeps_seq<T, TX, TY, HALO, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
+    store_pairs<T, TX, TY, HALO>(x, xs, g, i0, j0);
 }
 
-// Tile shape by level: 64 x 32 where the level has many tiles, 16 x 16 on coarse levels
-// (more workgroups, shorter sweeps; the halo overhead is irrelevant there).
+// Tile shape by level: 16 x 16 on coarse levels (more workgroups, short sweeps; the halo
+// overhead is irrelevant there); on finer levels the tiles whose padded region is a whole
+// number of 256-pair rounds: post (5 halo rings) 54 x 22 -> 64 x 32 region, 4 pairs per
+// thread; pre (7 rings) 50 x 34 -> 64 x 48 region, 6 pairs per thread.
 constexpr int kSmallLevel = 256;
-
+constexpr int kPreTX = 50, kPreTY = 34, kPostTX = 54, kPostTY = 22;
 
 template <typename T, int NH>
 void pre_launch(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc, int zero_x, hipStream_t s) {
@@ -200,8 +279,8 @@ void pre_launch(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* 
         dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
         hipLaunchKernelGGL((k_vpre2d<T, NH, 16, 16>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
     } else {
-        dim3 grd(cdiv(g.n - 1, 64), cdiv(g.n - 1, 32));
-        hipLaunchKernelGGL((k_vpre2d<T, NH, 64, 32>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
+        dim3 grd(cdiv(g.n - 1, kPreTX), cdiv(g.n - 1, kPreTY));
+        hipLaunchKernelGGL((k_vpre2d<T, NH, kPreTX, kPreTY>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
     }
 }
 template <typename T, int NH>
@@ -211,8 +290,9 @@ void post_launch(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, co
         dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
         hipExtLaunchKernelGGL((k_vpost2d<T, NH, 16, 16>), grd, dim3(THREADS), 0, s, ev0, ev1, 0, y, x, f, xc, g, gc);
     } else {
-        dim3 grd(cdiv(g.n - 1, 64), cdiv(g.n - 1, 32));
-        hipExtLaunchKernelGGL((k_vpost2d<T, NH, 64, 32>), grd, dim3(THREADS), 0, s, ev0, ev1, 0, y, x, f, xc, g, gc);
+        dim3 grd(cdiv(g.n - 1, kPostTX), cdiv(g.n - 1, kPostTY));
+        hipExtLaunchKernelGGL((k_vpost2d<T, NH, kPostTX, kPostTY>), grd, dim3(THREADS), 0, s, ev0, ev1, 0, y, x, f, xc,
+                              g, gc);
     }
 }
 
