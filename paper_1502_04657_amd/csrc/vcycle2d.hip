@@ -23,8 +23,6 @@ namespace fmg {
 
 namespace {
 
-constexpr int THREADS = 256;
-
 template <typename T>
 __device__ inline T gs2f(T f, T w, T e, T s, T n) {
     return (f + ((w + e) + (s + n))) * T(0.25);
@@ -33,27 +31,27 @@ __device__ inline T gs2f(T f, T w, T e, T s, T n) {
 // The LDS region of a workgroup: its TX x TY tile plus HALO rings, RW x RH nodes, region
 // column c / row r <-> global node (i0 - HALO + c, j0 - HALO + r).  The region is cut into
 // horizontal node pairs (columns 2p, 2p+1 of a row; RW is even); thread t owns pairs
-// t, t + THREADS, ... for the whole pass and keeps their x and f in registers.  LDS holds
+// t, t + NT, ... for the whole pass and keeps their f in registers.  LDS holds
 // only x, for the neighbour reads of the sweeps.  Each half sweep updates, in every owned
 // pair, the node of the sweep's colour, so all owners of pairs inside the sweep's
 // rectangle work in every half sweep.
-template <int TX, int TY, int HALO>
+template <int TX, int TY, int HALO, int NT>
 struct Region {
     static constexpr int RW = TX + 2 * HALO, RH = TY + 2 * HALO;
     static constexpr int HP = RW / 2;                         // pairs per row
     static constexpr int NP = HP * RH;                        // pairs
-    static constexpr int K = (NP + THREADS - 1) / THREADS;    // pairs per thread
+    static constexpr int K = (NP + NT - 1) / NT;              // pairs per thread
     static_assert(RW % 2 == 0, "region rows hold whole pairs");
 };
 
 // per-thread values of the owned pairs
-template <typename T, int TX, int TY, int HALO>
-using PairVals = T[Region<TX, TY, HALO>::K];
+template <typename T, int TX, int TY, int HALO, int NT>
+using PairVals = T[Region<TX, TY, HALO, NT>::K];
 
-template <int TX, int TY, int HALO>
+template <int TX, int TY, int HALO, int NT>
 __device__ inline void pair_coords(int k, int i0, int j0, int& c, int& r, int& gi, int& gj, bool& valid) {
-    using Rg = Region<TX, TY, HALO>;
-    const int P = threadIdx.x + k * THREADS;
+    using Rg = Region<TX, TY, HALO, NT>;
+    const int P = threadIdx.x + k * NT;
     valid = P < Rg::NP;
     r = P / Rg::HP;
     c = 2 * (P - r * Rg::HP);
@@ -65,10 +63,10 @@ __device__ inline bool interior(int gi, int gj, int n) { return gi >= 1 && gi <=
 
 // Half sweep S of NH (colour col) on the owned pairs: the colour-col node of each pair
 // within distance ext = R + NH - 1 - S of the tile, clipped to the domain interior.
-template <typename T, int TX, int TY, int HALO, int NH, int R, int S>
-__device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO>& fa, const PairVals<T, TX, TY, HALO>& fb,
+template <typename T, int TX, int TY, int HALO, int NT, int NH, int R, int S>
+__device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO, NT>& fa, const PairVals<T, TX, TY, HALO, NT>& fb,
                                   int i0, int j0, int n, int col) {
-    using Rg = Region<TX, TY, HALO>;
+    using Rg = Region<TX, TY, HALO, NT>;
     constexpr int RW = Rg::RW;
     constexpr int ext = R + NH - 1 - S;
     const int ia = max(1, i0 - ext), ib = min(n - 1, i0 + TX - 1 + ext);
@@ -77,7 +75,7 @@ __device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO>& fa, co
     for (int k = 0; k < Rg::K; ++k) {
         int c, r, gi, gj;
         bool valid;
-        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         const int sel = ((gi + gj) & 1) ^ col;   // 0: the even-column node has colour col
         const int g = gi + sel;
         if (valid && g >= ia && g <= ib && gj >= ja && gj <= jb) {
@@ -88,27 +86,27 @@ __device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO>& fa, co
     __syncthreads();
 }
 
-template <typename T, int TX, int TY, int HALO, int NH, int R, int... S>
-__device__ inline void half_sweeps_seq(T* xs, const PairVals<T, TX, TY, HALO>& fa,
-                                       const PairVals<T, TX, TY, HALO>& fb, int i0, int j0, int n,
+template <typename T, int TX, int TY, int HALO, int NT, int NH, int R, int... S>
+__device__ inline void half_sweeps_seq(T* xs, const PairVals<T, TX, TY, HALO, NT>& fa,
+                                       const PairVals<T, TX, TY, HALO, NT>& fb, int i0, int j0, int n,
                                        std::integer_sequence<int, S...>) {
-    (half_sweep<T, TX, TY, HALO, NH, R, S>(xs, fa, fb, i0, j0, n, S & 1), ...);
+    (half_sweep<T, TX, TY, HALO, NT, NH, R, S>(xs, fa, fb, i0, j0, n, S & 1), ...);
 }
 
 // x and f of the owned pairs (zero outside the domain; x zero when zero_x).  Every load of
 // the thread is issued before the first use.
-template <typename T, int TX, int TY, int HALO>
-__device__ inline void load_pairs(PairVals<T, TX, TY, HALO>& xa, PairVals<T, TX, TY, HALO>& xb,
-                                  PairVals<T, TX, TY, HALO>& fa, PairVals<T, TX, TY, HALO>& fb,
+template <typename T, int TX, int TY, int HALO, int NT>
+__device__ inline void load_pairs(PairVals<T, TX, TY, HALO, NT>& xa, PairVals<T, TX, TY, HALO, NT>& xb,
+                                  PairVals<T, TX, TY, HALO, NT>& fa, PairVals<T, TX, TY, HALO, NT>& fb,
                                   const T* __restrict__ x, const T* __restrict__ f, const Grid& g, int i0, int j0,
                                   int zero_x) {
-    using Rg = Region<TX, TY, HALO>;
+    using Rg = Region<TX, TY, HALO, NT>;
     const int n = g.n;
 #pragma unroll
     for (int k = 0; k < Rg::K; ++k) {
         int c, r, gi, gj;
         bool valid;
-        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         xa[k] = T(0); xb[k] = T(0); fa[k] = T(0); fb[k] = T(0);
         const bool row = valid && gj >= 0 && gj <= n;
         const int q = gi + (int)g.pitch * gj;   // level arrays hold < 2^31 elements
@@ -124,15 +122,15 @@ __device__ inline void load_pairs(PairVals<T, TX, TY, HALO>& xa, PairVals<T, TX,
 }
 
 // owned x into the LDS region
-template <typename T, int TX, int TY, int HALO>
-__device__ inline void put_pairs(T* xs, const PairVals<T, TX, TY, HALO>& xa,
-                                 const PairVals<T, TX, TY, HALO>& xb, int i0, int j0) {
-    using Rg = Region<TX, TY, HALO>;
+template <typename T, int TX, int TY, int HALO, int NT>
+__device__ inline void put_pairs(T* xs, const PairVals<T, TX, TY, HALO, NT>& xa,
+                                 const PairVals<T, TX, TY, HALO, NT>& xb, int i0, int j0) {
+    using Rg = Region<TX, TY, HALO, NT>;
 #pragma unroll
     for (int k = 0; k < Rg::K; ++k) {
         int c, r, gi, gj;
         bool valid;
-        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (valid) {
             xs[c + Rg::RW * r] = xa[k];
             xs[c + 1 + Rg::RW * r] = xb[k];
@@ -141,15 +139,15 @@ __device__ inline void put_pairs(T* xs, const PairVals<T, TX, TY, HALO>& xa,
 }
 
 // the tile nodes of the owned pairs, from the LDS region, to the level array
-template <typename T, int TX, int TY, int HALO>
+template <typename T, int TX, int TY, int HALO, int NT>
 __device__ inline void store_pairs(T* __restrict__ out, const T* xs, const Grid& g, int i0, int j0) {
-    using Rg = Region<TX, TY, HALO>;
+    using Rg = Region<TX, TY, HALO, NT>;
     const int n = g.n;
 #pragma unroll
     for (int k = 0; k < Rg::K; ++k) {
         int c, r, gi, gj;
         bool valid;
-        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (!valid || gj < j0 || gj > min(n - 1, j0 + TY - 1)) continue;
         const int q = gi + (int)g.pitch * gj;
         const int p = c + Rg::RW * r;
@@ -159,30 +157,30 @@ __device__ inline void store_pairs(T* __restrict__ out, const T* xs, const Grid&
 }
 
 // pre-smoothing + residual + restriction
-template <typename T, int NH, int TX, int TY>
-__global__ __launch_bounds__(THREADS) void k_vpre2d(const T* __restrict__ x, T* __restrict__ y,
+template <typename T, int NH, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_vpre2d(const T* __restrict__ x, T* __restrict__ y,
                                                     const T* __restrict__ f, T* __restrict__ rc, Grid g, Grid gc,
                                                     int zero_x) {
     constexpr int R = 2;                 // x must be final within 2 rings for the residual ring
     constexpr int HALO = NH + R;
-    using Rg = Region<TX, TY, HALO>;
+    using Rg = Region<TX, TY, HALO, NT>;
     constexpr int RW = Rg::RW;
     __shared__ T xs[RW * Rg::RH];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n;
     T xa[Rg::K], xb[Rg::K], fa[Rg::K], fb[Rg::K];
-    load_pairs<T, TX, TY, HALO>(xa, xb, fa, fb, x, f, g, i0, j0, zero_x);
-    put_pairs<T, TX, TY, HALO>(xs, xa, xb, i0, j0);
+    load_pairs<T, TX, TY, HALO, NT>(xa, xb, fa, fb, x, f, g, i0, j0, zero_x);
+    put_pairs<T, TX, TY, HALO, NT>(xs, xa, xb, i0, j0);
     __syncthreads();
-    half_sweeps_seq<T, TX, TY, HALO, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
-    store_pairs<T, TX, TY, HALO>(y, xs, g, i0, j0);
+    half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
+    store_pairs<T, TX, TY, HALO, NT>(y, xs, g, i0, j0);
     // residual r = f - K x on the tile and one ring (kept in fa/fb; f elsewhere)
     const int ia = i0 - 1, ib = i0 + TX, ja = j0 - 1, jb = j0 + TY;
 #pragma unroll
     for (int k = 0; k < Rg::K; ++k) {
         int c, r, gi, gj;
         bool valid;
-        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (!valid || gj < ja || gj > jb) continue;
         const int p = c + RW * r;
         if (gi >= ia && gi <= ib && interior(gi, gj, n))
@@ -191,13 +189,13 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(const T* __restrict__ x, T* 
             fb[k] = fb[k] - (T(4) * xs[p + 1] - ((xs[p] + xs[p + 2]) + (xs[p + 1 - RW] + xs[p + 1 + RW])));
     }
     __syncthreads();
-    put_pairs<T, TX, TY, HALO>(xs, fa, fb, i0, j0);   // the residuals replace x in LDS
+    put_pairs<T, TX, TY, HALO, NT>(xs, fa, fb, i0, j0);   // the residuals replace x in LDS
     __syncthreads();
     // restriction for the coarse nodes whose centre 2I, 2J lies in this tile
     {
         constexpr int CW = TX / 2, CH = TY / 2;
         const int nc = gc.n;
-        for (int t = threadIdx.x; t < CW * CH; t += THREADS) {
+        for (int t = threadIdx.x; t < CW * CH; t += NT) {
             const int r = t / CW, c = t - r * CW;
             const int I = (i0 + 1) / 2 + c, J = (j0 + 1) / 2 + r;
             if (I > nc - 1 || J > nc - 1) continue;
@@ -209,13 +207,13 @@ __global__ __launch_bounds__(THREADS) void k_vpre2d(const T* __restrict__ x, T* 
 }
 
 // prolongation + correction + post-smoothing
-template <typename T, int NH, int TX, int TY>
-__global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T* __restrict__ x,
+template <typename T, int NH, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_vpost2d(const T* __restrict__ y, T* __restrict__ x,
                                                      const T* __restrict__ f, const T* __restrict__ xc, Grid g,
                                                      Grid gc) {
     constexpr int R = 0;
     constexpr int HALO = NH > 0 ? NH + R : 1;
-    using Rg = Region<TX, TY, HALO>;
+    using Rg = Region<TX, TY, HALO, NT>;
     constexpr int RW = Rg::RW;
     // coarse values under the region: coarse node (I, J) for I in [(i0 - HALO) >> 1, ...]
     constexpr int CRW = Rg::RW / 2 + 2, CRH = Rg::RH / 2 + 2;
@@ -225,19 +223,19 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T*
     const int n = g.n, nc = gc.n;
     const int I0 = (i0 - HALO) >> 1, J0 = (j0 - HALO) >> 1;
     T xa[Rg::K], xb[Rg::K], fa[Rg::K], fb[Rg::K];
-    constexpr int KC = (CRW * CRH + THREADS - 1) / THREADS;
+    constexpr int KC = (CRW * CRH + NT - 1) / NT;
     T cv[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int t = threadIdx.x + k * THREADS;
+        const int t = threadIdx.x + k * NT;
         const int r = t / CRW, c = t - r * CRW;
         const int I = I0 + c, J = J0 + r;
         cv[k] = (t < CRW * CRH && I >= 0 && I <= nc && J >= 0 && J <= nc) ? xc[I + (int)gc.pitch * J] : T(0);
     }
-    load_pairs<T, TX, TY, HALO>(xa, xb, fa, fb, y, f, g, i0, j0, 0);
+    load_pairs<T, TX, TY, HALO, NT>(xa, xb, fa, fb, y, f, g, i0, j0, 0);
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int t = threadIdx.x + k * THREADS;
+        const int t = threadIdx.x + k * NT;
         if (t < CRW * CRH) cs[t] = cv[k];
     }
     __syncthreads();
@@ -246,7 +244,7 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T*
     for (int k = 0; k < Rg::K; ++k) {
         int c, r, gi, gj;
         bool valid;
-        pair_coords<TX, TY, HALO>(k, i0, j0, c, r, gi, gj, valid);
+        pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (!valid) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -260,10 +258,10 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T*
             else xa[k] += v;
         }
     }
-    put_pairs<T, TX, TY, HALO>(xs, xa, xb, i0, j0);
+    put_pairs<T, TX, TY, HALO, NT>(xs, xa, xb, i0, j0);
     __syncthreads();
-    half_sweeps_seq<T, TX, TY, HALO, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
-    store_pairs<T, TX, TY, HALO>(x, xs, g, i0, j0);
+    half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
+    store_pairs<T, TX, TY, HALO, NT>(x, xs, g, i0, j0);
 }
 
 // Tile shape by level: 16 x 16 on coarse levels (more workgroups, short sweeps; the halo
@@ -271,16 +269,27 @@ __global__ __launch_bounds__(THREADS) void k_vpost2d(const T* __restrict__ y, T*
 // number of 256-pair rounds: post (5 halo rings) 54 x 22 -> 64 x 32 region, 4 pairs per
 // thread; pre (7 rings) 50 x 34 -> 64 x 48 region, 6 pairs per thread.
 constexpr int kSmallLevel = 256;
-constexpr int kPreTX = 50, kPreTY = 34, kPostTX = 54, kPostTY = 22;
+#ifndef FMG_VC_PRE_TILE
+#define FMG_VC_PRE_TILE 50, 34, 256
+#define FMG_VC_POST_TILE 54, 22, 256
+#endif
+
+template <int TX, int TY, int NT>
+struct Tile {
+    static constexpr int tx = TX, ty = TY, nt = NT;
+};
+using PreWide = Tile<FMG_VC_PRE_TILE>;
+using PostWide = Tile<FMG_VC_POST_TILE>;
 
 template <typename T, int NH>
 void pre_launch(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc, int zero_x, hipStream_t s) {
     if (g.n <= kSmallLevel) {
         dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
-        hipLaunchKernelGGL((k_vpre2d<T, NH, 16, 16>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
+        hipLaunchKernelGGL((k_vpre2d<T, NH, 16, 16, 256>), grd, dim3(256), 0, s, x, y, f, rc, g, gc, zero_x);
     } else {
-        dim3 grd(cdiv(g.n - 1, kPreTX), cdiv(g.n - 1, kPreTY));
-        hipLaunchKernelGGL((k_vpre2d<T, NH, kPreTX, kPreTY>), grd, dim3(THREADS), 0, s, x, y, f, rc, g, gc, zero_x);
+        using W = PreWide;
+        dim3 grd(cdiv(g.n - 1, W::tx), cdiv(g.n - 1, W::ty));
+        hipLaunchKernelGGL((k_vpre2d<T, NH, W::tx, W::ty, W::nt>), grd, dim3(W::nt), 0, s, x, y, f, rc, g, gc, zero_x);
     }
 }
 template <typename T, int NH>
@@ -288,11 +297,12 @@ void post_launch(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, co
                  hipEvent_t ev0, hipEvent_t ev1) {
     if (g.n <= kSmallLevel) {
         dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
-        hipExtLaunchKernelGGL((k_vpost2d<T, NH, 16, 16>), grd, dim3(THREADS), 0, s, ev0, ev1, 0, y, x, f, xc, g, gc);
+        hipExtLaunchKernelGGL((k_vpost2d<T, NH, 16, 16, 256>), grd, dim3(256), 0, s, ev0, ev1, 0, y, x, f, xc, g, gc);
     } else {
-        dim3 grd(cdiv(g.n - 1, kPostTX), cdiv(g.n - 1, kPostTY));
-        hipExtLaunchKernelGGL((k_vpost2d<T, NH, kPostTX, kPostTY>), grd, dim3(THREADS), 0, s, ev0, ev1, 0, y, x, f, xc,
-                              g, gc);
+        using W = PostWide;
+        dim3 grd(cdiv(g.n - 1, W::tx), cdiv(g.n - 1, W::ty));
+        hipExtLaunchKernelGGL((k_vpost2d<T, NH, W::tx, W::ty, W::nt>), grd, dim3(W::nt), 0, s, ev0, ev1, 0, y, x, f,
+                              xc, g, gc);
     }
 }
 
