@@ -224,6 +224,19 @@ def bench_serve(count, budget_gb, rates=(0.5, 0.9, 1.25)):
             "rates": rows}
 
 
+def bench_omega(steps, warmup, lam_ref):
+    """The fixed-iteration-count variant of the augmented solves (Section 3.3) against
+    solving each augmented problem to convergence, on the default workload: correction
+    steps, nonlinear iterations and time to reach |dlambda|/lambda <= 1e-9."""
+    rows = []
+    for k in (0, 1, 2, 3):
+        res, _, total, lat = time_solves(W.LARGE_2D, W.Options(tol_lambda=TOL, newton_fixed_iters=k), steps, warmup)
+        rows.append({"newton_fixed_iters": k or "converged", "ms_per_solve": total / steps * 1e3,
+                     "steps_total": res.steps_total, "newton_total": res.newton_total, "status": res.status,
+                     "lambda_rel_err_vs_oracle": abs(res.lam - lam_ref) / lam_ref if lam_ref else None})
+    return {"metric": "fixed-iteration augmented solves vs converged ones (2D n=2048, zeta=100)", "rows": rows}
+
+
 def cpu_baseline():
     """The oracle, as it stands, on a bounded sample of the same workload family: the same
     problem (zeta = 100, W = x^2 + y^2, coarsest h = 1/16, same schedule and tolerance)
@@ -251,7 +264,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a cold plain copy of known size (memory-counter scaling)")
-    ap.add_argument("--workload", choices=["fmg2d", "batch", "serve"], default="fmg2d",
+    ap.add_argument("--workload", choices=["fmg2d", "batch", "serve", "omega"], default="fmg2d",
                     help="fmg2d: the default line; batch / serve: the batched and serving workloads")
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget of the server")
@@ -277,6 +290,9 @@ def main():
     gpath = os.path.join(ROOT, "tests", "golden", "large_2d.json")
     if os.path.exists(gpath):
         lam_ref = json.load(open(gpath))["large_2d"]["lambda_ref"]
+    if args.workload == "omega":
+        print(json.dumps(bench_omega(args.steps, args.warmup, lam_ref)))
+        return
 
     print(f"bench: FP64 {args.warmup}+{args.steps} solves, n={prob.n_fine}", file=sys.stderr, flush=True)
     res, u, total, lat = time_solves(prob, W.Options(tol_lambda=TOL), args.steps, args.warmup)

@@ -76,7 +76,11 @@ typedef struct {
     int32_t precision;    /* FMG_FP64, or FMG_MIXED: FP32 V-cycles inside an FP64          */
                           /* iterative-refinement loop (residual, quadratures, Rayleigh   */
                           /* quotient and the small eigensolves stay FP64)                */
-    int32_t reserved;
+    int32_t newton_fixed_iters; /* 0: every augmented problem (3.6) is solved to          */
+                          /* newton_tol; k > 0: exactly k nonlinear iterations per        */
+                          /* augmented problem, accepted without a residual test (the     */
+                          /* fixed-iteration-count variant of Section 3.3; the coarse     */
+                          /* problem of Algorithm 3.2 step 1 is still solved to newton_tol)*/
 } fmg_options;
 
 #define FMG_HISTORY_MAX 512

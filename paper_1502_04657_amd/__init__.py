@@ -53,6 +53,7 @@ def to_c_options(o) -> fmg_options:
     co.newton_max_iter = int(getattr(o, "newton_max_iter", 40))
     co.newton_tol = float(getattr(o, "scf_tol", 1e-13))
     co.precision = FMG_MIXED if o.precision == "mixed" else FMG_FP64
+    co.newton_fixed_iters = int(getattr(o, "newton_fixed_iters", 0))
     return co
 
 

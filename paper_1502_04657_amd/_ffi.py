@@ -21,7 +21,7 @@ class fmg_problem(C.Structure):
 class fmg_options(C.Structure):
     _fields_ = [("tol_lambda", C.c_double), ("m", C.c_int32), ("p", C.c_int32), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("max_final_steps", C.c_int32), ("newton_max_iter", C.c_int32),
-                ("newton_tol", C.c_double), ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("newton_tol", C.c_double), ("precision", C.c_int32), ("newton_fixed_iters", C.c_int32)]
 
 
 class fmg_kernel_profile(C.Structure):

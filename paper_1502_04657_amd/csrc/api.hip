@@ -71,6 +71,8 @@ int check_options(const fmg_options* o) {
     if (o->max_final_steps < 0) return set_error(FMG_EINVAL, "max_final_steps must be >= 0");
     if (o->newton_max_iter < 1) return set_error(FMG_EINVAL, "newton_max_iter must be >= 1");
     if (!(o->newton_tol > 0.0)) return set_error(FMG_EINVAL, "newton_tol must be > 0");
+    if (o->newton_fixed_iters < 0 || o->newton_fixed_iters > o->newton_max_iter)
+        return set_error(FMG_EINVAL, "newton_fixed_iters must be in [0, newton_max_iter]");
     if (o->precision != FMG_FP64 && o->precision != FMG_MIXED) return set_error(FMG_EINVAL, "precision invalid");
     return 0;
 }
@@ -176,7 +178,8 @@ static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, 
     // (3.6): augmented nonlinear eigenproblem on V_H + span{u~}
     double* mom = at<double>(ws, lo.mom);
     launch_moments(lo.dim, lo.nc, g, ph, u, at<double>(ws, lo.momscr), mom, s);
-    int rc = launch_aug_newton(lo.dim, lo.nc, ph, opt->newton_max_iter, opt->newton_tol, mom, at<double>(ws, lo.arena),
+    int rc = launch_aug_newton(lo.dim, lo.nc, ph, opt->newton_max_iter, opt->newton_fixed_iters, opt->newton_tol, mom,
+                               at<double>(ws, lo.arena),
                                at<double>(ws, lo.fac), at<double>(ws, lo.xc), st, final_flag, certify, 1, s);
     if (rc) return set_error(rc, "augmented solve launch failed");
     launch_form_u(g, lo.g[0], u, at<double>(ws, lo.xc), &st->c, s);
@@ -541,7 +544,8 @@ static int small_common(const fmg_problem* prob, const fmg_options* opt, double*
     double* arena = at<double>(scratch, align256(sizeof(SmallState)));
     double* fac = at<double>(scratch, align256(sizeof(SmallState)) + align256(small_arena_bytes(prob->dim, prob->n_coarse)));
     FMG_HIP_CHECK(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    int rc = aug ? launch_aug_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter, opt->newton_tol,
+    int rc = aug ? launch_aug_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter,
+                                     opt->newton_fixed_iters, opt->newton_tol,
                                      mom, arena, fac, xc, st, 0, 1, 0, s)
                  : launch_coarse_newton(prob->dim, prob->n_coarse, make_phys(prob), opt->newton_max_iter,
                                         opt->newton_tol, arena, fac, xc, st, s);

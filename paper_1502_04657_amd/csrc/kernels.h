@@ -87,7 +87,8 @@ int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double t
 // c into state->c, lambda into state (history appended, tolerance flag updated).
 // certify: ground-state inertia check (0 never, 1 always, 2 only when the step meets the
 // lambda tolerance); reuse: start from the stored factor.
-int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments,
+// fixed_iters > 0: accept the iterate after exactly that many iterations (no residual test)
+int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, int fixed_iters, double tol, const double* moments,
                       double* arena, double* fac, double* xc_level, SmallState* state, int final_level,
                       int certify, int reuse, hipStream_t s);
 // Dense augmented matrices A, B, S(x) (row-major (N+1)^2 each) for tests.

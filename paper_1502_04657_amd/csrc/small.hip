@@ -141,6 +141,7 @@ struct Args {
     int nc;
     Phys ph;
     int max_iter;
+    int fixed_iters;     // augmented solve: > 0 accepts the iterate after that many iterations
     double tol;
     const double* mom;
     double* arena;       // global arena (used when the problem does not fit in LDS)
@@ -1247,7 +1248,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         // x^T B x = 1 up to the rounding of an N-term dot product; an intermediate stage of
         // the coarse continuation (tol above the requested one) only needs tol
         const double f2_tol = tol > a.tol ? tol : 4.0 * N1 * 1.1e-16;
-        if (res <= tol && fabs(F2) <= f2_tol) {
+        if ((res <= tol && fabs(F2) <= f2_tol) || (AUG && a.fixed_iters > 0 && it == a.fixed_iters)) {
             const double sN = 1.0 / sqrt(ar.sc[5]);
             for (int i = tid; i < N1; i += kThreads) ar.x[i] *= sN;
             if (tid == 0) ar.sc[6] = mu;
@@ -1733,11 +1734,13 @@ int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double t
                                   : launch_small(k_newton<3, false, true, false>, k_newton<3, false, false, false>, b, a, s);
 }
 
-int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, double tol, const double* moments, double* arena,
+int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, int fixed_iters, double tol, const double* moments,
+                      double* arena,
                       double* fac, double* xc_level, SmallState* state, int final_level, int certify, int reuse,
                       hipStream_t s) {
     Args a{};
-    a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.tol = tol; a.mom = moments; a.arena = arena;
+    a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.fixed_iters = fixed_iters; a.tol = tol; a.mom = moments;
+    a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = final_level;
     a.certify = certify; a.fac = fac; a.reuse = reuse;
     if (dim == 2) {

@@ -57,6 +57,11 @@ def test_workspace_bytes_and_validation(lib):
     assert lib.fmg_workspace_bytes(C.byref(bad), C.byref(o), C.byref(n)) == -1
     bad_o = to_c_options(W.Options(m=0))
     assert lib.fmg_workspace_bytes(C.byref(p), C.byref(bad_o), C.byref(n)) == -1
+    bad_o = to_c_options(W.Options(newton_fixed_iters=-1))
+    assert lib.fmg_workspace_bytes(C.byref(p), C.byref(bad_o), C.byref(n)) == -1
+    bad_o = to_c_options(W.Options(newton_fixed_iters=1000))
+    assert lib.fmg_workspace_bytes(C.byref(p), C.byref(bad_o), C.byref(n)) == -1
+    assert b"newton_fixed_iters" in lib.fmg_last_error()
 
 
 def test_level_layout(lib):

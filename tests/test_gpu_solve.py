@@ -93,3 +93,20 @@ def test_solve_reports_nonconvergence_cap():
     with pytest.raises(FmgError) as e:
         s.solve()
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("fixed", [1, 2, 3])
+def test_fixed_iteration_count_variant_reaches_the_same_solution(fixed):
+    # a fixed number of nonlinear iterations per augmented problem (Section 3.3) changes
+    # the iterates but not the fixed point of Algorithm 3.1, where u~ already solves (3.6)
+    rec = GOLD["small_2d_z100"]
+    prob = _problem(rec)
+    conv, _ = _solve(prob, W.Options(tol_lambda=1e-13, max_final_steps=200))
+    res, u = _solve(prob, W.Options(tol_lambda=1e-13, max_final_steps=200, newton_fixed_iters=fixed))
+    assert res.status == 0
+    assert res.lam == pytest.approx(rec["lambda_ref"], rel=1e-10)
+    h = oracle_hierarchy(prob)
+    M = h.M[h.L - 1]
+    d = u.cpu().numpy() - np.asarray(rec["u_ref"])
+    assert math.sqrt(d @ (M @ d)) < 1e-8
+    assert res.newton_total < conv.newton_total
