@@ -5,7 +5,8 @@ Readings of the paper used here (each is also stated where the HIP library imple
   * V_H = V_{h_1}: the coarse space of every augmented problem is the coarsest level.
   * The auxiliary problem (3.4) uses a-hat only (the stiffness matrix K); W and the cubic
     term sit in the right-hand side  b = lambda M u - M_W u - zeta N(u),  N(u)_a = int u^3 phi_a.
-  * MG(V_k, b, u, m) is m red-black SGS V(nu_pre, nu_post)-cycles (see mg.py).
+  * MG(V_k, b, u, m) is m V(nu_pre, nu_post)-cycles with red-black SGS smoothing, or with
+    nu CG steps as the smoother (opts.smoother = "cg", the paper's experiments; see mg.py).
   * The basis of V_{H,h_k} is Z = [Pi_k, u~]: the coarsest hat functions written on level
     k (the composite P1 interpolation Pi_k) and u~; the augmented Newton starts from u = u~
     normalised.
@@ -105,7 +106,7 @@ def augmented_solve(h: Hierarchy, l: int, ut: np.ndarray):
 def correction_step(h: Hierarchy, l: int, lam: float, u: np.ndarray, opts):
     """(lambda, u) <- EigenMG(V_H, lambda, u, V_l, m): Algorithm 3.1."""
     b = h.rhs(l, lam, u)
-    ut = h.mg.mg(l, b, u, opts.m, opts.nu_pre, opts.nu_post)
+    ut = h.mg.mg(l, b, u, opts.m, opts.nu_pre, opts.nu_post, getattr(opts, "smoother", "sgs"))
     mu, unew, it, _ = augmented_solve(h, l, ut)
     return mu, h.fix_sign(l, unew), it
 

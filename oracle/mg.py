@@ -5,10 +5,12 @@ The paper leaves the cycle and the smoother open (its experiments use 3 CG smoot
 steps).  The reading implemented here, shared with the HIP library by specification
 only: a V(nu_pre, nu_post) cycle whose smoother is symmetric Gauss-Seidel in red-black
 order (red = (i+j[+k]) even): one SGS sweep is a forward pass (red, then black) followed
-by a backward pass (black, then red).  Level operators are the rediscretised stiffness
-matrices (equal to the Galerkin products P^T K P, checked in the tests), transfers are
-P1 interpolation and its transpose, and the coarsest level is solved exactly (dense
-Cholesky).  There is no damping.
+by a backward pass (black, then red).  The smoother of the paper's experiments is
+available too: nu_pre / nu_post steps of the plain conjugate gradient method on K_l x = f
+started from the current x (the cycle is then a nonlinear, variable preconditioner).
+Level operators are the rediscretised stiffness matrices (equal to the Galerkin products
+P^T K P, checked in the tests), transfers are P1 interpolation and its transpose, and the
+coarsest level is solved exactly (dense Cholesky).  There is no damping.
 """
 from __future__ import annotations
 
@@ -48,6 +50,33 @@ def sgs_sweep(lv: Level, x, f) -> None:
     gs_half_sweep(lv, x, f, lv.red)
 
 
+def cg_steps(lv: Level, x: np.ndarray, f: np.ndarray, steps: int) -> None:
+    """`steps` iterations of the conjugate gradient method for K x = f from x (in place):
+    r = f - K x, p = r; per step q = K p, alpha = (r.r)/(p.q), x += alpha p,
+    r -= alpha q, beta = (r'.r')/(r.r), p = r' + beta p.  Stops early on r = 0."""
+    r = f - lv.K @ x
+    p = r.copy()
+    rr = float(r @ r)
+    for _ in range(steps):
+        if rr == 0.0:
+            return
+        q = lv.K @ p
+        alpha = rr / float(p @ q)
+        x += alpha * p
+        r -= alpha * q
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+
+
+def smooth(lv: Level, x, f, nu: int, smoother: str) -> None:
+    if smoother == "cg":
+        cg_steps(lv, x, f, nu)
+        return
+    for _ in range(nu):
+        sgs_sweep(lv, x, f)
+
+
 def gs_sequential(K: sp.csr_matrix, x, f, order) -> None:
     """Textbook Gauss-Seidel visiting the dofs one by one in the given order (tiny cases)."""
     Kd = K.toarray()
@@ -69,25 +98,25 @@ class MGHierarchy:
     def coarse_solve(self, f):
         return sla.cho_solve(self.coarse_chol, f)
 
-    def vcycle(self, l: int, x: np.ndarray, f: np.ndarray, nu_pre: int, nu_post: int) -> np.ndarray:
+    def vcycle(self, l: int, x: np.ndarray, f: np.ndarray, nu_pre: int, nu_post: int,
+               smoother: str = "sgs") -> np.ndarray:
         """One V(nu_pre, nu_post) cycle for K_l x = f; returns the new x."""
         if l == 0:
             return self.coarse_solve(f)
         lv = self.levels[l]
         x = x.copy()
-        for _ in range(nu_pre):
-            sgs_sweep(lv, x, f)
+        smooth(lv, x, f, nu_pre, smoother)
         r = f - lv.K @ x
         rc = self.P[l].T @ r
-        ec = self.vcycle(l - 1, np.zeros_like(rc), rc, nu_pre, nu_post)
+        ec = self.vcycle(l - 1, np.zeros_like(rc), rc, nu_pre, nu_post, smoother)
         x += self.P[l] @ ec
-        for _ in range(nu_post):
-            sgs_sweep(lv, x, f)
+        smooth(lv, x, f, nu_post, smoother)
         return x
 
-    def mg(self, l: int, f: np.ndarray, x0: np.ndarray, m: int, nu_pre: int, nu_post: int):
+    def mg(self, l: int, f: np.ndarray, x0: np.ndarray, m: int, nu_pre: int, nu_post: int,
+           smoother: str = "sgs"):
         """MG(V_l, f, x0, m) of (3.5): m V-cycles started from x0."""
         x = x0
         for _ in range(m):
-            x = self.vcycle(l, x, f, nu_pre, nu_post)
+            x = self.vcycle(l, x, f, nu_pre, nu_post, smoother)
         return x

@@ -89,3 +89,40 @@ def test_coarse_solve_is_exact():
     K0 = H.levels[0].K
     f = np.random.default_rng(4).standard_normal(K0.shape[0])
     assert np.allclose(K0 @ H.coarse_solve(f), f, rtol=1e-13, atol=1e-13)
+
+
+def test_cg_smoother_is_the_conjugate_gradient_method():
+    # pinned against scipy's CG (same iterates in exact arithmetic) and against CG's finite
+    # termination on a small SPD system
+    import scipy.sparse.linalg as spla
+    from oracle.mg import MGHierarchy, cg_steps
+    h = MGHierarchy(2, 4, 2)
+    lv = h.levels[1]
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(lv.K.shape[0])
+    x0 = rng.standard_normal(lv.K.shape[0])
+    for k in (1, 2, 3):
+        x = x0.copy()
+        cg_steps(lv, x, f, k)
+        ref, _ = spla.cg(lv.K, f, x0=x0.copy(), rtol=0.0, atol=0.0, maxiter=k)
+        assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+    x = x0.copy()
+    cg_steps(lv, x, f, lv.K.shape[0])
+    assert np.abs(lv.K @ x - f).max() <= 1e-9 * np.abs(f).max()
+
+
+def test_cg_smoothed_vcycle_contracts():
+    from oracle.mg import MGHierarchy
+    h = MGHierarchy(3, 2, 3)
+    l = 2
+    K = h.levels[l].K
+    rng = np.random.default_rng(4)
+    xs = rng.standard_normal(K.shape[0])
+    f = K @ xs
+    x = np.zeros_like(f)
+    errs = []
+    for _ in range(4):
+        x = h.vcycle(l, x, f, 3, 3, "cg")
+        errs.append(np.linalg.norm(x - xs))
+    assert errs[-1] < 1e-3 * np.linalg.norm(xs)
+    assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))

@@ -59,6 +59,7 @@ class Options:
     scf_tol: float = 1e-13
     precision: str = "fp64"    # "fp64" or "mixed" (FP32 V-cycle inside FP64 refinement)
     newton_fixed_iters: int = 0  # >0: that many nonlinear iterations per augmented solve (GPU library)
+    smoother: str = "sgs"      # "sgs": red-black symmetric Gauss-Seidel sweeps; "cg": CG steps
 
 
 # --- fixed workloads --------------------------------------------------------------------
