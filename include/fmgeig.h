@@ -48,6 +48,7 @@ enum {
 };
 
 enum { FMG_FP64 = 0, FMG_MIXED = 1 };
+enum { FMG_SMOOTH_SGS = 0, FMG_SMOOTH_CG = 1 };
 
 /* The problem of Example 4.1 generalised to dim = 2, 3 and an anisotropic harmonic W.
  * (2.1), (4.1); the mesh sequence of (3.1)-(3.2).                                      */
@@ -81,6 +82,10 @@ typedef struct {
                           /* augmented problem, accepted without a residual test (the     */
                           /* fixed-iteration-count variant of Section 3.3; the coarse     */
                           /* problem of Algorithm 3.2 step 1 is still solved to newton_tol)*/
+    int32_t smoother;     /* FMG_SMOOTH_SGS: nu red-black symmetric Gauss-Seidel sweeps;   */
+                          /* FMG_SMOOTH_CG: nu conjugate-gradient steps on K x = f (the     */
+                          /* smoother of the paper's experiments, Section 4)              */
+    int32_t reserved;
 } fmg_options;
 
 #define FMG_HISTORY_MAX 512
@@ -228,6 +233,14 @@ int fmg_op_rhs(const fmg_problem* prob, int32_t n, double lambda, const double* 
  * FMG_FP64 (double*) or FMG_MIXED meaning FP32 (float* passed as void*).                 */
 int fmg_op_smooth(int32_t dim, int32_t n, int32_t precision, void* d_x, const void* d_f,
                   int32_t sweeps, void* stream);
+
+/* `steps` iterations of the conjugate gradient method on K x = f started from x (the
+ * smoother of the paper's experiments, Section 4): r = f - K x, p = r; per step q = K p,
+ * alpha = r.r / p.q, x += alpha p, r -= alpha q, p = r + (r'.r' / r.r) p.  Dot products in
+ * FP64 with a fixed summation order.  d_scratch: device, 256-B aligned, at least
+ * 3 * round256(s * fmg_level_elems(dim, n)) + 8 * (512 + 8) bytes, s = 8 (FMG_FP64) or 4. */
+int fmg_op_cg_smooth(int32_t dim, int32_t n, int32_t precision, void* d_x, const void* d_f,
+                     int32_t steps, void* d_scratch, size_t scratch_bytes, void* stream);
 
 /* r_c = P^T (f - K x): residual of the fine level (n cells) restricted to level n/2.      */
 int fmg_op_residual_restrict(int32_t dim, int32_t n, int32_t precision, const void* d_x,

@@ -54,6 +54,7 @@ def to_c_options(o) -> fmg_options:
     co.newton_tol = float(getattr(o, "scf_tol", 1e-13))
     co.precision = FMG_MIXED if o.precision == "mixed" else FMG_FP64
     co.newton_fixed_iters = int(getattr(o, "newton_fixed_iters", 0))
+    co.smoother = _ffi.FMG_SMOOTH_CG if getattr(o, "smoother", "sgs") == "cg" else _ffi.FMG_SMOOTH_SGS
     return co
 
 

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libfmgeig.so")
 FMG_OK, FMG_PENDING = 0, 1
 FMG_EINVAL, FMG_ENOMEM, FMG_ENOCONV, FMG_ENONFINITE, FMG_EHIP = -1, -2, -3, -4, -5
 FMG_FP64, FMG_MIXED = 0, 1
+FMG_SMOOTH_SGS, FMG_SMOOTH_CG = 0, 1
 HISTORY_MAX = 512
 
 
@@ -21,7 +22,8 @@ class fmg_problem(C.Structure):
 class fmg_options(C.Structure):
     _fields_ = [("tol_lambda", C.c_double), ("m", C.c_int32), ("p", C.c_int32), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("max_final_steps", C.c_int32), ("newton_max_iter", C.c_int32),
-                ("newton_tol", C.c_double), ("precision", C.c_int32), ("newton_fixed_iters", C.c_int32)]
+                ("newton_tol", C.c_double), ("precision", C.c_int32), ("newton_fixed_iters", C.c_int32),
+                ("smoother", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fmg_kernel_profile(C.Structure):
@@ -67,6 +69,7 @@ SIGNATURES = {
     "fmg_unpack": (C.c_int, [I32, I32, P, P, P]),
     "fmg_op_rhs": (C.c_int, [P, I32, D, P, P, P]),
     "fmg_op_smooth": (C.c_int, [I32, I32, I32, P, P, I32, P]),
+    "fmg_op_cg_smooth": (C.c_int, [I32, I32, I32, P, P, I32, P, SZ, P]),
     "fmg_op_residual_restrict": (C.c_int, [I32, I32, I32, P, P, P, P]),
     "fmg_op_prolong": (C.c_int, [I32, I32, I32, P, P, I32, P]),
     "fmg_op_coarse_solve": (C.c_int, [I32, I32, I32, P, P, P]),

@@ -74,14 +74,15 @@ int check_options(const fmg_options* o) {
     if (o->newton_fixed_iters < 0 || o->newton_fixed_iters > o->newton_max_iter)
         return set_error(FMG_EINVAL, "newton_fixed_iters must be in [0, newton_max_iter]");
     if (o->precision != FMG_FP64 && o->precision != FMG_MIXED) return set_error(FMG_EINVAL, "precision invalid");
+    if (o->smoother != FMG_SMOOTH_SGS && o->smoother != FMG_SMOOTH_CG) return set_error(FMG_EINVAL, "smoother invalid");
     return 0;
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-Layout make_layout(int dim, int nc, int levels, int mixed) {
+Layout make_layout(int dim, int nc, int levels, int mixed, int cg) {
     Layout lo;
-    lo.dim = dim; lo.nc = nc; lo.L = levels; lo.mixed = mixed;
+    lo.dim = dim; lo.nc = nc; lo.L = levels; lo.mixed = mixed; lo.cg = cg;
     for (int l = 0; l < levels; ++l) lo.g.push_back(make_grid(dim, nc << l));
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
@@ -99,6 +100,13 @@ Layout make_layout(int dim, int nc, int levels, int mixed) {
         // the fused passes run in the V-cycle precision; the coarsest level needs none
         lo.tv[l] = (dim == 2 && l > 0) ? take(ts * lo.g[l].elems) : 0;
     }
+    if (cg) {
+        // CG smoothing: r, p, q sized for the finest level (zero rings: inside the zeroed range)
+        const size_t e = ts * lo.g[levels - 1].elems;
+        lo.cgr = take(e);
+        lo.cgp = take(e);
+        lo.cgq = take(e);
+    }
     const int64_t ncell = dim == 2 ? (int64_t)nc * nc : (int64_t)nc * nc * nc;
     const int ne = dim == 2 ? 2 : 6;
     lo.mom = take(sizeof(double) * ncell * ne * moments_per_element(dim));
@@ -108,8 +116,13 @@ Layout make_layout(int dim, int nc, int levels, int mixed) {
     lo.arena = take(small_arena_bytes(dim, nc));
     lo.fac = take(small_factor_bytes(dim, nc));
     lo.forms = take(sizeof(double) * (kReduceBlocks * 4 + 8));
+    if (cg) lo.cgsc = take(sizeof(double) * (kReduceBlocks + 8));   // partials, then 4 scalars
     lo.total = off;
     return lo;
+}
+
+Layout layout_for(const fmg_problem* p, const fmg_options* o) {
+    return make_layout(p->dim, p->n_coarse, p->n_refine + 1, o->precision == FMG_MIXED, o->smoother == FMG_SMOOTH_CG);
 }
 
 template <typename T>
@@ -128,7 +141,7 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
     }
     T* xc = at<T>(ws, lo.xv[l - 1]);
     T* fc = at<T>(ws, lo.fv[l - 1]);
-    if (lo.dim == 2 && nu_pre <= 2 && nu_post <= 2 && g_fused) {
+    if (lo.dim == 2 && nu_pre <= 2 && nu_post <= 2 && g_fused && !lo.cg) {
         T* y = at<T>(ws, lo.tv[l]);
         launch_vpre2d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
         vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
@@ -144,13 +157,24 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
         }
         return;
     }
+    // unfused: red-black SGS (nu sweeps = 2 nu + 1 half sweeps) or nu CG steps
+    auto smooth = [&](int nu) {
+        if (nu <= 0) return;
+        if (lo.cg) {
+            double* part = at<double>(ws, lo.cgsc);
+            launch_cg_smooth<T>(g, x, f, nu, at<T>(ws, lo.cgr), at<T>(ws, lo.cgp), at<T>(ws, lo.cgq), part,
+                                part + kReduceBlocks, s);
+        } else {
+            launch_smooth<T>(g, x, f, 2 * nu + 1, 0, s);
+        }
+    };
     if (zero_x) launch_fill<T>(x, g.elems, T(0), s);
-    if (nu_pre > 0) launch_smooth<T>(g, x, f, 2 * nu_pre + 1, 0, s);
+    smooth(nu_pre);
     launch_resid_restrict<T>(g, lo.g[l - 1], x, f, fc, s);
     launch_fill<T>(xc, lo.g[l - 1].elems, T(0), s);
     vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s);
     launch_prolong<T>(lo.g[l - 1], g, xc, x, 1, s);
-    if (nu_post > 0) launch_smooth<T>(g, x, f, 2 * nu_post + 1, 0, s);
+    smooth(nu_post);
 }
 
 // one correction step (Algorithm 3.1) on level k
@@ -363,7 +387,7 @@ int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t*
     if (int rc = check_problem(prob)) return rc;
     if (int rc = check_options(opt)) return rc;
     if (!bytes) return set_error(FMG_EINVAL, "bytes is NULL");
-    Layout lo = make_layout(prob->dim, prob->n_coarse, prob->n_refine + 1, opt->precision == FMG_MIXED);
+    Layout lo = layout_for(prob, opt);
     *bytes = lo.total;
     return 0;
 }
@@ -382,7 +406,7 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     SolveJob j;
     j.prob = *prob;
     j.opt = *opt;
-    j.lo = make_layout(prob->dim, prob->n_coarse, prob->n_refine + 1, opt->precision == FMG_MIXED);
+    j.lo = layout_for(prob, opt);
     if (ws_bytes < j.lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, j.lo.total);
     JobHost host;
     j.ws = ws;
@@ -433,6 +457,30 @@ int fmg_op_smooth(int32_t dim, int32_t n, int32_t precision, void* x, const void
     return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "smooth launch failed");
 }
 
+int fmg_op_cg_smooth(int32_t dim, int32_t n, int32_t precision, void* x, const void* f, int32_t steps, void* scratch,
+                     size_t scratch_bytes, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 2 || steps < 0 || !x || !f || !scratch)
+        return set_error(FMG_EINVAL, "bad CG smoothing arguments");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256) return set_error(FMG_EINVAL, "scratch must be 256-byte aligned");
+    Grid g = make_grid(dim, n);
+    const size_t ts = precision == FMG_MIXED ? sizeof(float) : sizeof(double);
+    const size_t e = align256(ts * g.elems);
+    if (scratch_bytes < 3 * e + sizeof(double) * (kReduceBlocks + 8))
+        return set_error(FMG_ENOMEM, "scratch %zu < %zu bytes", scratch_bytes, 3 * e + sizeof(double) * (kReduceBlocks + 8));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* b = static_cast<char*>(scratch);
+    double* part = reinterpret_cast<double*>(b + 3 * e);
+    if (precision == FMG_MIXED)
+        launch_cg_smooth<float>(g, static_cast<float*>(x), static_cast<const float*>(f), steps, reinterpret_cast<float*>(b),
+                                reinterpret_cast<float*>(b + e), reinterpret_cast<float*>(b + 2 * e), part,
+                                part + kReduceBlocks, s);
+    else
+        launch_cg_smooth<double>(g, static_cast<double*>(x), static_cast<const double*>(f), steps,
+                                 reinterpret_cast<double*>(b), reinterpret_cast<double*>(b + e),
+                                 reinterpret_cast<double*>(b + 2 * e), part, part + kReduceBlocks, s);
+    return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "CG smoothing launch failed");
+}
+
 int fmg_op_residual_restrict(int32_t dim, int32_t n, int32_t precision, const void* x, const void* f, void* rc,
                              void* stream) {
     if ((dim != 2 && dim != 3) || n < 4 || (n & 1) || !x || !f || !rc) return set_error(FMG_EINVAL, "bad restrict arguments");
@@ -477,7 +525,7 @@ int fmg_op_vcycle(int32_t dim, int32_t n_coarse, int32_t levels, int32_t nu_pre,
     p.dim = dim; p.n_coarse = n_coarse; p.n_refine = levels - 1;
     if (int rc = check_problem(&p)) return rc;
     if (nu_pre < 0 || nu_post < 0 || !x || !f || !ws) return set_error(FMG_EINVAL, "bad vcycle arguments");
-    Layout lo = make_layout(dim, n_coarse, levels, 0);
+    Layout lo = make_layout(dim, n_coarse, levels, 0, 0);
     if (ws_bytes < lo.total) return set_error(FMG_ENOMEM, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int l = 0; l < levels; ++l) {

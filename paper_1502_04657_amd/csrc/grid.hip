@@ -533,12 +533,25 @@ __global__ __launch_bounds__(256) void k_forms(const double* __restrict__ u, Gri
     }
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partial, int nblk, int width, double* __restrict__ out) {
-    // one block; thread q sums column q in index order
-    for (int q = threadIdx.x; q < width; q += blockDim.x) {
-        double v = 0.0;
-        for (int b = 0; b < nblk; ++b) v += partial[b * width + q];
-        out[q] = v;
+// fixed-order sum of nblk partials (stride width, column q) by one 256-thread block:
+// thread t adds rows t, t + 256, ...; then the wavefront tree and the 4 wavefronts in order
+__device__ double block_sum_partials(const double* __restrict__ partial, int nblk, int width, int q) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[b * width + q];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int nblk, int width,
+                                                      double* __restrict__ out) {
+    for (int q = 0; q < width; ++q) {
+        const double v = block_sum_partials(partial, nblk, width, q);
+        if (threadIdx.x == 0) out[q] = v;
     }
 }
 
@@ -547,7 +560,172 @@ void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partia
         hipLaunchKernelGGL(k_forms<2>, dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, partial);
     else
         hipLaunchKernelGGL(k_forms<3>, dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partial, kReduceBlocks, 4, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, kReduceBlocks, 4, out);
 }
+
+// ------------------------------------------------------------------------------------------
+// Conjugate-gradient smoothing (the smoother of the paper's experiments): `steps`
+// iterations of CG on K x = f from the current x.  r, p, q are level arrays with zero
+// rings; sc holds (r.r, p.q, alpha, beta) in FP64.  Dot products are block partials in a
+// fixed grid added in a fixed order (deterministic); alpha and beta are formed on the
+// device, so the host only enqueues.  rr = 0 makes alpha = beta = 0 (x stays put, as an
+// exact solve would leave it).
+template <int D, typename T>
+__device__ inline T apply_K(const T* __restrict__ x, int64_t q, int64_t P, int64_t S, T h) {
+    if (D == 2) return T(4) * x[q] - ((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P]));
+    return h * (T(6) * x[q] - (((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P])) + (x[q - S] + x[q + S])));
+}
+
+template <int D>
+__device__ inline int64_t interior_node(const Grid& g, int64_t t) {
+    const int m = g.n - 1;
+    const int i = (int)(t % m) + 1;
+    const int64_t r = t / m;
+    const int j = (int)(r % m) + 1, k = (D == 3) ? (int)(r / m) + 1 : 0;
+    return i + g.pitch * j + g.plane * k;
+}
+
+__device__ inline void block_partial(double v, double* __restrict__ partial) {
+    __shared__ double red[4];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+#define CG_NODES(D, g)                                                                                   \
+    const int64_t total_ = (D == 2) ? (int64_t)((g).n - 1) * ((g).n - 1)                                 \
+                                    : (int64_t)((g).n - 1) * ((g).n - 1) * ((g).n - 1);                  \
+    for (int64_t t_ = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t_ < total_;                       \
+         t_ += (int64_t)gridDim.x * blockDim.x)
+
+// zero the Dirichlet ring of a level array (the CG scratch arrays serve several levels, so
+// their ring positions for this level may hold values of another level's layout)
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_zero_ring(T* __restrict__ a, Grid g) {
+    const int n = g.n, w = n + 1;
+    const int64_t per = (D == 2) ? (int64_t)w : (int64_t)w * w;
+    const int64_t total = per * (2 * D);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int face = (int)(t / per);
+        const int64_t rem = t - face * per;
+        const int u = (int)(rem % w), v = (D == 3) ? (int)(rem / w) : 0;
+        const int side = (face & 1) ? n : 0, axis = face >> 1;
+        int c[3] = {u, v, 0};
+        if (D == 2) {
+            c[0] = axis == 0 ? side : u;
+            c[1] = axis == 0 ? u : side;
+        } else {
+            c[0] = axis == 0 ? side : u;
+            c[1] = axis == 1 ? side : (axis == 0 ? u : v);
+            c[2] = axis == 2 ? side : v;
+        }
+        a[c[0] + g.pitch * c[1] + g.plane * c[2]] = T(0);
+    }
+}
+
+// r = f - K x, p = r; partial r.r
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_start(const T* __restrict__ x, const T* __restrict__ f, T* __restrict__ r,
+                                                  T* __restrict__ p, Grid g, double* __restrict__ partial) {
+    double acc = 0.0;
+    CG_NODES(D, g) {
+        const int64_t q = interior_node<D>(g, t_);
+        const T v = resid_at<D, T>(x, f, q, g.pitch, g.plane, T(g.h));
+        r[q] = v;
+        p[q] = v;
+        acc += (double)v * (double)v;
+    }
+    block_partial(acc, partial);
+}
+
+// q = K p; partial p.q
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_apply(const T* __restrict__ p, T* __restrict__ qv, Grid g,
+                                                  double* __restrict__ partial) {
+    double acc = 0.0;
+    CG_NODES(D, g) {
+        const int64_t q = interior_node<D>(g, t_);
+        const T v = apply_K<D, T>(p, q, g.pitch, g.plane, T(g.h));
+        qv[q] = v;
+        acc += (double)p[q] * (double)v;
+    }
+    block_partial(acc, partial);
+}
+
+// x += alpha p, r -= alpha q; partial r.r
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                   const T* __restrict__ qv, Grid g, const double* __restrict__ sc,
+                                                   double* __restrict__ partial) {
+    const T alpha = T(sc[2]);
+    double acc = 0.0;
+    CG_NODES(D, g) {
+        const int64_t q = interior_node<D>(g, t_);
+        x[q] += alpha * p[q];
+        const T v = r[q] - alpha * qv[q];
+        r[q] = v;
+        acc += (double)v * (double)v;
+    }
+    block_partial(acc, partial);
+}
+
+// p = r + beta p
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_direction(const T* __restrict__ r, T* __restrict__ p, Grid g,
+                                                      const double* __restrict__ sc) {
+    const T beta = T(sc[3]);
+    CG_NODES(D, g) {
+        const int64_t q = interior_node<D>(g, t_);
+        p[q] = r[q] + beta * p[q];
+    }
+}
+#undef CG_NODES
+
+// stage 0: sc[0] = r.r; 1: sc[1] = p.q, alpha = r.r / p.q; 2: beta = r'.r' / r.r, sc[0] = r'.r'
+__global__ __launch_bounds__(256) void k_cg_scalars(const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ sc, int stage) {
+    const double v = block_sum_partials(partial, nblk, 1, 0);
+    if (threadIdx.x != 0) return;
+    if (stage == 0) {
+        sc[0] = v;
+    } else if (stage == 1) {
+        sc[1] = v;
+        sc[2] = (sc[0] == 0.0) ? 0.0 : sc[0] / v;
+    } else {
+        sc[3] = (sc[0] == 0.0) ? 0.0 : v / sc[0];
+        sc[0] = v;
+    }
+}
+
+template <typename T>
+void launch_cg_smooth(const Grid& g, T* x, const T* f, int steps, T* r, T* p, T* q, double* partial, double* sc,
+                      hipStream_t s) {
+    if (steps <= 0 || g.n < 2) return;
+    const dim3 grd(kReduceBlocks), blk(256);
+    if (g.dim == 2) {
+        hipLaunchKernelGGL((k_zero_ring<2, T>), dim3(cdiv(4 * (int64_t)(g.n + 1), 256)), blk, 0, s, p, g);
+        hipLaunchKernelGGL((k_cg_start<2, T>), grd, blk, 0, s, x, f, r, p, g, partial);
+    } else {
+        hipLaunchKernelGGL((k_zero_ring<3, T>), dim3(cdiv(6 * (int64_t)(g.n + 1) * (g.n + 1), 256)), blk, 0, s, p, g);
+        hipLaunchKernelGGL((k_cg_start<3, T>), grd, blk, 0, s, x, f, r, p, g, partial);
+    }
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), blk, 0, s, partial, kReduceBlocks, sc, 0);
+    for (int it = 0; it < steps; ++it) {
+        if (g.dim == 2) hipLaunchKernelGGL((k_cg_apply<2, T>), grd, blk, 0, s, p, q, g, partial);
+        else hipLaunchKernelGGL((k_cg_apply<3, T>), grd, blk, 0, s, p, q, g, partial);
+        hipLaunchKernelGGL(k_cg_scalars, dim3(1), blk, 0, s, partial, kReduceBlocks, sc, 1);
+        if (g.dim == 2) hipLaunchKernelGGL((k_cg_update<2, T>), grd, blk, 0, s, x, r, p, q, g, sc, partial);
+        else hipLaunchKernelGGL((k_cg_update<3, T>), grd, blk, 0, s, x, r, p, q, g, sc, partial);
+        if (it + 1 == steps) break;   // the last direction is never used
+        hipLaunchKernelGGL(k_cg_scalars, dim3(1), blk, 0, s, partial, kReduceBlocks, sc, 2);
+        if (g.dim == 2) hipLaunchKernelGGL((k_cg_direction<2, T>), grd, blk, 0, s, r, p, g, sc);
+        else hipLaunchKernelGGL((k_cg_direction<3, T>), grd, blk, 0, s, r, p, g, sc);
+    }
+}
+template void launch_cg_smooth<double>(const Grid&, double*, const double*, int, double*, double*, double*, double*,
+                                       double*, hipStream_t);
+template void launch_cg_smooth<float>(const Grid&, float*, const float*, int, float*, float*, float*, double*, double*,
+                                      hipStream_t);
 
 }  // namespace fmg

@@ -21,9 +21,12 @@ struct Layout {
     size_t state, xc, mom, momscr, arena, fac, forms;
     std::vector<size_t> u, b, xv, fv;   // per level (u[0] = xc)
     std::vector<size_t> tv;             // per level: target of the fused 2D pre pass
+    int cg = 0;                         // CG smoothing: r, p, q arrays and reduction scratch
+    size_t cgr = 0, cgp = 0, cgq = 0, cgsc = 0;
     size_t total;
 };
-Layout make_layout(int dim, int nc, int levels, int mixed);
+Layout make_layout(int dim, int nc, int levels, int mixed, int cg);
+Layout layout_for(const fmg_problem* p, const fmg_options* o);
 
 // What the host reads back between chunks.
 struct JobHost {

@@ -20,6 +20,10 @@ template <typename T> void launch_resid_restrict(const Grid& gf, const Grid& gc,
 template <typename T> void launch_prolong(const Grid& gc, const Grid& gf, const T* xc, T* xf, int accumulate,
                                           hipStream_t s);
 template <typename T> void launch_coarse_solve(const Grid& g, const T* f, T* x, hipStream_t s);
+// `steps` conjugate-gradient iterations on K x = f from x; r, p, q: level arrays of g with
+// zero rings; partial: kReduceBlocks doubles; sc: 4 doubles
+template <typename T> void launch_cg_smooth(const Grid& g, T* x, const T* f, int steps, T* r, T* p, T* q,
+                                            double* partial, double* sc, hipStream_t s);
 // b = lambda M u - M_W u - zeta N(u); lambda = *lam_dev if lam_dev else lam_host
 void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev,
                 double lam_host, hipStream_t s);

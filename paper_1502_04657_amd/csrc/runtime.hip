@@ -253,7 +253,7 @@ class Scheduler {
 int validate(const fmg_problem* p, const fmg_options* o, size_t* bytes) {
     if (int rc = check_problem(p)) return rc;
     if (int rc = check_options(o)) return rc;
-    *bytes = make_layout(p->dim, p->n_coarse, p->n_refine + 1, o->precision == FMG_MIXED).total;
+    *bytes = layout_for(p, o).total;
     return 0;
 }
 
@@ -337,8 +337,7 @@ int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* 
         t->ticket = i;
         t->job.prob = probs[i];
         t->job.opt = opts[i];
-        t->job.lo = make_layout(probs[i].dim, probs[i].n_coarse, probs[i].n_refine + 1,
-                                opts[i].precision == FMG_MIXED);
+        t->job.lo = layout_for(&probs[i], &opts[i]);
         t->job.u_out = u_out[i];
         total += align256(t->bytes);
         tasks[i] = std::move(t);
@@ -419,7 +418,7 @@ int fmg_server_submit(fmg_server* sv, const fmg_problem* prob, const fmg_options
                          sv->pool.size());
     t->job.prob = *prob;
     t->job.opt = *opt;
-    t->job.lo = make_layout(prob->dim, prob->n_coarse, prob->n_refine + 1, opt->precision == FMG_MIXED);
+    t->job.lo = layout_for(prob, opt);
     t->keep_ws = true;
     t->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);

@@ -50,6 +50,17 @@ def smooth(dim, n, x_level, f_level, sweeps):
     return x_level
 
 
+def cg_smooth(dim, n, x_level, f_level, steps):
+    es = x_level.element_size()
+    e = (es * level_elems(dim, n) + 255) // 256 * 256
+    nbytes = 3 * e + 8 * (512 + 8)
+    scratch = torch.zeros(nbytes // 8 + 64, dtype=torch.float64, device=x_level.device)
+    base = (scratch.data_ptr() + 255) // 256 * 256
+    _check(lib().fmg_op_cg_smooth(dim, n, _prec(x_level), _ptr(x_level), _ptr(f_level), steps, C.c_void_p(base),
+                                  C.c_size_t(nbytes), _stream()))
+    return x_level
+
+
 def residual_restrict(dim, n, x_level, f_level):
     rc = torch.zeros(level_elems(dim, n // 2), dtype=x_level.dtype, device=x_level.device)
     _check(lib().fmg_op_residual_restrict(dim, n, _prec(x_level), _ptr(x_level), _ptr(f_level), _ptr(rc), _stream()))
