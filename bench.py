@@ -237,6 +237,31 @@ def bench_omega(steps, warmup, lam_ref):
     return {"metric": "fixed-iteration augmented solves vs converged ones (2D n=2048, zeta=100)", "rows": rows}
 
 
+def bench_paper(steps, warmup):
+    """The setting of the paper's Examples 4.1 (zeta = 1) and 4.2 (zeta = 100): 3D unit cube,
+    W = x^2 + y^2 + z^2, coarsest h = 1/8 refined to h = 1/128, m = p = 1 with 3 + 3 CG
+    smoothing steps, one FMG pass (fixed schedule).  Per mesh: DOF, time per solve and per
+    DOF (the linear-complexity trend of Tables 1-2), lambda, and its distance to the
+    converged discrete eigenvalue of the same mesh; the default smoother (SGS(2,2),
+    m = 1, p = 2) beside it."""
+    from paper_1502_04657_amd import Solver
+    rows = []
+    for zeta in (1.0, 100.0):
+        for refine in range(1, 5):
+            prob = W.Problem(3, 8, refine, (1.0, 1.0, 1.0), 0.0, zeta)
+            conv, _ = Solver(prob, W.Options(tol_lambda=1e-13, max_final_steps=200)).solve(check=False)
+            row = {"zeta": zeta, "n": 8 << refine, "dof": prob.dofs(), "lambda_converged": conv.lam}
+            for tag, opts in (("cg_m1p1", W.Options(m=1, p=1, nu_pre=3, nu_post=3, smoother="cg")),
+                              ("sgs_m1p2", W.Options())):
+                res, _, total, _ = time_solves(prob, opts, steps, warmup)
+                ms = total / steps * 1e3
+                row[tag] = {"ms": ms, "us_per_kdof": ms * 1e6 / prob.dofs(), "lambda": res.lam,
+                            "rel_dist_to_converged": abs(res.lam - conv.lam) / conv.lam, "status": res.status}
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    return {"metric": "paper setting (Examples 4.1/4.2): time per solve and per DOF vs mesh", "rows": rows}
+
+
 def cpu_baseline():
     """The oracle, as it stands, on a bounded sample of the same workload family: the same
     problem (zeta = 100, W = x^2 + y^2, coarsest h = 1/16, same schedule and tolerance)
@@ -264,7 +289,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a cold plain copy of known size (memory-counter scaling)")
-    ap.add_argument("--workload", choices=["fmg2d", "batch", "serve", "omega"], default="fmg2d",
+    ap.add_argument("--workload", choices=["fmg2d", "batch", "serve", "omega", "paper"], default="fmg2d",
                     help="fmg2d: the default line; batch / serve: the batched and serving workloads")
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget of the server")
@@ -290,6 +315,9 @@ def main():
     gpath = os.path.join(ROOT, "tests", "golden", "large_2d.json")
     if os.path.exists(gpath):
         lam_ref = json.load(open(gpath))["large_2d"]["lambda_ref"]
+    if args.workload == "paper":
+        print(json.dumps(bench_paper(args.steps, args.warmup)))
+        return
     if args.workload == "omega":
         print(json.dumps(bench_omega(args.steps, args.warmup, lam_ref)))
         return
