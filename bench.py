@@ -55,7 +55,7 @@ def time_solves(prob, opts, steps, warmup):
     return res, u, total, lat
 
 
-VPOST_KERNEL = "k_vpost2d<double, 5, 54, 22>"
+VPOST_KERNEL = "k_vpost2d<double, 5, 54, 22, 256>"
 PMC_FILE = os.path.join(ROOT, "profiles", "k_vpost2d_f64_pmc.md")
 VPOST_SRC = os.path.join(ROOT, "paper_1502_04657_amd", "csrc", "vcycle2d.hip")
 
