@@ -48,6 +48,20 @@ struct Region {
 template <typename T, int TX, int TY, int HALO, int NT>
 using PairVals = T[Region<TX, TY, HALO, NT>::K];
 
+// The region's x in LDS as two colour planes (red nodes, black nodes), each RH rows of HP
+// values: node (c, r) of colour k = (c + r + base) & 1 sits at plane k, row r, slot c / 2.
+// The nodes a half sweep updates, and the neighbours it reads, are then consecutive in LDS
+// across the lanes (no bank conflicts from the every-other-node pattern of one colour).
+template <typename T, int TX, int TY, int HALO, int NT>
+struct Planes {
+    using Rg = Region<TX, TY, HALO, NT>;
+    static constexpr int PL = Rg::RH * Rg::HP;
+    T* x;
+    int base;   // colour of region node (0, 0)
+    __device__ T& at(int c, int r) const { return x[((c + r + base) & 1) * PL + r * Rg::HP + (c >> 1)]; }
+    __device__ T& plane(int k, int r, int slot) const { return x[k * PL + r * Rg::HP + slot]; }
+};
+
 template <int TX, int TY, int HALO, int NT>
 __device__ inline void pair_coords(int k, int i0, int j0, int& c, int& r, int& gi, int& gj, bool& valid) {
     using Rg = Region<TX, TY, HALO, NT>;
@@ -64,10 +78,9 @@ __device__ inline bool interior(int gi, int gj, int n) { return gi >= 1 && gi <=
 // Half sweep S of NH (colour col) on the owned pairs: the colour-col node of each pair
 // within distance ext = R + NH - 1 - S of the tile, clipped to the domain interior.
 template <typename T, int TX, int TY, int HALO, int NT, int NH, int R, int S>
-__device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO, NT>& fa, const PairVals<T, TX, TY, HALO, NT>& fb,
-                                  int i0, int j0, int n, int col) {
+__device__ inline void half_sweep(const Planes<T, TX, TY, HALO, NT>& X, const PairVals<T, TX, TY, HALO, NT>& fa,
+                                  const PairVals<T, TX, TY, HALO, NT>& fb, int i0, int j0, int n, int col) {
     using Rg = Region<TX, TY, HALO, NT>;
-    constexpr int RW = Rg::RW;
     constexpr int ext = R + NH - 1 - S;
     const int ia = max(1, i0 - ext), ib = min(n - 1, i0 + TX - 1 + ext);
     const int ja = max(1, j0 - ext), jb = min(n - 1, j0 + TY - 1 + ext);
@@ -79,18 +92,21 @@ __device__ inline void half_sweep(T* xs, const PairVals<T, TX, TY, HALO, NT>& fa
         const int sel = ((gi + gj) & 1) ^ col;   // 0: the even-column node has colour col
         const int g = gi + sel;
         if (valid && g >= ia && g <= ib && gj >= ja && gj <= jb) {
-            const int p = c + sel + RW * r;
-            xs[p] = gs2f<T>(sel ? fb[k] : fa[k], xs[p - 1], xs[p + 1], xs[p - RW], xs[p + RW]);
+            // node (c + sel, r) has colour col; its four neighbours have the other colour:
+            // W, E in this row at slots pc - 1 + sel, pc + sel; S, N at slot pc of rows r -+ 1
+            const int o = col ^ 1, pc = c >> 1;
+            X.plane(col, r, pc) = gs2f<T>(sel ? fb[k] : fa[k], X.plane(o, r, pc - 1 + sel), X.plane(o, r, pc + sel),
+                                          X.plane(o, r - 1, pc), X.plane(o, r + 1, pc));
         }
     }
     __syncthreads();
 }
 
 template <typename T, int TX, int TY, int HALO, int NT, int NH, int R, int... S>
-__device__ inline void half_sweeps_seq(T* xs, const PairVals<T, TX, TY, HALO, NT>& fa,
+__device__ inline void half_sweeps_seq(const Planes<T, TX, TY, HALO, NT>& X, const PairVals<T, TX, TY, HALO, NT>& fa,
                                        const PairVals<T, TX, TY, HALO, NT>& fb, int i0, int j0, int n,
                                        std::integer_sequence<int, S...>) {
-    (half_sweep<T, TX, TY, HALO, NT, NH, R, S>(xs, fa, fb, i0, j0, n, S & 1), ...);
+    (half_sweep<T, TX, TY, HALO, NT, NH, R, S>(X, fa, fb, i0, j0, n, S & 1), ...);
 }
 
 // x and f of the owned pairs (zero outside the domain; x zero when zero_x).  Every load of
@@ -123,7 +139,7 @@ __device__ inline void load_pairs(PairVals<T, TX, TY, HALO, NT>& xa, PairVals<T,
 
 // owned x into the LDS region
 template <typename T, int TX, int TY, int HALO, int NT>
-__device__ inline void put_pairs(T* xs, const PairVals<T, TX, TY, HALO, NT>& xa,
+__device__ inline void put_pairs(const Planes<T, TX, TY, HALO, NT>& X, const PairVals<T, TX, TY, HALO, NT>& xa,
                                  const PairVals<T, TX, TY, HALO, NT>& xb, int i0, int j0) {
     using Rg = Region<TX, TY, HALO, NT>;
 #pragma unroll
@@ -132,15 +148,16 @@ __device__ inline void put_pairs(T* xs, const PairVals<T, TX, TY, HALO, NT>& xa,
         bool valid;
         pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (valid) {
-            xs[c + Rg::RW * r] = xa[k];
-            xs[c + 1 + Rg::RW * r] = xb[k];
+            X.at(c, r) = xa[k];
+            X.at(c + 1, r) = xb[k];
         }
     }
 }
 
 // the tile nodes of the owned pairs, from the LDS region, to the level array
 template <typename T, int TX, int TY, int HALO, int NT>
-__device__ inline void store_pairs(T* __restrict__ out, const T* xs, const Grid& g, int i0, int j0) {
+__device__ inline void store_pairs(T* __restrict__ out, const Planes<T, TX, TY, HALO, NT>& X, const Grid& g, int i0,
+                                   int j0) {
     using Rg = Region<TX, TY, HALO, NT>;
     const int n = g.n;
 #pragma unroll
@@ -150,9 +167,8 @@ __device__ inline void store_pairs(T* __restrict__ out, const T* xs, const Grid&
         pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (!valid || gj < j0 || gj > min(n - 1, j0 + TY - 1)) continue;
         const int q = gi + (int)g.pitch * gj;
-        const int p = c + Rg::RW * r;
-        if (gi >= i0 && gi <= min(n - 1, i0 + TX - 1)) out[q] = xs[p];
-        if (gi + 1 >= i0 && gi + 1 <= min(n - 1, i0 + TX - 1)) out[q + 1] = xs[p + 1];
+        if (gi >= i0 && gi <= min(n - 1, i0 + TX - 1)) out[q] = X.at(c, r);
+        if (gi + 1 >= i0 && gi + 1 <= min(n - 1, i0 + TX - 1)) out[q + 1] = X.at(c + 1, r);
     }
 }
 
@@ -164,16 +180,16 @@ __global__ __launch_bounds__(NT) void k_vpre2d(const T* __restrict__ x, T* __res
     constexpr int R = 2;                 // x must be final within 2 rings for the residual ring
     constexpr int HALO = NH + R;
     using Rg = Region<TX, TY, HALO, NT>;
-    constexpr int RW = Rg::RW;
-    __shared__ T xs[RW * Rg::RH];
+    __shared__ T xs[2 * Rg::RH * Rg::HP];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n;
+    const Planes<T, TX, TY, HALO, NT> X{xs, (i0 + j0) & 1};
     T xa[Rg::K], xb[Rg::K], fa[Rg::K], fb[Rg::K];
     load_pairs<T, TX, TY, HALO, NT>(xa, xb, fa, fb, x, f, g, i0, j0, zero_x);
-    put_pairs<T, TX, TY, HALO, NT>(xs, xa, xb, i0, j0);
+    put_pairs<T, TX, TY, HALO, NT>(X, xa, xb, i0, j0);
     __syncthreads();
-    half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
-    store_pairs<T, TX, TY, HALO, NT>(y, xs, g, i0, j0);
+    half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(X, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
+    store_pairs<T, TX, TY, HALO, NT>(y, X, g, i0, j0);
     // residual r = f - K x on the tile and one ring (kept in fa/fb; f elsewhere)
     const int ia = i0 - 1, ib = i0 + TX, ja = j0 - 1, jb = j0 + TY;
 #pragma unroll
@@ -182,14 +198,14 @@ __global__ __launch_bounds__(NT) void k_vpre2d(const T* __restrict__ x, T* __res
         bool valid;
         pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (!valid || gj < ja || gj > jb) continue;
-        const int p = c + RW * r;
         if (gi >= ia && gi <= ib && interior(gi, gj, n))
-            fa[k] = fa[k] - (T(4) * xs[p] - ((xs[p - 1] + xs[p + 1]) + (xs[p - RW] + xs[p + RW])));
+            fa[k] = fa[k] - (T(4) * X.at(c, r) - ((X.at(c - 1, r) + X.at(c + 1, r)) + (X.at(c, r - 1) + X.at(c, r + 1))));
         if (gi + 1 >= ia && gi + 1 <= ib && interior(gi + 1, gj, n))
-            fb[k] = fb[k] - (T(4) * xs[p + 1] - ((xs[p] + xs[p + 2]) + (xs[p + 1 - RW] + xs[p + 1 + RW])));
+            fb[k] = fb[k] - (T(4) * X.at(c + 1, r) -
+                             ((X.at(c, r) + X.at(c + 2, r)) + (X.at(c + 1, r - 1) + X.at(c + 1, r + 1))));
     }
     __syncthreads();
-    put_pairs<T, TX, TY, HALO, NT>(xs, fa, fb, i0, j0);   // the residuals replace x in LDS
+    put_pairs<T, TX, TY, HALO, NT>(X, fa, fb, i0, j0);   // the residuals replace x in LDS
     __syncthreads();
     // restriction for the coarse nodes whose centre 2I, 2J lies in this tile
     {
@@ -199,9 +215,10 @@ __global__ __launch_bounds__(NT) void k_vpre2d(const T* __restrict__ x, T* __res
             const int r = t / CW, c = t - r * CW;
             const int I = (i0 + 1) / 2 + c, J = (j0 + 1) / 2 + r;
             if (I > nc - 1 || J > nc - 1) continue;
-            const int p = (2 * I - i0 + HALO) + RW * (2 * J - j0 + HALO);
-            const T e = (xs[p - 1] + xs[p + 1]) + (xs[p - RW] + xs[p + RW]) + (xs[p - 1 - RW] + xs[p + 1 + RW]);
-            rc[I + gc.pitch * J] = xs[p] + T(0.5) * e;
+            const int cc = 2 * I - i0 + HALO, rr = 2 * J - j0 + HALO;
+            const T e = (X.at(cc - 1, rr) + X.at(cc + 1, rr)) + (X.at(cc, rr - 1) + X.at(cc, rr + 1)) +
+                        (X.at(cc - 1, rr - 1) + X.at(cc + 1, rr + 1));
+            rc[I + gc.pitch * J] = X.at(cc, rr) + T(0.5) * e;
         }
     }
 }
@@ -214,10 +231,9 @@ __global__ __launch_bounds__(NT) void k_vpost2d(const T* __restrict__ y, T* __re
     constexpr int R = 0;
     constexpr int HALO = NH > 0 ? NH + R : 1;
     using Rg = Region<TX, TY, HALO, NT>;
-    constexpr int RW = Rg::RW;
     // coarse values under the region: coarse node (I, J) for I in [(i0 - HALO) >> 1, ...]
     constexpr int CRW = Rg::RW / 2 + 2, CRH = Rg::RH / 2 + 2;
-    __shared__ T xs[RW * Rg::RH];
+    __shared__ T xs[2 * Rg::RH * Rg::HP];
     __shared__ T cs[CRW * CRH];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n, nc = gc.n;
@@ -258,10 +274,11 @@ __global__ __launch_bounds__(NT) void k_vpost2d(const T* __restrict__ y, T* __re
             else xa[k] += v;
         }
     }
-    put_pairs<T, TX, TY, HALO, NT>(xs, xa, xb, i0, j0);
+    const Planes<T, TX, TY, HALO, NT> X{xs, (i0 + j0) & 1};
+    put_pairs<T, TX, TY, HALO, NT>(X, xa, xb, i0, j0);
     __syncthreads();
-    half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(xs, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
-    store_pairs<T, TX, TY, HALO, NT>(x, xs, g, i0, j0);
+    half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(X, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
+    store_pairs<T, TX, TY, HALO, NT>(x, X, g, i0, j0);
 }
 
 // Tile shape by level: 16 x 16 on coarse levels (more workgroups, short sweeps; the halo
