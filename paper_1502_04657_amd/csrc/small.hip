@@ -481,12 +481,102 @@ __device__ __forceinline__ double elem_corner(const double* U, const double* UU,
     return s1 + 2.0 * c * s2 + c * c * mo[L::T0];
 }
 
-// S(x): coarse stencil Sst, border sH, corner sc[3].  One pass per colour class; within a
+// S(x): coarse stencil Sst, border sH, corner sc[3], in one pass.  One thread per coarse
+// node builds its own row: for every cell around the node and every simplex of that cell
+// containing it, the simplex's row of that vertex, in a fixed order (no other thread writes
+// the row, so no colouring and no atomics).  The corner term is summed over the simplices
+// by a second loop of the same pass.
+template <int D, bool AUG>
+__device__ __forceinline__ void assemble_S_nodes(Arena<D, AUG>& ar, const Args& a, const double* x) {
+    constexpr int NS = Geo<D>::NS;
+    constexpr int NE = Geo<D>::NE;
+    constexpr int V = D + 1;
+    constexpr int NCV = 1 << D;
+    using L = MomLayout<D>;
+    const int N = ar.z.N, nc = a.nc, m = ar.z.m;
+    const double H = 1.0 / nc;
+    const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
+    const double c = AUG ? x[N] : 0.0;
+    for (int i = threadIdx.x; i < N; i += kThreads) {
+        int P[3];
+        node_pos<D>(i, m, P);
+        double row[NS];
+        static_for<NS>([&](auto sc_) { row[decltype(sc_)::value] = 0.0; });
+        double shs = 0.0;
+        auto corner = [&](auto cvc) {
+            constexpr int cv = decltype(cvc)::value;
+            // the node is cell vertex cv of the cell with origin P - (cv bits)
+            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 3) ? P[2] - ((cv >> 2) & 1) : 0;
+            if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc))) return;
+            const int cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
+            for_simplices<D>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                constexpr int aa = VertOf<D, t, cv>::value;
+                if constexpr (aa >= 0) {
+                    int nd[V];
+                    double U[V];
+                    static_for<V>([&](auto vc) {
+                        constexpr int v = decltype(vc)::value;
+                        nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
+                        U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
+                    });
+                    double UU[V * (V + 1) / 2];
+#pragma unroll
+                    for (int p = 0; p < V; ++p)
+#pragma unroll
+                        for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+                    const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
+                    double Sr[V], sh = 0.0;
+                    elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
+                    static_for<V>([&](auto bc) {
+                        constexpr int bb = decltype(bc)::value;
+                        if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
+                    });
+                    shs += sh;
+                }
+            });
+        };
+        if constexpr (D == 2) static_for<NCV>(corner);
+        else rolled_for<NCV>(corner);
+        double* out = ar.Sst + (size_t)i * NS;
+        static_for<NS>([&](auto sc_) { out[decltype(sc_)::value] = row[decltype(sc_)::value]; });
+        if (AUG) ar.sH[i] = shs;
+    }
+    if (AUG) {
+        double sU = 0.0;
+        const int nsimp = ((D == 2) ? nc * nc : nc * nc * nc) * NE;
+        for (int e = threadIdx.x; e < nsimp; e += kThreads) {
+            const int cl = e / NE, te = e - cl * NE;
+            const int C0 = cl % nc, C1 = (cl / nc) % nc, C2 = (D == 3) ? cl / (nc * nc) : 0;
+            dispatch<NE>(te, [&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                double U[V];
+                static_for<V>([&](auto vc) {
+                    constexpr int v = decltype(vc)::value;
+                    const int nd = vert_node<D, t, v>(C0, C1, C2, m);
+                    U[v] = nd >= 0 ? x[nd] : 0.0;
+                });
+                double UU[V * (V + 1) / 2];
+#pragma unroll
+                for (int p = 0; p < V; ++p)
+#pragma unroll
+                    for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+                sU += elem_corner<D>(U, UU, a.mom + (size_t)(cl * NE + t) * L::SIZE, c);
+            });
+        }
+        sU = bsum1(ar.red, sU);
+        if (threadIdx.x == 0) ar.sc[3] = sU;
+    }
+    __syncthreads();
+}
+
+// S(x) by colour classes (3D; the one-pass version needs more registers than the 3D
+// kernels can give without spilling).  One pass per colour class; within a
 // pass one thread per (cell, cell vertex) adds the rows of that vertex from every simplex
 // of the cell that contains it (the cell vertex is uniform per wavefront).  The corner
 // term of each simplex is added by the thread of its vertex 0 (the cell origin).
 template <int D, bool AUG>
-__device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
+__device__ __forceinline__ void assemble_S_colours(Arena<D, AUG>& ar, const Args& a, const double* x) {
     constexpr int NS = Geo<D>::NS;
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
@@ -550,6 +640,12 @@ __device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, con
         if (threadIdx.x == 0) ar.sc[3] = sU;
         __syncthreads();
     }
+}
+
+template <int D, bool AUG>
+__device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
+    if constexpr (D == 2) assemble_S_nodes<D, AUG>(ar, a, x);
+    else assemble_S_colours<D, AUG>(ar, a, x);
 }
 
 // y = (A + zs S) x, z = B x (with borders); sc[4] = x^T y, sc[5] = x^T z
