@@ -379,12 +379,52 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
     using L = MomLayout<D>;
     const int N = ar.z.N, m = ar.z.m, nc = a.nc;
     if (!AUG) return;
+    double v3[3] = {0.0, 0.0, 0.0};
+    if constexpr (D == 2) {
+        // one pass: each node gathers its border entries from the simplices around it; the
+        // scalars are summed over simplices by a second loop
+        for (int i = threadIdx.x; i < N; i += kThreads) {
+            int P[3];
+            node_pos<D>(i, m, P);
+            double sa = 0.0, sb = 0.0;
+            static_for<(1 << D)>([&](auto cvc) {
+                constexpr int cv = decltype(cvc)::value;
+                const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1);
+                if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc) return;
+                const int cl = C0 + nc * C1;
+                for_simplices<D>([&](auto tc) {
+                    constexpr int t = decltype(tc)::value;
+                    constexpr int v = VertOf<D, t, cv>::value;
+                    if constexpr (v >= 0) {
+                        const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
+                        sa += mo[L::KG + v] + mo[L::AW1 + v];
+                        sb += mo[L::B1 + v];
+                    }
+                });
+            });
+            ar.aH[i] = sa;
+            ar.bH[i] = sb;
+        }
+        for (int e = threadIdx.x; e < nc * nc * NE; e += kThreads) {
+            const double* mo = a.mom + (size_t)e * L::SIZE;
+            static_for<V>([&](auto vc) { v3[2] += mo[L::B1 + decltype(vc)::value]; });
+            v3[0] += mo[L::Q] + mo[L::AW2];
+            v3[1] += mo[L::B2];
+        }
+        bsum<3>(ar.red, v3);
+        if (threadIdx.x == 0) {
+            ar.sc[0] = v3[0];  // aU
+            ar.sc[1] = v3[1];  // bU
+            ar.sc[2] = v3[2];  // int u~
+        }
+        __syncthreads();
+        return;
+    }
     for (int i = threadIdx.x; i < N; i += kThreads) {
         ar.aH[i] = 0.0;
         ar.bH[i] = 0.0;
     }
     __syncthreads();
-    double v3[3] = {0.0, 0.0, 0.0};
     for (int color = 0; color < (1 << D); ++color) {
         const ColorClass cc = color_class<D>(nc, color);
         for (int q = threadIdx.x; q < cc.ncol; q += kThreads) {
