@@ -13,9 +13,10 @@ potential W = sum_k w_k x_k^2 + c gives the exact potential-mass row
     int W phi_i phi_j = h^d [ sum_k w_k (X_k^2 m0 + 2 X_k h m1[k] + h^2 m2[k]) + c m0 ],
 and m0 h^d is the consistent mass stencil.  It also emits the exact degree-4 quadrature
 rules used for the fine-grid moment integrals: on triangles two symmetric orbits
-(a, a, 1-2a), (b, b, 1-2b) of 3 points each, whose parameters and weights are the root of the
-four moment equations of the symmetric polynomials up to degree 4 (solved to 40 digits
-and checked on every monomial); on tetrahedra orbits with rational points.
+(a, a, 1-2a), (b, b, 1-2b) of 3 points each; on tetrahedra the centroid, the orbit
+(a, a, a, 1-3a) (4 points) and the orbit (c, c, 1/2-c, 1/2-c) (6 points).  Parameters and
+weights are the root of the moment equations of the symmetric polynomials up to degree 4
+(solved to 40 digits and checked on every monomial).
 """
 from __future__ import annotations
 
@@ -122,44 +123,34 @@ def rule_2d():
     return pts, wts
 
 
-def solve_rule(dim, orbits):
-    """Weights (relative to the simplex volume) making the orbit rule exact to degree 4."""
-    lam = sp.symbols(f"l0:{dim + 1}")
-    e = [sp.Integer(1)]
-    # symmetric polynomials of the barycentrics up to degree 4
-    el = lambda k: sum(sp.Mul(*c) for c in itertools.combinations(lam, k))
-    conds = [sp.Integer(1), el(2), el(3), el(2) ** 2] + ([el(4)] if dim == 3 else [])
-    w = sp.symbols(f"w0:{len(orbits)}")
-
-    def exact(f):
-        return exact_simplex(f, lam, dim)
+def rule_3d():
+    """11-point degree-4 rule on tetrahedra: centroid (weight w0), orbit (a, a, a, 1-3a)
+    (w1 per point), orbit (c, c, 1/2-c, 1/2-c) (w2 per point); the five unknowns solve the
+    moment equations of 1, e2, e3, e4, e2^2.  (The centroid weight comes out negative; the
+    rule integrates the polynomial integrands exactly all the same.)"""
+    lam = sp.symbols("l0:4")
+    a, c, w0, w1, w2 = sp.symbols("a c w0 w1 w2")
+    el = lambda k: sum(sp.Mul(*cc) for cc in itertools.combinations(lam, k))
+    q = sp.Rational(1, 4)
+    s31 = lambda t: [tuple(1 - 3 * t if i == j else t for i in range(4)) for j in range(4)]
+    s22 = lambda t: [tuple(t if i in pr else sp.Rational(1, 2) - t for i in range(4))
+                     for pr in itertools.combinations(range(4), 2)]
     eqs = []
-    for f in conds:
-        s = 0
-        for wi, orb in zip(w, orbits):
-            for p in orb:
-                s += wi * f.subs(dict(zip(lam, p)))
-        eqs.append(sp.Eq(s, exact(f)))
-    sol = sp.solve(eqs, w, dict=True)[0]
-    ws = [sol[wi] for wi in w]
-    # verify on every monomial of degree <= 4
-    for mon in itertools.product(range(5), repeat=dim + 1):
+    for f in (sp.Integer(1), el(2), el(3), el(4), el(2) ** 2):
+        sub = lambda p: f.subs(dict(zip(lam, p)))
+        s = w0 * sub((q, q, q, q)) + sum(w1 * sub(p) for p in s31(a)) + sum(w2 * sub(p) for p in s22(c))
+        eqs.append(sp.expand(s - exact_simplex(f, lam, 3)))
+    ra, rc, rw0, rw1, rw2 = sp.nsolve(eqs, [a, c, w0, w1, w2], [0.1, 0.1, -0.05, 0.05, 0.1], prec=40)
+    assert 0 < ra < sp.Rational(1, 4) and 0 < rc < sp.Rational(1, 2) and rw1 > 0 and rw2 > 0
+    pts = [(q, q, q, q)] + s31(ra) + s22(rc)
+    wts = [rw0] + [rw1] * 4 + [rw2] * 6
+    for mon in itertools.product(range(5), repeat=4):
         if sum(mon) > 4:
             continue
-        f = sp.Mul(*[lam[i] ** mon[i] for i in range(dim + 1)])
-        s = sum(wi * f.subs(dict(zip(lam, p))) for wi, orb in zip(ws, orbits) for p in orb)
-        assert sp.simplify(s - exact(f)) == 0
-    return ws
-
-
-def orbits_3d():
-    h = sp.Rational(1, 2); q = sp.Rational(1, 4); s6 = sp.Rational(1, 6); t3 = sp.Rational(1, 3)
-    verts = [tuple(1 if i == j else 0 for i in range(4)) for j in range(4)]
-    mids = [tuple(h if i in pr else 0 for i in range(4)) for pr in itertools.combinations(range(4), 2)]
-    cen = [(q, q, q, q)]
-    fac = [tuple(0 if i == j else t3 for i in range(4)) for j in range(4)]
-    hs = [tuple(h if i == j else s6 for i in range(4)) for j in range(4)]
-    return [verts, mids, cen, fac, hs]
+        f = sp.Mul(*[lam[i] ** mon[i] for i in range(4)])
+        val = sum(w * f.subs(dict(zip(lam, p))) for w, p in zip(wts, pts))
+        assert abs(val - exact_simplex(f, lam, 3)) < sp.Float(1e-30)
+    return pts, wts
 
 
 def cell_elements(dim):
@@ -239,14 +230,7 @@ def main():
     out.append("static constexpr double kQuadPt2D[%d][3] = {%s};" % (
         len(pts), ", ".join("{" + ", ".join(fmt(c) for c in p) + "}" for p in pts)))
     out.append("static constexpr double kQuadW2D[%d] = {%s};" % (len(pts), ", ".join(fmt(w) for w in wts)))
-    orb3 = orbits_3d()
-    w3 = solve_rule(3, orb3)
-    pts, wts = [], []
-    for wi, orb in zip(w3, orb3):
-        if wi == 0:
-            continue
-        for p in orb:
-            pts.append(p); wts.append(wi)
+    pts, wts = rule_3d()
     out.append(f"// exact degree-4 rule on tetrahedra: barycentric points, weights / volume (sum 1)")
     out.append(f"constexpr int kQuad3D = {len(pts)};")
     out.append("static constexpr double kQuadPt3D[%d][4] = {%s};" % (

@@ -10,9 +10,10 @@
 //
 // Pass 1 (k_moments_raw): block (coarse cell, chunk, coarse simplex type) integrates
 // u~^a X^b over the fine simplices of that coarse simplex with an exact degree-4 rule
-// (tables.h) and writes one partial sum per block.  In 2D a block walks only the fine
-// cells of its coarse triangle (a triangular index set, folded into full rows); in 3D it
-// walks the fine cells of the coarse cell and skips those of other coarse tetrahedra.  Pass 2 (k_moments_final): one thread
+// (tables.h) and writes one partial sum per block.  A block walks only the fine cells that
+// meet its coarse simplex: in 2D the cells (a0, a1) on one side of the diagonal (a
+// triangular index set, folded into full rows), in 3D the cells whose coordinates are
+// ordered as the coarse tetrahedron's axis permutation orders them (sorted triples).  Pass 2 (k_moments_final): one thread
 // per coarse simplex adds the partials in chunk order and converts the X-monomial moments
 // to the barycentric form.  Both passes are deterministic.
 #include <utility>
@@ -34,11 +35,13 @@ static int64_t ipow(int64_t b, int e) {
 
 // cells_per: fine cells one block list covers.  2D: the fine cells (a0, a1) of one coarse
 // triangle, a0 >= a1 or a0 <= a1 (diagonal cells included, s (s + 1) / 2 of them), as s / 2
-// rows of s + 1 cells (s = n / nc is even on every level that has moments).
+// rows of s + 1 cells (s = n / nc is even on every level that has moments).  3D: the cells
+// with a_p0 >= a_p1 >= a_p2 for the coarse tetrahedron's axis order (p0, p1, p2),
+// s (s + 1) (s + 2) / 6 of them.
 static void chunk_shape(int dim, int nc, int n, int64_t& ncell, int64_t& cells_per, int64_t& nchunk) {
     const int s = n / nc;
     ncell = ipow(nc, dim);
-    cells_per = dim == 2 ? (int64_t)(s / 2) * (s + 1) : ipow(s, dim);
+    cells_per = dim == 2 ? (int64_t)(s / 2) * (s + 1) : (int64_t)s * (s + 1) * (s + 2) / 6;
     nchunk = (cells_per + kChunkCells - 1) / kChunkCells;
 }
 
@@ -109,11 +112,23 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
             a[1] = type == 0 ? lo : hi;
             a[2] = 0;
         } else {
-            a[0] = (int)(idx % s);
-            a[1] = (int)((idx / s) % s);
-            a[2] = (int)(idx / ((int64_t)s * s));
-            // quick reject: fine cells whose simplices all map to other coarse types
-            if (a[0] != a[1] && a[1] != a[2] && a[0] != a[2] && coarse_type<D>(a, 0) != type) continue;
+            // idx -> sorted triple i >= j >= k: i from the tetrahedral numbers i(i+1)(i+2)/6,
+            // then (j, k) from the triangular numbers j(j+1)/2
+            const int64_t t = idx;
+            int i = (int)cbrt(6.0 * (double)t);
+            while ((int64_t)i * (i + 1) * (i + 2) / 6 > t) --i;
+            while ((int64_t)(i + 1) * (i + 2) * (i + 3) / 6 <= t) ++i;
+            const int r = (int)(t - (int64_t)i * (i + 1) * (i + 2) / 6);
+            int j = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
+            while (j * (j + 1) / 2 > r) --j;
+            while ((j + 1) * (j + 2) / 2 <= r) ++j;
+            const int k = r - j * (j + 1) / 2;
+            // type 2 p0 + q: largest axis p0; q = 1 puts the larger remaining axis second
+            const int p0 = type >> 1, o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
+            const int p1 = (type & 1) ? o2 : o1, p2 = (type & 1) ? o1 : o2;
+            a[p0] = i;
+            a[p1] = j;
+            a[p2] = k;
         }
         const int i = C[0] * s + a[0], j = C[1] * s + a[1], k = D == 3 ? C[2] * s + a[2] : 0;
         const int64_t base = i + P * j + S * k;
