@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -221,7 +222,9 @@ static bool tol_mode(const SolveJob& j) { return j.opt.tol_lambda > 0.0 && j.lo.
 // device state (and the Rayleigh-quotient forms after the final chunk) into the host mirror
 static int end_chunk(SolveJob& j, bool final_chunk) {
     SmallState* st = at<SmallState>(j.ws, j.lo.state);
-    FMG_HIP_CHECK(hipMemcpyAsync(&j.host->st, st, sizeof(SmallState), hipMemcpyDeviceToHost, j.s));
+    // a tolerance check needs only the scalars in front of the lambda history
+    const size_t bytes = final_chunk ? sizeof(SmallState) : offsetof(SmallState, hist);
+    FMG_HIP_CHECK(hipMemcpyAsync(&j.host->st, st, bytes, hipMemcpyDeviceToHost, j.s));
     if (final_chunk)
         FMG_HIP_CHECK(hipMemcpyAsync(j.host->forms, at<double>(j.ws, j.lo.forms), sizeof(j.host->forms),
                                      hipMemcpyDeviceToHost, j.s));
@@ -408,11 +411,18 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     j.opt = *opt;
     j.lo = layout_for(prob, opt);
     if (ws_bytes < j.lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, j.lo.total);
-    JobHost host;
+    // host mirror in pinned memory (one per calling thread, kept for the process): the
+    // chunk-end copies are then direct DMA instead of staged pageable copies
+    static thread_local JobHost* pinned = nullptr;
+    if (!pinned && hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(JobHost), hipHostMallocDefault) != hipSuccess) {
+        pinned = nullptr;
+        (void)hipGetLastError();
+    }
+    JobHost local;
     j.ws = ws;
     j.s = static_cast<hipStream_t>(stream);
     j.u_out = u_out;
-    j.host = &host;
+    j.host = pinned ? pinned : &local;
     // each chunk ends with the device state copied into `host`; wait for it, then continue
     int rc = job_start(j);
     while (!rc && j.phase != 3) {

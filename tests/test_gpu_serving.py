@@ -123,3 +123,32 @@ def test_caller_allocator_is_used():
     assert calls == {"alloc": 1, "free": 1}
     s, su = _solo(*MIX[0])
     _same(res[0], us[0], s, su)
+
+
+def test_a_failing_instance_does_not_disturb_the_others():
+    # a tolerance that cannot be met within one extra step fails that instance only
+    from paper_1502_04657_amd import batch_solve
+    bad = (W.Problem(2, 8, 2, (1.0, 1.0, 0.0), 0.0, 1000.0), W.Options(tol_lambda=1e-15, max_final_steps=1))
+    mix = [MIX[0], bad, MIX[1]]
+    res, us = batch_solve([p for p, _ in mix], [o for _, o in mix], check=False)
+    assert res[1].status == -3
+    for i in (0, 2):
+        s, su = _solo(*mix[i])
+        _same(res[i], us[i], s, su)
+
+
+def test_server_destroy_with_requests_outstanding():
+    from paper_1502_04657_amd import Server
+    sv = Server(hbm_budget=1 << 28, max_slots=2)
+    for p, o in MIX:
+        sv.submit(p, o)
+    sv.close()   # running requests finish, queued and unpolled ones are dropped
+    with Server(hbm_budget=1 << 28, max_slots=2) as sv2:
+        t = sv2.submit(*MIX[1])
+        r = None
+        t0 = time.time()
+        while r is None:
+            assert time.time() - t0 < 30
+            r = sv2.poll(t)
+        s, su = _solo(*MIX[1])
+        _same(r[0], r[1], s, su)
