@@ -146,6 +146,7 @@ struct Args {
     const double* mom;
     double* arena;       // global arena (used when the problem does not fit in LDS)
     int use_lds;
+    int stage_blocks;    // global-arena kernels: blocks inverted at a time in dynamic LDS
     double* xc;          // coarsest padded level array receiving x_H
     Grid gc;
     SmallState* st;
@@ -203,6 +204,8 @@ struct Arena {
     double* Sst;                                   // S(x) stencil, N x NS
     double* x; double* xs; double* xk; double* y; double* z2; double* F; double* rhs;
     double* xp; double* fp;                        // previous iterate and chord step (acceleration)
+    double* stage = nullptr;                       // LDS staging of block inversions (global arena)
+    int stage_blocks = 0;
     double* aH; double* bH; double* sH; double* sc; double* red;
     double* Dm; double* Fm; double* Rm;            // block factor (nb blocks each)
     double* S1; double* S2;                        // scratch
@@ -1080,14 +1083,14 @@ __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
 // Steps alternate between the blocks and the scratch S1 (one barrier per step).  Pivots
 // are those of an LDL^T of each block; returns the number of negative pivots, or -1 if one
 // is zero relative to `scale`.
-template <int D, bool AUG>
-__device__ __forceinline__ int block_invert(Arena<D, AUG>& ar, int first, int step, int cnt, double scale) {
-    const int bs = ar.z.bs, B2 = ar.z.B2;
+// Gauss-Jordan inversion of cnt blocks of size bs, in place in bufA (block stride strideA),
+// alternating with bufB (stride strideB) at every step (one barrier per step).  Pivots are
+// those of an LDL^T of each block; returns the number of negative pivots, or -1 if one is
+// zero relative to `scale`.
+__device__ __forceinline__ int gj_invert(double* bufA, size_t strideA, double* bufB, size_t strideB, int bs, int cnt,
+                                         double scale) {
+    const int B2 = bs * bs;
     int neg = 0;
-    double* bufA = ar.Dm + (size_t)first * B2;
-    const size_t strideA = (size_t)step * B2;
-    double* bufB = ar.S1;
-    const size_t strideB = B2;
     for (int k = 0; k < bs; ++k) {
         const bool fromA = (k & 1) == 0;
         const double* src = fromA ? bufA : bufB;
@@ -1125,6 +1128,36 @@ __device__ __forceinline__ int block_invert(Arena<D, AUG>& ar, int first, int st
     if (bs & 1) {   // the result sits in the scratch after an odd number of steps
         for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads)
             for (int i = 0; i < cnt; ++i) bufA[(size_t)i * strideA + e2] = bufB[(size_t)i * strideB + e2];
+        __syncthreads();
+    }
+    return neg;
+}
+
+// Inversion of the pivot blocks Dm[first + step*i], i < cnt, in place.  With a global-memory
+// arena the blocks go through LDS in groups of stage_blocks (the Gauss-Jordan steps then
+// touch LDS only); otherwise in place with the scratch S1.
+template <int D, bool AUG>
+__device__ __forceinline__ int block_invert(Arena<D, AUG>& ar, int first, int step, int cnt, double scale) {
+    const int bs = ar.z.bs, B2 = ar.z.B2;
+    if (ar.stage_blocks <= 0)
+        return gj_invert(ar.Dm + (size_t)first * B2, (size_t)step * B2, ar.S1, B2, bs, cnt, scale);
+    int neg = 0;
+    for (int g0 = 0; g0 < cnt; g0 += ar.stage_blocks) {
+        const int gc = min(ar.stage_blocks, cnt - g0);
+        double* A = ar.stage;
+        double* Bb = ar.stage + (size_t)gc * B2;
+        for (int i = 0; i < gc; ++i) {
+            const double* src = ar.Dm + (size_t)(first + step * (g0 + i)) * B2;
+            for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) A[(size_t)i * B2 + e2] = src[e2];
+        }
+        __syncthreads();
+        const int r = gj_invert(A, B2, Bb, B2, bs, gc, scale);
+        if (r < 0) return -1;
+        neg += r;
+        for (int i = 0; i < gc; ++i) {
+            double* dst = ar.Dm + (size_t)(first + step * (g0 + i)) * B2;
+            for (int e2 = threadIdx.x; e2 < B2; e2 += kThreads) dst[e2] = A[(size_t)i * B2 + e2];
+        }
         __syncthreads();
     }
     return neg;
@@ -1626,8 +1659,13 @@ template <int D, bool AUG, bool LDS, bool MF>
 __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     extern __shared__ double lds[];
     Arena<D, AUG> ar;
-    if constexpr (LDS) ar.carve(lds, a.nc);
-    else ar.carve(a.arena, a.nc);
+    if constexpr (LDS) {
+        ar.carve(lds, a.nc);
+    } else {
+        ar.carve(a.arena, a.nc);
+        ar.stage = lds;
+        ar.stage_blocks = a.stage_blocks;
+    }
     if (AUG && a.st->done) return;   // tolerance loop already satisfied
     FMG_T0(t_all);
     FMG_T0(t_setup);
@@ -1814,10 +1852,21 @@ inline bool small_blocks(int dim, int nc, size_t bytes) {
     return (dim == 2 ? m : m * m) <= 16 && bytes <= kLdsLimit;
 }
 
+// blocks a global-arena kernel inverts at a time in LDS (two buffers of B2 doubles each)
+inline int stage_blocks_for(int dim, int nc) {
+    const int m = nc - 1, bs = dim == 2 ? m : m * m, nb = m;
+    const size_t pair = 2 * sizeof(double) * (size_t)bs * bs;
+    const int most = (nb + 1) / 2;   // pivot blocks inverted together at the first level
+    return (int)std::min<size_t>(most, kLdsLimit / pair);
+}
+
 template <typename K>
 int launch_small(K kern_lds, K kern_glb, size_t bytes, Args& a, hipStream_t s) {
     a.use_lds = bytes <= kLdsLimit;
-    size_t shm = a.use_lds ? bytes : 0;
+    const int dim = a.gc.dim;
+    a.stage_blocks = a.use_lds ? 0 : stage_blocks_for(dim, a.nc);
+    const int m = a.nc - 1, bs = dim == 2 ? m : m * m;
+    size_t shm = a.use_lds ? bytes : 2 * sizeof(double) * (size_t)bs * bs * a.stage_blocks;
     K kern = a.use_lds ? kern_lds : kern_glb;
     if (shm > 64 * 1024) {
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -110,3 +110,18 @@ def test_fixed_iteration_count_variant_reaches_the_same_solution(fixed):
     d = u.cpu().numpy() - np.asarray(rec["u_ref"])
     assert math.sqrt(d @ (M @ d)) < 1e-8
     assert res.newton_total < conv.newton_total
+
+
+def test_fixed_schedule_with_global_memory_small_solves_matches_oracle():
+    # coarsest h = 1/8 in 3D: N_H = 343, 49 x 49 blocks; the small-solve arena lives in
+    # global memory and the block inversions go through LDS in groups
+    from oracle import fmg as ofmg
+    prob = W.Problem(3, 8, 1, (1.0, 1.0, 1.0), 0.0, 10.0)
+    ref = ofmg.fmg(prob, W.Options(), hierarchy=oracle_hierarchy(prob))
+    res, u = _solve(prob, W.Options())
+    assert len(res.history) == len(ref.history)
+    for a, (_, _, b) in zip(res.history, ref.history):
+        assert a == pytest.approx(b, rel=1e-10)
+    h = oracle_hierarchy(prob)
+    d = u.cpu().numpy() - ref.u
+    assert math.sqrt(d @ (h.M[h.L - 1] @ d)) < 1e-9
