@@ -423,9 +423,13 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
         __syncthreads();
         return;
     }
+    // with a global-memory arena the border accumulates in the LDS staging area
+    const bool staged = ar.stage_blocks > 0 && (size_t)(2 * N) <= 2 * (size_t)ar.stage_blocks * ar.z.B2;
+    double* aH = staged ? ar.stage : ar.aH;
+    double* bH = staged ? ar.stage + N : ar.bH;
     for (int i = threadIdx.x; i < N; i += kThreads) {
-        ar.aH[i] = 0.0;
-        ar.bH[i] = 0.0;
+        aH[i] = 0.0;
+        bH[i] = 0.0;
     }
     __syncthreads();
     for (int color = 0; color < (1 << D); ++color) {
@@ -440,8 +444,8 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
                     constexpr int v = decltype(vc)::value;
                     const int nd = vert_node<D, t, v>(C0, C1, C2, m);
                     if (nd >= 0) {
-                        ar.aH[nd] += mo[L::KG + v] + mo[L::AW1 + v];
-                        ar.bH[nd] += mo[L::B1 + v];
+                        aH[nd] += mo[L::KG + v] + mo[L::AW1 + v];
+                        bH[nd] += mo[L::B1 + v];
                     }
                     v3[2] += mo[L::B1 + v];
                 });
@@ -450,6 +454,12 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
             });
         }
         __syncthreads();
+    }
+    if (staged) {
+        for (int i = threadIdx.x; i < N; i += kThreads) {
+            ar.aH[i] = aH[i];
+            ar.bH[i] = bH[i];
+        }
     }
     bsum<3>(ar.red, v3);
     if (threadIdx.x == 0) {
@@ -629,9 +639,20 @@ __device__ __forceinline__ void assemble_S_colours(Arena<D, AUG>& ar, const Args
     const double H = 1.0 / nc;
     const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
     const double c = AUG ? x[N] : 0.0;
-    for (int t = threadIdx.x; t < N * NS; t += kThreads) ar.Sst[t] = 0.0;
+    // with a global-memory arena the rows, the border and x live in the LDS staging area
+    // while the passes scatter into them (copied out at the end)
+    const bool staged = ar.stage_blocks > 0 &&
+                        (size_t)(N * NS + 2 * N + 2) <= 2 * (size_t)ar.stage_blocks * ar.z.B2;
+    double* Sst = staged ? ar.stage : ar.Sst;
+    double* sH = staged ? ar.stage + (size_t)N * NS : ar.sH;
+    if (staged) {
+        double* xs = ar.stage + (size_t)N * NS + N;
+        for (int i = threadIdx.x; i < N + 1; i += kThreads) xs[i] = x[i];
+        x = xs;
+    }
+    for (int t = threadIdx.x; t < N * NS; t += kThreads) Sst[t] = 0.0;
     if (AUG)
-        for (int i = threadIdx.x; i < N; i += kThreads) ar.sH[i] = 0.0;
+        for (int i = threadIdx.x; i < N; i += kThreads) sH[i] = 0.0;
     __syncthreads();
     double sU = 0.0;
     for (int color = 0; color < NCV; ++color) {
@@ -663,12 +684,12 @@ __device__ __forceinline__ void assemble_S_colours(Arena<D, AUG>& ar, const Args
                             if (nd[aa] >= 0) {
                                 double Sr[V], sh = 0.0;
                                 elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
-                                double* row = ar.Sst + (size_t)nd[aa] * NS;
+                                double* row = Sst + (size_t)nd[aa] * NS;
                                 static_for<V>([&](auto bc) {
                                     constexpr int bb = decltype(bc)::value;
                                     if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
                                 });
-                                if (AUG) ar.sH[nd[aa]] += sh;
+                                if (AUG) sH[nd[aa]] += sh;
                             }
                             if (AUG && aa == 0) sU += elem_corner<D>(U, UU, mo, c);
                         }
@@ -676,6 +697,12 @@ __device__ __forceinline__ void assemble_S_colours(Arena<D, AUG>& ar, const Args
                 });
             }
         }
+        __syncthreads();
+    }
+    if (staged) {
+        for (int t = threadIdx.x; t < N * NS; t += kThreads) ar.Sst[t] = Sst[t];
+        if (AUG)
+            for (int i = threadIdx.x; i < N; i += kThreads) ar.sH[i] = sH[i];
         __syncthreads();
     }
     if (AUG) {
