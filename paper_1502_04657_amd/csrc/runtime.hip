@@ -136,7 +136,11 @@ struct Task {
     bool keep_ws = false;             // server: workspace held until poll copies u out
 };
 
-// Streams, events and pinned host mirrors of the slots; the scheduling pass.
+// Streams, events and pinned host mirrors of the slots, and the scheduling pass.  Several
+// host threads pump at once (kernel launches cost microseconds of host time each, so one
+// thread enqueueing for many solves would limit the device): worker w of nw owns slots
+// w, w + nw, ...; the queue, the pool, the finished list and the slot table are shared and
+// guarded by one mutex, held only around their updates, never across HIP launches.
 class Scheduler {
   public:
     int init(int slots, hipStream_t user) {
@@ -144,13 +148,14 @@ class Scheduler {
         slots_ = slots;
         str_.assign(slots, nullptr);
         ev_.assign(slots, nullptr);
+        uev_.assign(slots, nullptr);
         busy_.assign(slots, nullptr);
         for (int i = 0; i < slots; ++i) {
             FMG_HIP_CHECK(hipStreamCreateWithFlags(&str_[i], hipStreamNonBlocking));
             FMG_HIP_CHECK(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
+            FMG_HIP_CHECK(hipEventCreateWithFlags(&uev_[i], hipEventDisableTiming));
         }
         FMG_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&host_), sizeof(JobHost) * slots, hipHostMallocDefault));
-        FMG_HIP_CHECK(hipEventCreateWithFlags(&user_ev_, hipEventDisableTiming));
         return 0;
     }
     void destroy() {
@@ -158,76 +163,90 @@ class Scheduler {
             if (s) (void)hipStreamDestroy(s);
         for (auto e : ev_)
             if (e) (void)hipEventDestroy(e);
-        if (user_ev_) (void)hipEventDestroy(user_ev_);
+        for (auto e : uev_)
+            if (e) (void)hipEventDestroy(e);
         if (host_) (void)hipHostFree(host_);
         str_.clear();
         ev_.clear();
+        uev_.clear();
         host_ = nullptr;
-        user_ev_ = nullptr;
     }
-    bool idle() const {
-        for (auto* t : busy_)
-            if (t) return false;
+    int slots() const { return slots_; }
+    // with mu held
+    bool idle(int w, int nw) const {
+        for (int i = w; i < slots_; i += nw)
+            if (busy_[i]) return false;
         return true;
     }
-    // Admit queued tasks (FIFO; the head blocks the queue until it fits) and advance running
-    // ones.  Returns the number of tasks that changed state; finished tasks are appended to
-    // `done`.  Launch failures end the task with that status.
-    int pump(std::deque<Task*>& queue, Pool& pool, std::vector<Task*>& done) {
+    // One pass over the slots of worker w: advance running tasks whose last chunk has
+    // completed, then fill free slots from the queue (FIFO; the head blocks the queue until
+    // its footprint fits the pool).  Returns the number of tasks that changed state;
+    // finished tasks are appended to `done`.  Launch failures end the task with that status.
+    int pump(int w, int nw, std::mutex& mu, std::deque<Task*>& queue, Pool& pool, std::vector<Task*>& done,
+             bool admit = true) {
         int changes = 0;
-        for (int i = 0; i < slots_; ++i) {
-            Task* t = busy_[i];
-            if (!t) continue;
-            const hipError_t q = hipEventQuery(ev_[i]);
-            if (q == hipErrorNotReady) continue;
-            int rc = (q == hipSuccess) ? job_step(t->job) : set_error(FMG_EHIP, "event query failed");
-            if (!rc && t->job.phase != 3) continue;   // next chunk enqueued
-            finish(i, rc, pool, done);
-            ++changes;
-        }
-        while (!queue.empty()) {
-            Task* t = queue.front();
-            int slot = -1;
-            for (int i = 0; i < slots_; ++i)
-                if (!busy_[i]) { slot = i; break; }
-            if (slot < 0 || !pool.alloc(t->bytes, &t->off)) break;
-            queue.pop_front();
-            start(slot, t, pool, done);
-            ++changes;
+        for (int i = w; i < slots_; i += nw) {
+            Task* t = busy_[i];   // written only by this worker (under mu)
+            if (t) {
+                const hipError_t q = hipEventQuery(ev_[i]);
+                if (q == hipErrorNotReady) continue;
+                const int rc = (q == hipSuccess) ? job_step(t->job) : set_error(FMG_EHIP, "event query failed");
+                if (!rc && t->job.phase != 3) continue;   // next chunk enqueued
+                finish(i, rc, mu, pool, done);
+                ++changes;
+            }
+            if (!admit) continue;
+            Task* nt = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!queue.empty() && pool.alloc(queue.front()->bytes, &queue.front()->off)) {
+                    nt = queue.front();
+                    queue.pop_front();
+                    nt->state = Task::RUNNING;
+                    busy_[i] = nt;
+                }
+            }
+            if (nt) {
+                start(i, nt, mu, pool, done);
+                ++changes;
+            }
         }
         return changes;
     }
 
   private:
-    void start(int i, Task* t, Pool& pool, std::vector<Task*>& done) {
-        t->state = Task::RUNNING;
+    void start(int i, Task* t, std::mutex& mu, Pool& pool, std::vector<Task*>& done) {
         t->slot = i;
         t->t_admit = std::chrono::steady_clock::now();
-        busy_[i] = t;
         SolveJob& j = t->job;
         j.ws = pool.base() + t->off;
         j.s = str_[i];
         j.ev = ev_[i];
         j.host = host_ + i;
-        // work the caller enqueued on its stream before the submission comes first
+        // work the caller enqueued on its stream before the admission comes first
         int rc = 0;
-        if (hipEventRecord(user_ev_, user_) != hipSuccess || hipStreamWaitEvent(str_[i], user_ev_, 0) != hipSuccess)
+        if (hipEventRecord(uev_[i], user_) != hipSuccess || hipStreamWaitEvent(str_[i], uev_[i], 0) != hipSuccess)
             rc = set_error(FMG_EHIP, "ordering after the caller's stream failed");
         if (!rc) rc = job_start(j);
-        if (rc) finish(i, rc, pool, done);
+        if (rc) finish(i, rc, mu, pool, done);
     }
-    void finish(int i, int rc, Pool& pool, std::vector<Task*>& done) {
+    void finish(int i, int rc, std::mutex& mu, Pool& pool, std::vector<Task*>& done) {
         Task* t = busy_[i];
+        int status;
+        std::string msg;
         if (rc) {
             // a launch failed: let what was enqueued drain before the memory is reused
             (void)hipStreamSynchronize(str_[i]);
-            t->rc = rc;
-            t->msg = g_err_message();
+            status = rc;
+            msg = fmg_last_error();
             t->res.status = rc;
         } else {
-            t->rc = job_result(t->job, &t->res);
-            if (t->rc) t->msg = g_err_message();
+            status = job_result(t->job, &t->res);
+            if (status) msg = fmg_last_error();
         }
+        std::lock_guard<std::mutex> lk(mu);
+        t->rc = status;
+        t->msg = msg;
         t->t_done = std::chrono::steady_clock::now();
         t->state = Task::DONE;
         t->job.host = nullptr;
@@ -239,16 +258,17 @@ class Scheduler {
         busy_[i] = nullptr;
         done.push_back(t);
     }
-    static std::string g_err_message() { return std::string(fmg_last_error()); }
 
     hipStream_t user_ = nullptr;
     int slots_ = 0;
     std::vector<hipStream_t> str_;
-    std::vector<hipEvent_t> ev_;
+    std::vector<hipEvent_t> ev_, uev_;
     std::vector<Task*> busy_;
     JobHost* host_ = nullptr;
-    hipEvent_t user_ev_ = nullptr;
 };
+
+// host threads that enqueue for a scheduler
+constexpr int kHostThreads = 8;
 
 int validate(const fmg_problem* p, const fmg_options* o, size_t* bytes) {
     if (int rc = check_problem(p)) return rc;
@@ -276,23 +296,30 @@ struct fmg_server {
     std::map<uint64_t, std::unique_ptr<fmg::Task>> tasks;
     uint64_t next_ticket = 1;
     bool stop = false;
-    int worker_rc = 0;
-    std::thread worker;
+    std::vector<std::thread> workers;
 
-    void run() {
+    // worker w of nw: pumps its slots until the server stops and its slots are idle
+    void run(int w, int nw) {
         (void)hipSetDevice(device);
         std::vector<fmg::Task*> done;
         for (;;) {
-            std::unique_lock<std::mutex> lk(mu);
-            if (stop) {
-                // no new admissions; let running solves finish so their memory is quiet
-                queue.clear();
-                if (sched.idle()) break;
+            bool stopping;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                stopping = stop;
+                if (stopping) {
+                    queue.clear();   // not admitted yet: dropped with the server
+                    if (sched.idle(w, nw)) break;
+                }
             }
-            const int changes = sched.pump(queue, pool, done);
+            const int changes = sched.pump(w, nw, mu, queue, pool, done, !stopping);
             done.clear();
-            if (changes) cv.notify_all();
-            else cv.wait_for(lk, std::chrono::microseconds(20));
+            if (changes) {
+                cv.notify_all();
+            } else {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait_for(lk, std::chrono::microseconds(20));
+            }
         }
         cv.notify_all();
     }
@@ -357,9 +384,24 @@ int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* 
         queue.push_back(t.get());
     }
     std::vector<Task*> done;
-    while (done.size() < (size_t)count) {
-        if (!sched.pump(queue, pool, done)) std::this_thread::sleep_for(std::chrono::microseconds(10));
-    }
+    std::mutex mu;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const int nw = std::min(sched.slots(), kHostThreads);
+    auto work = [&](int w) {
+        if (w) (void)hipSetDevice(dev);
+        for (;;) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (done.size() == (size_t)count) return;
+            }
+            if (!sched.pump(w, nw, mu, queue, pool, done)) std::this_thread::sleep_for(std::chrono::microseconds(10));
+        }
+    };
+    std::vector<std::thread> helpers;
+    for (int w = 1; w < nw; ++w) helpers.emplace_back(work, w);
+    work(0);
+    for (auto& th : helpers) th.join();
     sched.destroy();
     pool.destroy();
     int first = 0;
@@ -405,7 +447,8 @@ fmg_server* fmg_server_create(size_t hbm_budget, int32_t max_slots, void* stream
         set_error(FMG_ENOMEM, "%s", m.c_str());
         return nullptr;
     }
-    sv->worker = std::thread([sv] { sv->run(); });
+    const int nw = std::min<int>(max_slots, kHostThreads);
+    for (int w = 0; w < nw; ++w) sv->workers.emplace_back([sv, w, nw] { sv->run(w, nw); });
     return sv;
 }
 
@@ -472,7 +515,8 @@ void fmg_server_destroy(fmg_server* sv) {
         sv->stop = true;
         sv->cv.notify_all();
     }
-    if (sv->worker.joinable()) sv->worker.join();
+    for (auto& th : sv->workers)
+        if (th.joinable()) th.join();
     sv->sched.destroy();
     sv->pool.destroy();
     delete sv;
