@@ -857,21 +857,6 @@ __device__ __forceinline__ Ops16 ops_mm(const Tile& t, const double* A, bool ta,
     }
     return o;
 }
-// op(A) times R right-hand sides X (column q = x[q*N + k])
-__device__ __forceinline__ Ops16 ops_mv(const Tile& t, const double* A, bool ta, const double* x, int N, int R,
-                                        int bs, double s) {
-    Ops16 o;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = 4 * j + t.kq;
-        const bool oka = t.i < bs && k < bs, okb = k < bs && t.i < R;
-        const double a = A[oka ? (ta ? k * bs + t.i : t.i * bs + k) : 0];
-        const double b = x[okb ? (size_t)t.i * N + k : 0];
-        o.av[j] = oka ? s * a : 0.0;
-        o.bv[j] = okb ? b : 0.0;
-    }
-    return o;
-}
 __device__ __forceinline__ d4_t mfma16(const Ops16& o, d4_t c) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(o.av[j], o.bv[j], c, 0, 0, 0);
@@ -881,11 +866,6 @@ __device__ __forceinline__ d4_t mfma16(const Ops16& o, d4_t c) {
 __device__ __forceinline__ d4_t mm16(const Tile& t, const double* A, bool ta, const double* B, bool tb, int bs,
                                      double s, d4_t c) {
     return mfma16(ops_mm(t, A, ta, B, tb, bs, s), c);
-}
-// c += s * op(A) X for a bs x bs block A and R right-hand sides X
-__device__ __forceinline__ d4_t mv16(const Tile& t, const double* A, bool ta, const double* x, int N, int R, int bs,
-                                     double s, d4_t c) {
-    return mfma16(ops_mv(t, A, ta, x, N, R, bs, s), c);
 }
 __device__ __forceinline__ d4_t load16(const Tile& t, const double* M, int bs) {
     d4_t c;
@@ -1037,12 +1017,43 @@ __device__ __forceinline__ int bcr_levels16(Arena<D, AUG>& ar, double scale) {
     return neg + r0;
 }
 
-// block solve for bs <= 16: one wavefront per block, all R right-hand sides in one product
+// Block-vector products for bs <= 16 on the vector ALU.  With one to three right-hand sides
+// a 16 x 16 x 4 FP64 matrix instruction would leave most of its columns empty, and on this
+// chip FP64 matrix and vector throughput are equal, so a wavefront splits each row's dot
+// product over four lanes instead: lane (i = l % 16, kq = l / 16) takes the columns
+// k = 4 j + kq, and two cross-lane additions (xor 16, xor 32) give every lane the sum of
+// row i.  All four lanes of a row then hold the same value, so lane kq stores column kq.
+template <int R>
+__device__ __forceinline__ void mvq_acc(const Tile& t, const double* A, bool ta, const double* x, int N, int bs,
+                                        double s, double (&acc)[R]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * j + t.kq;
+        const bool ok = t.i < bs && k < bs;
+        const double a = s * A[ok ? (ta ? k * bs + t.i : t.i * bs + k) : 0];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double b = x[k < bs ? (size_t)q * N + k : 0];
+            acc[q] = fma(ok ? a : 0.0, b, acc[q]);
+        }
+    }
+}
+template <int R>
+__device__ __forceinline__ void mvq_reduce(double (&acc)[R]) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        acc[q] += __shfl_xor(acc[q], 16, 64);
+        acc[q] += __shfl_xor(acc[q], 32, 64);
+    }
+}
+// block solve for bs <= 16: one wavefront per block, all R (<= 4) right-hand sides at once
 template <int D, bool AUG, int R>
 __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
+    static_assert(R >= 1 && R <= 4, "one lane quarter stores each right-hand side");
     const int N = ar.z.N, nb = ar.z.nb, bs = ar.z.bs, B2 = ar.z.B2;
     const int wid = threadIdx.x >> 6;
     const Tile t = tile_lane();
+    const bool writer = t.i < bs;
     __syncthreads();
     int top = 1;
     while (2 * top < nb) top *= 2;
@@ -1052,32 +1063,29 @@ __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
         #pragma unroll 1
         for (int ka = wid; ka < na; ka += kWaves) {
             const int aa = 2 * st * ka, e1 = aa + st, e0 = aa - st;
-            // (a missing neighbour contributes a zero operand set)
-            const Ops16 o1 = ops_mv(t, ar.Fm + (size_t)(e1 < nb ? e1 : aa) * B2, true, rhs + (e1 < nb ? e1 : aa) * bs,
-                                    N, R, bs, e1 < nb ? 1.0 : 0.0);
-            const Ops16 o0 = ops_mv(t, ar.Rm + (size_t)(e0 >= 0 ? e0 : aa) * B2, true, rhs + (e0 >= 0 ? e0 : aa) * bs,
-                                    N, R, bs, e0 >= 0 ? 1.0 : 0.0);
-            d4_t c = {0.0, 0.0, 0.0, 0.0};
-            c = mfma16(o1, c);
-            c = mfma16(o0, c);
+            double acc[R];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = t.kq + 4 * r;
-                if (row < bs && t.i < R) rhs[(size_t)t.i * N + aa * bs + row] -= c[r];
-            }
+            for (int q = 0; q < R; ++q) acc[q] = 0.0;
+            if (e1 < nb) mvq_acc<R>(t, ar.Fm + (size_t)e1 * B2, true, rhs + e1 * bs, N, bs, 1.0, acc);
+            if (e0 >= 0) mvq_acc<R>(t, ar.Rm + (size_t)e0 * B2, true, rhs + e0 * bs, N, bs, 1.0, acc);
+            mvq_reduce<R>(acc);
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (writer && t.kq == q) rhs[(size_t)q * N + aa * bs + t.i] -= acc[q];
         }
         __syncthreads();
     }
     // last block, then up: x_e = P_e b_e - G_l(e) x_l - G_r(e) x_r (in place: only this
-    // wavefront reads b_e, and it has read it before writing)
+    // wavefront reads b_e, and every lane has read it before the reduction)
     if (wid == 0) {
-        d4_t c = {0.0, 0.0, 0.0, 0.0};
-        c = mv16(t, ar.Dm, false, rhs, N, R, bs, 1.0, c);
+        double acc[R];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = t.kq + 4 * r;
-            if (row < bs && t.i < R) rhs[(size_t)t.i * N + row] = c[r];
-        }
+        for (int q = 0; q < R; ++q) acc[q] = 0.0;
+        mvq_acc<R>(t, ar.Dm, false, rhs, N, bs, 1.0, acc);
+        mvq_reduce<R>(acc);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (writer && t.kq == q) rhs[(size_t)q * N + t.i] = acc[q];
     }
     __syncthreads();
     if (nb > 1) {
@@ -1087,19 +1095,16 @@ __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
             #pragma unroll 1
             for (int i = wid; i < ne; i += kWaves) {
                 const int e = st * (2 * i + 1), l = e - st, rr = e + st;
-                const Ops16 op = ops_mv(t, ar.Dm + (size_t)e * B2, false, rhs + e * bs, N, R, bs, 1.0);
-                const Ops16 ol = ops_mv(t, ar.Fm + (size_t)e * B2, false, rhs + l * bs, N, R, bs, -1.0);
-                const Ops16 orr = ops_mv(t, ar.Rm + (size_t)e * B2, false, rhs + (rr < nb ? rr : l) * bs, N, R, bs,
-                                         rr < nb ? -1.0 : 0.0);
-                d4_t c = {0.0, 0.0, 0.0, 0.0};
-                c = mfma16(op, c);
-                c = mfma16(ol, c);
-                c = mfma16(orr, c);
+                double acc[R];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = t.kq + 4 * r;
-                    if (row < bs && t.i < R) rhs[(size_t)t.i * N + e * bs + row] = c[r];
-                }
+                for (int q = 0; q < R; ++q) acc[q] = 0.0;
+                mvq_acc<R>(t, ar.Dm + (size_t)e * B2, false, rhs + e * bs, N, bs, 1.0, acc);
+                mvq_acc<R>(t, ar.Fm + (size_t)e * B2, false, rhs + l * bs, N, bs, -1.0, acc);
+                if (rr < nb) mvq_acc<R>(t, ar.Rm + (size_t)e * B2, false, rhs + rr * bs, N, bs, -1.0, acc);
+                mvq_reduce<R>(acc);
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (writer && t.kq == q) rhs[(size_t)q * N + e * bs + t.i] = acc[q];
             }
             __syncthreads();
         }
