@@ -209,6 +209,7 @@ struct Arena {
     double* aH; double* bH; double* sH; double* sc; double* red;
     double* Dm; double* Fm; double* Rm;            // block factor (nb blocks each)
     double* S1; double* S2;                        // scratch
+    bool s_stale = false;                          // Sst, sH, sc[3] not at the current x
 
     __device__ void carve(double* base, int nc) {
         z = sizes<D, AUG>(nc);
@@ -767,6 +768,115 @@ __device__ __forceinline__ void apply(Arena<D, AUG>& ar, const Args& a, double z
         }
         ar.sc[4] = v[0];
         ar.sc[5] = v[1];
+    }
+    __syncthreads();
+}
+
+// Whether apply_direct can run: 2D bordered solves whose per-simplex values fit the
+// scratch S1, S2 (contiguous; free between factorisations and block solves).
+template <int D, bool AUG>
+__device__ __forceinline__ bool direct_ok(const Arena<D, AUG>& ar) {
+    return D == 2 && AUG && (size_t)ar.z.nel * (D + 1) <= (size_t)ar.z.sz1 + (size_t)ar.z.h * ar.z.B2;
+}
+
+// y = (A + zs S) x and z = B x (with borders) as apply() gives them, without the stencil of
+// S(x).  With w = c u~ + u_H, row i of S(x) x plus c times the border column is the integral
+// of w^3 phi_i, and the border row's share is the integral of w^3 u~.  One pass over the
+// simplices evaluates the first for each vertex (into S1, S2) and sums the second; a pass
+// over the nodes then adds the values of the simplices around each node in a fixed order.
+// The chord steps need this residual but not the Jacobian, so S(x) is assembled only when
+// the Jacobian is refactored or its border columns are frozen again.
+template <int D, bool AUG>
+__device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, double zs, const double* x, double* y,
+                                             double* z) {
+    static_assert(D == 2 && AUG, "two-dimensional bordered solves only");
+    constexpr int NE = Geo<D>::NE;
+    constexpr int V = D + 1;
+    constexpr int NCV = 1 << D;
+    using L = MomLayout<D>;
+    const int N = ar.z.N, nc = a.nc, m = ar.z.m;
+    const double H = 1.0 / nc;
+    const double Hd = H * H;
+    const double vol = 0.5 * H * H;
+    const double c = x[N];
+    double* tv = ar.S1;   // nel x V
+    double sb = 0.0;
+    for (int e = threadIdx.x; e < ar.z.nel; e += kThreads) {
+        const int cl = e / NE, te = e - cl * NE;
+        const int C0 = cl % nc, C1 = cl / nc;
+        dispatch<NE>(te, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            double U[V];
+            static_for<V>([&](auto vc) {
+                constexpr int v = decltype(vc)::value;
+                const int nd = vert_node<D, t, v>(C0, C1, 0, m);
+                U[v] = nd >= 0 ? x[nd] : 0.0;
+            });
+            double UU[V * (V + 1) / 2];
+#pragma unroll
+            for (int p = 0; p < V; ++p)
+#pragma unroll
+                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+            const double* mo = a.mom + (size_t)e * L::SIZE;
+            double su = 0.0;
+            static_for<V>([&](auto ac) {
+                constexpr int aa = decltype(ac)::value;
+                double Sr[V], sh = 0.0;
+                elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
+                double r = c * sh;
+#pragma unroll
+                for (int b = 0; b < V; ++b) r += Sr[b] * U[b];
+                tv[(size_t)e * V + aa] = r;
+                su += U[aa] * sh;
+            });
+            sb += su + c * elem_corner<D>(U, UU, mo, c);
+        });
+    }
+    __syncthreads();
+    double v[5] = {0.0, 0.0, 0.0, 0.0, sb};
+    for (int i = threadIdx.x; i < N; i += kThreads) {
+        int P[3];
+        node_pos<D>(i, m, P);
+        const double X[3] = {P[0] * H, P[1] * H, 0.0};
+        double yi = 0.0, zi = 0.0, gi = 0.0;
+        for_slots<D>([&](auto sc_) {
+            constexpr int s = decltype(sc_)::value;
+            const int j = nbr<D, s>(P, m);
+            if (j >= 0) {
+                double as, bs;
+                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+                yi += as * x[j];
+                zi += bs * x[j];
+            }
+        });
+        static_for<NCV>([&](auto cvc) {
+            constexpr int cv = decltype(cvc)::value;
+            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1);
+            if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc) return;
+            const int cl = C0 + nc * C1;
+            for_simplices<D>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                constexpr int aa = VertOf<D, t, cv>::value;
+                if constexpr (aa >= 0) gi += tv[(size_t)(cl * NE + t) * V + aa];
+            });
+        });
+        yi += zs * gi + ar.aH[i] * c;
+        zi += ar.bH[i] * c;
+        v[2] += ar.aH[i] * x[i];
+        v[3] += ar.bH[i] * x[i];
+        y[i] = yi;
+        z[i] = zi;
+        v[0] += x[i] * yi;
+        v[1] += x[i] * zi;
+    }
+    bsum<5>(ar.red, v);
+    if (threadIdx.x == 0) {
+        const double yU = v[2] + ar.sc[0] * c + zs * v[4];
+        const double zU = v[3] + ar.sc[1] * c;
+        y[N] = yU;
+        z[N] = zU;
+        ar.sc[4] = v[0] + c * yU;
+        ar.sc[5] = v[1] + c * zU;
     }
     __syncthreads();
 }
@@ -1429,10 +1539,18 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
     for (int it = 0; it <= a.max_iter; ++it) {
         FMG_TCNT(8);
         FMG_T0(t_as);
-        assemble_S<D, AUG>(ar, a, ar.x);
+        // a chord step reuses the frozen Jacobian and border columns: residual only
+        const bool direct = frozen && !need_fresh && direct_ok<D, AUG>(ar);
+        if (!direct) assemble_S<D, AUG>(ar, a, ar.x);
+        ar.s_stale = direct;
         FMG_TACC(1, t_as);
         FMG_T0(t_ap);
-        apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
+        if constexpr (D == 2 && AUG) {
+            if (direct) apply_direct<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
+            else apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
+        } else {
+            apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
+        }
         if (it == 0) mu = ar.sc[4] / ar.sc[5];
         const double F2 = 0.5 * (1.0 - ar.sc[5]);
         double fz[2] = {0.0, 0.0};
@@ -1595,6 +1713,10 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
 template <int D, bool AUG, bool MF>
 __device__ __forceinline__ int count_below(Arena<D, AUG>& ar, const Args& a, double zs, double sigma) {
     const int N = ar.z.N;
+    if (ar.s_stale) {   // the last steps evaluated the residual only
+        assemble_S<D, AUG>(ar, a, ar.x);
+        ar.s_stale = false;
+    }
     int neg = bcr_factor<D, AUG, MF>(ar, a, zs, sigma);
     if (neg < 0) return 1;
     if (AUG) {
