@@ -53,10 +53,40 @@ struct Phys {
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 // Warp (wavefront = 64 lanes) reduction of doubles.
+// ---- cross-lane sums without the LDS crossbar: DPP moves inside each row of 16 lanes,
+// the gfx950 permlane swaps across rows.  Each step adds two values that every lane of
+// the pair combines in the same order, so all lanes end with the same bits.
+__device__ inline double dbl_from(unsigned lo, unsigned hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return dbl_from(lo, hi);
+}
+// v(row 2r) + v(row 2r+1) at the same position of the row (rows of 16 lanes)
+__device__ inline double xsum16(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return dbl_from(lo[0], hi[0]) + dbl_from(lo[1], hi[1]);
+}
+// v(lane l mod 32) + v(32 + l mod 32)
+__device__ inline double xsum32(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return dbl_from(lo[0], hi[0]) + dbl_from(lo[1], hi[1]);
+}
+// sum over the 64 lanes of a full wavefront (all lanes active)
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of each half row
+    v += dpp_f64<0x140>(v);   // row_mirror: the other half of each row
+    return xsum32(xsum16(v));
 }
 
 }  // namespace fmg

@@ -1003,6 +1003,14 @@ __device__ __forceinline__ double recip(double p) {
     return fma(r, e, r);
 }
 
+// value of v in lane `lane` (uniform across the wavefront), through scalar registers
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double sel4(const d4_t& v, int r) {
     return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
 }
@@ -1024,21 +1032,23 @@ __device__ __forceinline__ int block_invert16(Arena<D, AUG>& ar, int first, int 
 #pragma unroll 1
         for (int k = 0; k < bs; ++k) {
             const int kr = k >> 2, kl = (k & 3) * 16;
-            const double piv = __shfl(sel4(m, kr), kl + k, 64);
-            if (!(fabs(piv) > 1e-15 * scale)) bad = 1;
-            if (piv < 0.0) ++neg;
-            const double inv = recip(piv);
-            const double pr = __shfl(sel4(m, kr), kl + t.i, 64);   // A[k][col]
+            // every cross-lane read of the step is issued before the reciprocal waits on one
+            const double rk = sel4(m, kr);                          // my entry of row k's group
+            const double pr = __shfl(rk, kl + t.i, 64);              // A[k][col]
             d4_t pc;                                                 // A[row][k] of my rows
 #pragma unroll
             for (int r = 0; r < 4; ++r) pc[r] = __shfl(m[r], t.kq * 16 + k, 64);
+            const double piv = readlane_f64(rk, kl + k);             // A[k][k], uniform
+            if (!(fabs(piv) > 1e-15 * scale)) bad = 1;
+            if (piv < 0.0) ++neg;
+            const double inv = recip(piv);
+            const double prinv = pr * inv;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = t.kq + 4 * r;
-                double v;
-                if (row == k) v = (t.i == k) ? inv : pr * inv;
-                else v = (t.i == k) ? -pc[r] * inv : m[r] - pc[r] * (pr * inv);
-                m[r] = v;
+                const double off = (t.i == k) ? -pc[r] * inv : fma(-pc[r], prinv, m[r]);
+                const double on = (t.i == k) ? inv : prinv;
+                m[r] = (row == k) ? on : off;
             }
         }
         store16(t, M, bs, m);
@@ -1131,8 +1141,8 @@ __device__ __forceinline__ int bcr_levels16(Arena<D, AUG>& ar, double scale) {
 // a 16 x 16 x 4 FP64 matrix instruction would leave most of its columns empty, and on this
 // chip FP64 matrix and vector throughput are equal, so a wavefront splits each row's dot
 // product over four lanes instead: lane (i = l % 16, kq = l / 16) takes the columns
-// k = 4 j + kq, and two cross-lane additions (xor 16, xor 32) give every lane the sum of
-// row i.  All four lanes of a row then hold the same value, so lane kq stores column kq.
+// k = 4 j + kq, and two cross-row additions (lane swaps across rows of 16) give every lane
+// the sum of row i.  All four lanes of a row then hold the same value, so lane kq stores column kq.
 template <int R>
 __device__ __forceinline__ void mvq_acc(const Tile& t, const double* A, bool ta, const double* x, int N, int bs,
                                         double s, double (&acc)[R]) {
@@ -1151,10 +1161,7 @@ __device__ __forceinline__ void mvq_acc(const Tile& t, const double* A, bool ta,
 template <int R>
 __device__ __forceinline__ void mvq_reduce(double (&acc)[R]) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        acc[q] += __shfl_xor(acc[q], 16, 64);
-        acc[q] += __shfl_xor(acc[q], 32, 64);
-    }
+    for (int q = 0; q < R; ++q) acc[q] = xsum32(xsum16(acc[q]));
 }
 // block solve for bs <= 16: one wavefront per block, all R (<= 4) right-hand sides at once
 template <int D, bool AUG, int R>
@@ -1590,6 +1597,7 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             FMG_T0(t_f);
             if (bcr_factor<D, AUG, MF>(ar, a, 3.0 * zs, mu) < 0) return -1;
             FMG_TACC(3, t_f);
+            FMG_TCNT(12);
             need_fresh = false;
             last_fresh = true;
             frozen = false;
@@ -1929,7 +1937,25 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         tt[6] = wall_clock64();
         for (int r = 0; r < reps; ++r) __syncthreads();
         tt[7] = wall_clock64();
+        unsigned long long tu[4];
+        tu[0] = wall_clock64();
+        if constexpr (MF) {
+            int sink = 0;
+            for (int r = 0; r < 10; ++r) sink += block_invert16<D, AUG>(ar, 1, 2, (ar.z.nb - 1) / 2, 1e-300);
+            __syncthreads();
+            tu[1] = wall_clock64();
+            for (int r = 0; r < 10; ++r) sink += block_invert16<D, AUG>(ar, 0, 1, 1, 1e-300);
+            __syncthreads();
+            tu[2] = wall_clock64();
+            for (int r = 0; r < 10; ++r) sink += bcr_levels16<D, AUG>(ar, 1e-300);
+            __syncthreads();
+            tu[3] = wall_clock64();
+            if (threadIdx.x == 0 && sink == 12345) g_small_t[31] = 1;
+        } else {
+            tu[1] = tu[2] = tu[3] = tu[0];
+        }
         if (threadIdx.x == 0) {
+            for (int k = 0; k < 3; ++k) atomicAdd(&g_small_t[9 + k], tu[k + 1] - tu[k]);
             for (int k = 0; k < 7; ++k) atomicAdd(&g_small_t[k], tt[k + 1] - tt[k]);
             atomicAdd(&g_small_t[7], 1ull);
             atomicAdd(&g_small_t[8], acc < 0.0 ? 1ull : 0ull);
