@@ -1144,18 +1144,34 @@ __device__ __forceinline__ int bcr_levels16(Arena<D, AUG>& ar, double scale) {
 // k = 4 j + kq, and two cross-row additions (lane swaps across rows of 16) give every lane
 // the sum of row i.  All four lanes of a row then hold the same value, so lane kq stores column kq.
 template <int R>
-__device__ __forceinline__ void mvq_acc(const Tile& t, const double* A, bool ta, const double* x, int N, int bs,
-                                        double s, double (&acc)[R]) {
+struct MvqOps {
+    double av[4], xv[R][4];
+};
+// operands of one product, loaded at fixed offsets from one base: entries outside the block
+// are read (the arena continues past every block and right-hand side) and zeroed in mvq_fma
+template <int R>
+__device__ __forceinline__ MvqOps<R> mvq_load(const Tile& t, const double* A, bool ta, const double* x, int N,
+                                              int bs) {
+    MvqOps<R> o;
+    const double* a0 = A + (ta ? t.kq * bs + t.i : t.i * bs + t.kq);
+    const int da = ta ? 4 * bs : 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o.av[j] = a0[j * da];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o.xv[q][j] = x[(size_t)q * N + 4 * j + t.kq];
+    return o;
+}
+// acc += s op(A) X over this lane's columns (s = 0 drops a missing neighbour)
+template <int R>
+__device__ __forceinline__ void mvq_fma(const Tile& t, const MvqOps<R>& o, int bs, double s, double (&acc)[R]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int k = 4 * j + t.kq;
-        const bool ok = t.i < bs && k < bs;
-        const double a = s * A[ok ? (ta ? k * bs + t.i : t.i * bs + k) : 0];
+        const double a = (t.i < bs && k < bs) ? s * o.av[j] : 0.0;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const double b = x[k < bs ? (size_t)q * N + k : 0];
-            acc[q] = fma(ok ? a : 0.0, b, acc[q]);
-        }
+        for (int q = 0; q < R; ++q) acc[q] = fma(a, k < bs ? o.xv[q][j] : 0.0, acc[q]);
     }
 }
 template <int R>
@@ -1183,8 +1199,12 @@ __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
             double acc[R];
 #pragma unroll
             for (int q = 0; q < R; ++q) acc[q] = 0.0;
-            if (e1 < nb) mvq_acc<R>(t, ar.Fm + (size_t)e1 * B2, true, rhs + e1 * bs, N, bs, 1.0, acc);
-            if (e0 >= 0) mvq_acc<R>(t, ar.Rm + (size_t)e0 * B2, true, rhs + e0 * bs, N, bs, 1.0, acc);
+            // (a missing neighbour reads block aa and is scaled by zero)
+            const int b1 = e1 < nb ? e1 : aa, b0 = e0 >= 0 ? e0 : aa;
+            const MvqOps<R> o1 = mvq_load<R>(t, ar.Fm + (size_t)b1 * B2, true, rhs + b1 * bs, N, bs);
+            const MvqOps<R> o0 = mvq_load<R>(t, ar.Rm + (size_t)b0 * B2, true, rhs + b0 * bs, N, bs);
+            mvq_fma<R>(t, o1, bs, e1 < nb ? 1.0 : 0.0, acc);
+            mvq_fma<R>(t, o0, bs, e0 >= 0 ? 1.0 : 0.0, acc);
             mvq_reduce<R>(acc);
 #pragma unroll
             for (int q = 0; q < R; ++q)
@@ -1198,7 +1218,7 @@ __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
         double acc[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) acc[q] = 0.0;
-        mvq_acc<R>(t, ar.Dm, false, rhs, N, bs, 1.0, acc);
+        mvq_fma<R>(t, mvq_load<R>(t, ar.Dm, false, rhs, N, bs), bs, 1.0, acc);
         mvq_reduce<R>(acc);
 #pragma unroll
         for (int q = 0; q < R; ++q)
@@ -1215,9 +1235,12 @@ __device__ __forceinline__ void bcr_solve16(Arena<D, AUG>& ar, double* rhs) {
                 double acc[R];
 #pragma unroll
                 for (int q = 0; q < R; ++q) acc[q] = 0.0;
-                mvq_acc<R>(t, ar.Dm + (size_t)e * B2, false, rhs + e * bs, N, bs, 1.0, acc);
-                mvq_acc<R>(t, ar.Fm + (size_t)e * B2, false, rhs + l * bs, N, bs, -1.0, acc);
-                if (rr < nb) mvq_acc<R>(t, ar.Rm + (size_t)e * B2, false, rhs + rr * bs, N, bs, -1.0, acc);
+                const MvqOps<R> op = mvq_load<R>(t, ar.Dm + (size_t)e * B2, false, rhs + e * bs, N, bs);
+                const MvqOps<R> ol = mvq_load<R>(t, ar.Fm + (size_t)e * B2, false, rhs + l * bs, N, bs);
+                const MvqOps<R> orr = mvq_load<R>(t, ar.Rm + (size_t)e * B2, false, rhs + (rr < nb ? rr : l) * bs, N, bs);
+                mvq_fma<R>(t, op, bs, 1.0, acc);
+                mvq_fma<R>(t, ol, bs, -1.0, acc);
+                mvq_fma<R>(t, orr, bs, rr < nb ? -1.0 : 0.0, acc);
                 mvq_reduce<R>(acc);
 #pragma unroll
                 for (int q = 0; q < R; ++q)
