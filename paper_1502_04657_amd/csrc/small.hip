@@ -954,16 +954,24 @@ struct Ops16 {
 };
 __device__ __forceinline__ Ops16 ops_mm(const Tile& t, const double* A, bool ta, const double* B, bool tb, int bs,
                                         double s) {
+    // fixed offsets from one base per operand (entries outside the block are read, the
+    // arena continues past every block, and zeroed)
     Ops16 o;
+    const double* a0 = A + (ta ? t.kq * bs + t.i : t.i * bs + t.kq);
+    const double* b0 = B + (tb ? t.i * bs + t.kq : t.kq * bs + t.i);
+    const int da = ta ? 4 * bs : 4, db = tb ? 4 : 4 * bs;
+    double a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j] = a0[j * da];
+        b[j] = b0[j * db];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int k = 4 * j + t.kq;
         const bool ok = t.i < bs && k < bs;
-        const int ia = ok ? (ta ? k * bs + t.i : t.i * bs + k) : 0;
-        const int ib = ok ? (tb ? t.i * bs + k : k * bs + t.i) : 0;
-        const double a = A[ia], b = B[ib];
-        o.av[j] = ok ? s * a : 0.0;
-        o.bv[j] = ok ? b : 0.0;
+        o.av[j] = ok ? s * a[j] : 0.0;
+        o.bv[j] = ok ? b[j] : 0.0;
     }
     return o;
 }
@@ -979,10 +987,13 @@ __device__ __forceinline__ d4_t mm16(const Tile& t, const double* A, bool ta, co
 }
 __device__ __forceinline__ d4_t load16(const Tile& t, const double* M, int bs) {
     d4_t c;
+    double v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = M[(t.kq + 4 * r) * bs + t.i];   // read past the block, zeroed
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = t.kq + 4 * r;
-        c[r] = (row < bs && t.i < bs) ? M[row * bs + t.i] : 0.0;
+        c[r] = (row < bs && t.i < bs) ? v[r] : 0.0;
     }
     return c;
 }
