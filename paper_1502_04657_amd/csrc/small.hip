@@ -1014,6 +1014,20 @@ __device__ __forceinline__ double recip(double p) {
     return fma(r, e, r);
 }
 
+// row group G (lanes 16 G .. 16 G + 15) of v copied to all four row groups
+template <int G>
+__device__ __forceinline__ double rowgroup_bcast(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    // permlane16_swap: [0] holds row groups (0, 0, 2, 2), [1] holds (1, 1, 3, 3)
+    const auto lo16 = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi16 = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const unsigned lo = (G & 1) ? lo16[1] : lo16[0], hi = (G & 1) ? hi16[1] : hi16[0];
+    // permlane32_swap: [0] repeats lanes 0..31, [1] repeats lanes 32..63
+    const auto lo32 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto hi32 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return (G & 2) ? dbl_from(lo32[1], hi32[1]) : dbl_from(lo32[0], hi32[0]);
+}
+
 // value of v in lane `lane` (uniform across the wavefront), through scalar registers
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -1022,9 +1036,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ double sel4(const d4_t& v, int r) {
-    return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
-}
 
 // Gauss-Jordan inversion of the pivot blocks Dm[first + step*i], i < cnt, one wavefront per
 // block with the block in registers (result layout of mm16); pivot rows and columns move
@@ -1040,16 +1051,20 @@ __device__ __forceinline__ int block_invert16(Arena<D, AUG>& ar, int first, int 
     for (int task = wid; task < cnt; task += kWaves) {
         double* M = ar.Dm + (size_t)(first + step * task) * B2;
         d4_t m = load16(t, M, bs);
-#pragma unroll 1
-        for (int k = 0; k < bs; ++k) {
-            const int kr = k >> 2, kl = (k & 3) * 16;
-            // every cross-lane read of the step is issued before the reciprocal waits on one
-            const double rk = sel4(m, kr);                          // my entry of row k's group
-            const double pr = __shfl(rk, kl + t.i, 64);              // A[k][col]
-            d4_t pc;                                                 // A[row][k] of my rows
+        // step k (unrolled: the lane moves take k as an immediate).  Row k of the block sits
+        // in row group k % 4 of the lanes, register k / 4; column k in lane k of each row.
+        static_for<16>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if (k >= bs) return;
+            constexpr int kr = k >> 2, g = k & 3;
+            const double rk = m[kr];
+            // A[k][col]: row group g copied to every row group (lane swaps across rows)
+            const double pr = rowgroup_bcast<g>(rk);
+            // A[row][k] of my rows: lane k of each row of 16
+            d4_t pc;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) pc[r] = __shfl(m[r], t.kq * 16 + k, 64);
-            const double piv = readlane_f64(rk, kl + k);             // A[k][k], uniform
+            for (int r = 0; r < 4; ++r) pc[r] = dpp_f64<0x150 + k>(m[r]);   // row_newbcast:k
+            const double piv = readlane_f64(rk, g * 16 + k);         // A[k][k], uniform
             if (!(fabs(piv) > 1e-15 * scale)) bad = 1;
             if (piv < 0.0) ++neg;
             const double inv = recip(piv);
@@ -1061,7 +1076,7 @@ __device__ __forceinline__ int block_invert16(Arena<D, AUG>& ar, int first, int 
                 const double on = (t.i == k) ? inv : prinv;
                 m[r] = (row == k) ? on : off;
             }
-        }
+        });
         store16(t, M, bs, m);
     }
     // combine the per-wavefront counts
