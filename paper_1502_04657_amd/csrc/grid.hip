@@ -321,29 +321,25 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
     const double h = g.h;
     const double X[3] = {i * h, j * h, k * h};
     constexpr int NS = (D == 2) ? kStencil2D : kStencil3D;
-    double mu = 0.0, mw = 0.0;
+    // (M_W u)_i = sum_o (sum_a w_a (X_a^2 m0_o + 2 X_a h M1_ao + h^2 M2_ao) + wc m0_o) u_o:
+    // the stencil sums of u against the constant tables m0, M1_a, M2_a first, then the
+    // position-dependent weights once per node
+    double mu = 0.0, s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
-        int64_t q;
-        double m0, cw = 0.0;
-        if (D == 2) {
-            q = p + kOff2D[o][0] + P * kOff2D[o][1];
-            m0 = kM0_2D[o];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-                cw += ph.w[a] * (X[a] * X[a] * m0 + 2.0 * X[a] * h * kM1_2D[a][o] + h * h * kM2_2D[a][o]);
-        } else {
-            q = p + kOff3D[o][0] + P * kOff3D[o][1] + S * kOff3D[o][2];
-            m0 = kM0_3D[o];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                cw += ph.w[a] * (X[a] * X[a] * m0 + 2.0 * X[a] * h * kM1_3D[a][o] + h * h * kM2_3D[a][o]);
-        }
-        cw += ph.wc * m0;
+        const int64_t q = (D == 2) ? p + kOff2D[o][0] + P * kOff2D[o][1]
+                                   : p + kOff3D[o][0] + P * kOff3D[o][1] + S * kOff3D[o][2];
         const double uq = u[q];
-        mu += m0 * uq;
-        mw += cw * uq;
+        mu += ((D == 2) ? kM0_2D[o] : kM0_3D[o]) * uq;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            s1[a] += ((D == 2) ? kM1_2D[a][o] : kM1_3D[a][o]) * uq;
+            s2[a] += ((D == 2) ? kM2_2D[a][o] : kM2_3D[a][o]) * uq;
+        }
     }
+    double mw = ph.wc * mu;
+#pragma unroll
+    for (int a = 0; a < D; ++a) mw += ph.w[a] * (X[a] * X[a] * mu + 2.0 * X[a] * h * s1[a] + h * h * s2[a]);
     const double hd = (D == 2) ? h * h : h * h * h;
     Mu = hd * mu;
     MWu = hd * mw;

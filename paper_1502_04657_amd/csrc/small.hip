@@ -26,8 +26,8 @@
 // goes back one step and the Jacobian is refactored there.  The fixed point is unchanged.
 //
 // On the coarsest space the iteration starts from the discrete sine mode and raises zeta in
-// geometric stages (factor 8 from a first stage <= 1, the step halved on failure); stages
-// before the last stop at a relative residual of 1e-8.
+// geometric stages (factor 8 from a first stage <= 2, the step halved on failure); stages
+// before the last stop at a relative residual of 1e-3.
 #include <utility>
 
 #include "kernels.h"
@@ -42,6 +42,10 @@ constexpr int kThreads = 256;               // four wavefronts
 #define FMG_SMALL_STAGE_TOL 1e-3
 #endif
 constexpr double kStageTol = FMG_SMALL_STAGE_TOL;   // residual for intermediate continuation stages
+#ifndef FMG_SMALL_FIRST_STAGE
+#define FMG_SMALL_FIRST_STAGE 2.0
+#endif
+constexpr double kFirstStage = FMG_SMALL_FIRST_STAGE;   // largest coupling of the first stage
 constexpr int kWaves = kThreads / 64;
 
 template <int D>
@@ -1906,7 +1910,7 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         iters = ok ? r : 0;
         reason = ok ? 0 : -r;
     } else {
-        // discrete sine mode, then zeta stages (first stage <= 1, factor 8); a failed stage
+        // discrete sine mode, then zeta stages (first stage <= 2, factor 8); a failed stage
         // goes back to the last converged iterate and retries with half the step
         const double H = 1.0 / a.nc;
         for (int i = tid; i < N; i += kThreads) {
@@ -1918,10 +1922,10 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         }
         __syncthreads();
         const double zeta = a.ph.zeta;
-        const bool direct = !(zeta > 1.0);
+        const bool direct = !(zeta > kFirstStage);
         const double lf = log(8.0);
         const double lt = direct ? 0.0 : log(zeta);
-        const int J = direct ? 0 : (int)ceil(lt / lf - 1e-12);
+        const int J = direct ? 0 : (int)ceil((lt - log(kFirstStage)) / lf - 1e-12);
         double lnext = lt - J * lf, step = lf, lcur = 0.0;
         bool have_cur = false;
         int first_tries = 0;
