@@ -143,6 +143,8 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
     T* xc = at<T>(ws, lo.xv[l - 1]);
     T* fc = at<T>(ws, lo.fv[l - 1]);
     if (lo.dim == 2 && nu_pre <= 2 && nu_post <= 2 && g_fused && !lo.cg) {
+        // a small level and everything below it: one workgroup, all levels in LDS
+        if (launch_vbottom2d<T>(lo.g.data(), l, x, f, nu_pre, nu_post, zero_x ? 1 : 0, s)) return;
         T* y = at<T>(ws, lo.tv[l]);
         launch_vpre2d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
         vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);

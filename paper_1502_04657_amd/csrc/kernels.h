@@ -50,6 +50,10 @@ template <typename T> bool launch_vpre2d(const Grid& g, const Grid& gc, const T*
                                          int nu, int zero_x, hipStream_t s);
 // levels above 256 cells per side use the wide tiles, smaller ones 16 x 16
 bool vpass2d_wide_tiles(const Grid& g);
+// levels l..0 of a 2D V-cycle in one workgroup (level-l mesh n <= 32, nu <= 2): x_l (+)= the
+// V-cycle's correction, bit-identical to the level-by-level passes; false if it does not apply
+template <typename T> bool launch_vbottom2d(const Grid* levels, int l, T* x, const T* f, int nu_pre, int nu_post,
+                                            int zero_x, hipStream_t s);
 template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc,
                                           int nu, hipStream_t s, hipEvent_t ev0 = nullptr,
                                           hipEvent_t ev1 = nullptr);

@@ -17,6 +17,7 @@
 
 #include <utility>
 
+#include "dst.h"
 #include "kernels.h"
 
 namespace fmg {
@@ -323,6 +324,131 @@ void post_launch(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, co
     }
 }
 
+// ---- the bottom of a V-cycle in one workgroup ------------------------------------------
+// Levels l, l-1, ..., 0 of a V-cycle whose level-l mesh is small: every level's x and f
+// stay in LDS for the whole cycle, so the 2 l + 1 launches of the level passes and of the
+// coarsest solve become one.  Measured on the 2D n = 2048 solve, this pays for the level
+// n = 32 only: from n = 64 on, one workgroup takes longer than the level passes spread over
+// the chip.  The steps are those of the unfused kernel sequence of grid.hip
+// (half sweeps R, B, R, ..., residual and P^T, exact coarsest solve, P x_c added, the post
+// sweeps) with the same expression at every node, so the result has the same bits.
+// Level q (mesh n_q = n_0 2^q) is a dense (n_q + 1)^2 array with its zero ring; the
+// coarsest-solve scratch follows the level arrays.
+#ifndef FMG_BOTTOM_THREADS
+#define FMG_BOTTOM_THREADS 512
+#endif
+#ifndef FMG_BOTTOM_MAX_N
+#define FMG_BOTTOM_MAX_N 32
+#endif
+constexpr int kBottomThreads = FMG_BOTTOM_THREADS;
+constexpr int kBottomMaxN = FMG_BOTTOM_MAX_N;
+constexpr int kBottomMaxLevels = 8;
+
+template <typename T>
+__host__ __device__ inline size_t bottom_level_elems(int n0, int l) {
+    size_t e = 0;
+    for (int q = 0; q <= l; ++q) {
+        const size_t p = (size_t)(n0 << q) + 1;
+        e += 2 * p * p;
+    }
+    return e;
+}
+// elements of the level arrays below level q (each level: x, then f)
+__device__ inline int bottom_off(int n0, int q) {
+    int e = 0;
+    for (int r = 0; r < q; ++r) e += 2 * ((n0 << r) + 1) * ((n0 << r) + 1);
+    return e;
+}
+template <typename T>
+inline size_t bottom_bytes(int n0, int l) {
+    const size_t m = (size_t)n0 - 1;
+    const size_t lv = (bottom_level_elems<T>(n0, l) * sizeof(T) + 7) / 8 * 8;
+    return lv + sizeof(double) * (m * m + m + 2 * m * m);
+}
+
+// nh alternating half sweeps, colour 0 first, of x <- (f + sum of the 4 neighbours) / 4
+template <typename T>
+__device__ inline void bottom_sweeps(T* X, const T* F, int n, int nh) {
+    const int P = n + 1, half = n / 2;
+    for (int h = 0; h < nh; ++h) {
+        const int c = h & 1;
+        for (int t = threadIdx.x; t < (n - 1) * half; t += blockDim.x) {
+            const int j = 1 + t / half, slot = t - (j - 1) * half;
+            const int i = (((1 + j) & 1) == c ? 1 : 2) + 2 * slot;
+            if (i > n - 1) continue;
+            const int p = i + P * j;
+            X[p] = gs2f<T>(F[p], X[p - 1], X[p + 1], X[p - P], X[p + P]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ inline T bottom_resid(const T* X, const T* F, int p, int P) {
+    return F[p] - (T(4) * X[p] - ((X[p - 1] + X[p + 1]) + (X[p - P] + X[p + P])));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBottomThreads) void k_vbottom2d(T* __restrict__ x, const T* __restrict__ f, Grid g,
+                                                              int n0, int l, int nh_pre, int nh_post, int zero_x) {
+    extern __shared__ double smem[];
+    // level arrays addressed as offsets from the LDS base (so every access stays an LDS access)
+    T* const base = reinterpret_cast<T*>(smem);
+    auto X = [&](int q) { return base + bottom_off(n0, q); };
+    auto F = [&](int q) { return base + bottom_off(n0, q) + ((n0 << q) + 1) * ((n0 << q) + 1); };
+    double* dsm = smem + (bottom_level_elems<T>(n0, l) * sizeof(T) + 7) / 8;
+    // lower levels start at zero (their rings stay zero); level l from global memory
+    for (int t = threadIdx.x; t < bottom_off(n0, l); t += blockDim.x) base[t] = T(0);
+    const int n = n0 << l, P = n + 1;
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
+        const int i = t % P, j = t / P;
+        const bool in = i >= 1 && i <= n - 1 && j >= 1 && j <= n - 1;
+        X(l)[t] = (in && !zero_x) ? x[i + g.pitch * j] : T(0);
+        F(l)[t] = in ? f[i + g.pitch * j] : T(0);
+    }
+    __syncthreads();
+    // down: pre sweeps, then f_{q-1} = P^T (f_q - K x_q)
+    for (int q = l; q >= 1; --q) {
+        const int nq = n0 << q, Pq = nq + 1, nc = nq / 2, Pc = nc + 1;
+        bottom_sweeps<T>(X(q), F(q), nq, nh_pre);
+        const T* Xq = X(q);
+        const T* Fq = F(q);
+        T* Fc = F(q - 1);
+        for (int t = threadIdx.x; t < (nc - 1) * (nc - 1); t += blockDim.x) {
+            const int I = 1 + t % (nc - 1), J = 1 + t / (nc - 1);
+            const int p = 2 * I + Pq * 2 * J;
+            T c = bottom_resid<T>(Xq, Fq, p, Pq);
+            T e = (bottom_resid<T>(Xq, Fq, p - 1, Pq) + bottom_resid<T>(Xq, Fq, p + 1, Pq)) +
+                  (bottom_resid<T>(Xq, Fq, p - Pq, Pq) + bottom_resid<T>(Xq, Fq, p + Pq, Pq)) +
+                  (bottom_resid<T>(Xq, Fq, p - 1 - Pq, Pq) + bottom_resid<T>(Xq, Fq, p + 1 + Pq, Pq));
+            Fc[I + Pc * J] = c + T(0.5) * e;
+        }
+        __syncthreads();
+    }
+    coarse_dst_solve<T>(F(0), X(0), n0 + 1, 0, n0, 2, dsm);
+    __syncthreads();
+    // up: x_q += P x_{q-1}, then the post sweeps
+    for (int q = 1; q <= l; ++q) {
+        const int nq = n0 << q, Pq = nq + 1, Pc = nq / 2 + 1;
+        const T* xc = X(q - 1);
+        T* Xq = X(q);
+        for (int t = threadIdx.x; t < (nq - 1) * (nq - 1); t += blockDim.x) {
+            const int i = 1 + t % (nq - 1), j = 1 + t / (nq - 1);
+            const int di = i & 1, dj = j & 1;
+            const int q0 = (i >> 1) + Pc * (j >> 1);
+            T v = xc[q0];
+            if (di | dj) v = T(0.5) * (v + xc[q0 + di + Pc * dj]);
+            Xq[i + Pq * j] += v;
+        }
+        __syncthreads();
+        bottom_sweeps<T>(Xq, F(q), nq, nh_post);
+    }
+    for (int t = threadIdx.x; t < (n - 1) * (n - 1); t += blockDim.x) {
+        const int i = 1 + t % (n - 1), j = 1 + t / (n - 1);
+        x[i + g.pitch * j] = X(l)[i + P * j];
+    }
+}
+
 }  // namespace
 
 bool vpass2d_wide_tiles(const Grid& g) { return g.n > kSmallLevel; }
@@ -355,5 +481,31 @@ template bool launch_vpost2d<double>(const Grid&, const Grid&, const double*, do
                                      const double*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template bool launch_vpost2d<float>(const Grid&, const Grid&, const float*, float*, const float*, const float*, int,
                                     hipStream_t, hipEvent_t, hipEvent_t);
+
+
+template <typename T>
+bool launch_vbottom2d(const Grid* levels, int l, T* x, const T* f, int nu_pre, int nu_post, int zero_x,
+                      hipStream_t s) {
+    const int n0 = levels[0].n;
+    if (l < 1 || l >= kBottomMaxLevels || levels[l].n > kBottomMaxN || levels[l].dim != 2 || nu_pre > 2 || nu_post > 2)
+        return false;
+    const size_t bytes = bottom_bytes<T>(n0, l);
+    if (bytes > 150 * 1024) return false;
+    // once per instantiation (thread-safe static initialisation)
+    static const bool attr = [] {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vbottom2d<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) == hipSuccess)
+            return true;
+        (void)hipGetLastError();
+        return false;
+    }();
+    if (!attr) return false;
+    const int nh_pre = nu_pre > 0 ? 2 * nu_pre + 1 : 0, nh_post = nu_post > 0 ? 2 * nu_post + 1 : 0;
+    hipLaunchKernelGGL(k_vbottom2d<T>, dim3(1), dim3(kBottomThreads), bytes, s, x, f, levels[l], n0, l, nh_pre,
+                       nh_post, zero_x);
+    return true;
+}
+template bool launch_vbottom2d<double>(const Grid*, int, double*, const double*, int, int, int, hipStream_t);
+template bool launch_vbottom2d<float>(const Grid*, int, float*, const float*, int, int, int, hipStream_t);
 
 }  // namespace fmg
