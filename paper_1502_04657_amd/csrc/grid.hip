@@ -244,6 +244,16 @@ __device__ inline double cubic_term(double v0, double v1, double v2, double v3) 
     return h3 + v0 * h2 + v0 * v0 * s1 + v0 * v0 * v0;
 }
 
+// interior node t (lexicographic, i fastest) -> (i, j, k); t < (n - 1)^D < 2^32 for every
+// admissible mesh, so 32-bit division (64-bit division is a long software sequence)
+__device__ inline void interior_ijk(int n, int D, int64_t t, int& i, int& j, int& k) {
+    const unsigned m = (unsigned)(n - 1), tt = (unsigned)t;
+    const unsigned r = tt / m, kk = (D == 3) ? r / m : 0u;
+    i = (int)(tt - r * m) + 1;
+    j = (int)(r - kk * m) + 1;
+    k = (D == 3) ? (int)kk + 1 : 0;
+}
+
 template <int D>
 __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, const Phys& ph, int i, int j, int k,
                                   double& Mu, double& MWu, double& Nu, double& Ku) {
@@ -434,9 +444,8 @@ __global__ __launch_bounds__(256) void k_forms(const double* __restrict__ u, Gri
     double a[4] = {0, 0, 0, 0};
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(t % m) + 1;
-        int64_t r = t / m;
-        int j = (int)(r % m) + 1, k = (D == 3) ? (int)(r / m) + 1 : 0;
+        int i, j, k;
+        interior_ijk(n, D, t, i, j, k);
         double Mu, MWu, Nu, Ku;
         node_forms<D>(u, g, ph, i, j, k, Mu, MWu, Nu, Ku);
         double u0 = u[i + g.pitch * j + g.plane * k];
@@ -505,10 +514,8 @@ __device__ inline T apply_K(const T* __restrict__ x, int64_t q, int64_t P, int64
 
 template <int D>
 __device__ inline int64_t interior_node(const Grid& g, int64_t t) {
-    const int m = g.n - 1;
-    const int i = (int)(t % m) + 1;
-    const int64_t r = t / m;
-    const int j = (int)(r % m) + 1, k = (D == 3) ? (int)(r / m) + 1 : 0;
+    int i, j, k;
+    interior_ijk(g.n, D, t, i, j, k);
     return i + g.pitch * j + g.plane * k;
 }
 
