@@ -287,12 +287,20 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
     const double u0 = u[p];
     double nl = 0.0;
     if (D == 2) {
+        // cubic_term<2>(u0, a, b) expanded in u0: 4 u0^3 + 3 u0^2 (a + b) + 2 u0 (a^2 + ab + b^2)
+        // + (a^3 + a^2 b + a b^2 + b^3); with s = a + b, q = ab the last two are s^2 - q and
+        // s (s^2 - 2q), summed over the star before the powers of u0 are applied
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
 #pragma unroll
         for (int e = 0; e < kStarElems2D; ++e) {
-            double v1 = u[p + kStarElem2D[e][0][0] + P * kStarElem2D[e][0][1]];
-            double v2 = u[p + kStarElem2D[e][1][0] + P * kStarElem2D[e][1][1]];
-            nl += cubic_term<2>(u0, v1, v2, 0.0);
+            const double a = u[p + kStarElem2D[e][0][0] + P * kStarElem2D[e][0][1]];
+            const double b = u[p + kStarElem2D[e][1][0] + P * kStarElem2D[e][1][1]];
+            const double sab = a + b, q = a * b, s2 = sab * sab;
+            t1 += sab;
+            t2 += s2 - q;
+            t3 += sab * (s2 - 2.0 * q);
         }
+        nl = u0 * (u0 * (4.0 * kStarElems2D * u0 + 3.0 * t1) + 2.0 * t2) + t3;
         Nu = nl * (h * h / 120.0);
         Ku = 4.0 * u0 - ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P]));
     } else {
