@@ -169,8 +169,21 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
                 for (int v = 0; v < V; ++v) {
                     double b = (D == 2) ? kQuadPt2D[qp][v] : kQuadPt3D[qp][v];
                     uq += b * uv[v];
+                    if (D == 3) {
 #pragma unroll
-                    for (int d = 0; d < D; ++d) x[d] += b * X[v][d];
+                        for (int d = 0; d < D; ++d) x[d] += b * X[v][d];
+                    }
+                }
+                if (D == 2) {
+                    // the point's offset in the fine cell is a constant of (tf, qp): one
+                    // multiply-add per coordinate instead of the vertex sum
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        double cd = 0.0;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) cd += kQuadPt2D[qp][v] * kCellElemVert2D[tf][v][d];
+                        x[d] = (a[d] + cd) * inv_s;
+                    }
                 }
                 const double wu = w * uq, wu2 = wu * uq, wu3 = wu2 * uq, wu4 = wu3 * uq;
                 if (D == 2) {
