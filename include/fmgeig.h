@@ -299,7 +299,8 @@ int fmg_op_coarse_nonlinear(const fmg_problem* prob, const fmg_options* opt, dou
                             void* d_scratch, size_t scratch_bytes, void* stream, double* lambda,
                             int32_t* newton_iters, int32_t* ground_state);
 
-/* u <- c u + Pi x_H on level n (Pi: P1 interpolation from the coarsest level). FP64.      */
+/* u <- c u + Pi x_H on level n (Pi: P1 interpolation from the coarsest level). FP64.
+ * n = n_coarse 2^k (a level of the hierarchy), else FMG_EINVAL.                          */
 int fmg_op_form_u(int32_t dim, int32_t n_coarse, int32_t n, double c, const double* d_xc_level,
                   double* d_u, void* d_scratch, void* stream);
 

@@ -639,6 +639,8 @@ int fmg_op_form_u(int32_t dim, int32_t n_coarse, int32_t n, double c, const doub
                   void* stream) {
     if ((dim != 2 && dim != 3) || n_coarse < 2 || n < n_coarse || n % n_coarse || !xc || !u || !scratch)
         return set_error(FMG_EINVAL, "bad form_u arguments");
+    if ((n / n_coarse) & (n / n_coarse - 1))
+        return set_error(FMG_EINVAL, "form_u: n / n_coarse = %d is not a power of two", n / n_coarse);
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* cd = static_cast<double*>(scratch);
     FMG_HIP_CHECK(hipMemcpyAsync(cd, &c, sizeof(double), hipMemcpyHostToDevice, s));

@@ -398,16 +398,16 @@ void launch_add_promote(const Grid& g, double* u, const float* e, hipStream_t s)
 // X, Y, Z), and the barycentric weights from the sorted coordinates.
 template <int D>
 __global__ __launch_bounds__(256) void k_form_u(double* __restrict__ u, const double* __restrict__ xc, Grid gf,
-                                                Grid gc, const double* __restrict__ coef) {
+                                                Grid gc, const double* __restrict__ coef, int ls) {
     const int i = 1 + blockIdx.x * 64 + threadIdx.x;
     const int j = 1 + blockIdx.y * 4 + threadIdx.y;
     const int k = (D == 3) ? 1 + (int)blockIdx.z : 0;
     const int n = gf.n, nc = gc.n;
     if (i > n - 1 || j > n - 1) return;
-    const int s = n / nc;
-    const double inv_s = 1.0 / s;
-    int c0[3] = {min(i / s, nc - 1), min(j / s, nc - 1), D == 3 ? min(k / s, nc - 1) : 0};
-    double t[3] = {(i - c0[0] * s) * inv_s, (j - c0[1] * s) * inv_s, D == 3 ? (k - c0[2] * s) * inv_s : 0.0};
+    // fine cells per coarse cell edge: s = n / nc = 2^ls (nested refinements)
+    const double inv_s = 1.0 / (double)(1 << ls);
+    int c0[3] = {min(i >> ls, nc - 1), min(j >> ls, nc - 1), D == 3 ? min(k >> ls, nc - 1) : 0};
+    double t[3] = {(i - (c0[0] << ls)) * inv_s, (j - (c0[1] << ls)) * inv_s, D == 3 ? (k - (c0[2] << ls)) * inv_s : 0.0};
     // sort axes by coordinate, descending (ties: lower axis first)
     int ax[3] = {0, 1, 2};
     if (D == 2) {
@@ -433,12 +433,14 @@ __global__ __launch_bounds__(256) void k_form_u(double* __restrict__ u, const do
 void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_level, const double* coef,
                    hipStream_t s) {
     const int n = gf.n;
+    int ls = 0;
+    while ((gc.n << ls) < n) ++ls;   // n = gc.n 2^ls on every level of the hierarchy
     dim3 blk(64, 4, 1);
     dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), gf.dim == 3 ? n - 1 : 1);
     if (gf.dim == 2)
-        hipLaunchKernelGGL(k_form_u<2>, grd, blk, 0, s, u, xc_level, gf, gc, coef);
+        hipLaunchKernelGGL(k_form_u<2>, grd, blk, 0, s, u, xc_level, gf, gc, coef, ls);
     else
-        hipLaunchKernelGGL(k_form_u<3>, grd, blk, 0, s, u, xc_level, gf, gc, coef);
+        hipLaunchKernelGGL(k_form_u<3>, grd, blk, 0, s, u, xc_level, gf, gc, coef, ls);
 }
 
 // ------------------------------------------------------------------------------------------
