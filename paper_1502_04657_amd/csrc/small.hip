@@ -805,7 +805,9 @@ __device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, d
     const double c = x[N];
     double* tv = ar.S1;   // nel x V
     double sb = 0.0;
-    for (int e = threadIdx.x; e < ar.z.nel; e += kThreads) {
+    constexpr int NM = L::T0 + 1;   // the moments used here: T3, T2, T1, T0 (leading entries)
+    static_assert(L::T3 == 0 && L::T2 < L::T1 && L::T1 < L::T0, "leading moment block");
+    auto simplex = [&](int e, const double* mo) {
         const int cl = e / NE, te = e - cl * NE;
         const int C0 = cl % nc, C1 = cl / nc;
         dispatch<NE>(te, [&](auto tc) {
@@ -821,7 +823,6 @@ __device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, d
             for (int p = 0; p < V; ++p)
 #pragma unroll
                 for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-            const double* mo = a.mom + (size_t)e * L::SIZE;
             double su = 0.0;
             static_for<V>([&](auto ac) {
                 constexpr int aa = decltype(ac)::value;
@@ -835,6 +836,21 @@ __device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, d
             });
             sb += su + c * elem_corner<D>(U, UU, mo, c);
         });
+    };
+    // two simplices per thread and pass, the moments of both loaded before either is used
+    for (int e0 = threadIdx.x; e0 < ar.z.nel; e0 += 2 * kThreads) {
+        const int e1 = e0 + kThreads;
+        const bool two = e1 < ar.z.nel;
+        const double* m0 = a.mom + (size_t)e0 * L::SIZE;
+        const double* m1 = a.mom + (size_t)(two ? e1 : e0) * L::SIZE;
+        double M0[NM], M1[NM];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+            M0[q] = m0[q];
+            M1[q] = m1[q];
+        }
+        simplex(e0, M0);
+        if (two) simplex(e1, M1);
     }
     __syncthreads();
     double v[5] = {0.0, 0.0, 0.0, 0.0, sb};
