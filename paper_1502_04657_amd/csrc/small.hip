@@ -26,7 +26,7 @@
 // goes back one step and the Jacobian is refactored there.  The fixed point is unchanged.
 //
 // On the coarsest space the iteration starts from the discrete sine mode and raises zeta in
-// geometric stages (factor 8 from a first stage <= 2, the step halved on failure); stages
+// geometric stages (factor 8 from a first stage <= 16, the step halved on failure); stages
 // before the last stop at a relative residual of 1e-3.
 #include <utility>
 
@@ -43,7 +43,7 @@ constexpr int kThreads = 256;               // four wavefronts
 #endif
 constexpr double kStageTol = FMG_SMALL_STAGE_TOL;   // residual for intermediate continuation stages
 #ifndef FMG_SMALL_FIRST_STAGE
-#define FMG_SMALL_FIRST_STAGE 2.0
+#define FMG_SMALL_FIRST_STAGE 16.0
 #endif
 constexpr double kFirstStage = FMG_SMALL_FIRST_STAGE;   // largest coupling of the first stage
 constexpr int kWaves = kThreads / 64;
@@ -1926,7 +1926,7 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         iters = ok ? r : 0;
         reason = ok ? 0 : -r;
     } else {
-        // discrete sine mode, then zeta stages (first stage <= 2, factor 8); a failed stage
+        // discrete sine mode, then zeta stages (first stage <= 16, factor 8); a failed stage
         // goes back to the last converged iterate and retries with half the step
         const double H = 1.0 / a.nc;
         for (int i = tid; i < N; i += kThreads) {
