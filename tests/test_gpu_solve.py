@@ -112,11 +112,14 @@ def test_fixed_iteration_count_variant_reaches_the_same_solution(fixed):
     assert res.newton_total < conv.newton_total
 
 
-def test_fixed_schedule_with_global_memory_small_solves_matches_oracle():
-    # coarsest h = 1/8 in 3D: N_H = 343, 49 x 49 blocks; the small-solve arena lives in
-    # global memory and the block inversions go through LDS in groups
+@pytest.mark.parametrize("prob", [W.Problem(3, 8, 1, (1.0, 1.0, 1.0), 0.0, 10.0),
+                                  W.Problem(2, 24, 2, (1.0, 1.0, 0.0), 0.0, 30.0)])
+def test_fixed_schedule_with_global_memory_small_solves_matches_oracle(prob):
+    # coarsest h = 1/8 in 3D (N_H = 343, 49 x 49 blocks) and h = 1/24 in 2D (N_H = 529,
+    # 23 x 23 blocks): the small-solve arena lives in global memory, the block inversions
+    # go through LDS in groups, and in 2D the chord steps' per-simplex residual values use
+    # global scratch
     from oracle import fmg as ofmg
-    prob = W.Problem(3, 8, 1, (1.0, 1.0, 1.0), 0.0, 10.0)
     ref = ofmg.fmg(prob, W.Options(), hierarchy=oracle_hierarchy(prob))
     res, u = _solve(prob, W.Options())
     assert len(res.history) == len(ref.history)
