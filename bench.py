@@ -295,8 +295,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget of the server")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; instances shard across GPUs with no communication "
-              "(see the design notes), but no multi-GPU figure is produced. Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: independent instances shard across GPUs with no communication, "
+              "and no multi-GPU figure is produced. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
