@@ -2,7 +2,9 @@
 eigensolves of the discrete problem (2.4) on the full space, the linear limit zeta = 0
 (lambda_h -> 2 pi^2 / 3 pi^2 with O(h^2) error, Assumption B1), the normalisation and
 Rayleigh-quotient identities of (2.2), and Theorems 3.1-3.2 behaviour."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -151,3 +153,25 @@ def test_augmented_problem_keeps_the_discrete_solution_fixed(small_run):
     mu, u, _, x = fmg.augmented_solve(h, l, r.u)
     assert mu == pytest.approx(r.lam, rel=1e-12)
     assert np.abs(x[:-1]).max() < 1e-8 and x[-1] == pytest.approx(1.0, abs=1e-8)
+
+
+_LIN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "linear_eigs.json")))["values"]
+
+
+@pytest.mark.parametrize("rec", _LIN, ids=lambda r: f"{r['dim']}d-n{r['n']}")
+def test_generic_assembly_reproduces_stencil_eigenvalues(rec):
+    """The oracle's element-by-element K and M have the lowest eigenvalue that the closed-form
+    stencils give (tests/golden/linear_eigs.json, written by make_linear_eigs.py without
+    the oracle)."""
+    m = Mesh(rec["dim"], rec["n"])
+    w = spla.eigsh(fem.stiffness(m).tocsc(), k=1, M=fem.mass(m).tocsc(), sigma=0.0, which="LM", tol=1e-14)[0]
+    assert float(w[0]) == pytest.approx(rec["lambda"], rel=1e-11)
+
+
+@pytest.mark.parametrize("dim, nc, refine", [(2, 8, 1), (2, 8, 3), (3, 4, 1)])
+def test_fmg_linear_limit_reaches_stored_eigenvalue(dim, nc, refine):
+    """zeta = 0, W = 0: the converged multigrid scheme ends at the stored linear eigenvalue."""
+    n = nc << refine
+    want = next(r["lambda"] for r in _LIN if r["dim"] == dim and r["n"] == n)
+    r = fmg.converged(W.Problem(dim, nc, refine, (0.0, 0.0, 0.0), 0.0, 0.0), OPTS)
+    assert r.lam == pytest.approx(want, rel=1e-12)
