@@ -104,6 +104,11 @@ typedef struct {
     double  wait_seconds; /* batch / server: time queued before admission (0 otherwise)   */
     int32_t history_len;  /* entries in history[]                                         */
     int32_t factor_total; /* banded LDL^T factorisations of the small solves (incl. checks)  */
+    double  residual;     /* |K u + M_W u + zeta N(u) - lambda M u|_2 / |lambda M u|_2 on the  */
+                          /* finest level: nodal residual of the discrete problem (2.4)    */
+    double  gamma_est;    /* contraction estimate of the finest-level correction steps     */
+                          /* (Theorem 3.1): |dlambda_last| / |dlambda_previous|; -1 when    */
+                          /* fewer than three finest-level steps ran                      */
     double  history[FMG_HISTORY_MAX]; /* lambda after the coarse step and after every      */
                                       /* correction step, in execution order              */
 } fmg_result;
@@ -147,7 +152,9 @@ int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t*
  * plus the tolerance loop on the finest level when opt->tol_lambda > 0.
  *   d_workspace : device memory of at least fmg_workspace_bytes() bytes, 256-B aligned;
  *                 contents on entry are ignored (the call initialises what it uses).
- *   d_u_out     : device, compact layout, u_len = (n-1)^dim; receives u_h with
+ *   d_u_out     : compact layout, u_len = (n-1)^dim, device or host memory (told apart with
+ *                 hipPointerGetAttributes; a host target is written by a device-to-host
+ *                 copy before the call returns); receives u_h with
  *                 b(u,u) = 1 and int u_h > 0.
  *   out         : host struct, filled on return (also on FMG_ENOCONV).
  * The coarsest solution and the returned state (last step of a fixed schedule, or the step
@@ -176,6 +183,13 @@ size_t fmg_footprint_bytes(const fmg_problem* prob, const fmg_options* opt);
  * is freed with the allocator that created it.  Applies to pools created afterwards.      */
 int fmg_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx),
                       void* ctx);
+
+/* fmg_solve with the workspace allocated for the call (through the allocator registered
+ * with fmg_set_allocator, else hipMalloc) and released before it returns: the problem
+ * statement alone in, (lambda, u_h) out.  Same arguments and errors as fmg_solve, plus
+ * FMG_ENOMEM when the allocation fails.                                                  */
+int fmg_solve_alloc(const fmg_problem* prob, const fmg_options* opt, void* stream, double* u_out, int64_t u_len,
+                    fmg_result* out);
 
 /* Solve `count` independent instances (probs[i], opts[i]) together: one pool holding every
  * workspace is allocated for the call, up to 8 instances run at once on streams of their

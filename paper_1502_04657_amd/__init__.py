@@ -14,7 +14,7 @@ import torch
 from . import _ffi
 from ._ffi import FMG_FP64, FMG_MIXED, fmg_options, fmg_problem, fmg_result
 
-__all__ = ["solve", "workspace_bytes", "footprint_bytes", "Solver", "batch_solve", "Server", "FmgError", "ops", "lib",
+__all__ = ["solve", "solve_alloc", "workspace_bytes", "footprint_bytes", "Solver", "batch_solve", "Server", "FmgError", "ops", "lib",
            "to_c_problem", "to_c_options"]
 
 
@@ -87,12 +87,14 @@ class Result:
     history: list
     factor_total: int = 0
     wait_seconds: float = 0.0
+    residual: float = 0.0
+    gamma_est: float = -1.0
 
 
 def _result(res: fmg_result) -> "Result":
     return Result(res.lambda_, res.lambda_rq, res.norm, res.dlambda, res.status, res.levels, res.steps_total,
                   res.newton_total, res.seconds, list(res.history[: res.history_len]), res.factor_total,
-                  res.wait_seconds)
+                  res.wait_seconds, res.residual, res.gamma_est)
 
 
 def footprint_bytes(problem, options) -> int:
@@ -136,6 +138,20 @@ class Solver:
 
 def solve(problem, options, device="cuda", check=True):
     return Solver(problem, options, device).solve(check=check)
+
+
+def solve_alloc(problem, options, u_out=None, stream=None, check=True):
+    """fmg_solve_alloc: the library allocates and frees the workspace.  u_out may be a CUDA
+    or a CPU tensor (float64, (n-1)^dim elements); a new CUDA tensor when None."""
+    if u_out is None:
+        u_out = torch.empty(_ndof(problem), dtype=torch.float64, device="cuda")
+    assert u_out.dtype == torch.float64 and u_out.is_contiguous()
+    res = fmg_result()
+    rc = lib().fmg_solve_alloc(C.byref(to_c_problem(problem)), C.byref(to_c_options(options)), _stream(stream),
+                               _ptr(u_out), C.c_int64(u_out.numel()), C.byref(res))
+    if check:
+        _check(rc)
+    return _result(res), u_out
 
 
 def batch_solve(problems, options, device="cuda", stream=None, check=True):

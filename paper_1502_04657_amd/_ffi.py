@@ -38,7 +38,8 @@ class fmg_result(C.Structure):
                 ("status", C.c_int32), ("levels", C.c_int32), ("steps_total", C.c_int32),
                 ("newton_total", C.c_int32), ("seconds", C.c_double), ("wait_seconds", C.c_double),
                 ("history_len", C.c_int32),
-                ("factor_total", C.c_int32), ("history", C.c_double * HISTORY_MAX)]
+                ("factor_total", C.c_int32), ("residual", C.c_double), ("gamma_est", C.c_double),
+                ("history", C.c_double * HISTORY_MAX)]
 
 
 P = C.c_void_p
@@ -56,6 +57,7 @@ SIGNATURES = {
     "fmg_profile_end": (C.c_int, [P]),
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),
     "fmg_solve": (C.c_int, [P, P, P, SZ, P, P, I64, P]),
+    "fmg_solve_alloc": (C.c_int, [P, P, P, P, I64, P]),
     "fmg_footprint_bytes": (SZ, [P, P]),
     "fmg_set_allocator": (C.c_int, [P, P, P]),
     "fmg_batch_solve": (C.c_int, [I32, P, P, P, P, P, P]),

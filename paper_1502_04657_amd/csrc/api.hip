@@ -38,6 +38,15 @@ int set_error(int code, const char* fmt, ...) {
     return code;
 }
 
+bool is_device_pointer(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();   // unregistered host memory
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
 static Phys make_phys(const fmg_problem* p) {
     Phys ph;
     for (int k = 0; k < 3; ++k) ph.w[k] = (k < p->dim) ? p->w_quad[k] : 0.0;
@@ -116,7 +125,7 @@ Layout make_layout(int dim, int nc, int levels, int mixed, int cg) {
     lo.momscr = take(std::max<size_t>(ms, 256));
     lo.arena = take(small_arena_bytes(dim, nc));
     lo.fac = take(small_factor_bytes(dim, nc));
-    lo.forms = take(sizeof(double) * (kReduceBlocks * 4 + 8));
+    lo.forms = take(sizeof(double) * (kReduceBlocks * 6 + 8));
     if (cg) lo.cgsc = take(sizeof(double) * (kReduceBlocks + 8));   // partials, then 4 scalars
     lo.total = off;
     return lo;
@@ -234,13 +243,22 @@ static int end_chunk(SolveJob& j, bool final_chunk) {
     return 0;
 }
 
-// Rayleigh quotient of the finest u, and the output copy when a target is set
+// Rayleigh quotient and residual of the finest u, and the output copy when a target is set
 static int final_chunk(SolveJob& j) {
     const Layout& lo = j.lo;
     const Grid& gf = lo.g[lo.L - 1];
     double* forms = at<double>(j.ws, lo.forms);
-    launch_forms(gf, make_phys(&j.prob), at<double>(j.ws, lo.u[lo.L - 1]), forms + 8, forms, j.s);
-    if (j.u_out) launch_unpack(gf, at<double>(j.ws, lo.u[lo.L - 1]), j.u_out, j.s);
+    const double* u = at<double>(j.ws, lo.u[lo.L - 1]);
+    launch_forms(gf, make_phys(&j.prob), u, forms + 8, forms, j.s, &at<SmallState>(j.ws, lo.state)->lambda);
+    if (j.u_out) launch_unpack(gf, u, j.u_out, j.s);
+    if (j.u_host) {
+        // host target: compact copy in the finest right-hand-side array (not needed any
+        // more), then one device-to-host copy
+        double* stage = at<double>(j.ws, lo.b[lo.L - 1]);
+        launch_unpack(gf, u, stage, j.s);
+        FMG_HIP_CHECK(hipMemcpyAsync(j.u_host, stage, sizeof(double) * compact_len(&j.prob), hipMemcpyDeviceToHost,
+                                     j.s));
+    }
     j.phase = 2;
     return end_chunk(j, true);
 }
@@ -304,7 +322,19 @@ int job_result(const SolveJob& j, fmg_result* out) {
     out->lambda = h.lambda;
     out->norm = f4[2];
     out->lambda_rq = (f4[0] + f4[1] + j.prob.zeta * f4[3]) / f4[2];
+    out->residual = f4[5] > 0.0 ? std::sqrt(f4[4] / f4[5]) : 0.0;
     out->dlambda = h.dlambda;
+    // contraction of the finest-level correction steps (Theorem 3.1): the ratio of the last
+    // two eigenvalue changes; the finest level starts from the previous level's eigenvalue
+    {
+        const int nh = std::min(h.hist_len, FMG_HISTORY_MAX);
+        const int fine = j.lo.L > 1 ? h.steps - (j.lo.L - 2) * j.opt.p : 0;   // steps on the finest level
+        out->gamma_est = -1.0;
+        if (fine >= 3 && nh >= 3 && nh == h.hist_len) {
+            const double d1 = std::fabs(h.hist[nh - 1] - h.hist[nh - 2]), d0 = std::fabs(h.hist[nh - 2] - h.hist[nh - 3]);
+            if (d0 > 0.0) out->gamma_est = d1 / d0;
+        }
+    }
     out->levels = j.lo.L;
     out->steps_total = h.steps;
     out->newton_total = h.newton_total;
@@ -406,7 +436,7 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     std::memset(out, 0, sizeof(*out));
     if (u_len != compact_len(prob))
         return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len, (long long)compact_len(prob));
-    if (!ws || !u_out) return set_error(FMG_EINVAL, "workspace and u_out must be device pointers");
+    if (!ws || !u_out) return set_error(FMG_EINVAL, "workspace and u_out must not be NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(FMG_EINVAL, "workspace must be 256-byte aligned");
     SolveJob j;
     j.prob = *prob;
@@ -423,7 +453,10 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t 
     JobHost local;
     j.ws = ws;
     j.s = static_cast<hipStream_t>(stream);
-    j.u_out = u_out;
+    if (is_device_pointer(u_out))
+        j.u_out = u_out;
+    else
+        j.u_host = u_out;
     j.host = pinned ? pinned : &local;
     // each chunk ends with the device state copied into `host`; wait for it, then continue
     int rc = job_start(j);

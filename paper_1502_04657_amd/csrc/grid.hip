@@ -445,13 +445,18 @@ void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_l
 
 // ------------------------------------------------------------------------------------------
 // Rayleigh-quotient pieces: (u^T K u, u^T M_W u, u^T M u, int u^4 = u^T N(u)), block sums
-// in a fixed grid, then one block adds the partials in index order (deterministic).
-template <int D>
+// in a fixed grid, then one block adds the partials in index order (deterministic).  With
+// lam set, two more sums: |r|^2 and |lam M u|^2 of the nodal residual of the discrete
+// problem (2.4), r = K u + M_W u + zeta N(u) - lam M u.
+template <int D, int NQ>
 __global__ __launch_bounds__(256) void k_forms(const double* __restrict__ u, Grid g, Phys ph,
-                                               double* __restrict__ partial) {
+                                               const double* __restrict__ lam, double* __restrict__ partial) {
     const int n = g.n, m = n - 1;
     const int64_t total = (D == 2) ? (int64_t)m * m : (int64_t)m * m * m;
-    double a[4] = {0, 0, 0, 0};
+    const double lv = (NQ > 4) ? *lam : 0.0;
+    double a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = 0.0;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         int i, j, k;
@@ -463,19 +468,24 @@ __global__ __launch_bounds__(256) void k_forms(const double* __restrict__ u, Gri
         a[1] += u0 * MWu;
         a[2] += u0 * Mu;
         a[3] += u0 * Nu;
+        if (NQ > 4) {
+            const double lm = lv * Mu, r = (Ku + MWu + ph.zeta * Nu) - lm;
+            a[4] += r * r;
+            a[5] += lm * lm;
+        }
     }
-    __shared__ double red[4][4];
+    __shared__ double red[4][NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         double v = wave_sum(a[q]);
         if (lane == 0) red[wv][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < NQ) {
         double v = 0.0;
         for (int w = 0; w < 4; ++w) v += red[w][threadIdx.x];
-        partial[blockIdx.x * 4 + threadIdx.x] = v;
+        partial[blockIdx.x * NQ + threadIdx.x] = v;
     }
 }
 
@@ -501,11 +511,20 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     }
 }
 
-void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s) {
+void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s,
+                  const double* lam) {
+    if (lam) {
+        if (g.dim == 2)
+            hipLaunchKernelGGL((k_forms<2, 6>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
+        else
+            hipLaunchKernelGGL((k_forms<3, 6>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, kReduceBlocks, 6, out);
+        return;
+    }
     if (g.dim == 2)
-        hipLaunchKernelGGL(k_forms<2>, dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, partial);
+        hipLaunchKernelGGL((k_forms<2, 4>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
     else
-        hipLaunchKernelGGL(k_forms<3>, dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, partial);
+        hipLaunchKernelGGL((k_forms<3, 4>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, kReduceBlocks, 4, out);
 }
 

@@ -13,6 +13,7 @@ namespace fmg {
 int check_problem(const fmg_problem* p);
 int check_options(const fmg_options* o);
 int64_t compact_len(const fmg_problem* p);   // (n - 1)^dim on the finest level
+bool is_device_pointer(const void* p);       // device (or managed) memory of the HIP runtime
 
 // Byte offsets into the caller's workspace (each region 256-B aligned).
 struct Layout {
@@ -31,7 +32,7 @@ Layout layout_for(const fmg_problem* p, const fmg_options* o);
 // What the host reads back between chunks.
 struct JobHost {
     SmallState st;
-    double forms[4];   // u^T K u, u^T M_W u, u^T M u, int u^4 of the finest u
+    double forms[6];   // u^T K u, u^T M_W u, u^T M u, int u^4 of the finest u; |r|^2, |lam M u|^2
 };
 
 struct SolveJob {
@@ -41,6 +42,7 @@ struct SolveJob {
     void* ws = nullptr;          // device workspace of at least lo.total bytes, 256-B aligned
     hipStream_t s = nullptr;
     double* u_out = nullptr;     // device, compact: the final chunk unpacks u into it when set
+    double* u_host = nullptr;    // host, compact: the final chunk copies u into it when set
     JobHost* host = nullptr;     // pinned memory when the driver does not synchronise per chunk
     hipEvent_t ev = nullptr;     // when set, recorded at the end of every chunk
     int phase = 0;               // 1: tolerance check pending, 2: final chunk pending, 3: done

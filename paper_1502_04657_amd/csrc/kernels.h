@@ -34,9 +34,12 @@ void launch_add_promote(const Grid& g, double* u, const float* e, hipStream_t s)
 void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_level, const double* coef,
                    hipStream_t s);
 // out[0..3] = (u^T K u, u^T M_W u, u^T M u, int u^4): two-stage fixed-order reduction,
-// partial must hold kReduceBlocks*4 doubles
+// partial must hold kReduceBlocks*4 doubles.  With lam (device scalar): also out[4..5] =
+// (|r|^2, |lam M u|^2) of the nodal residual r = K u + M_W u + zeta N(u) - lam M u, and
+// partial must hold kReduceBlocks*6 doubles.
 constexpr int kReduceBlocks = 512;
-void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s);
+void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s,
+                  const double* lam = nullptr);
 
 // ---- vcycle2d.hip ----------------------------------------------------------------------
 // fused 2D V-cycle level passes (nu symmetric sweeps = 2 nu + 1 half sweeps, nu <= 2);

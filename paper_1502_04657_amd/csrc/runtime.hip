@@ -345,6 +345,18 @@ size_t fmg_footprint_bytes(const fmg_problem* prob, const fmg_options* opt) {
     return align256(bytes);
 }
 
+int fmg_solve_alloc(const fmg_problem* prob, const fmg_options* opt, void* stream, double* u_out, int64_t u_len,
+                    fmg_result* out) {
+    size_t bytes = 0;
+    if (int rc = validate(prob, opt, &bytes)) return rc;
+    DeviceBlock blk;
+    if (int rc = blk.get(align256(bytes))) return rc;
+    const int rc = fmg_solve(prob, opt, blk.p, align256(bytes), stream, u_out, u_len, out);
+    // fmg_solve has synchronised the stream, so the workspace is free to go
+    blk.put();
+    return rc;
+}
+
 int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* opts, void* stream,
                     double* const* u_out, const int64_t* u_len, fmg_result* out) {
     auto t0 = std::chrono::steady_clock::now();

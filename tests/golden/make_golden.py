@@ -5,6 +5,10 @@ oracle (oracle/), never the HIP library.
                                                   # results of the small workloads
     python tests/golden/make_golden.py large_2d   # long (tens of minutes): converged
                                                   # lambda of the 2D 4.2M-dof workload
+    python tests/golden/make_golden.py mid_2d     # minutes: 2D n = 512 (wide V-cycle tiles),
+                                                  # fixed-schedule history and u, converged u
+    python tests/golden/make_golden.py large_3d   # long (about an hour): 3D 128^3, fixed-
+                                                  # schedule history and u, converged u
 
 Each JSON file holds, per workload: the problem, the oracle's fixed-schedule lambda history
 (Algorithm 3.2 with m = 1, p = 2, SGS(2,2)), the converged discrete eigenvalue lambda_ref
@@ -32,7 +36,50 @@ SMALL = {
     "small_2d_z100": W.Problem(2, 16, 2, (1.0, 1.0, 0.0), 0.0, 100.0),
     "small_2d_z1000": W.Problem(2, 16, 2, (0.7, 1.6, 0.0), 0.0, 1000.0),
     "small_3d": W.Problem(3, 4, 2, (1.0, 1.0, 1.0), 0.0, 10.0),
+    # coarsest h = 1/6: 25 x 25 coarse blocks, the largest 3D coarse space whose small-solve
+    # arena fits in LDS
+    "small_3d_nc6": W.Problem(3, 6, 2, (1.0, 1.0, 1.0), 0.0, 30.0),
+    # coarsest h = 1/12 (N_H = 1331): the coarse space chosen for 3D n = 192 at large zeta
+    "small_3d_nc12": W.Problem(3, 12, 1, (0.8, 1.3, 1.7), 0.0, 300.0),
 }
+# Arrays too large for JSON go to compressed .npz files next to it.
+MID_2D = W.Problem(2, 16, 5, (1.0, 1.0, 0.0), 0.0, 100.0)        # n = 512
+MID_3D = W.Problem(3, 4, 5, (1.0, 1.0, 1.0), 0.0, 10.0)          # n = 128
+
+
+def fold_sym3(n: int, u: np.ndarray) -> np.ndarray:
+    """Values of a 3D interior vector at the nodes i <= j <= k (x-fastest compact order).
+    W = x^2 + y^2 + z^2 and the Kuhn mesh are invariant under axis permutations, so the
+    ground state is too; the fold is checked before it is taken."""
+    m = n - 1
+    a = u.reshape(m, m, m)                         # [k, j, i]
+    for perm in ((0, 2, 1), (1, 0, 2), (2, 1, 0)):
+        asym = float(np.abs(a - a.transpose(perm)).max())
+        assert asym <= 1e-12 * float(np.abs(a).max()), asym
+    k, j, i = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    keep = (i <= j) & (j <= k)
+    return a[keep]
+
+
+def run_npz(name, prob, sym3=False):
+    """Fixed-schedule history and u, converged lambda_ref and u_ref, into <name>.npz."""
+    t0 = time.time()
+    opts = W.Options()
+    h = fmg.Hierarchy(prob)
+    r = fmg.fmg(prob, opts, h)
+    print(f"{name}: fixed schedule lambda={r.lam:.15f} ({time.time() - t0:.1f}s)", flush=True)
+    rc = fmg.converged(prob, opts, h)
+    l = h.L - 1
+    n = prob.n_fine
+    fold = (lambda v: fold_sym3(n, v)) if sym3 else (lambda v: v)
+    meta = {"problem": dataclasses.asdict(prob), "options": dataclasses.asdict(opts),
+            "folded_sym3": bool(sym3), "converged_steps": int(rc.steps_total),
+            "norm_M": float(rc.u @ (h.M[l] @ rc.u)), "oracle_seconds": time.time() - t0}
+    path = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(path, meta=json.dumps(meta), fixed_history=np.array([x[2] for x in r.history]),
+                        fixed_u=fold(r.u), lambda_ref=np.array(rc.lam), u_ref=fold(rc.u))
+    print(f"{name}: lambda_ref={rc.lam:.15f} steps={rc.steps_total} ({time.time() - t0:.1f}s)", flush=True)
+    print("wrote", path)
 
 
 def run(name, prob, fixed=True, samples=64):
@@ -65,6 +112,12 @@ def main(which):
     if which == "small":
         res = {k: run(k, p) for k, p in SMALL.items()}
         path = os.path.join(HERE, "small.json")
+    elif which == "mid_2d":
+        run_npz("mid_2d", MID_2D)
+        return
+    elif which == "large_3d":
+        run_npz("mid_3d", MID_3D, sym3=True)
+        return
     elif which == "large_2d":
         res = {"large_2d": run("large_2d", W.LARGE_2D, fixed=False, samples=256)}
         path = os.path.join(HERE, "large_2d.json")

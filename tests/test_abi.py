@@ -127,3 +127,28 @@ def test_batch_validates_every_instance_before_any_work(lib):
     assert b"instance 1" in lib.fmg_last_error() and b"u_len" in lib.fmg_last_error()
     assert lib.fmg_batch_solve(0, None, None, None, None, None, None) == 0
     assert lib.fmg_batch_solve(-1, None, None, None, None, None, None) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of fmg_problem, fmg_options and fmg_result have the field offsets
+    and sizes a C compiler gives the header's structs."""
+    from paper_1502_04657_amd import _ffi
+    structs = {"fmg_problem": _ffi.fmg_problem, "fmg_options": _ffi.fmg_options, "fmg_result": _ffi.fmg_result}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fmgeig.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            cname = "lambda" if fname == "lambda_" else fname
+            lines.append(f'printf("{sname} {fname} %zu\\n", offsetof({sname}, {cname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        sname, field, val = line.split()
+        cls = structs[sname]
+        got = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), line

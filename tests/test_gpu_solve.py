@@ -32,7 +32,10 @@ def _solve(prob, opts):
     return Solver(prob, opts).solve()
 
 
-@pytest.mark.parametrize("name", ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000"])
+ALL = ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000", "small_3d_nc6", "small_3d_nc12"]
+
+
+@pytest.mark.parametrize("name", ALL)
 def test_fixed_schedule_matches_oracle_step_by_step(name):
     rec = GOLD[name]
     prob = _problem(rec)
@@ -48,7 +51,7 @@ def test_fixed_schedule_matches_oracle_step_by_step(name):
     assert res.norm == pytest.approx(1.0, abs=1e-12)
 
 
-@pytest.mark.parametrize("name", ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000"])
+@pytest.mark.parametrize("name", ALL)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_converged_matches_discrete_solution(name, precision):
     rec = GOLD[name]
@@ -128,3 +131,35 @@ def test_fixed_schedule_with_global_memory_small_solves_matches_oracle(prob):
     h = oracle_hierarchy(prob)
     d = u.cpu().numpy() - ref.u
     assert math.sqrt(d @ (h.M[h.L - 1] @ d)) < 1e-9
+
+
+def test_result_reports_residual_and_contraction():
+    """A converged solve has a tiny nodal residual of (2.4) and a correction-step contraction
+    estimate below 1 (Theorem 3.1); a fixed schedule with p = 2 has too few finest steps."""
+    rec = GOLD["small_2d_z100"]
+    prob = _problem(rec)
+    res, _ = _solve(prob, W.Options(tol_lambda=1e-12, max_final_steps=100))
+    assert res.status == 0
+    assert 0.0 <= res.residual < 1e-9
+    assert 0.0 < res.gamma_est < 1.0
+    fixed, _ = _solve(prob, W.Options())
+    assert fixed.gamma_est == -1.0
+    assert fixed.residual > res.residual
+
+
+def test_host_output_and_library_allocated_workspace_match_device_solve():
+    from paper_1502_04657_amd import Solver, solve_alloc
+    prob = _problem(GOLD["small_3d"])
+    opts = W.Options(tol_lambda=1e-10)
+    s = Solver(prob, opts)
+    r_dev, u_dev = s.solve()
+    u_host = torch.zeros(s.ndof, dtype=torch.float64)
+    r_host, _ = s.solve(u_host)
+    assert r_host.lam == r_dev.lam
+    assert torch.equal(u_host, u_dev.cpu())
+    r_a, u_a = solve_alloc(prob, opts)
+    assert r_a.lam == r_dev.lam and r_a.history == r_dev.history
+    assert torch.equal(u_a, u_dev)
+    u_ah = torch.zeros(s.ndof, dtype=torch.float64)
+    r_ah, _ = solve_alloc(prob, opts, u_out=u_ah)
+    assert torch.equal(u_ah, u_dev.cpu())
