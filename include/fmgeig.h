@@ -167,6 +167,20 @@ int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* d_workspace
               size_t workspace_bytes, void* stream, double* d_u_out, int64_t u_len,
               fmg_result* out);
 
+/* fmg_solve for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the workspace is a static device array of
+ * FMG_STATIC_WORKSPACE_BYTES bytes that the library holds on every GPU it runs on until the
+ * process ends, and the call allocates no device memory and no pinned host memory (the
+ * host mirror of the device state lives on the caller's stack).  Same problem, options,
+ * output and errors as fmg_solve; FMG_ENOMEM, before any device work, when the problem's
+ * workspace (fmg_workspace_bytes) exceeds FMG_STATIC_WORKSPACE_BYTES (e.g. 2D up to
+ * n = 1024, 3D up to n = 64 in FP64).  Every call on one GPU uses that GPU's one array,
+ * whose contents the call initialises itself: calls that overlap on the same GPU (other
+ * threads or streams) race and must be serialised by the caller.                       */
+#define FMG_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int fmg_solve_static(const fmg_problem* prob, const fmg_options* opt, void* stream, double* u_out, int64_t u_len,
+                     fmg_result* out);
+
 /* ---- many solves: footprint, allocator, batch, serving -------------------------------- */
 /* Every instance below is the problem and method of fmg_solve (Section 2 problem, the
  * mesh sequence of (3.1)-(3.2), Algorithm 3.2 with the tolerance loop); results are bitwise

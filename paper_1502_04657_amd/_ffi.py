@@ -58,6 +58,7 @@ SIGNATURES = {
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),
     "fmg_solve": (C.c_int, [P, P, P, SZ, P, P, I64, P]),
     "fmg_solve_alloc": (C.c_int, [P, P, P, P, I64, P]),
+    "fmg_solve_static": (C.c_int, [P, P, P, P, I64, P]),
     "fmg_footprint_bytes": (SZ, [P, P]),
     "fmg_set_allocator": (C.c_int, [P, P, P]),
     "fmg_batch_solve": (C.c_int, [I32, P, P, P, P, P, P]),

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/fmgeig.h"
@@ -15,6 +16,7 @@
 
 namespace fmg {
 
+constexpr int kMaxDevices = 64;
 static thread_local char g_err[512] = "";
 // fused 2D V-cycle passes (1) or the unfused kernel sequence (0); both give identical bits
 static int g_fused = 1;
@@ -358,6 +360,81 @@ int job_result(const SolveJob& j, fmg_result* out) {
     return 0;
 }
 
+// fmg_solve inside a given workspace.  pinned_mirror: keep a pinned host mirror of the
+// device state per calling thread (allocated once with hipHostMalloc); otherwise the
+// chunk-end copies go to a pageable mirror on the stack and nothing is allocated.
+static int solve_in(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t ws_bytes, void* stream,
+                    double* u_out, int64_t u_len, fmg_result* out, bool pinned_mirror) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = check_problem(prob)) return rc;
+    if (int rc = check_options(opt)) return rc;
+    if (!out) return set_error(FMG_EINVAL, "result is NULL");
+    std::memset(out, 0, sizeof(*out));
+    if (u_len != compact_len(prob))
+        return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len, (long long)compact_len(prob));
+    if (!ws || !u_out) return set_error(FMG_EINVAL, "workspace and u_out must not be NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(FMG_EINVAL, "workspace must be 256-byte aligned");
+    SolveJob j;
+    j.prob = *prob;
+    j.opt = *opt;
+    j.lo = layout_for(prob, opt);
+    if (ws_bytes < j.lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, j.lo.total);
+    // host mirror in pinned memory (one per calling thread, kept for the process): the
+    // chunk-end copies are then direct DMA instead of staged pageable copies
+    static thread_local JobHost* pinned = nullptr;
+    if (pinned_mirror && !pinned &&
+        hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(JobHost), hipHostMallocDefault) != hipSuccess) {
+        pinned = nullptr;
+        (void)hipGetLastError();
+    }
+    JobHost local;
+    j.ws = ws;
+    j.s = static_cast<hipStream_t>(stream);
+    if (is_device_pointer(u_out))
+        j.u_out = u_out;
+    else
+        j.u_host = u_out;
+    j.host = (pinned_mirror && pinned) ? pinned : &local;
+    // each chunk ends with the device state copied into `host`; wait for it, then continue
+    int rc = job_start(j);
+    while (!rc && j.phase != 3) {
+        FMG_HIP_CHECK(hipStreamSynchronize(j.s));
+        rc = job_step(j);
+    }
+    if (rc) return rc;
+    FMG_HIP_CHECK(hipGetLastError());
+    const int status = job_result(j, out);
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+// Workspace of fmg_solve_static: a file-scope device array, one copy per GPU the library
+// runs on, held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in for the symbol); it uses the device
+// address that hipGetSymbolAddress returns, looked up once per device with that device
+// current.
+constexpr size_t kStaticWorkspaceBytes = FMG_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxDevices] = {};
+
+static int static_workspace(void** out) {
+    int dev = 0;
+    FMG_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FMG_EINVAL, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(FMG_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return 0;
+}
+
 }  // namespace fmg
 
 using namespace fmg;
@@ -396,7 +473,7 @@ int fmg_profile_end(fmg_kernel_profile* out) {
         if (hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) rc = FMG_EHIP;
         ms_total += ms;
     }
-    for (auto& e : g_prof.ev) hipEventDestroy(e);
+    for (auto& e : g_prof.ev) (void)hipEventDestroy(e);
     g_prof.ev.clear();
     if (rc) return set_error(rc, "profile events failed");
     if (out) {
@@ -429,46 +506,21 @@ int fmg_workspace_bytes(const fmg_problem* prob, const fmg_options* opt, size_t*
 
 int fmg_solve(const fmg_problem* prob, const fmg_options* opt, void* ws, size_t ws_bytes, void* stream, double* u_out,
               int64_t u_len, fmg_result* out) {
-    auto t0 = std::chrono::steady_clock::now();
+    return solve_in(prob, opt, ws, ws_bytes, stream, u_out, u_len, out, true);
+}
+
+int fmg_solve_static(const fmg_problem* prob, const fmg_options* opt, void* stream, double* u_out, int64_t u_len,
+                     fmg_result* out) {
     if (int rc = check_problem(prob)) return rc;
     if (int rc = check_options(opt)) return rc;
-    if (!out) return set_error(FMG_EINVAL, "result is NULL");
-    std::memset(out, 0, sizeof(*out));
-    if (u_len != compact_len(prob))
-        return set_error(FMG_EINVAL, "u_len %lld != (n-1)^dim = %lld", (long long)u_len, (long long)compact_len(prob));
-    if (!ws || !u_out) return set_error(FMG_EINVAL, "workspace and u_out must not be NULL");
-    if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(FMG_EINVAL, "workspace must be 256-byte aligned");
-    SolveJob j;
-    j.prob = *prob;
-    j.opt = *opt;
-    j.lo = layout_for(prob, opt);
-    if (ws_bytes < j.lo.total) return set_error(FMG_ENOMEM, "workspace %zu < required %zu bytes", ws_bytes, j.lo.total);
-    // host mirror in pinned memory (one per calling thread, kept for the process): the
-    // chunk-end copies are then direct DMA instead of staged pageable copies
-    static thread_local JobHost* pinned = nullptr;
-    if (!pinned && hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(JobHost), hipHostMallocDefault) != hipSuccess) {
-        pinned = nullptr;
-        (void)hipGetLastError();
-    }
-    JobHost local;
-    j.ws = ws;
-    j.s = static_cast<hipStream_t>(stream);
-    if (is_device_pointer(u_out))
-        j.u_out = u_out;
-    else
-        j.u_host = u_out;
-    j.host = pinned ? pinned : &local;
-    // each chunk ends with the device state copied into `host`; wait for it, then continue
-    int rc = job_start(j);
-    while (!rc && j.phase != 3) {
-        FMG_HIP_CHECK(hipStreamSynchronize(j.s));
-        rc = job_step(j);
-    }
-    if (rc) return rc;
-    FMG_HIP_CHECK(hipGetLastError());
-    const int status = job_result(j, out);
-    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return status;
+    const size_t need = layout_for(prob, opt).total;
+    if (need > kStaticWorkspaceBytes)
+        return set_error(FMG_ENOMEM, "fmg_solve_static: this problem needs %zu bytes of workspace, more than the "
+                                     "%zu bytes of the library's static workspace; use fmg_solve",
+                         need, kStaticWorkspaceBytes);
+    void* ws = nullptr;
+    if (int rc = static_workspace(&ws)) return rc;
+    return solve_in(prob, opt, ws, kStaticWorkspaceBytes, stream, u_out, u_len, out, false);
 }
 
 // ---- single steps ----------------------------------------------------------------------
