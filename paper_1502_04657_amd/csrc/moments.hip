@@ -9,17 +9,27 @@
 // re-assembles on the fine grid in every nonlinear iteration; the result is the same.)
 //
 // Pass 1 (k_moments_raw): block (coarse cell, chunk, coarse simplex type) integrates
-// u~^a X^b over the fine simplices of that coarse simplex with an exact degree-4 rule
-// (tables.h) and writes one partial sum per block.  A block walks only the fine cells that
-// meet its coarse simplex: in 2D the cells (a0, a1) on one side of the diagonal (a
-// triangular index set, folded into full rows), in 3D the cells whose coordinates are
-// ordered as the coarse tetrahedron's axis permutation orders them (sorted triples).  Pass 2 (k_moments_final): one thread
-// per coarse simplex adds the partials in chunk order and converts the X-monomial moments
-// to the barycentric form.  Both passes are deterministic.
+// u~^k X^b (X: coarse-local coordinates) over the fine cells of that coarse simplex and
+// writes one partial sum per block.  Integration is exact and needs no quadrature points:
+// on a fine cell with corner A (in fine-cell units of the coarse cell) and cell coordinates
+// Y, X = (A + Y) / s, and every local moment int u~^k Y^b is a fixed rational combination
+// of products of the cell's corner values (moment_tables.h, derived in
+// gen_moment_tables.py); the local moments are then shifted to (A + Y)^b one coordinate
+// at a time (binomial expansion), and the powers of s and h are applied once per block.
+// A block walks only the fine cells that meet its coarse simplex, in two groups:
+//   * interior cells, whose coordinates are strictly ordered as the coarse simplex's axis
+//     permutation orders them (all fine simplices of the cell lie in the coarse simplex):
+//     the whole-cell tables, grouped by corner products;
+//   * cells on the coarse simplex's internal faces (ties among the coordinates): the
+//     per-simplex tables for the fine simplices that belong to this coarse simplex.
+// Blocks hold one group each, so a wavefront never mixes the two.  Pass 2
+// (k_moments_final): one thread per coarse simplex adds the partials in chunk order and
+// converts the X-monomial moments to the barycentric form.  Both passes are deterministic.
 #include <utility>
 
 #include "kernels.h"
 #include "layout.h"
+#include "moment_tables.h"
 
 namespace fmg {
 
@@ -33,24 +43,31 @@ static int64_t ipow(int64_t b, int e) {
     return r;
 }
 
-// cells_per: fine cells one block list covers.  2D: the fine cells (a0, a1) of one coarse
-// triangle, a0 >= a1 or a0 <= a1 (diagonal cells included, s (s + 1) / 2 of them), as s / 2
-// rows of s + 1 cells (s = n / nc is even on every level that has moments).  3D: the cells
-// with a_p0 >= a_p1 >= a_p2 for the coarse tetrahedron's axis order (p0, p1, p2),
-// s (s + 1) (s + 2) / 6 of them.
-static void chunk_shape(int dim, int nc, int n, int64_t& ncell, int64_t& cells_per, int64_t& nchunk) {
-    const int s = n / nc;
-    ncell = ipow(nc, dim);
-    cells_per = dim == 2 ? (int64_t)(s / 2) * (s + 1) : (int64_t)s * (s + 1) * (s + 2) / 6;
-    nchunk = (cells_per + kChunkCells - 1) / kChunkCells;
+// Cells one coarse simplex holds, s = n / nc fine cells per coarse edge:
+//   interior: 2D the cells (a0, a1) with a0 > a1 (type 0; a0 < a1 for type 1), s (s - 1) / 2;
+//             3D the cells with a_p0 > a_p1 > a_p2 for the type's axis order, s (s-1) (s-2) / 6;
+//   ties:     2D the s diagonal cells; 3D the s^2 cells with a_p0 = a_p1 >= a_p2 or
+//             a_p0 >= a_p1 = a_p2.
+// Chunks of kChunkCells cells: the interior chunks first, then the tie chunks.
+struct ChunkShape {
+    int64_t ncell, n_int, n_tie, c_int, c_tie;
+};
+static ChunkShape chunk_shape(int dim, int nc, int n) {
+    const int64_t s = n / nc;
+    ChunkShape c;
+    c.ncell = ipow(nc, dim);
+    c.n_int = dim == 2 ? s * (s - 1) / 2 : s * (s - 1) * (s - 2) / 6;
+    c.n_tie = dim == 2 ? s : s * s;
+    c.c_int = (c.n_int + kChunkCells - 1) / kChunkCells;
+    c.c_tie = (c.n_tie + kChunkCells - 1) / kChunkCells;
+    return c;
 }
 
 size_t moments_scratch_bytes(int dim, int nc, int n) {
-    int64_t ncell, cells_per, nchunk;
-    chunk_shape(dim, nc, n, ncell, cells_per, nchunk);
+    const ChunkShape c = chunk_shape(dim, nc, n);
     const int raw = dim == 2 ? RawLayout<2>::SIZE : RawLayout<3>::SIZE;
     const int ne = dim == 2 ? 2 : 6;
-    return sizeof(double) * (size_t)(ncell * ne * nchunk * raw);
+    return sizeof(double) * (size_t)(c.ncell * ne * (c.c_int + c.c_tie) * raw);
 }
 
 // coarse simplex type of a fine simplex of fine type tf in the fine cell at coarse-local
@@ -73,171 +90,6 @@ __device__ inline int coarse_type(const int* a, int tf) {
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ ut, Grid g, int nc,
-                                                     int64_t cells_per, int s, double* __restrict__ partial) {
-    using R = RawLayout<D>;
-    constexpr int V = D + 1;
-    constexpr int NF = (D == 2) ? 2 : 6;   // fine simplices per fine cell
-    const int64_t cell = blockIdx.x;
-    const int64_t chunk = blockIdx.y;
-    const int type = blockIdx.z;
-    const int64_t nchunk = gridDim.y;
-    int C[3] = {(int)(cell % nc), (int)((cell / nc) % nc), D == 3 ? (int)(cell / ((int64_t)nc * nc)) : 0};
-    const int64_t start = chunk * kChunkCells;
-    const int64_t end = min(cells_per, start + (int64_t)kChunkCells);
-    const double inv_s = 1.0 / s;
-    const double h = g.h;
-    const double vol = (D == 2) ? 0.5 * h * h : h * h * h / 6.0;
-    const int64_t P = g.pitch, S = g.plane;
-    double acc[R::SIZE];
-#pragma unroll
-    for (int q = 0; q < R::SIZE; ++q) acc[q] = 0.0;
-
-    for (int64_t idx = start + threadIdx.x; idx < end; idx += blockDim.x) {
-        int a[3];
-        if (D == 2) {
-            // row pair (r, s-1-r) of the triangular set: s - r cells of row r, then r + 1 of
-            // row s-1-r; (lo, hi) = (row, column) with hi >= lo
-            const int t = (int)idx, r = t / (s + 1), x = t - r * (s + 1);
-            int lo, hi;
-            if (x < s - r) {
-                lo = r;
-                hi = r + x;
-            } else {
-                lo = s - 1 - r;
-                hi = lo + (x - (s - r));
-            }
-            a[0] = type == 0 ? hi : lo;
-            a[1] = type == 0 ? lo : hi;
-            a[2] = 0;
-        } else {
-            // idx -> sorted triple i >= j >= k: i from the tetrahedral numbers i(i+1)(i+2)/6,
-            // then (j, k) from the triangular numbers j(j+1)/2
-            const int64_t t = idx;
-            int i = (int)cbrt(6.0 * (double)t);
-            while ((int64_t)i * (i + 1) * (i + 2) / 6 > t) --i;
-            while ((int64_t)(i + 1) * (i + 2) * (i + 3) / 6 <= t) ++i;
-            const int r = (int)(t - (int64_t)i * (i + 1) * (i + 2) / 6);
-            int j = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
-            while (j * (j + 1) / 2 > r) --j;
-            while ((j + 1) * (j + 2) / 2 <= r) ++j;
-            const int k = r - j * (j + 1) / 2;
-            // type 2 p0 + q: largest axis p0; q = 1 puts the larger remaining axis second
-            const int p0 = type >> 1, o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
-            const int p1 = (type & 1) ? o2 : o1, p2 = (type & 1) ? o1 : o2;
-            a[p0] = i;
-            a[p1] = j;
-            a[p2] = k;
-        }
-        const int i = C[0] * s + a[0], j = C[1] * s + a[1], k = D == 3 ? C[2] * s + a[2] : 0;
-        const int64_t base = i + P * j + S * k;
-#pragma unroll
-        for (int tf = 0; tf < NF; ++tf) {
-            if (coarse_type<D>(a, tf) != type) continue;
-            double uv[V], X[V][3];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                int o[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) o[d] = (d < D) ? (D == 2 ? kCellElemVert2D[tf][v][d] : kCellElemVert3D[tf][v][d]) : 0;
-                uv[v] = ut[base + o[0] + P * o[1] + S * o[2]];
-#pragma unroll
-                for (int d = 0; d < D; ++d) X[v][d] = (a[d] + o[d]) * inv_s;
-            }
-            // gradient moments
-            double gr[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-#pragma unroll
-                for (int d = 0; d < D; ++d)
-                    gr[d] += uv[v] * (D == 2 ? kCellElemBary2D[tf][v][1 + d] : kCellElemBary3D[tf][v][1 + d]);
-            double g2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                acc[R::G + d] += vol * gr[d] / h;
-                g2 += gr[d] * gr[d];
-            }
-            acc[R::Q] += vol * g2 / (h * h);
-            // exact degree-4 rule
-            constexpr int NQ = (D == 2) ? kQuad2D : kQuad3D;
-#pragma unroll
-            for (int qp = 0; qp < NQ; ++qp) {
-                double w = vol * (D == 2 ? kQuadW2D[qp] : kQuadW3D[qp]);
-                double uq = 0.0, x[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    double b = (D == 2) ? kQuadPt2D[qp][v] : kQuadPt3D[qp][v];
-                    uq += b * uv[v];
-                    if (D == 3) {
-#pragma unroll
-                        for (int d = 0; d < D; ++d) x[d] += b * X[v][d];
-                    }
-                }
-                if (D == 2) {
-                    // the point's offset in the fine cell is a constant of (tf, qp): one
-                    // multiply-add per coordinate instead of the vertex sum
-#pragma unroll
-                    for (int d = 0; d < 2; ++d) {
-                        double cd = 0.0;
-#pragma unroll
-                        for (int v = 0; v < V; ++v) cd += kQuadPt2D[qp][v] * kCellElemVert2D[tf][v][d];
-                        x[d] = (a[d] + cd) * inv_s;
-                    }
-                }
-                const double wu = w * uq, wu2 = wu * uq, wu3 = wu2 * uq, wu4 = wu3 * uq;
-                if (D == 2) {
-                    const double X1 = x[0], Y1 = x[1];
-                    const double X2 = X1 * X1, XY = X1 * Y1, Y2 = Y1 * Y1;
-                    const double m[10] = {1.0, X1, Y1, X2, XY, Y2, X2 * X1, X2 * Y1, X1 * Y2, Y2 * Y1};
-#pragma unroll
-                    for (int q = 0; q < 10; ++q) acc[R::P1 + q] += wu * m[q];
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) acc[R::P2 + q] += wu2 * m[q];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) acc[R::P3 + q] += wu3 * m[q];
-                } else {
-                    double m[20];
-#pragma unroll
-                    for (int q = 0; q < 20; ++q) {
-                        double t = 1.0;
-#pragma unroll
-                        for (int d = 0; d < 3; ++d)
-#pragma unroll
-                            for (int e = 0; e < kMon3[q][d]; ++e) t *= x[d];
-                        m[q] = t;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 20; ++q) acc[R::P1 + q] += wu * m[q];
-#pragma unroll
-                    for (int q = 0; q < 10; ++q) acc[R::P2 + q] += wu2 * m[q];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[R::P3 + q] += wu3 * m[q];
-                }
-                acc[R::P4] += wu4;
-            }
-        }
-    }
-    // block reduction (fixed order)
-    __shared__ double red[4][R::SIZE];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < R::SIZE; ++q) {
-        double v = wave_sum(acc[q]);
-        if (lane == 0) red[wv][q] = v;
-    }
-    __syncthreads();
-    const int64_t ncell = gridDim.x;
-    for (int q = threadIdx.x; q < R::SIZE; q += blockDim.x) {
-        double v = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-        partial[(((int64_t)type * ncell + cell) * nchunk + chunk) * R::SIZE + q] = v;
-    }
-}
-
-// ---- pass 2 ------------------------------------------------------------------------------
-// Polynomials of the coarse-local coordinates are coefficient arrays over the graded
-// monomial lists of layout.h (degree <= 3).  All loops below have compile-time bounds and
-// indices, so the products are straight-line register code.
 template <int N, typename F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
     (f(std::integral_constant<int, I>{}), ...);
@@ -251,19 +103,325 @@ template <int D>
 struct Mono {
     static constexpr int NM = (D == 2) ? 10 : 20;        // degree <= 3
     static constexpr int N2 = (D == 2) ? 6 : 10;         // degree <= 2
+    static constexpr int N1 = D + 1;                     // degree <= 1
     static constexpr int exp(int q, int k) { return D == 2 ? kMon2[q][k] : kMon3[q][k]; }
-    // index of monomial q times x_d, -1 above degree 3
-    static constexpr int times_x(int q, int d) {
+    static constexpr int deg(int q) {
+        int t = 0;
+        for (int k = 0; k < D; ++k) t += exp(q, k);
+        return t;
+    }
+    // index of the monomial equal to q with the exponent of x_d replaced by e
+    static constexpr int with_exp(int q, int d, int e) {
         for (int r = 0; r < NM; ++r) {
             bool ok = true;
-            for (int k = 0; k < D; ++k) ok = ok && exp(r, k) == exp(q, k) + (k == d ? 1 : 0);
+            for (int k = 0; k < D; ++k) ok = ok && exp(r, k) == (k == d ? e : exp(q, k));
             if (ok) return r;
         }
         return -1;
     }
+    // index of monomial q times x_d, -1 above degree 3
+    static constexpr int times_x(int q, int d) { return with_exp(q, d, exp(q, d) + 1); }
     static constexpr int square(int d) { return times_x(times_x(0, d), d); }   // x_d^2
 };
 
+// Replace local moments L[q] = int f Y^{m_q} (monomials q < NQ of degree <= 3) by
+// int f (A + Y)^{m_q}, one coordinate at a time: along d,
+//   (A_d + Y_d)^e = sum_j C(e, j) A_d^(e-j) Y_d^j.
+// Entries with a larger exponent of x_d are updated first, so every update reads
+// unshifted values of the lower exponents.
+template <int D, int NQ>
+__device__ __forceinline__ void shift_moments(double* L, const double* A) {
+    using M = Mono<D>;
+    static_for<D>([&](auto d_) {
+        constexpr int d = decltype(d_)::value;
+        const double a1 = A[d], a2 = a1 * a1, a3 = a2 * a1;
+        static_for<NQ>([&](auto qq) {
+            constexpr int q = NQ - 1 - decltype(qq)::value;   // descending: higher degrees first
+            constexpr int e = M::exp(q, d);
+            if constexpr (e == 1) {
+                L[q] += a1 * L[M::with_exp(q, d, 0)];
+            } else if constexpr (e == 2) {
+                L[q] += 2.0 * a1 * L[M::with_exp(q, d, 1)] + a2 * L[M::with_exp(q, d, 0)];
+            } else if constexpr (e == 3) {
+                L[q] += 3.0 * a1 * L[M::with_exp(q, d, 2)] + 3.0 * a2 * L[M::with_exp(q, d, 1)] +
+                        a3 * L[M::with_exp(q, d, 0)];
+            }
+        });
+    });
+}
+
+// complete homogeneous symmetric polynomial of degree 4 of V values, from power sums
+template <int V>
+__device__ __forceinline__ double h4(const double* x) {
+    double p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const double x2 = x[v] * x[v];
+        p1 += x[v];
+        p2 += x2;
+        p3 += x2 * x[v];
+        p4 += x2 * x2;
+    }
+    const double p11 = p1 * p1;
+    return (p11 * (p11 + 6.0 * p2) + 3.0 * p2 * p2 + 8.0 * p1 * p3 + 6.0 * p4) * (1.0 / 24.0);
+}
+
+// table accessors by dimension (the other dimension's table is never indexed)
+template <int D> __host__ __device__ constexpr double tC1(int c, int q) { if constexpr (D == 2) return kC1_2D[c][q]; else return kC1_3D[c][q]; }
+template <int D> __host__ __device__ constexpr double tC2(int p, int q) { if constexpr (D == 2) return kC2_2D[p][q]; else return kC2_3D[p][q]; }
+template <int D> __host__ __device__ constexpr double tC3(int t, int q) { if constexpr (D == 2) return kC3_2D[t][q]; else return kC3_3D[t][q]; }
+template <int D> __host__ __device__ constexpr double tCG(int c, int d) { if constexpr (D == 2) return kCG2D[c][d]; else return kCG3D[c][d]; }
+template <int D> __host__ __device__ constexpr double tE1(int f, int v, int q) { if constexpr (D == 2) return kE1_2D[f][v][q]; else return kE1_3D[f][v][q]; }
+template <int D> __host__ __device__ constexpr double tE2(int f, int p, int q) { if constexpr (D == 2) return kE2_2D[f][p][q]; else return kE2_3D[f][p][q]; }
+template <int D> __host__ __device__ constexpr double tE3(int f, int t, int q) { if constexpr (D == 2) return kE3_2D[f][t][q]; else return kE3_3D[f][t][q]; }
+template <int D> __host__ __device__ constexpr int tPair(int p, int k) { if constexpr (D == 2) return kPair2D[p][k]; else return kPair3D[p][k]; }
+template <int D> __host__ __device__ constexpr int tTrip(int t, int k) { if constexpr (D == 2) return kTrip2D[t][k]; else return kTrip3D[t][k]; }
+template <int D> __host__ __device__ constexpr int tTripPair(int t) { if constexpr (D == 2) return kTripPair2D[t]; else return kTripPair3D[t]; }
+template <int D> __host__ __device__ constexpr int tCorner(int f, int v) { if constexpr (D == 2) return kCorner2D[f][v]; else return kCorner3D[f][v]; }
+template <int D> __host__ __device__ constexpr double tBary(int f, int v, int k) { if constexpr (D == 2) return kCellElemBary2D[f][v][k]; else return kCellElemBary3D[f][v][k]; }
+
+// Local moments of the cell with corner values uc[] (unit cell), accumulated into L1 (deg
+// <= 3), L2 (deg <= 2), L3 (deg <= 1), L4 and the gradient sums G (int d u~/dY_d), Q
+// (int |grad_Y u~|^2).  WHOLE: all fine simplices of the cell; otherwise the fine simplices
+// of the cell at coarse-local offset a[] that belong to coarse simplex `type`.
+template <int D, bool WHOLE>
+__device__ __forceinline__ void cell_moments(const double* uc, const int* a, int type, double* L1, double* L2,
+                                             double* L3, double& L4, double* G, double& Q) {
+    using M = Mono<D>;
+    constexpr int V = D + 1;
+    constexpr int NF = (D == 2) ? 2 : 6;
+    constexpr double k4 = (D == 2) ? 1.0 / 30.0 : 1.0 / 210.0;    // 4! / (D + 4)!
+    constexpr double vs = (D == 2) ? 0.5 : 1.0 / 6.0;             // simplex measure in the unit cell
+    if constexpr (WHOLE) {
+        constexpr int NC = 1 << D;
+        constexpr int NP = (D == 2) ? kPairs2D : kPairs3D;
+        constexpr int NT = (D == 2) ? kTrips2D : kTrips3D;
+        static_for<NC>([&](auto c_) {
+            constexpr int c = decltype(c_)::value;
+            static_for<M::NM>([&](auto q) { L1[q] += uc[c] * tC1<D>(c, q); });
+            static_for<D>([&](auto d) { G[d] += uc[c] * tCG<D>(c, d); });
+        });
+        double pr[NP];
+        static_for<NP>([&](auto p_) {
+            constexpr int p = decltype(p_)::value;
+            constexpr int a = tPair<D>(p, 0);
+            constexpr int b = tPair<D>(p, 1);
+            pr[p] = uc[a] * uc[b];
+            static_for<M::N2>([&](auto q) { L2[q] += pr[p] * tC2<D>(p, q); });
+        });
+        static_for<NT>([&](auto t_) {
+            constexpr int t = decltype(t_)::value;
+            constexpr int p = tTripPair<D>(t);
+            constexpr int c = tTrip<D>(t, 2);
+            const double w = pr[p] * uc[c];
+            static_for<M::N1>([&](auto q) { L3[q] += w * tC3<D>(t, q); });
+        });
+        static_for<NF>([&](auto f_) {
+            constexpr int f = decltype(f_)::value;
+            double uv[V], g[D];
+            static_for<V>([&](auto v) { uv[v] = uc[tCorner<D>(f, v)]; });
+            L4 += k4 * h4<V>(uv);
+            static_for<D>([&](auto d_) {
+                constexpr int d = decltype(d_)::value;
+                g[d] = 0.0;
+                static_for<V>([&](auto v_) {
+                    constexpr int v = decltype(v_)::value;
+                    constexpr double gb = tBary<D>(f, v, 1 + d);
+                    if constexpr (gb != 0.0) g[d] += gb * uv[v];
+                });
+            });
+            double g2 = 0.0;
+            static_for<D>([&](auto d) { g2 += g[d] * g[d]; });
+            Q += vs * g2;
+        });
+    } else {
+        static_for<NF>([&](auto f_) {
+            constexpr int f = decltype(f_)::value;
+            if (coarse_type<D>(a, f) != type) return;
+            double uv[V], g[D];
+            static_for<V>([&](auto v) { uv[v] = uc[tCorner<D>(f, v)]; });
+            static_for<V>([&](auto v) {
+                static_for<M::NM>([&](auto q) { L1[q] += uv[v] * tE1<D>(f, v, q); });
+            });
+            // vertex pairs v <= w and triples v <= w <= x in lexicographic order
+            int pi = 0, ti = 0;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int w = v; w < V; ++w) {
+                    const double pw = uv[v] * uv[w];
+#pragma unroll
+                    for (int q = 0; q < M::N2; ++q) L2[q] += pw * tE2<D>(f, pi, q);
+                    ++pi;
+                }
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int w = v; w < V; ++w)
+#pragma unroll
+                    for (int x = w; x < V; ++x) {
+                        const double tw = uv[v] * uv[w] * uv[x];
+#pragma unroll
+                        for (int q = 0; q < M::N1; ++q) L3[q] += tw * tE3<D>(f, ti, q);
+                        ++ti;
+                    }
+            L4 += k4 * h4<V>(uv);
+            static_for<D>([&](auto d_) {
+                constexpr int d = decltype(d_)::value;
+                g[d] = 0.0;
+                static_for<V>([&](auto v_) {
+                    constexpr int v = decltype(v_)::value;
+                    constexpr double gb = tBary<D>(f, v, 1 + d);
+                    if constexpr (gb != 0.0) g[d] += gb * uv[v];
+                });
+                G[d] += vs * g[d];
+            });
+            double g2 = 0.0;
+            static_for<D>([&](auto d) { g2 += g[d] * g[d]; });
+            Q += vs * g2;
+        });
+    }
+}
+
+// coarse-local cell offset of interior cell t (strictly ordered coordinates)
+template <int D>
+__device__ inline void interior_cell(int64_t t, int type, int* a) {
+    if (D == 2) {
+        // t -> (i', j'), i' >= j' >= 0 (triangular numbers); (hi, lo) = (i' + 1, j')
+        int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((int64_t)i * (i + 1) / 2 > t) --i;
+        while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = (int)(t - (int64_t)i * (i + 1) / 2);
+        const int hi = i + 1, lo = j;
+        a[0] = type == 0 ? hi : lo;
+        a[1] = type == 0 ? lo : hi;
+        a[2] = 0;
+    } else {
+        // t -> sorted triple i' >= j' >= k' (tetrahedral, then triangular numbers);
+        // (i, j, k) = (i' + 2, j' + 1, k') is strictly decreasing
+        int i = (int)cbrt(6.0 * (double)t);
+        while ((int64_t)i * (i + 1) * (i + 2) / 6 > t) --i;
+        while ((int64_t)(i + 1) * (i + 2) * (i + 3) / 6 <= t) ++i;
+        const int r = (int)(t - (int64_t)i * (i + 1) * (i + 2) / 6);
+        int j = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
+        while (j * (j + 1) / 2 > r) --j;
+        while ((j + 1) * (j + 2) / 2 <= r) ++j;
+        const int k = r - j * (j + 1) / 2;
+        // type 2 p0 + q: largest axis p0; q = 1 puts the larger remaining axis second
+        const int p0 = type >> 1, o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
+        const int p1 = (type & 1) ? o2 : o1, p2 = (type & 1) ? o1 : o2;
+        a[p0] = i + 2;
+        a[p1] = j + 1;
+        a[p2] = k;
+    }
+}
+
+// coarse-local cell offset of tie cell t (s: fine cells per coarse edge)
+template <int D>
+__device__ inline void tie_cell(int64_t t, int type, int s, int* a) {
+    if (D == 2) {
+        a[0] = a[1] = (int)t;
+        a[2] = 0;
+    } else {
+        // three groups: i = j > k (s (s - 1) / 2 cells), i > j = k (as many), i = j = k (s)
+        const int64_t half = (int64_t)s * (s - 1) / 2;
+        int i, j, k;
+        if (t < 2 * half) {
+            const int64_t r = t < half ? t : t - half;
+            int p = (int)((sqrt(8.0 * (double)r + 1.0) - 1.0) * 0.5);   // p >= q >= 0 over s - 1
+            while ((int64_t)p * (p + 1) / 2 > r) --p;
+            while ((int64_t)(p + 1) * (p + 2) / 2 <= r) ++p;
+            const int q = (int)(r - (int64_t)p * (p + 1) / 2);
+            if (t < half) { i = j = p + 1; k = q; }
+            else { i = p + 1; j = k = q; }
+        } else {
+            i = j = k = (int)(t - 2 * half);
+        }
+        const int p0 = type >> 1, o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
+        const int p1 = (type & 1) ? o2 : o1, p2 = (type & 1) ? o1 : o2;
+        a[p0] = i;
+        a[p1] = j;
+        a[p2] = k;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ ut, Grid g, int nc, int64_t n_int,
+                                                     int64_t n_tie, int c_int, int s, double* __restrict__ partial) {
+    using R = RawLayout<D>;
+    using M = Mono<D>;
+    constexpr int NC = 1 << D;
+    const int64_t cell = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const int type = blockIdx.z;
+    const int64_t nchunk = gridDim.y;
+    const bool ties = chunk >= c_int;
+    const int64_t start = (int64_t)(ties ? chunk - c_int : chunk) * kChunkCells;
+    const int64_t end = min(ties ? n_tie : n_int, start + (int64_t)kChunkCells);
+    const int C[3] = {(int)(cell % nc), (int)((cell / nc) % nc), D == 3 ? (int)(cell / ((int64_t)nc * nc)) : 0};
+    const int64_t P = g.pitch, S = g.plane;
+    double acc[R::SIZE];
+#pragma unroll
+    for (int q = 0; q < R::SIZE; ++q) acc[q] = 0.0;
+
+    for (int64_t idx = start + threadIdx.x; idx < end; idx += blockDim.x) {
+        int a[3];
+        if (ties) tie_cell<D>(idx, type, s, a);
+        else interior_cell<D>(idx, type, a);
+        const int64_t base = (C[0] * s + a[0]) + P * (C[1] * s + a[1]) + S * (D == 3 ? C[2] * s + a[2] : 0);
+        double uc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uc[c] = ut[base + (c & 1) + P * ((c >> 1) & 1) + S * ((c >> 2) & 1)];
+        double L1[M::NM], L2[M::N2], L3[M::N1], L4 = 0.0, G[D], Q = 0.0;
+        static_for<M::NM>([&](auto q) { L1[q] = 0.0; });
+        static_for<M::N2>([&](auto q) { L2[q] = 0.0; });
+        static_for<M::N1>([&](auto q) { L3[q] = 0.0; });
+        static_for<D>([&](auto d) { G[d] = 0.0; });
+        if (!ties)
+            cell_moments<D, true>(uc, a, type, L1, L2, L3, L4, G, Q);
+        else
+            cell_moments<D, false>(uc, a, type, L1, L2, L3, L4, G, Q);
+        const double A[3] = {(double)a[0], (double)a[1], (double)a[2]};
+        shift_moments<D, M::NM>(L1, A);
+        shift_moments<D, M::N2>(L2, A);
+        shift_moments<D, M::N1>(L3, A);
+        static_for<M::NM>([&](auto q) { acc[R::P1 + q] += L1[q]; });
+        static_for<M::N2>([&](auto q) { acc[R::P2 + q] += L2[q]; });
+        static_for<M::N1>([&](auto q) { acc[R::P3 + q] += L3[q]; });
+        acc[R::P4] += L4;
+        static_for<D>([&](auto d) { acc[R::G + d] += G[d]; });
+        acc[R::Q] += Q;
+    }
+    // block reduction (fixed order), then the scales: unit cells -> h^D, (A + Y)^b -> X^b = s^-|b|,
+    // d/dY -> h d/dx
+    __shared__ double red[4][R::SIZE];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < R::SIZE; ++q) {
+        double v = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    const int64_t ncell = gridDim.x;
+    const double h = g.h, hd = (D == 2) ? h * h : h * h * h, inv_s = 1.0 / s;
+    for (int q = threadIdx.x; q < R::SIZE; q += blockDim.x) {
+        double v = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+        double sc = hd;
+        int deg = 0;
+        if (q < R::P2) deg = M::deg(q);
+        else if (q < R::P3) deg = M::deg(q - R::P2);
+        else if (q < R::P4) deg = M::deg(q - R::P3);
+        for (int e = 0; e < deg; ++e) sc *= inv_s;
+        if (q >= R::G && q < R::Q) sc = hd / h;
+        if (q == R::Q) sc = hd / (h * h);
+        partial[(((int64_t)type * ncell + cell) * nchunk + chunk) * R::SIZE + q] = v * sc;
+    }
+}
+
+// ---- pass 2 ------------------------------------------------------------------------------
+// Polynomials of the coarse-local coordinates are coefficient arrays over the graded
+// monomial lists of layout.h (degree <= 3).  All loops below have compile-time bounds and
+// indices, so the products are straight-line register code.
 // out = A * (l[0] + sum_d l[1+d] x_d) for A of degree <= 2 (its first N2 coefficients)
 template <int D>
 __device__ __forceinline__ void mul_affine(const double* A, const double* l, double* out) {
@@ -367,17 +525,19 @@ __global__ __launch_bounds__(64) void k_moments_final(const double* __restrict__
 
 void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double* ut, double* scratch, double* out,
                     hipStream_t s) {
-    int64_t ncell, cells_per, nchunk;
-    chunk_shape(dim, nc, g.n, ncell, cells_per, nchunk);
+    const ChunkShape c = chunk_shape(dim, nc, g.n);
     const int sc = g.n / nc;
+    const unsigned nchunk = (unsigned)(c.c_int + c.c_tie);
     if (dim == 2) {
-        hipLaunchKernelGGL(k_moments_raw<2>, dim3((unsigned)ncell, (unsigned)nchunk, 2), dim3(256), 0, s, ut, g, nc,
-                           cells_per, sc, scratch);
-        hipLaunchKernelGGL(k_moments_final<2>, dim3(cdiv(ncell * 2, 64)), dim3(64), 0, s, scratch, nc, nchunk, ph, out);
+        hipLaunchKernelGGL(k_moments_raw<2>, dim3((unsigned)c.ncell, nchunk, 2), dim3(256), 0, s, ut, g, nc, c.n_int,
+                           c.n_tie, (int)c.c_int, sc, scratch);
+        hipLaunchKernelGGL(k_moments_final<2>, dim3(cdiv(c.ncell * 2, 64)), dim3(64), 0, s, scratch, nc,
+                           (int64_t)nchunk, ph, out);
     } else {
-        hipLaunchKernelGGL(k_moments_raw<3>, dim3((unsigned)ncell, (unsigned)nchunk, 6), dim3(256), 0, s, ut, g, nc,
-                           cells_per, sc, scratch);
-        hipLaunchKernelGGL(k_moments_final<3>, dim3(cdiv(ncell * 6, 64)), dim3(64), 0, s, scratch, nc, nchunk, ph, out);
+        hipLaunchKernelGGL(k_moments_raw<3>, dim3((unsigned)c.ncell, nchunk, 6), dim3(256), 0, s, ut, g, nc, c.n_int,
+                           c.n_tie, (int)c.c_int, sc, scratch);
+        hipLaunchKernelGGL(k_moments_final<3>, dim3(cdiv(c.ncell * 6, 64)), dim3(64), 0, s, scratch, nc,
+                           (int64_t)nchunk, ph, out);
     }
 }
 

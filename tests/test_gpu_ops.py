@@ -188,7 +188,8 @@ def _unique(arr, order):
     return np.stack([arr[(slice(None),) + t] for t in idx], axis=-1)
 
 
-@pytest.mark.parametrize("prob", AUG_CASES)
+@pytest.mark.parametrize("prob", AUG_CASES + [W.Problem(3, 2, 3, (0.6, 1.4, 1.1), 0.2, 5.0),
+                                              W.Problem(2, 2, 5, (1.2, 0.8, 0.0), 0.1, 5.0)])
 def test_moments_match_oracle_per_coarse_simplex(ops, prob):
     from oracle import fem
     h = oracle_hierarchy(prob)

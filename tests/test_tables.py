@@ -1,53 +1,102 @@
-"""Pins for the constant tables the HIP kernels compile in (csrc/tables.h), read from the
-header text and checked without the generator: the quadrature rules integrate every
-monomial of degree <= 4 exactly on the reference simplex, and the star mass moments
-add up to int phi_0 = 1 (unit lattice)."""
+"""Pins for the constant tables the HIP kernels compile in (csrc/tables.h and
+csrc/moment_tables.h), read from the header text and checked without the generators:
+
+* the star mass moments add up to int phi_0 = 1 (unit lattice);
+* the moment tables reproduce, for seeded integer corner values of a P1 function u on the
+  unit cell, every integral int u^k Y^b (k = 1, 2, 3 with |b| <= 4 - k) over the whole cell
+  and over each of its simplices, and the cell integrals of grad u, as computed by exact
+  iterated integration with sympy (no barycentric formula involved)."""
 import itertools
-import math
 import os
 import re
 
 import numpy as np
+import pytest
+import sympy as sp
 
-HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1502_04657_amd", "csrc",
-                   "tables.h")
+from tests.symbolic import X, integrate_simplex, p1_basis
+
+CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1502_04657_amd", "csrc")
 
 
-def _array(name):
-    text = open(HDR).read()
-    m = re.search(r"%s\[[^=]*=\s*\{(.*?)\};" % re.escape(name), text, flags=re.S)
+def _array(name, header="tables.h"):
+    text = open(os.path.join(CSRC, header)).read()
+    m = re.search(r"%s((?:\[\d+\])+)\s*=\s*\{(.*?)\};" % re.escape(name), text, flags=re.S)
     assert m, name
-    return np.array([float(v) for v in re.findall(r"-?\d+(?:\.\d+)?(?:[eE][-+]?\d+)?", m.group(1))])
-
-
-def _exact(mon):
-    # int over the unit simplex of prod l_i^a_i / volume = d! prod a_i! / (d + sum a)!
-    d = len(mon) - 1
-    num = math.factorial(d)
-    for a in mon:
-        num *= math.factorial(a)
-    return num / math.factorial(d + sum(mon))
-
-
-def _check_rule(pts, wts, nb):
-    pts = pts.reshape(-1, nb)
-    assert len(pts) == len(wts)
-    assert np.allclose(pts.sum(axis=1), 1.0, atol=1e-15)
-    for mon in itertools.product(range(5), repeat=nb):
-        if sum(mon) > 4:
-            continue
-        q = float(np.sum(wts * np.prod(pts ** np.array(mon), axis=1)))
-        assert abs(q - _exact(mon)) <= 2e-16 * max(1.0, abs(_exact(mon))) * 8, (mon, q, _exact(mon))
-
-
-def test_triangle_rule_is_exact_to_degree_4():
-    _check_rule(_array("kQuadPt2D"), _array("kQuadW2D"), 3)
-
-
-def test_tetrahedron_rule_is_exact_to_degree_4():
-    _check_rule(_array("kQuadPt3D"), _array("kQuadW3D"), 4)
+    dims = [int(x) for x in re.findall(r"\[(\d+)\]", m.group(1))]
+    vals = np.array([float(v) for v in re.findall(r"-?\d+(?:\.\d+)?(?:[eE][-+]?\d+)?", m.group(2))])
+    return vals.reshape(dims)
 
 
 def test_star_mass_moments_integrate_the_hat():
     for name in ("kM0_2D", "kM0_3D"):
         assert abs(_array(name).sum() - 1.0) < 1e-15
+
+
+MON = {2: [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1), (1, 2), (0, 3)],
+       3: [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (1, 1, 0), (1, 0, 1), (0, 2, 0), (0, 1, 1),
+           (0, 0, 2), (3, 0, 0), (2, 1, 0), (2, 0, 1), (1, 2, 0), (1, 1, 1), (1, 0, 2), (0, 3, 0), (0, 2, 1),
+           (0, 1, 2), (0, 0, 3)]}
+
+
+def _cell_simplices(D):
+    if D == 2:
+        return [[(0, 0), (1, 0), (1, 1)], [(0, 0), (1, 1), (0, 1)]]
+    out = []
+    for perm in itertools.permutations(range(3)):
+        v = [0, 0, 0]
+        verts = [tuple(v)]
+        for ax in perm:
+            v = list(v)
+            v[ax] += 1
+            verts.append(tuple(v))
+        out.append(verts)
+    return out
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_moment_tables_are_exact(D):
+    H = "moment_tables.h"
+    rng = np.random.default_rng(11 + D)
+    uc = [int(v) for v in rng.integers(-3, 4, size=1 << D)]
+    simp = _cell_simplices(D)
+    corner = _array(f"kCorner{D}D", H).astype(int)
+    # the simplices of the table are those of the mesh description, in the same order
+    for t, verts in enumerate(simp):
+        assert [sum(c << i for i, c in enumerate(v)) for v in verts] == list(corner[t])
+    nk = {1: len(MON[D]), 2: sum(1 for m in MON[D] if sum(m) <= 2), 3: D + 1}
+    exact = {k: np.zeros(nk[k]) for k in (1, 2, 3)}
+    per_simplex = []
+    grad = np.zeros(D)
+    for t, verts in enumerate(simp):
+        lam = p1_basis(verts)
+        u = sum(uc[corner[t][v]] * lam[v] for v in range(D + 1))
+        mine = {}
+        for k in (1, 2, 3):
+            mine[k] = np.array([float(integrate_simplex(u ** k * sp.Mul(*[X[d] ** m[d] for d in range(D)]), verts))
+                                for m in MON[D][: nk[k]]])
+            exact[k] += mine[k]
+        per_simplex.append(mine)
+        for d in range(D):
+            grad[d] += float(integrate_simplex(sp.diff(u, X[d]), verts))
+    # whole-cell tables, grouped by corner products
+    C1, C2, C3 = _array(f"kC1_{D}D", H), _array(f"kC2_{D}D", H), _array(f"kC3_{D}D", H)
+    pairs, trips = _array(f"kPair{D}D", H).astype(int), _array(f"kTrip{D}D", H).astype(int)
+    L1 = sum(uc[c] * C1[c] for c in range(1 << D))
+    L2 = sum(uc[a] * uc[b] * C2[p] for p, (a, b) in enumerate(pairs))
+    L3 = sum(uc[a] * uc[b] * uc[c] * C3[q] for q, (a, b, c) in enumerate(trips))
+    for got, k in ((L1, 1), (L2, 2), (L3, 3)):
+        assert np.allclose(got, exact[k], rtol=0, atol=1e-13), k
+    CG = _array(f"kCG{D}D", H)
+    assert np.allclose(sum(uc[c] * CG[c] for c in range(1 << D)), grad, rtol=0, atol=1e-14)
+    # per-simplex tables: vertex multisets in lexicographic order
+    E1, E2, E3 = _array(f"kE1_{D}D", H), _array(f"kE2_{D}D", H), _array(f"kE3_{D}D", H)
+    for t in range(len(simp)):
+        uv = [uc[corner[t][v]] for v in range(D + 1)]
+        l1 = sum(uv[v] * E1[t][v] for v in range(D + 1))
+        l2 = sum(uv[a] * uv[b] * E2[t][i]
+                 for i, (a, b) in enumerate(itertools.combinations_with_replacement(range(D + 1), 2)))
+        l3 = sum(uv[a] * uv[b] * uv[c] * E3[t][i]
+                 for i, (a, b, c) in enumerate(itertools.combinations_with_replacement(range(D + 1), 3)))
+        for got, k in ((l1, 1), (l2, 2), (l3, 3)):
+            assert np.allclose(got, per_simplex[t][k], rtol=0, atol=1e-13), (t, k)
