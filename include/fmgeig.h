@@ -116,10 +116,23 @@ typedef struct {
 const char* fmg_last_error(void);
 const char* fmg_version(void);
 
-/* Select the 2D V-cycle implementation for later calls in this process: 1 (default) fused
- * temporally blocked level passes, 0 the unfused kernel sequence.  Both execute the same
- * floating-point operations and give identical results.  Not thread-safe.                */
+/* Select the V-cycle implementation for later calls in this process: 1 (default) fused
+ * temporally blocked level passes (2D; 3D levels with n >= 16 and nu_pre = nu_post in
+ * {1, 2}), 0 the unfused kernel sequence.  Both execute the same floating-point operations
+ * and give identical results.  Not thread-safe.                                          */
 int fmg_set_fused_vcycle(int32_t enable);
+
+/* ---- kernel tuning ------------------------------------------------------------------------ */
+/* Launch choices of the fused V-cycle passes, process-wide (not thread-safe; set them before
+ * solves start).  They change speed only: every choice gives the same bits.  The values come
+ * from fmg_autotune_vcycle or a cache of its results.                                    */
+typedef struct {
+    int32_t vpass3d_variant;  /* 3D pass tiles: 0 = 256-thread blocks, 1 = 512-thread blocks */
+    int32_t vpass3d_min_n;    /* smallest 3D level (cells per side) on the fused passes      */
+    int32_t reserved[6];
+} fmg_tuning;
+int fmg_get_tuning(fmg_tuning* out);
+int fmg_set_tuning(const fmg_tuning* in);   /* FMG_EINVAL for values out of range            */
 
 /* ---- measurement hooks ------------------------------------------------------------------ */
 /* Per-launch timing of one kernel inside later solves: a pair of HIP events is stamped by

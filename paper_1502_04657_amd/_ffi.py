@@ -26,6 +26,10 @@ class fmg_options(C.Structure):
                 ("smoother", C.c_int32), ("reserved", C.c_int32)]
 
 
+class fmg_tuning(C.Structure):
+    _fields_ = [("vpass3d_variant", C.c_int32), ("vpass3d_min_n", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
 class fmg_kernel_profile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double)]
 
@@ -53,6 +57,8 @@ SIGNATURES = {
     "fmg_last_error": (C.c_char_p, []),
     "fmg_version": (C.c_char_p, []),
     "fmg_set_fused_vcycle": (C.c_int, [I32]),
+    "fmg_get_tuning": (C.c_int, [P]),
+    "fmg_set_tuning": (C.c_int, [P]),
     "fmg_profile_begin": (C.c_int, [I32, I32]),
     "fmg_profile_end": (C.c_int, [P]),
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),

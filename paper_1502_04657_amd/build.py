@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfmgeig.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["grid.hip", "vcycle2d.hip", "moments.hip", "small.hip", "api.hip", "runtime.hip"]
+SOURCES = ["grid.hip", "vcycle2d.hip", "vcycle3d.hip", "moments.hip", "small.hip", "api.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions are kept out of all device code

@@ -110,7 +110,7 @@ Layout make_layout(int dim, int nc, int levels, int mixed, int cg) {
         lo.xv[l] = top_only ? 0 : take(ts * lo.g[l].elems);
         lo.fv[l] = top_only ? 0 : take(ts * lo.g[l].elems);
         // the fused passes run in the V-cycle precision; the coarsest level needs none
-        lo.tv[l] = (dim == 2 && l > 0) ? take(ts * lo.g[l].elems) : 0;
+        lo.tv[l] = l > 0 ? take(ts * lo.g[l].elems) : 0;
     }
     if (cg) {
         // CG smoothing: r, p, q sized for the finest level (zero rings: inside the zeroed range)
@@ -169,6 +169,13 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
             g_prof.bytes += (3.0 * nf + ncs) * sizeof(double);
             ++g_prof.used;
         }
+        return;
+    }
+    if (lo.dim == 3 && g_fused && !lo.cg && vpass3d_applies(g, nu_pre, nu_post)) {
+        T* y = at<T>(ws, lo.tv[l]);
+        T* xs = launch_vpre3d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
+        vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
+        launch_vpost3d<T>(g, lo.g[l - 1], xs, xs == x ? y : x, x, f, xc, nu_post, s);
         return;
     }
     // unfused: red-black SGS (nu sweeps = 2 nu + 1 half sweeps) or nu CG steps
@@ -447,6 +454,24 @@ int fmg_set_fused_vcycle(int32_t enable) {
     g_fused = enable ? 1 : 0;
     return 0;
 }
+int fmg_get_tuning(fmg_tuning* out) {
+    if (!out) return set_error(FMG_EINVAL, "tuning is NULL");
+    std::memset(out, 0, sizeof(*out));
+    int v = 0, mn = 0;
+    get_vpass3d_tuning(&v, &mn);
+    out->vpass3d_variant = v;
+    out->vpass3d_min_n = mn;
+    return 0;
+}
+
+int fmg_set_tuning(const fmg_tuning* in) {
+    if (!in) return set_error(FMG_EINVAL, "tuning is NULL");
+    if (in->vpass3d_variant < 0 || in->vpass3d_variant > 1) return set_error(FMG_EINVAL, "vpass3d_variant must be 0 or 1");
+    if (in->vpass3d_min_n < 16) return set_error(FMG_EINVAL, "vpass3d_min_n must be >= 16");
+    set_vpass3d_tuning(in->vpass3d_variant, in->vpass3d_min_n);
+    return 0;
+}
+
 int fmg_profile_begin(int32_t kernel, int32_t max_launches) {
     if (kernel != FMG_PROF_VPOST2D_F64 || max_launches < 1 || max_launches > (1 << 20))
         return set_error(FMG_EINVAL, "bad profile request");

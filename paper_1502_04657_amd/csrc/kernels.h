@@ -61,6 +61,22 @@ template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T
                                           int nu, hipStream_t s, hipEvent_t ev0 = nullptr,
                                           hipEvent_t ev1 = nullptr);
 
+// ---- vcycle3d.hip ----------------------------------------------------------------------
+// fused 3D V-cycle level passes (z-pipelined red-black half sweeps): applies to levels with
+// n >= 16 and nu_pre = nu_post in {1, 2}.  pre: x (zero_x: taken as zero) -> smoothed, and
+// rc = P^T (f - K x_smoothed); returns the array (x or y) that holds the smoothed values.
+// post: x = post smoothing of (that array + P xc); the other array is scratch.
+bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post);
+// tile variant (0: 256 threads, 1: 512 threads) and the smallest level that takes the
+// fused passes (negative / 0: keep the current value)
+void set_vpass3d_tuning(int variant, int min_n);
+void get_vpass3d_tuning(int* variant, int* min_n);
+template <typename T> T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu,
+                                       int zero_x, hipStream_t s);
+template <typename T> void launch_vpost3d(const Grid& g, const Grid& gc, T* xs, T* scratch, T* x_out, const T* f,
+                                          const T* xc, int nu, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                          hipEvent_t ev1 = nullptr);
+
 // ---- moments.hip ------------------------------------------------------------------------
 int moments_per_element(int dim);            // doubles per coarse element in the output
 size_t moments_scratch_bytes(int dim, int nc, int n);

@@ -96,7 +96,8 @@ def test_coarse_solve_is_exact(ops, dim, n):
     assert rel_err(host_compact(dim, n, x32), ref) < 1e-5
 
 
-@pytest.mark.parametrize("dim, nc, levels", [(2, 8, 3), (2, 16, 4), (2, 12, 4), (2, 6, 7), (3, 4, 3), (3, 2, 4)])
+@pytest.mark.parametrize("dim, nc, levels", [(2, 8, 3), (2, 16, 4), (2, 12, 4), (2, 6, 7), (3, 4, 3), (3, 2, 4),
+                                             (3, 3, 4), (3, 4, 5), (3, 5, 4)])
 def test_vcycle(ops, dim, nc, levels):
     from oracle.mg import MGHierarchy
     from paper_1502_04657_amd import lib
@@ -143,6 +144,37 @@ def test_fused_vcycle_large_levels_bitwise(ops, nc, levels):
         lib().fmg_set_fused_vcycle(1)
     assert torch.equal(got, unf)
     assert bool(torch.isfinite(got).all())
+
+
+@pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (3, 6), (5, 5), (4, 4)])
+@pytest.mark.parametrize("nu", [1, 2])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fused_vcycle_3d_bitwise(ops, nc, levels, nu, variant):
+    """3D levels from n = 16 on run the z-pipelined level passes (forced through the tuning
+    interface; ragged tiles and z-chunks at n = 96, 80, 160): the same bits as the unfused
+    kernel sequence, for V(1,1) (one pass per side) and V(2,2) (two passes per side), with
+    both tile variants."""
+    import ctypes as C
+    from paper_1502_04657_amd import _ffi, lib
+    saved = _ffi.fmg_tuning()
+    assert lib().fmg_get_tuning(C.byref(saved)) == 0
+    t = _ffi.fmg_tuning()
+    t.vpass3d_variant, t.vpass3d_min_n = variant, 16
+    assert lib().fmg_set_tuning(C.byref(t)) == 0
+    n = nc << (levels - 1)
+    x0 = W.random_interior(3, n, seed=31)
+    f = W.random_interior(3, n, seed=32)
+    prob = W.Problem(3, nc, levels - 1)
+    opts = W.Options(nu_pre=nu, nu_post=nu)
+    try:
+        got = ops.vcycle(prob, opts, dev_level(3, n, x0), dev_level(3, n, f))
+        lib().fmg_set_fused_vcycle(0)
+        unf = ops.vcycle(prob, opts, dev_level(3, n, x0), dev_level(3, n, f))
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+        assert lib().fmg_set_tuning(C.byref(saved)) == 0
+    assert bool(torch.isfinite(got).all())
+    assert torch.equal(got, unf)
 
 
 RHS_CASES = [W.Problem(2, 4, 2, (1.5, 0.5, 0.0), 0.25, 7.0), W.Problem(2, 12, 3, (1.0, 2.0, 0.0), 0.0, 100.0),
