@@ -158,6 +158,7 @@ struct Args {
     int certify;         // ground-state inertia check: 0 never, 1 always, 2 when the step meets tol_lambda
     double* fac;         // persistent block factor, may be null
     int reuse;           // start from the stored factor when it exists
+    double* esc;         // global scratch: per-simplex values of the 3D assembly (kEsc each)
     // dump mode
     const double* xin;
     double* Aout;
@@ -388,83 +389,36 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
     const int N = ar.z.N, m = ar.z.m, nc = a.nc;
     if (!AUG) return;
     double v3[3] = {0.0, 0.0, 0.0};
-    if constexpr (D == 2) {
-        // one pass: each node gathers its border entries from the simplices around it; the
-        // scalars are summed over simplices by a second loop
-        for (int i = threadIdx.x; i < N; i += kThreads) {
-            int P[3];
-            node_pos<D>(i, m, P);
-            double sa = 0.0, sb = 0.0;
-            static_for<(1 << D)>([&](auto cvc) {
-                constexpr int cv = decltype(cvc)::value;
-                const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1);
-                if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc) return;
-                const int cl = C0 + nc * C1;
-                for_simplices<D>([&](auto tc) {
-                    constexpr int t = decltype(tc)::value;
-                    constexpr int v = VertOf<D, t, cv>::value;
-                    if constexpr (v >= 0) {
-                        const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
-                        sa += mo[L::KG + v] + mo[L::AW1 + v];
-                        sb += mo[L::B1 + v];
-                    }
-                });
-            });
-            ar.aH[i] = sa;
-            ar.bH[i] = sb;
-        }
-        for (int e = threadIdx.x; e < nc * nc * NE; e += kThreads) {
-            const double* mo = a.mom + (size_t)e * L::SIZE;
-            static_for<V>([&](auto vc) { v3[2] += mo[L::B1 + decltype(vc)::value]; });
-            v3[0] += mo[L::Q] + mo[L::AW2];
-            v3[1] += mo[L::B2];
-        }
-        bsum<3>(ar.red, v3);
-        if (threadIdx.x == 0) {
-            ar.sc[0] = v3[0];  // aU
-            ar.sc[1] = v3[1];  // bU
-            ar.sc[2] = v3[2];  // int u~
-        }
-        __syncthreads();
-        return;
-    }
-    // with a global-memory arena the border accumulates in the LDS staging area
-    const bool staged = ar.stage_blocks > 0 && (size_t)(2 * N) <= 2 * (size_t)ar.stage_blocks * ar.z.B2;
-    double* aH = staged ? ar.stage : ar.aH;
-    double* bH = staged ? ar.stage + N : ar.bH;
+    // one pass: each node gathers its border entries from the simplices around it in a fixed
+    // order; the scalars are summed over the simplices by a second loop
     for (int i = threadIdx.x; i < N; i += kThreads) {
-        aH[i] = 0.0;
-        bH[i] = 0.0;
-    }
-    __syncthreads();
-    for (int color = 0; color < (1 << D); ++color) {
-        const ColorClass cc = color_class<D>(nc, color);
-        for (int q = threadIdx.x; q < cc.ncol; q += kThreads) {
-            int C0, C1, C2, cl;
-            cell_of<D>(cc, q, nc, C0, C1, C2, cl);
+        int P[3];
+        node_pos<D>(i, m, P);
+        double sa = 0.0, sb = 0.0;
+        static_for<(1 << D)>([&](auto cvc) {
+            constexpr int cv = decltype(cvc)::value;
+            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 3) ? P[2] - ((cv >> 2) & 1) : 0;
+            if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc))) return;
+            const int cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
             for_simplices<D>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
-                const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
-                static_for<V>([&](auto vc) {
-                    constexpr int v = decltype(vc)::value;
-                    const int nd = vert_node<D, t, v>(C0, C1, C2, m);
-                    if (nd >= 0) {
-                        aH[nd] += mo[L::KG + v] + mo[L::AW1 + v];
-                        bH[nd] += mo[L::B1 + v];
-                    }
-                    v3[2] += mo[L::B1 + v];
-                });
-                v3[0] += mo[L::Q] + mo[L::AW2];
-                v3[1] += mo[L::B2];
+                constexpr int v = VertOf<D, t, cv>::value;
+                if constexpr (v >= 0) {
+                    const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
+                    sa += mo[L::KG + v] + mo[L::AW1 + v];
+                    sb += mo[L::B1 + v];
+                }
             });
-        }
-        __syncthreads();
+        });
+        ar.aH[i] = sa;
+        ar.bH[i] = sb;
     }
-    if (staged) {
-        for (int i = threadIdx.x; i < N; i += kThreads) {
-            ar.aH[i] = aH[i];
-            ar.bH[i] = bH[i];
-        }
+    const int nsimp = ((D == 2) ? nc * nc : nc * nc * nc) * NE;
+    for (int e = threadIdx.x; e < nsimp; e += kThreads) {
+        const double* mo = a.mom + (size_t)e * L::SIZE;
+        static_for<V>([&](auto vc) { v3[2] += mo[L::B1 + decltype(vc)::value]; });
+        v3[0] += mo[L::Q] + mo[L::AW2];
+        v3[1] += mo[L::B2];
     }
     bsum<3>(ar.red, v3);
     if (threadIdx.x == 0) {
@@ -628,99 +582,109 @@ __device__ __forceinline__ void assemble_S_nodes(Arena<D, AUG>& ar, const Args& 
     __syncthreads();
 }
 
-// S(x) by colour classes (3D; the one-pass version needs more registers than the 3D
-// kernels can give without spilling).  One pass per colour class; within a
-// pass one thread per (cell, cell vertex) adds the rows of that vertex from every simplex
-// of the cell that contains it (the cell vertex is uniform per wavefront).  The corner
-// term of each simplex is added by the thread of its vertex 0 (the cell origin).
+// S(x) in two passes (3D, where one thread per node would leave most lanes idle on small
+// coarse spaces and the per-node version of 2D spills registers):
+//   1. one thread per simplex computes its element matrix of S (the rows of elem_row; 10
+//      unique entries), its border entries (4) and its corner term into the global scratch;
+//   2. one thread per node adds, in a fixed order, the entries of the simplices around it
+//      (the loop structure of assemble_S_nodes), so no colouring and no atomics.
+constexpr int kEsc = 16;   // per-simplex scratch: 10 matrix entries, 4 border entries, corner
 template <int D, bool AUG>
-__device__ __forceinline__ void assemble_S_colours(Arena<D, AUG>& ar, const Args& a, const double* x) {
+__device__ __forceinline__ void assemble_S_simplices(Arena<D, AUG>& ar, const Args& a, const double* x) {
     constexpr int NS = Geo<D>::NS;
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
     constexpr int NCV = 1 << D;
+    constexpr int NSYM = V * (V + 1) / 2;
+    static_assert(NSYM + V + 1 <= kEsc, "per-simplex scratch");
     using L = MomLayout<D>;
     const int N = ar.z.N, nc = a.nc, m = ar.z.m;
     const double H = 1.0 / nc;
     const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
     const double c = AUG ? x[N] : 0.0;
-    // with a global-memory arena the rows, the border and x live in the LDS staging area
-    // while the passes scatter into them (copied out at the end)
-    const bool staged = ar.stage_blocks > 0 &&
-                        (size_t)(N * NS + 2 * N + 2) <= 2 * (size_t)ar.stage_blocks * ar.z.B2;
-    double* Sst = staged ? ar.stage : ar.Sst;
-    double* sH = staged ? ar.stage + (size_t)N * NS : ar.sH;
-    if (staged) {
-        double* xs = ar.stage + (size_t)N * NS + N;
-        for (int i = threadIdx.x; i < N + 1; i += kThreads) xs[i] = x[i];
-        x = xs;
-    }
-    for (int t = threadIdx.x; t < N * NS; t += kThreads) Sst[t] = 0.0;
-    if (AUG)
-        for (int i = threadIdx.x; i < N; i += kThreads) sH[i] = 0.0;
-    __syncthreads();
+    double* es = a.esc;
+    const int ncell = (D == 2) ? nc * nc : nc * nc * nc;
+    const int nsimp = ncell * NE;
     double sU = 0.0;
-    for (int color = 0; color < NCV; ++color) {
-        const ColorClass cc = color_class<D>(nc, color);
-        for (int task = threadIdx.x; task < NCV * cc.ncolp; task += kThreads) {
-            const int cvv = task / cc.ncolp, q = task - cvv * cc.ncolp;
-            if (q < cc.ncol) {
-                int C0, C1, C2, cl;
-                cell_of<D>(cc, q, nc, C0, C1, C2, cl);
-                dispatch<NCV>(cvv, [&](auto cvc) {
-                    constexpr int cv = decltype(cvc)::value;
-                    for_simplices<D>([&](auto tc) {
-                        constexpr int t = decltype(tc)::value;
-                        constexpr int aa = VertOf<D, t, cv>::value;
-                        if constexpr (aa >= 0) {
-                            int nd[V];
-                            double U[V];
-                            static_for<V>([&](auto vc) {
-                                constexpr int v = decltype(vc)::value;
-                                nd[v] = vert_node<D, t, v>(C0, C1, C2, m);
-                                U[v] = nd[v] >= 0 ? x[nd[v]] : 0.0;
-                            });
-                            double UU[V * (V + 1) / 2];
+    // simplices in type-major order, so that the simplex type (a compile-time branch) is
+    // uniform across a wavefront except where two types meet
+    for (int f = threadIdx.x; f < nsimp; f += kThreads) {
+        const int te = f / ncell, cl = f - te * ncell;
+        const int e = cl * NE + te;
+        const int C0 = cl % nc, C1 = (cl / nc) % nc, C2 = (D == 3) ? cl / (nc * nc) : 0;
+        dispatch<NE>(te, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            double U[V];
+            static_for<V>([&](auto vc) {
+                constexpr int v = decltype(vc)::value;
+                const int nd = vert_node<D, t, v>(C0, C1, C2, m);
+                U[v] = nd >= 0 ? x[nd] : 0.0;
+            });
+            double UU[NSYM];
 #pragma unroll
-                            for (int p = 0; p < V; ++p)
+            for (int p = 0; p < V; ++p)
 #pragma unroll
-                                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-                            const double* mo = AUG ? a.mom + (size_t)(cl * NE + t) * L::SIZE : nullptr;
-                            if (nd[aa] >= 0) {
-                                double Sr[V], sh = 0.0;
-                                elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
-                                double* row = Sst + (size_t)nd[aa] * NS;
-                                static_for<V>([&](auto bc) {
-                                    constexpr int bb = decltype(bc)::value;
-                                    if (nd[bb] >= 0) row[QSlot<D, t, aa, bb>::value] += Sr[bb];
-                                });
-                                if (AUG) sH[nd[aa]] += sh;
-                            }
-                            if (AUG && aa == 0) sU += elem_corner<D>(U, UU, mo, c);
-                        }
-                    });
+                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+            const double* mo = AUG ? a.mom + (size_t)e * L::SIZE : nullptr;
+            double* out = es + (size_t)e * kEsc;
+            static_for<V>([&](auto ac) {
+                constexpr int aa = decltype(ac)::value;
+                double Sr[V], sh = 0.0;
+                elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
+                static_for<V - aa>([&](auto bc) {
+                    constexpr int bb = aa + decltype(bc)::value;
+                    out[sym2(aa, bb, V)] = Sr[bb];
                 });
-            }
-        }
-        __syncthreads();
+                if (AUG) out[NSYM + aa] = sh;
+            });
+            if (AUG) sU += elem_corner<D>(U, UU, mo, c);
+        });
     }
-    if (staged) {
-        for (int t = threadIdx.x; t < N * NS; t += kThreads) ar.Sst[t] = Sst[t];
-        if (AUG)
-            for (int i = threadIdx.x; i < N; i += kThreads) ar.sH[i] = sH[i];
-        __syncthreads();
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += kThreads) {
+        int P[3];
+        node_pos<D>(i, m, P);
+        double row[NS];
+        static_for<NS>([&](auto sc_) { row[decltype(sc_)::value] = 0.0; });
+        double shs = 0.0;
+        // every entry is loaded (from a clamped simplex where the cell is off the mesh) and
+        // added with a 0/1 factor, so all loads of the node are independent of branches and
+        // can be in flight together; adding a zero leaves every sum unchanged
+        static_for<NCV>([&](auto cvc) {
+            constexpr int cv = decltype(cvc)::value;
+            // the node is cell vertex cv of the cell with origin P - (cv bits)
+            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 3) ? P[2] - ((cv >> 2) & 1) : 0;
+            const bool cin = !(C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc)));
+            const int cl = cin ? ((D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2)) : 0;
+            for_simplices<D>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                constexpr int aa = VertOf<D, t, cv>::value;
+                if constexpr (aa >= 0) {
+                    const double* in = es + (size_t)(cl * NE + t) * kEsc;
+                    static_for<V>([&](auto bc) {
+                        constexpr int bb = decltype(bc)::value;
+                        const double w = (cin && vert_node<D, t, bb>(C0, C1, C2, m) >= 0) ? 1.0 : 0.0;
+                        row[QSlot<D, t, aa, bb>::value] += w * in[sym2(aa, bb, V)];
+                    });
+                    if (AUG) shs += (cin ? 1.0 : 0.0) * in[NSYM + aa];
+                }
+            });
+        });
+        double* outr = ar.Sst + (size_t)i * NS;
+        static_for<NS>([&](auto sc_) { outr[decltype(sc_)::value] = row[decltype(sc_)::value]; });
+        if (AUG) ar.sH[i] = shs;
     }
     if (AUG) {
         sU = bsum1(ar.red, sU);
         if (threadIdx.x == 0) ar.sc[3] = sU;
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 template <int D, bool AUG>
 __device__ __forceinline__ void assemble_S(Arena<D, AUG>& ar, const Args& a, const double* x) {
     if constexpr (D == 2) assemble_S_nodes<D, AUG>(ar, a, x);
-    else assemble_S_colours<D, AUG>(ar, a, x);
+    else assemble_S_simplices<D, AUG>(ar, a, x);
 }
 
 // y = (A + zs S) x, z = B x (with borders); sc[4] = x^T y, sc[5] = x^T z
@@ -2141,11 +2105,20 @@ extern "C" int fmg_debug_small_timers(double* out, int reset) {
 }
 #endif
 
-size_t small_arena_bytes(int dim, int nc) {
+// the global arena of a solve: the arena itself (used when it does not fit in LDS), then the
+// per-simplex scratch of the 3D assembly (always in global memory)
+static size_t arena_part(int dim, int nc) {
     size_t a = dim == 2 ? std::max(arena_bytes_t<2, true>(nc), arena_bytes_t<2, false>(nc))
                         : std::max(arena_bytes_t<3, true>(nc), arena_bytes_t<3, false>(nc));
     return (a + 255) / 256 * 256;
 }
+static size_t esc_bytes(int dim, int nc) {
+    const size_t nel = (dim == 2 ? (size_t)nc * nc * 2 : (size_t)nc * nc * nc * 6);
+    return (nel * kEsc * sizeof(double) + 255) / 256 * 256;
+}
+static double* esc_of(double* arena, int dim, int nc) { return arena + arena_part(dim, nc) / sizeof(double); }
+
+size_t small_arena_bytes(int dim, int nc) { return arena_part(dim, nc) + esc_bytes(dim, nc); }
 
 size_t small_factor_bytes(int dim, int nc) {
     const size_t n = dim == 2 ? factor_doubles<2>(nc) : factor_doubles<3>(nc);
@@ -2157,7 +2130,7 @@ int launch_coarse_newton(int dim, int nc, const Phys& ph, int max_iter, double t
     Args a{};
     a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.tol = tol; a.mom = nullptr; a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = 0; a.certify = 1;
-    a.fac = fac; a.reuse = 0;
+    a.fac = fac; a.reuse = 0; a.esc = esc_of(arena, dim, nc);
     if (dim == 2) {
         const size_t b = arena_bytes_t<2, false>(nc);
         return small_blocks(2, nc, b) ? launch_small(k_newton<2, false, true, true>, k_newton<2, false, true, true>, b, a, s)
@@ -2176,7 +2149,7 @@ int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, int fixed_i
     a.nc = nc; a.ph = ph; a.max_iter = max_iter; a.fixed_iters = fixed_iters; a.tol = tol; a.mom = moments;
     a.arena = arena;
     a.xc = xc_level; a.gc = make_grid(dim, nc); a.st = state; a.final_level = final_level;
-    a.certify = certify; a.fac = fac; a.reuse = reuse;
+    a.certify = certify; a.fac = fac; a.reuse = reuse; a.esc = esc_of(arena, dim, nc);
     if (dim == 2) {
         const size_t b = arena_bytes_t<2, true>(nc);
         return small_blocks(2, nc, b) ? launch_small(k_newton<2, true, true, true>, k_newton<2, true, true, true>, b, a, s)
@@ -2191,6 +2164,7 @@ int launch_aug_dump(int dim, int nc, const Phys& ph, const double* moments, cons
                     double* B, double* S, hipStream_t s) {
     Args a{};
     a.nc = nc; a.ph = ph; a.mom = moments; a.arena = arena; a.xin = x; a.Aout = A; a.Bout = B; a.Sout = S;
+    a.esc = esc_of(arena, dim, nc);
     a.gc = make_grid(dim, nc);
     return dim == 2 ? launch_small(k_aug_dump<2, true>, k_aug_dump<2, false>, arena_bytes_t<2, true>(nc), a, s)
                     : launch_small(k_aug_dump<3, true>, k_aug_dump<3, false>, arena_bytes_t<3, true>(nc), a, s);
