@@ -127,7 +127,8 @@ int fmg_set_fused_vcycle(int32_t enable);
  * solves start).  They change speed only: every choice gives the same bits.  The values come
  * from fmg_autotune_vcycle or a cache of its results.                                    */
 typedef struct {
-    int32_t vpass3d_variant;  /* 3D pass tiles: 0 = 256-thread blocks, 1 = 512-thread blocks */
+    int32_t vpass3d_variant;  /* 3D pass tiles (region columns x rows, threads): 0 = 32 x 16,  */
+                              /* 256; 1 = 32 x 32, 512; 2 = 64 x 16, 512                      */
     int32_t vpass3d_min_n;    /* smallest 3D level (cells per side) on the fused passes      */
     int32_t reserved[6];
 } fmg_tuning;
@@ -138,17 +139,34 @@ int fmg_set_tuning(const fmg_tuning* in);   /* FMG_EINVAL for values out of rang
 /* Per-launch timing of one kernel inside later solves: a pair of HIP events is stamped by
  * each launch's own dispatch on its stream (hipExtLaunchKernel start/stop events, so the
  * interval is the kernel's execution without launch gaps; up to max_launches), with the
- * algorithmic bytes of each launch.  FMG_PROF_VPOST2D_F64 is the fused 2D FP64 post-smoothing level pass
- * (prolongation-add plus the post half-sweeps; bytes = 8 * (3 N_l + N_{l-1}), reading x,
- * f and the coarse correction and writing x) on the finest level of each solve, when that
- * level has more than 256 cells per side (the wide-tile build of the kernel).  Not thread-safe; one profile at a time.
- * The events are created without a system-scope fence (timing only); fmg_profile_end
- * synchronises the device and fills *out.                                               */
-enum { FMG_PROF_VPOST2D_F64 = 1 };
+ * algorithmic bytes and the units of work of each launch.  Only launches on the finest level
+ * of each solve are recorded (N_l: interior nodes of that level, N_{l-1} of the next coarser):
+ *   FMG_PROF_VPOST2D_F64  fused 2D FP64 post-smoothing level pass (prolongation-add plus the
+ *                         post half sweeps) when the level has more than 256 cells per side;
+ *                         bytes 8 (3 N_l + N_{l-1}) (read x, f, the coarse correction; write x);
+ *                         units N_l.
+ *   FMG_PROF_VPOST3D_F64  fused 3D FP64 pass of prolongation-add plus three post half sweeps;
+ *                         bytes 8 (3 N_l + N_{l-1}); units N_l.
+ *   FMG_PROF_VPRE3D_F64   fused 3D FP64 pass of the first three pre half sweeps (out of place);
+ *                         bytes 8 * 3 N_l (read x, f; write the new iterate); units N_l.
+ *   FMG_PROF_MOMENTS3D    3D fine-grid moment pass (the per-block partial integrals of the
+ *                         augmented problem); bytes 8 N_l (read u~; the partials are small);
+ *                         units: fine cells n^3.
+ *   FMG_PROF_RHS3D        3D right-hand side (3.4); bytes 16 N_l (read u, write b); units N_l.
+ * Not thread-safe; one profile at a time.  The events are created without a system-scope
+ * fence (timing only); fmg_profile_end synchronises the device and fills *out.             */
+enum {
+    FMG_PROF_VPOST2D_F64 = 1,
+    FMG_PROF_VPOST3D_F64 = 2,
+    FMG_PROF_VPRE3D_F64 = 3,
+    FMG_PROF_MOMENTS3D = 4,
+    FMG_PROF_RHS3D = 5
+};
 typedef struct {
     int64_t launches;   /* launches recorded                                               */
     double seconds;     /* sum of the per-launch event intervals                           */
     double bytes;       /* sum of the algorithmic bytes of those launches                  */
+    double units;       /* sum of the units of work (nodes or cells) of those launches     */
 } fmg_kernel_profile;
 int fmg_profile_begin(int32_t kernel, int32_t max_launches);
 int fmg_profile_end(fmg_kernel_profile* out);

@@ -31,10 +31,10 @@ class fmg_tuning(C.Structure):
 
 
 class fmg_kernel_profile(C.Structure):
-    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double)]
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double), ("units", C.c_double)]
 
 
-FMG_PROF_VPOST2D_F64 = 1
+FMG_PROF_VPOST2D_F64, FMG_PROF_VPOST3D_F64, FMG_PROF_VPRE3D_F64, FMG_PROF_MOMENTS3D, FMG_PROF_RHS3D = 1, 2, 3, 4, 5
 
 
 class fmg_result(C.Structure):

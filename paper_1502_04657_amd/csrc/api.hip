@@ -22,15 +22,26 @@ static thread_local char g_err[512] = "";
 static int g_fused = 1;
 
 // Optional per-launch timing of one kernel (instrumentation for measurements): HIP events
-// recorded around each launch on the stream it runs on, plus the algorithmic bytes of
-// each launch.  Not thread-safe.
+// recorded around each launch on the stream it runs on, plus the algorithmic bytes and the
+// units of work of each launch.  Not thread-safe.
 struct KernelProfiler {
     int kernel = 0;                  // FMG_PROF_* being recorded, 0: off
     int cap = 0, used = 0;
     std::vector<hipEvent_t> ev;      // 2 per launch
-    double bytes = 0.0;
+    double bytes = 0.0, units = 0.0;
 };
 static KernelProfiler g_prof;
+
+// is the next launch of `kind` to be recorded
+static bool prof_on(int kind) { return g_prof.kernel == kind && g_prof.used < g_prof.cap; }
+// start (k = 0) or stop (k = 1) event of the next recorded launch, or none
+static hipEvent_t prof_ev(bool on, int k) { return on ? g_prof.ev[2 * (size_t)g_prof.used + k] : nullptr; }
+static void prof_add(double bytes, double units) {
+    g_prof.bytes += bytes;
+    g_prof.units += units;
+    ++g_prof.used;
+}
+static double interior_nodes(const Grid& g) { return std::pow((double)(g.n - 1), (double)g.dim); }
 
 int set_error(int code, const char* fmt, ...) {
     va_list ap;
@@ -159,23 +170,30 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
         T* y = at<T>(ws, lo.tv[l]);
         launch_vpre2d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
         vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
-        const bool rec = g_prof.kernel == FMG_PROF_VPOST2D_F64 && sizeof(T) == 8 && l == lo.L - 1 &&
-                         vpass2d_wide_tiles(g) && g_prof.used < g_prof.cap;
-        launch_vpost2d<T>(g, lo.g[l - 1], y, x, f, xc, nu_post, s, rec ? g_prof.ev[2 * g_prof.used] : nullptr,
-                          rec ? g_prof.ev[2 * g_prof.used + 1] : nullptr);
-        if (rec) {
-            // read x, f and the coarse correction, write x (interior values)
-            const double nf = std::pow((double)(g.n - 1), 2), ncs = std::pow((double)(lo.g[l - 1].n - 1), 2);
-            g_prof.bytes += (3.0 * nf + ncs) * sizeof(double);
-            ++g_prof.used;
-        }
+        const bool rec = sizeof(T) == 8 && l == lo.L - 1 && vpass2d_wide_tiles(g) && prof_on(FMG_PROF_VPOST2D_F64);
+        launch_vpost2d<T>(g, lo.g[l - 1], y, x, f, xc, nu_post, s, prof_ev(rec, 0), prof_ev(rec, 1));
+        // read x, f and the coarse correction, write x (interior values)
+        if (rec) prof_add((3.0 * interior_nodes(g) + interior_nodes(lo.g[l - 1])) * sizeof(double), interior_nodes(g));
         return;
     }
+    if (lo.dim == 3 && g_fused && !lo.cg &&
+        launch_vbottom3d<T>(lo.g.data(), l, x, f, nu_pre, nu_post, zero_x ? 1 : 0, s))
+        return;
     if (lo.dim == 3 && g_fused && !lo.cg && vpass3d_applies(g, nu_pre, nu_post)) {
         T* y = at<T>(ws, lo.tv[l]);
-        T* xs = launch_vpre3d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s);
+        const bool top = sizeof(T) == 8 && l == lo.L - 1;
+        const double nf = interior_nodes(g), ncs = interior_nodes(lo.g[l - 1]);
+        const bool rpre = top && prof_on(FMG_PROF_VPRE3D_F64);
+        T* xs = launch_vpre3d<T>(g, lo.g[l - 1], x, y, f, fc, nu_pre, zero_x ? 1 : 0, s, prof_ev(rpre, 0),
+                                 prof_ev(rpre, 1));
+        // first pre pass: read x (unless it enters as zero) and f, write the new iterate (and,
+        // for one sweep, the restricted residual)
+        if (rpre) prof_add(((zero_x ? 2.0 : 3.0) * nf + (nu_pre == 1 ? ncs : 0.0)) * sizeof(double), nf);
         vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
-        launch_vpost3d<T>(g, lo.g[l - 1], xs, xs == x ? y : x, x, f, xc, nu_post, s);
+        const bool rpost = top && prof_on(FMG_PROF_VPOST3D_F64);
+        launch_vpost3d<T>(g, lo.g[l - 1], xs, xs == x ? y : x, x, f, xc, nu_post, s, prof_ev(rpost, 0),
+                          prof_ev(rpost, 1));
+        if (rpost) prof_add((3.0 * nf + ncs) * sizeof(double), nf);
         return;
     }
     // unfused: red-black SGS (nu sweeps = 2 nu + 1 half sweeps) or nu CG steps
@@ -206,8 +224,11 @@ static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, 
     SmallState* st = at<SmallState>(ws, lo.state);
     double* u = at<double>(ws, lo.u[k]);
     double* b = at<double>(ws, lo.b[k]);
+    const bool fin3 = lo.dim == 3 && k == lo.L - 1;
     // (3.4): right-hand side lambda u - f(x, u) in the weak form
-    launch_rhs(g, ph, u, b, &st->lambda, 0.0, s);
+    const bool rr = fin3 && prof_on(FMG_PROF_RHS3D);
+    launch_rhs(g, ph, u, b, &st->lambda, 0.0, s, prof_ev(rr, 0), prof_ev(rr, 1));
+    if (rr) prof_add(2.0 * interior_nodes(g) * sizeof(double), interior_nodes(g));
     // (3.5): m multigrid iterations started from u
     for (int j = 0; j < opt->m; ++j) {
         if (opt->precision == FMG_MIXED) {
@@ -222,7 +243,9 @@ static int correction_step(const Layout& lo, void* ws, const fmg_problem* prob, 
     }
     // (3.6): augmented nonlinear eigenproblem on V_H + span{u~}
     double* mom = at<double>(ws, lo.mom);
-    launch_moments(lo.dim, lo.nc, g, ph, u, at<double>(ws, lo.momscr), mom, s);
+    const bool rm = fin3 && prof_on(FMG_PROF_MOMENTS3D);
+    launch_moments(lo.dim, lo.nc, g, ph, u, at<double>(ws, lo.momscr), mom, s, prof_ev(rm, 0), prof_ev(rm, 1));
+    if (rm) prof_add(interior_nodes(g) * sizeof(double), std::pow((double)g.n, 3.0));
     int rc = launch_aug_newton(lo.dim, lo.nc, ph, opt->newton_max_iter, opt->newton_fixed_iters, opt->newton_tol, mom,
                                at<double>(ws, lo.arena),
                                at<double>(ws, lo.fac), at<double>(ws, lo.xc), st, final_flag, certify, 1, s);
@@ -466,14 +489,14 @@ int fmg_get_tuning(fmg_tuning* out) {
 
 int fmg_set_tuning(const fmg_tuning* in) {
     if (!in) return set_error(FMG_EINVAL, "tuning is NULL");
-    if (in->vpass3d_variant < 0 || in->vpass3d_variant > 1) return set_error(FMG_EINVAL, "vpass3d_variant must be 0 or 1");
+    if (in->vpass3d_variant < 0 || in->vpass3d_variant > 2) return set_error(FMG_EINVAL, "vpass3d_variant must be 0, 1 or 2");
     if (in->vpass3d_min_n < 16) return set_error(FMG_EINVAL, "vpass3d_min_n must be >= 16");
     set_vpass3d_tuning(in->vpass3d_variant, in->vpass3d_min_n);
     return 0;
 }
 
 int fmg_profile_begin(int32_t kernel, int32_t max_launches) {
-    if (kernel != FMG_PROF_VPOST2D_F64 || max_launches < 1 || max_launches > (1 << 20))
+    if (kernel < FMG_PROF_VPOST2D_F64 || kernel > FMG_PROF_RHS3D || max_launches < 1 || max_launches > (1 << 20))
         return set_error(FMG_EINVAL, "bad profile request");
     if (g_prof.kernel) return set_error(FMG_EINVAL, "a profile is already running");
     g_prof.ev.resize(2 * (size_t)max_launches);
@@ -482,6 +505,7 @@ int fmg_profile_begin(int32_t kernel, int32_t max_launches) {
     g_prof.cap = max_launches;
     g_prof.used = 0;
     g_prof.bytes = 0.0;
+    g_prof.units = 0.0;
     g_prof.kernel = kernel;
     return 0;
 }
@@ -505,6 +529,7 @@ int fmg_profile_end(fmg_kernel_profile* out) {
         out->launches = g_prof.used;
         out->seconds = ms_total * 1e-3;
         out->bytes = g_prof.bytes;
+        out->units = g_prof.units;
     }
     return 0;
 }

@@ -20,14 +20,14 @@ unit cell, so the cell measure is 1):
   per simplex type t (vertex multisets in lexicographic order):
     E1[t][v][q]   = int_t l_v Y^{m_q}                        |m_q| <= 3
     E2[t][vw][q]  = mult(v,w) int_t l_v l_w Y^{m_q}          |m_q| <= 2
-    E3[t][vwx][q] = mult(v,w,x) int_t l_v l_w l_x Y^{m_q}    |m_q| <= 1
   for the whole cell, grouped by cell corners c (c = o_0 + 2 o_1 (+ 4 o_2)):
-    C1[c][q], C2[pair][q], C3[triple][q]: the sums of the above over the cell's simplices
-    with the same corner multiset (pairs and triples that share a simplex),
+    C1[c][q], C2[pair][q]: the sums of the above over the cell's simplices with the same
+    corner multiset (pairs that share a simplex),
     CG[c][d] = sum_t |t| d l_{v(c)} / dY_d,
-with the monomial orders of layout.h (graded: degree 0, 1, 2, 3).  The quartic term needs
-no table: int_t u~^4 = |t| D! 4! / (D+4)! h_4(u_v) (h_4: the complete homogeneous
-symmetric polynomial of degree 4 of the vertex values).
+with the monomial orders of layout.h (graded: degree 0, 1, 2, 3).  The cubic and quartic
+terms need no table: with h_k the complete homogeneous symmetric polynomials of the
+vertex values, int_t u~^k = |t| D! k! / (D+k)! h_k and
+int_t u~^3 l_w = |t| D! 3! / (D+4)! (h_3 + u_w h_2 + u_w^2 h_1 + u_w^3).
 """
 from __future__ import annotations
 
@@ -101,11 +101,11 @@ def multiplicity(ms):
 
 def tables(D):
     NS = len(VERT[D])
-    deg_count = {1: len(MON[D]), 2: sum(1 for m in MON[D] if sum(m) <= 2), 3: D + 1}
-    E = {k: [] for k in (1, 2, 3)}
-    cells = {k: {} for k in (1, 2, 3)}
+    deg_count = {1: len(MON[D]), 2: sum(1 for m in MON[D] if sum(m) <= 2)}
+    E = {k: [] for k in (1, 2)}
+    cells = {k: {} for k in (1, 2)}
     for t, verts in enumerate(VERT[D]):
-        for k in (1, 2, 3):
+        for k in (1, 2):
             rows = []
             for ms in itertools.combinations_with_replacement(range(D + 1), k):
                 lp = {tuple([0] * (D + 1)): Fraction(1)}
@@ -171,22 +171,15 @@ def main():
         E, cells, CG = tables(D)
         nc = 1 << D
         pairs = sorted(cells[2])
-        trips = sorted(cells[3])
         out.append(f"// ---- {D}D: cell corners c = o0 + 2 o1" + (" + 4 o2" if D == 3 else ""))
         out.append(arr(f"kCorner{D}D", [[corner(v) for v in verts] for verts in VERT[D]], "int"))
         out.append(f"constexpr int kPairs{D}D = {len(pairs)};")
-        out.append(f"constexpr int kTrips{D}D = {len(trips)};")
         out.append(arr(f"kPair{D}D", [list(p) for p in pairs], "int"))
-        out.append(arr(f"kTrip{D}D", [list(t) for t in trips], "int"))
-        # each triple as (pair index, corner): the product of a stored pair and one corner
-        out.append(arr(f"kTripPair{D}D", [pairs.index(t[:2]) for t in trips], "int"))
         out.append(arr(f"kC1_{D}D", [cells[1][(c,)] for c in range(nc)]))
         out.append(arr(f"kC2_{D}D", [cells[2][p] for p in pairs]))
-        out.append(arr(f"kC3_{D}D", [cells[3][t] for t in trips]))
         out.append(arr(f"kCG{D}D", [CG[c] for c in range(nc)]))
         out.append(arr(f"kE1_{D}D", E[1]))
         out.append(arr(f"kE2_{D}D", E[2]))
-        out.append(arr(f"kE3_{D}D", E[3]))
         out.append("")
     with open(os.path.join(HERE, "moment_tables.h"), "w") as f:
         f.write("\n".join(out))

@@ -10,6 +10,8 @@
 // P is P1 interpolation: a fine node at a coarse node takes its value; any other fine node
 // is the midpoint of one coarse edge (2D: x, y or (1,1) direction; 3D: the 7 Kuhn edge
 // directions, which are exactly the nonzero parity patterns (i&1, j&1, k&1)).
+#include <hip/hip_ext.h>
+
 #include "dst.h"
 #include "kernels.h"
 
@@ -234,15 +236,6 @@ template void launch_coarse_solve<float>(const Grid&, const float*, float*, hipS
 // N(u)_i = int u_h^3 phi_i sums, over the elements e around node i, the exact value
 //   |e| D! 3! / (D+4)! (h_3 + u_i h_2 + u_i^2 h_1 + u_i^3),
 // h_k the complete homogeneous symmetric polynomials of the vertex values of e.
-template <int D>
-__device__ inline double cubic_term(double v0, double v1, double v2, double v3) {
-    double s1 = v0 + v1 + v2 + (D == 3 ? v3 : 0.0);
-    double p2 = v0 * v0 + v1 * v1 + v2 * v2 + (D == 3 ? v3 * v3 : 0.0);
-    double p3 = v0 * v0 * v0 + v1 * v1 * v1 + v2 * v2 * v2 + (D == 3 ? v3 * v3 * v3 : 0.0);
-    double h2 = 0.5 * (s1 * s1 + p2);
-    double h3 = (s1 * s1 * s1 + 3.0 * s1 * p2 + 2.0 * p3) * (1.0 / 6.0);
-    return h3 + v0 * h2 + v0 * v0 * s1 + v0 * v0 * v0;
-}
 
 // interior node t (lexicographic, i fastest) -> (i, j, k); t < (n - 1)^D < 2^32 for every
 // admissible mesh, so 32-bit division (64-bit division is a long software sequence)
@@ -287,7 +280,7 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
     const double u0 = u[p];
     double nl = 0.0;
     if (D == 2) {
-        // cubic_term<2>(u0, a, b) expanded in u0: 4 u0^3 + 3 u0^2 (a + b) + 2 u0 (a^2 + ab + b^2)
+        // the element term of (u0, a, b) expanded in u0: 4 u0^3 + 3 u0^2 (a + b) + 2 u0 (a^2 + ab + b^2)
         // + (a^3 + a^2 b + a b^2 + b^3); with s = a + b, q = ab the last two are s^2 - q and
         // s (s^2 - 2q), summed over the star before the powers of u0 are applied
         double t1 = 0.0, t2 = 0.0, t3 = 0.0;
@@ -304,13 +297,23 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
         Nu = nl * (h * h / 120.0);
         Ku = 4.0 * u0 - ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P]));
     } else {
+        // h_k(u0, a, b, c) = sum_j u0^j h_{k-j}(a, b, c), so the element term is
+        // H3 + 2 u0 H2 + 3 u0^2 H1 + 4 u0^3 with H_k = h_k(a, b, c) of the element's other
+        // vertices; with the elementary symmetric e1, e2, e3 of (a, b, c): H1 = e1,
+        // H2 = e1^2 - e2, H3 = e1 (e1^2 - 2 e2) + e3.  The H_k are summed over the star first.
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
 #pragma unroll
         for (int e = 0; e < kStarElems3D; ++e) {
-            double v1 = u[p + kStarElem3D[e][0][0] + P * kStarElem3D[e][0][1] + S * kStarElem3D[e][0][2]];
-            double v2 = u[p + kStarElem3D[e][1][0] + P * kStarElem3D[e][1][1] + S * kStarElem3D[e][1][2]];
-            double v3 = u[p + kStarElem3D[e][2][0] + P * kStarElem3D[e][2][1] + S * kStarElem3D[e][2][2]];
-            nl += cubic_term<3>(u0, v1, v2, v3);
+            const double a = u[p + kStarElem3D[e][0][0] + P * kStarElem3D[e][0][1] + S * kStarElem3D[e][0][2]];
+            const double b = u[p + kStarElem3D[e][1][0] + P * kStarElem3D[e][1][1] + S * kStarElem3D[e][1][2]];
+            const double c = u[p + kStarElem3D[e][2][0] + P * kStarElem3D[e][2][1] + S * kStarElem3D[e][2][2]];
+            const double ab = a * b, apb = a + b;
+            const double e1 = apb + c, e2 = c * apb + ab, e3 = ab * c, e11 = e1 * e1;
+            t1 += e1;
+            t2 += e11 - e2;
+            t3 += e1 * (e11 - 2.0 * e2) + e3;
         }
+        nl = t3 + u0 * (2.0 * t2 + u0 * (3.0 * t1 + (4.0 * kStarElems3D) * u0));
         Nu = nl * (h * h * h / 840.0);
         Ku = h * (6.0 * u0 - (((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P])) + (u[p - S] + u[p + S])));
     }
@@ -331,14 +334,14 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ u, doubl
 }
 
 void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev, double lam_host,
-                hipStream_t s) {
+                hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int n = g.n;
     dim3 blk(64, 4, 1);
     dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
     if (g.dim == 2)
-        hipLaunchKernelGGL(k_rhs<2>, grd, blk, 0, s, u, b, g, ph, lam_dev, lam_host);
+        hipExtLaunchKernelGGL(k_rhs<2>, grd, blk, 0, s, ev0, ev1, 0, u, b, g, ph, lam_dev, lam_host);
     else
-        hipLaunchKernelGGL(k_rhs<3>, grd, blk, 0, s, u, b, g, ph, lam_dev, lam_host);
+        hipExtLaunchKernelGGL(k_rhs<3>, grd, blk, 0, s, ev0, ev1, 0, u, b, g, ph, lam_dev, lam_host);
 }
 
 // ------------------------------------------------------------------------------------------

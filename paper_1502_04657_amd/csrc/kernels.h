@@ -26,7 +26,7 @@ template <typename T> void launch_cg_smooth(const Grid& g, T* x, const T* f, int
                                             double* partial, double* sc, hipStream_t s);
 // b = lambda M u - M_W u - zeta N(u); lambda = *lam_dev if lam_dev else lam_host
 void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev,
-                double lam_host, hipStream_t s);
+                double lam_host, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // mixed precision: r32 = (float)(b - K u); u += (double)e32
 void launch_residual_demote(const Grid& g, const double* u, const double* b, float* r, hipStream_t s);
 void launch_add_promote(const Grid& g, double* u, const float* e, hipStream_t s);
@@ -57,6 +57,9 @@ bool vpass2d_wide_tiles(const Grid& g);
 // V-cycle's correction, bit-identical to the level-by-level passes; false if it does not apply
 template <typename T> bool launch_vbottom2d(const Grid* levels, int l, T* x, const T* f, int nu_pre, int nu_post,
                                             int zero_x, hipStream_t s);
+// the same for 3D (level-l mesh n <= 16, all levels' x and f in LDS)
+template <typename T> bool launch_vbottom3d(const Grid* levels, int l, T* x, const T* f, int nu_pre, int nu_post,
+                                            int zero_x, hipStream_t s);
 template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc,
                                           int nu, hipStream_t s, hipEvent_t ev0 = nullptr,
                                           hipEvent_t ev1 = nullptr);
@@ -72,7 +75,8 @@ bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post);
 void set_vpass3d_tuning(int variant, int min_n);
 void get_vpass3d_tuning(int* variant, int* min_n);
 template <typename T> T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu,
-                                       int zero_x, hipStream_t s);
+                                       int zero_x, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                       hipEvent_t ev1 = nullptr);
 template <typename T> void launch_vpost3d(const Grid& g, const Grid& gc, T* xs, T* scratch, T* x_out, const T* f,
                                           const T* xc, int nu, hipStream_t s, hipEvent_t ev0 = nullptr,
                                           hipEvent_t ev1 = nullptr);
@@ -81,7 +85,7 @@ template <typename T> void launch_vpost3d(const Grid& g, const Grid& gc, T* xs, 
 int moments_per_element(int dim);            // doubles per coarse element in the output
 size_t moments_scratch_bytes(int dim, int nc, int n);
 void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double* ut, double* scratch,
-                    double* out, hipStream_t s);
+                    double* out, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- small.hip --------------------------------------------------------------------------
 struct SmallState {

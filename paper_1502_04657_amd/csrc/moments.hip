@@ -14,7 +14,8 @@
 // on a fine cell with corner A (in fine-cell units of the coarse cell) and cell coordinates
 // Y, X = (A + Y) / s, and every local moment int u~^k Y^b is a fixed rational combination
 // of products of the cell's corner values (moment_tables.h, derived in
-// gen_moment_tables.py); the local moments are then shifted to (A + Y)^b one coordinate
+// gen_moment_tables.py) for u~ and u~^2, and of the power sums of each fine simplex's vertex
+// values for u~^3 and u~^4; the local moments are then shifted to (A + Y)^b one coordinate
 // at a time (binomial expansion), and the powers of s and h are applied once per block.
 // A block walks only the fine cells that meet its coarse simplex, in two groups:
 //   * interior cells, whose coordinates are strictly ordered as the coarse simplex's axis
@@ -25,6 +26,8 @@
 // Blocks hold one group each, so a wavefront never mixes the two.  Pass 2
 // (k_moments_final): one thread per coarse simplex adds the partials in chunk order and
 // converts the X-monomial moments to the barycentric form.  Both passes are deterministic.
+#include <hip/hip_ext.h>
+
 #include <utility>
 
 #include "kernels.h"
@@ -150,35 +153,53 @@ __device__ __forceinline__ void shift_moments(double* L, const double* A) {
     });
 }
 
-// complete homogeneous symmetric polynomial of degree 4 of V values, from power sums
-template <int V>
-__device__ __forceinline__ double h4(const double* x) {
-    double p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const double x2 = x[v] * x[v];
-        p1 += x[v];
-        p2 += x2;
-        p3 += x2 * x[v];
-        p4 += x2 * x2;
-    }
-    const double p11 = p1 * p1;
-    return (p11 * (p11 + 6.0 * p2) + 3.0 * p2 * p2 + 8.0 * p1 * p3 + 6.0 * p4) * (1.0 / 24.0);
-}
-
 // table accessors by dimension (the other dimension's table is never indexed)
 template <int D> __host__ __device__ constexpr double tC1(int c, int q) { if constexpr (D == 2) return kC1_2D[c][q]; else return kC1_3D[c][q]; }
 template <int D> __host__ __device__ constexpr double tC2(int p, int q) { if constexpr (D == 2) return kC2_2D[p][q]; else return kC2_3D[p][q]; }
-template <int D> __host__ __device__ constexpr double tC3(int t, int q) { if constexpr (D == 2) return kC3_2D[t][q]; else return kC3_3D[t][q]; }
 template <int D> __host__ __device__ constexpr double tCG(int c, int d) { if constexpr (D == 2) return kCG2D[c][d]; else return kCG3D[c][d]; }
 template <int D> __host__ __device__ constexpr double tE1(int f, int v, int q) { if constexpr (D == 2) return kE1_2D[f][v][q]; else return kE1_3D[f][v][q]; }
 template <int D> __host__ __device__ constexpr double tE2(int f, int p, int q) { if constexpr (D == 2) return kE2_2D[f][p][q]; else return kE2_3D[f][p][q]; }
-template <int D> __host__ __device__ constexpr double tE3(int f, int t, int q) { if constexpr (D == 2) return kE3_2D[f][t][q]; else return kE3_3D[f][t][q]; }
 template <int D> __host__ __device__ constexpr int tPair(int p, int k) { if constexpr (D == 2) return kPair2D[p][k]; else return kPair3D[p][k]; }
-template <int D> __host__ __device__ constexpr int tTrip(int t, int k) { if constexpr (D == 2) return kTrip2D[t][k]; else return kTrip3D[t][k]; }
-template <int D> __host__ __device__ constexpr int tTripPair(int t) { if constexpr (D == 2) return kTripPair2D[t]; else return kTripPair3D[t]; }
 template <int D> __host__ __device__ constexpr int tCorner(int f, int v) { if constexpr (D == 2) return kCorner2D[f][v]; else return kCorner3D[f][v]; }
 template <int D> __host__ __device__ constexpr double tBary(int f, int v, int k) { if constexpr (D == 2) return kCellElemBary2D[f][v][k]; else return kCellElemBary3D[f][v][k]; }
+
+// Cubic and quartic moments of one fine simplex f of the cell (unit cell, |t| D! = 1), from
+// the power sums p_k of its vertex values (u2, u3, u4: the corner values' powers) and the
+// complete homogeneous symmetric polynomials h_k they give:
+//   int u~^3 = 3!/(D+3)! h3,   int u~^3 l_w = 3!/(D+4)! (h3 + u_w h2 + u_w^2 h1 + u_w^3),
+//   int u~^4 = 4!/(D+4)! h4,   Y_d = sum of the l_v of the vertices with y_vd = 1.
+// Adds h3 to s3, h4 to s4 and sum over those vertices of the l_w bracket to sy[d]; the
+// constants are applied by the caller.
+template <int D, int f>
+__device__ __forceinline__ void simplex_cubic_quartic(const double* uc, const double* u2, const double* u3,
+                                                      const double* u4, double& s3, double& s4, double* sy) {
+    constexpr int V = D + 1;
+    double p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+    static_for<V>([&](auto v_) {
+        constexpr int c = tCorner<D>(f, decltype(v_)::value);
+        p1 += uc[c];
+        p2 += u2[c];
+        p3 += u3[c];
+        p4 += u4[c];
+    });
+    const double p11 = p1 * p1;
+    const double h2 = 0.5 * (p11 + p2);
+    const double h3 = (p1 * (p11 + 3.0 * p2) + 2.0 * p3) * (1.0 / 6.0);
+    s3 += h3;
+    s4 += (p11 * (p11 + 6.0 * p2) + 3.0 * p2 * p2 + 8.0 * p1 * p3 + 6.0 * p4) * (1.0 / 24.0);
+    double g[V];
+    static_for<V>([&](auto v_) {
+        constexpr int c = tCorner<D>(f, decltype(v_)::value);
+        g[decltype(v_)::value] = h3 + uc[c] * (h2 + uc[c] * (p1 + uc[c]));
+    });
+    static_for<D>([&](auto d_) {
+        constexpr int d = decltype(d_)::value;
+        static_for<V>([&](auto v_) {
+            constexpr int v = decltype(v_)::value;
+            if constexpr (((tCorner<D>(f, v) >> d) & 1) != 0) sy[d] += g[v];
+        });
+    });
+}
 
 // Local moments of the cell with corner values uc[] (unit cell), accumulated into L1 (deg
 // <= 3), L2 (deg <= 2), L3 (deg <= 1), L4 and the gradient sums G (int d u~/dY_d), Q
@@ -191,11 +212,12 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
     constexpr int V = D + 1;
     constexpr int NF = (D == 2) ? 2 : 6;
     constexpr double k4 = (D == 2) ? 1.0 / 30.0 : 1.0 / 210.0;    // 4! / (D + 4)!
+    constexpr double k3 = (D == 2) ? 1.0 / 20.0 : 1.0 / 120.0;    // 3! / (D + 3)!
+    constexpr double k3w = (D == 2) ? 1.0 / 120.0 : 1.0 / 840.0;  // 3! / (D + 4)!
     constexpr double vs = (D == 2) ? 0.5 : 1.0 / 6.0;             // simplex measure in the unit cell
     if constexpr (WHOLE) {
         constexpr int NC = 1 << D;
         constexpr int NP = (D == 2) ? kPairs2D : kPairs3D;
-        constexpr int NT = (D == 2) ? kTrips2D : kTrips3D;
         static_for<NC>([&](auto c_) {
             constexpr int c = decltype(c_)::value;
             static_for<M::NM>([&](auto q) { L1[q] += uc[c] * tC1<D>(c, q); });
@@ -209,18 +231,18 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
             pr[p] = uc[a] * uc[b];
             static_for<M::N2>([&](auto q) { L2[q] += pr[p] * tC2<D>(p, q); });
         });
-        static_for<NT>([&](auto t_) {
-            constexpr int t = decltype(t_)::value;
-            constexpr int p = tTripPair<D>(t);
-            constexpr int c = tTrip<D>(t, 2);
-            const double w = pr[p] * uc[c];
-            static_for<M::N1>([&](auto q) { L3[q] += w * tC3<D>(t, q); });
+        double u2[NC], u3[NC], u4[NC], s3 = 0.0, s4 = 0.0, sy[D];
+        static_for<NC>([&](auto c) {
+            u2[c] = uc[c] * uc[c];
+            u3[c] = u2[c] * uc[c];
+            u4[c] = u2[c] * u2[c];
         });
+        static_for<D>([&](auto d) { sy[d] = 0.0; });
         static_for<NF>([&](auto f_) {
             constexpr int f = decltype(f_)::value;
+            simplex_cubic_quartic<D, f>(uc, u2, u3, u4, s3, s4, sy);
             double uv[V], g[D];
             static_for<V>([&](auto v) { uv[v] = uc[tCorner<D>(f, v)]; });
-            L4 += k4 * h4<V>(uv);
             static_for<D>([&](auto d_) {
                 constexpr int d = decltype(d_)::value;
                 g[d] = 0.0;
@@ -234,7 +256,18 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
             static_for<D>([&](auto d) { g2 += g[d] * g[d]; });
             Q += vs * g2;
         });
+        L3[0] += k3 * s3;
+        static_for<D>([&](auto d) { L3[1 + d] += k3w * sy[d]; });
+        L4 += k4 * s4;
     } else {
+        constexpr int NC = 1 << D;
+        double u2[NC], u3[NC], u4[NC], s3 = 0.0, s4 = 0.0, sy[D];
+        static_for<NC>([&](auto c) {
+            u2[c] = uc[c] * uc[c];
+            u3[c] = u2[c] * uc[c];
+            u4[c] = u2[c] * u2[c];
+        });
+        static_for<D>([&](auto d) { sy[d] = 0.0; });
         static_for<NF>([&](auto f_) {
             constexpr int f = decltype(f_)::value;
             if (coarse_type<D>(a, f) != type) return;
@@ -243,8 +276,8 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
             static_for<V>([&](auto v) {
                 static_for<M::NM>([&](auto q) { L1[q] += uv[v] * tE1<D>(f, v, q); });
             });
-            // vertex pairs v <= w and triples v <= w <= x in lexicographic order
-            int pi = 0, ti = 0;
+            // vertex pairs v <= w in lexicographic order
+            int pi = 0;
 #pragma unroll
             for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -254,18 +287,7 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
                     for (int q = 0; q < M::N2; ++q) L2[q] += pw * tE2<D>(f, pi, q);
                     ++pi;
                 }
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-#pragma unroll
-                for (int w = v; w < V; ++w)
-#pragma unroll
-                    for (int x = w; x < V; ++x) {
-                        const double tw = uv[v] * uv[w] * uv[x];
-#pragma unroll
-                        for (int q = 0; q < M::N1; ++q) L3[q] += tw * tE3<D>(f, ti, q);
-                        ++ti;
-                    }
-            L4 += k4 * h4<V>(uv);
+            simplex_cubic_quartic<D, f>(uc, u2, u3, u4, s3, s4, sy);
             static_for<D>([&](auto d_) {
                 constexpr int d = decltype(d_)::value;
                 g[d] = 0.0;
@@ -280,6 +302,9 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
             static_for<D>([&](auto d) { g2 += g[d] * g[d]; });
             Q += vs * g2;
         });
+        L3[0] += k3 * s3;
+        static_for<D>([&](auto d) { L3[1 + d] += k3w * sy[d]; });
+        L4 += k4 * s4;
     }
 }
 
@@ -524,18 +549,18 @@ __global__ __launch_bounds__(64) void k_moments_final(const double* __restrict__
 }
 
 void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double* ut, double* scratch, double* out,
-                    hipStream_t s) {
+                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const ChunkShape c = chunk_shape(dim, nc, g.n);
     const int sc = g.n / nc;
     const unsigned nchunk = (unsigned)(c.c_int + c.c_tie);
     if (dim == 2) {
-        hipLaunchKernelGGL(k_moments_raw<2>, dim3((unsigned)c.ncell, nchunk, 2), dim3(256), 0, s, ut, g, nc, c.n_int,
-                           c.n_tie, (int)c.c_int, sc, scratch);
+        hipExtLaunchKernelGGL(k_moments_raw<2>, dim3((unsigned)c.ncell, nchunk, 2), dim3(256), 0, s, ev0, ev1, 0, ut, g,
+                              nc, c.n_int, c.n_tie, (int)c.c_int, sc, scratch);
         hipLaunchKernelGGL(k_moments_final<2>, dim3(cdiv(c.ncell * 2, 64)), dim3(64), 0, s, scratch, nc,
                            (int64_t)nchunk, ph, out);
     } else {
-        hipLaunchKernelGGL(k_moments_raw<3>, dim3((unsigned)c.ncell, nchunk, 6), dim3(256), 0, s, ut, g, nc, c.n_int,
-                           c.n_tie, (int)c.c_int, sc, scratch);
+        hipExtLaunchKernelGGL(k_moments_raw<3>, dim3((unsigned)c.ncell, nchunk, 6), dim3(256), 0, s, ev0, ev1, 0, ut, g,
+                              nc, c.n_int, c.n_tie, (int)c.c_int, sc, scratch);
         hipLaunchKernelGGL(k_moments_final<3>, dim3(cdiv(c.ncell * 6, 64)), dim3(64), 0, s, scratch, nc,
                            (int64_t)nchunk, ph, out);
     }

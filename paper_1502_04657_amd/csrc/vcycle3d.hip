@@ -27,6 +27,7 @@
 
 #include <utility>
 
+#include "dst.h"
 #include "kernels.h"
 
 #ifndef FMG_VPASS3D_PREFETCH
@@ -391,15 +392,133 @@ __global__ __launch_bounds__(NT) void k_vpass3d(const T* __restrict__ xin, T* __
                                                  std::make_integer_sequence<int, U>{});
 }
 
+
+// ---- small levels: the whole V-cycle below a level in one workgroup ----------------------
+// A level with at most kBottom3MaxN cells per side and every level below it run in one
+// workgroup, with each level's x and f as a dense (n_q + 1)^3 array (zero ring) in LDS:
+// the pre half sweeps, the residual and its restriction, the exact coarsest solve, the
+// prolongation and the post half sweeps of the unfused kernel sequence (grid.hip), node by
+// node with the same expressions, so the result has the same bits, in one launch instead of
+// about a dozen per level.  The coarsest-solve scratch follows the level arrays.
+constexpr int kBottom3Threads = 512;
+constexpr int kBottom3MaxN = 16;
+constexpr size_t kBottom3MaxBytes = 150 * 1024;
+
+__host__ __device__ inline int b3_elems(int n0, int q) {
+    const int p = (n0 << q) + 1;
+    return p * p * p;
+}
+// elements of the level arrays below level q (each level: x, then f)
+__host__ __device__ inline int b3_off(int n0, int q) {
+    int e = 0;
+    for (int r = 0; r < q; ++r) e += 2 * b3_elems(n0, r);
+    return e;
+}
+template <typename T>
+size_t b3_bytes(int n0, int l) {
+    const size_t m = (size_t)n0 - 1;
+    return ((size_t)b3_off(n0, l + 1) * sizeof(T) + 7) / 8 * 8 + sizeof(double) * (m * m + m + 2 * m * m * m);
+}
+
+// nh alternating half sweeps, colour 0 first
+template <typename T>
+__device__ void b3_sweeps(T* X, const T* F, int n, int nh) {
+    const int P = n + 1, S = P * P, half = n / 2, m = n - 1;
+    const T inv_h = T(n);
+    for (int hs = 0; hs < nh; ++hs) {
+        const int c = hs & 1;
+        for (int t = threadIdx.x; t < m * m * half; t += blockDim.x) {
+            const int row = t / half, slot = t - row * half;
+            const int j = 1 + row % m, k = 1 + row / m;
+            const int i = (((1 + j + k) & 1) == c ? 1 : 2) + 2 * slot;
+            if (i > m) continue;
+            const int p = i + P * j + S * k;
+            X[p] = gs3f<T>(F[p], inv_h, X[p - 1], X[p + 1], X[p - P], X[p + P], X[p - S], X[p + S]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ inline T b3_resid(const T* X, const T* F, int q, int P, int S, T h) {
+    return F[q] - h * (T(6) * X[q] - (((X[q - 1] + X[q + 1]) + (X[q - P] + X[q + P])) + (X[q - S] + X[q + S])));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBottom3Threads) void k_vbottom3d(T* __restrict__ x, const T* __restrict__ f, Grid g,
+                                                               int n0, int l, int nh_pre, int nh_post, int zero_x) {
+    extern __shared__ double smem[];
+    T* const base = reinterpret_cast<T*>(smem);
+    auto X = [&](int q) { return base + b3_off(n0, q); };
+    auto F = [&](int q) { return base + b3_off(n0, q) + b3_elems(n0, q); };
+    double* dsm = smem + ((size_t)b3_off(n0, l + 1) * sizeof(T) + 7) / 8;
+    // lower levels start at zero (their rings stay zero); level l from global memory
+    for (int t = threadIdx.x; t < b3_off(n0, l); t += blockDim.x) base[t] = T(0);
+    const int n = n0 << l, P = n + 1, S = P * P;
+    for (int t = threadIdx.x; t < P * S; t += blockDim.x) {
+        const int i = t % P, j = (t / P) % P, k = t / S;
+        const bool in = i >= 1 && i < n && j >= 1 && j < n && k >= 1 && k < n;
+        const int64_t gp = i + g.pitch * j + g.plane * k;
+        X(l)[t] = (in && !zero_x) ? x[gp] : T(0);
+        F(l)[t] = in ? f[gp] : T(0);
+    }
+    __syncthreads();
+    // down: pre sweeps, then f_{q-1} = P^T (f_q - K x_q)
+    for (int q = l; q >= 1; --q) {
+        const int nq = n0 << q, Pq = nq + 1, Sq = Pq * Pq, nc = nq / 2, Pc = nc + 1, mc = nc - 1;
+        const T hq = T(1.0 / nq);
+        b3_sweeps<T>(X(q), F(q), nq, nh_pre);
+        const T* Xq = X(q);
+        const T* Fq = F(q);
+        T* Fc = F(q - 1);
+        const int d[7] = {1, Pq, Sq, 1 + Pq, Pq + Sq, 1 + Sq, 1 + Pq + Sq};
+        for (int t = threadIdx.x; t < mc * mc * mc; t += blockDim.x) {
+            const int I = 1 + t % mc, J = 1 + (t / mc) % mc, K = 1 + t / (mc * mc);
+            const int p = 2 * I + Pq * 2 * J + Sq * 2 * K;
+            const T c = b3_resid<T>(Xq, Fq, p, Pq, Sq, hq);
+            T e = T(0);
+#pragma unroll
+            for (int r = 0; r < 7; ++r)
+                e += b3_resid<T>(Xq, Fq, p - d[r], Pq, Sq, hq) + b3_resid<T>(Xq, Fq, p + d[r], Pq, Sq, hq);
+            Fc[I + Pc * J + Pc * Pc * K] = c + T(0.5) * e;
+        }
+        __syncthreads();
+    }
+    coarse_dst_solve<T>(F(0), X(0), n0 + 1, (int64_t)(n0 + 1) * (n0 + 1), n0, 3, dsm);
+    __syncthreads();
+    // up: x_q += P x_{q-1}, then the post sweeps
+    for (int q = 1; q <= l; ++q) {
+        const int nq = n0 << q, Pq = nq + 1, Sq = Pq * Pq, Pc = nq / 2 + 1, Sc = Pc * Pc, m = nq - 1;
+        const T* xc = X(q - 1);
+        T* Xq = X(q);
+        for (int t = threadIdx.x; t < m * m * m; t += blockDim.x) {
+            const int i = 1 + t % m, j = 1 + (t / m) % m, k = 1 + t / (m * m);
+            const int di = i & 1, dj = j & 1, dk = k & 1;
+            const int q0 = (i >> 1) + Pc * (j >> 1) + Sc * (k >> 1);
+            T v = xc[q0];
+            if (di | dj | dk) v = T(0.5) * (v + xc[q0 + di + Pc * dj + Sc * dk]);
+            Xq[i + Pq * j + Sq * k] += v;
+        }
+        __syncthreads();
+        b3_sweeps<T>(Xq, F(q), nq, nh_post);
+    }
+    const int m = n - 1;
+    for (int t = threadIdx.x; t < m * m * m; t += blockDim.x) {
+        const int i = 1 + t % m, j = 1 + (t / m) % m, k = 1 + t / (m * m);
+        x[i + g.pitch * j + g.plane * k] = X(l)[i + P * j + S * k];
+    }
+}
+
 }  // namespace
 
 // ---- launch --------------------------------------------------------------------------------
 // Tile shapes: one region pair per thread ((TX + 2G) / 2 * (TY + 2G) = NT), in two sizes:
-// variant 0 with 256 threads, variant 1 with 512 (wider tiles, less halo).
+// variant 0: 256 threads, 32 x 16 region; variant 1: 512 threads, 32 x 32; variant 2: 512
+// threads, 64 x 16 (longer contiguous rows per plane).
 template <int G, int V>
 struct Shape3 {
     static constexpr int NT = V ? 512 : 256;
-    static constexpr int RX = 32, RY = NT / 16;                 // 16 pairs per region row
+    static constexpr int RX = V == 2 ? 64 : 32, RY = 2 * NT / RX;   // RX / 2 pairs per region row
     static constexpr int TX = RX - 2 * G, TY = RY - 2 * G;
     static_assert(TX > 0 && TY > 0 && TX % 2 == 0, "tile shape");
 };
@@ -457,14 +576,16 @@ static void pass3d_v(const Grid& g, const Grid& gc, const T* xin, T* xout, const
 template <typename T, int NS, int MODE, int C1>
 static void pass3d(const Grid& g, const Grid& gc, const T* xin, T* xout, const T* f, T* rc, const T* xc,
                    int zero_x, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (g_var3)
+    if (g_var3 == 2)
+        pass3d_v<T, NS, MODE, C1, 2>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
+    else if (g_var3 == 1)
         pass3d_v<T, NS, MODE, C1, 1>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
     else
         pass3d_v<T, NS, MODE, C1, 0>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
 }
 
 void set_vpass3d_tuning(int variant, int min_n) {
-    if (variant >= 0) g_var3 = variant ? 1 : 0;
+    if (variant >= 0) g_var3 = variant > 2 ? 2 : variant;
     if (min_n > 0) g_min_n3 = min_n;
 }
 void get_vpass3d_tuning(int* variant, int* min_n) {
@@ -479,17 +600,18 @@ bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post) {
 // pre smoothing (2 nu + 1 half sweeps) + residual + restriction: x -> y (result in x for the
 // two-pass split, in y for the one-pass one); returns the array that holds the smoothed x
 template <typename T>
-T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu, int zero_x, hipStream_t s) {
+T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu, int zero_x, hipStream_t s,
+                 hipEvent_t ev0, hipEvent_t ev1) {
     if (nu == 2) {
         // five half sweeps in two passes; the residual and its restriction then as their own
         // streaming kernel (a pass that also restricts needs a 4-ring halo, which costs more
         // than reading x and f once more)
-        pass3d<T, 3, kPlain, 0>(g, gc, x, y, f, nullptr, nullptr, zero_x, s, nullptr, nullptr);
+        pass3d<T, 3, kPlain, 0>(g, gc, x, y, f, nullptr, nullptr, zero_x, s, ev0, ev1);
         pass3d<T, 2, kPlain, 1>(g, gc, y, x, f, nullptr, nullptr, 0, s, nullptr, nullptr);
         launch_resid_restrict<T>(g, gc, x, f, rc, s);
         return x;
     }
-    pass3d<T, 3, kPre, 0>(g, gc, x, y, f, rc, nullptr, zero_x, s, nullptr, nullptr);
+    pass3d<T, 3, kPre, 0>(g, gc, x, y, f, rc, nullptr, zero_x, s, ev0, ev1);
     return y;
 }
 
@@ -509,12 +631,36 @@ void launch_vpost3d(const Grid& g, const Grid& gc, T* xs, T* scratch, T* x_out, 
 }
 
 template double* launch_vpre3d<double>(const Grid&, const Grid&, double*, double*, const double*, double*, int, int,
-                                       hipStream_t);
+                                       hipStream_t, hipEvent_t, hipEvent_t);
 template float* launch_vpre3d<float>(const Grid&, const Grid&, float*, float*, const float*, float*, int, int,
-                                     hipStream_t);
+                                     hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_vpost3d<double>(const Grid&, const Grid&, double*, double*, double*, const double*,
                                      const double*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_vpost3d<float>(const Grid&, const Grid&, float*, float*, float*, const float*, const float*, int,
                                     hipStream_t, hipEvent_t, hipEvent_t);
+
+template <typename T>
+bool launch_vbottom3d(const Grid* levels, int l, T* x, const T* f, int nu_pre, int nu_post, int zero_x,
+                      hipStream_t s) {
+    if (l < 1 || levels[l].dim != 3 || levels[l].n > kBottom3MaxN || nu_pre > 2 || nu_post > 2) return false;
+    const int n0 = levels[0].n;
+    const size_t bytes = b3_bytes<T>(n0, l);
+    if (bytes > kBottom3MaxBytes) return false;
+    // once per instantiation (thread-safe static initialisation)
+    static const bool attr = [] {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vbottom3d<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBottom3MaxBytes) == hipSuccess)
+            return true;
+        (void)hipGetLastError();
+        return false;
+    }();
+    if (!attr) return false;
+    const int nh_pre = nu_pre > 0 ? 2 * nu_pre + 1 : 0, nh_post = nu_post > 0 ? 2 * nu_post + 1 : 0;
+    hipLaunchKernelGGL(k_vbottom3d<T>, dim3(1), dim3(kBottom3Threads), bytes, s, x, f, levels[l], n0, l, nh_pre,
+                       nh_post, zero_x);
+    return true;
+}
+template bool launch_vbottom3d<double>(const Grid*, int, double*, const double*, int, int, int, hipStream_t);
+template bool launch_vbottom3d<float>(const Grid*, int, float*, const float*, int, int, int, hipStream_t);
 
 }  // namespace fmg

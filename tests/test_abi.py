@@ -129,11 +129,21 @@ def test_batch_validates_every_instance_before_any_work(lib):
     assert lib.fmg_batch_solve(-1, None, None, None, None, None, None) == -1
 
 
+def test_profile_requests_are_validated(lib):
+    """Unknown kinds and bad capacities are refused before any event is created, and ending
+    a profile that was never begun is an error."""
+    from paper_1502_04657_amd import _ffi
+    for kind, cap in ((0, 8), (6, 8), (_ffi.FMG_PROF_MOMENTS3D, 0), (_ffi.FMG_PROF_RHS3D, -1)):
+        assert lib.fmg_profile_begin(kind, cap) == _ffi.FMG_EINVAL
+    assert lib.fmg_profile_end(None) == _ffi.FMG_EINVAL
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """The ctypes mirrors of fmg_problem, fmg_options and fmg_result have the field offsets
     and sizes a C compiler gives the header's structs."""
     from paper_1502_04657_amd import _ffi
-    structs = {"fmg_problem": _ffi.fmg_problem, "fmg_options": _ffi.fmg_options, "fmg_result": _ffi.fmg_result}
+    structs = {"fmg_problem": _ffi.fmg_problem, "fmg_options": _ffi.fmg_options, "fmg_result": _ffi.fmg_result,
+               "fmg_tuning": _ffi.fmg_tuning, "fmg_kernel_profile": _ffi.fmg_kernel_profile}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fmgeig.h"', "int main(void) {"]
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')

@@ -146,14 +146,16 @@ def test_fused_vcycle_large_levels_bitwise(ops, nc, levels):
     assert bool(torch.isfinite(got).all())
 
 
-@pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (3, 6), (5, 5), (4, 4)])
+@pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (3, 6), (5, 5), (4, 4), (4, 3), (8, 2), (2, 4)])
 @pytest.mark.parametrize("nu", [1, 2])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_fused_vcycle_3d_bitwise(ops, nc, levels, nu, variant):
-    """3D levels from n = 16 on run the z-pipelined level passes (forced through the tuning
-    interface; ragged tiles and z-chunks at n = 96, 80, 160): the same bits as the unfused
-    kernel sequence, for V(1,1) (one pass per side) and V(2,2) (two passes per side), with
-    both tile variants."""
+    """3D levels above n = 16 run the z-pipelined level passes (forced through the tuning
+    interface; ragged tiles and z-chunks at n = 96, 80, 160), and levels up to n = 16 with
+    everything below them the one-workgroup bottom kernel (the whole V-cycle for n = 16 on
+    coarsest meshes of 2, 4 and 8 cells per side): the same bits as the unfused kernel
+    sequence, for V(1,1) (one pass per side) and V(2,2) (two passes per side), with all three
+    tile variants."""
     import ctypes as C
     from paper_1502_04657_amd import _ffi, lib
     saved = _ffi.fmg_tuning()
