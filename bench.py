@@ -306,26 +306,43 @@ def copy_calibration():
 
 
 def bench_batch(steps, warmup, count=64):
-    """Config 4: `count` uneven 2D instances (workloads.batch_instances, seed 0) per
-    fmg_batch_solve call, mixed precision, tolerance 1e-9 on |dlambda|/lambda.  value =
-    fine DOF of the batch / seconds per call; latency = each instance's completion time
-    within its call.  The same instances solved one after another through fmg_solve are
-    timed beside it."""
+    """Config 4: `count` uneven 2D instances (workloads.batch_instances, seed 0), mixed
+    precision, tolerance 1e-9 on |dlambda|/lambda.  value = fine DOF of the batch / seconds
+    per replay of a batch plan (each instance's kernels captured once into HIP graphs and
+    replayed on 16 streams, 2D tile choices from the autotuner); latency = each instance's
+    completion time within its replay.
+    The same instances through fmg_batch_solve (no graphs, 8 streams, eight enqueueing host
+    threads) and one after another through fmg_solve are timed beside it."""
     import torch
-    from paper_1502_04657_amd import Solver, batch_solve
+    from paper_1502_04657_amd import BatchPlan, Solver, batch_solve, tuning
     probs = W.batch_instances(count, 0)
     opts = W.Options(tol_lambda=TOL, precision="mixed")
     dofs = sum(p.dofs() for p in probs)
+    # the 2D tile choices, measured now on the largest level of the batch (no cache)
+    t0 = time.perf_counter()
+    choice = tuning.autotune(2, max(p.n_fine for p in probs), "mixed", cache=None)
+    t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = BatchPlan(probs, opts)
+    t_create = time.perf_counter() - t0
     for _ in range(warmup):
-        batch_solve(probs, opts, check=False)
+        plan.run(check=False)
     torch.cuda.synchronize()
     lat, fails = [], 0
     t0 = time.perf_counter()
     for _ in range(steps):
-        res, _ = batch_solve(probs, opts, check=False)
+        res, _ = plan.run(check=False)
         lat += [r.seconds for r in res]
         fails += sum(r.status != 0 for r in res)
     total = time.perf_counter() - t0
+    plan.close()
+    for _ in range(warmup):
+        batch_solve(probs, opts, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch_solve(probs, opts, check=False)
+    tb = (time.perf_counter() - t0) / steps
     solvers = [Solver(p, opts) for p in probs]
     for s in solvers:
         s.solve(check=False)
@@ -342,8 +359,10 @@ def bench_batch(steps, warmup, count=64):
             "config": {"workload": f"{count} 2D GP instances, n in {{256,512,1024}}, zeta log-uniform [0.1,1000], "
                                    "W=a x^2+b y^2, a,b in [0.5,2], coarsest h=1/16, seed 0", "global_batch": count},
             "instance_latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
-            "failed_instances": fails, "sequential_fmg_solve_ms": seq * 1e3,
-            "speedup_vs_sequential": seq / (total / steps)}
+            "failed_instances": fails, "tuning": choice, "autotune_ms": t_tune * 1e3,
+            "plan_create_ms": t_create * 1e3,
+            "batch_solve_ms": tb * 1e3, "sequential_fmg_solve_ms": seq * 1e3,
+            "speedup_vs_batch_solve": tb / (total / steps), "speedup_vs_sequential": seq / (total / steps)}
 
 
 def bench_serve(count, budget_gb, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.25)):

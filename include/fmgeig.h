@@ -130,10 +130,26 @@ typedef struct {
     int32_t vpass3d_variant;  /* 3D pass tiles (region columns x rows, threads): 0 = 32 x 16,  */
                               /* 256; 1 = 32 x 32, 512; 2 = 64 x 16, 512                      */
     int32_t vpass3d_min_n;    /* smallest 3D level (cells per side) on the fused passes      */
-    int32_t reserved[6];
+    int32_t vpass2d_wide_min_n; /* 2D levels with more cells per side use the wide tiles    */
+                                /* (0 in fmg_set_tuning: the default 256)                    */
+    int32_t vbottom2d_max_n;  /* 2D levels with at most this many cells per side run the    */
+                              /* one-workgroup V-cycle bottom (0: the default 32; -1: never; */
+                              /* at most 64)                                                 */
+    int32_t reserved[4];
 } fmg_tuning;
 int fmg_get_tuning(fmg_tuning* out);
 int fmg_set_tuning(const fmg_tuning* in);   /* FMG_EINVAL for values out of range            */
+/* Tile autotuner: times whole V(2,2) cycles (every level down to the exact coarsest solve)
+ * of a level with n cells per side, in FP64 (precision FMG_FP64) or FP32 (FMG_MIXED), on a
+ * scratch hierarchy it allocates and frees, and returns the fastest choice in *out: in 3D
+ * over every pass variant and smallest fused level (16, 32, ... up to "none"), in 2D over
+ * the level from which the wide tiles are used (64 .. n, or none) and the largest level of
+ * the one-workgroup bottom (none, 16, 32, 64).  The other dimension's fields keep their
+ * current values.  The current tuning is left as it was; apply the result with
+ * fmg_set_tuning.  n must be n_c 2^k with 2 <= n_c <= 7 (3D, 16 <= n <= 1024) or
+ * 8 <= n_c <= 31 (2D, 64 <= n <= 32768).  Synchronises `stream`; not to be called while
+ * solves run.                                                                            */
+int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream, fmg_tuning* out);
 
 /* ---- measurement hooks ------------------------------------------------------------------ */
 /* Per-launch timing of one kernel inside later solves: a pair of HIP events is stamped by
@@ -246,6 +262,26 @@ int fmg_solve_alloc(const fmg_problem* prob, const fmg_options* opt, void* strea
  * FMG_ENOMEM before any work for bad arguments or a failed pool allocation.              */
 int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* opts, void* stream,
                     double* const* d_u_out, const int64_t* u_len, fmg_result* out);
+
+/* A batch plan: the instances of a batch set up once (one pool for all their workspaces,
+ * through the allocator of fmg_set_allocator else hipMalloc) and each instance's kernel
+ * sequence captured into HIP graphs: the first chunk of its solve (state initialisation,
+ * Algorithm 3.2 step 1 and every level's p correction steps), one more finest-level
+ * correction step (replayed while the lambda tolerance is not met) and the final chunk
+ * (Rayleigh quotient and residual).  fmg_batch_plan_run replays them for every instance,
+ * the instances spread over up to 16 streams of the plan (their graphs overlap on the
+ * device), one host thread deciding between the chunks from the copied-back state, and
+ * writes each u into d_u_out[i] (device, compact, u_len[i] = (n_i - 1)^dim_i).  Results
+ * are bitwise those of fmg_solve.  Work already enqueued on `stream` runs before a run's
+ * first graph; run returns after every instance is done, out[i] as for fmg_batch_solve.
+ * A plan runs any number of times; runs of one plan must not overlap.  create returns
+ * NULL on failure (fmg_last_error says why): invalid instances, FMG_ENOMEM, or a capture
+ * failure.                                                                               */
+typedef struct fmg_batch_plan fmg_batch_plan;
+fmg_batch_plan* fmg_batch_plan_create(int32_t count, const fmg_problem* probs, const fmg_options* opts,
+                                      void* stream);
+int fmg_batch_plan_run(fmg_batch_plan* plan, double* const* d_u_out, const int64_t* u_len, fmg_result* out);
+void fmg_batch_plan_destroy(fmg_batch_plan* plan);
 
 /* Serving: continuous batching of requests of different sizes.  The server owns a pool of
  * hbm_budget bytes (0: half of the free device memory) and up to max_slots (1..64)

@@ -14,7 +14,7 @@ import torch
 from . import _ffi
 from ._ffi import FMG_FP64, FMG_MIXED, fmg_options, fmg_problem, fmg_result
 
-__all__ = ["solve", "solve_alloc", "workspace_bytes", "footprint_bytes", "Solver", "batch_solve", "Server", "FmgError", "ops", "lib",
+__all__ = ["solve", "solve_alloc", "workspace_bytes", "footprint_bytes", "Solver", "batch_solve", "BatchPlan", "Server", "FmgError", "ops", "lib",
            "to_c_problem", "to_c_options"]
 
 
@@ -169,6 +169,53 @@ def batch_solve(problems, options, device="cuda", stream=None, check=True):
     if check:
         _check(rc)
     return [_result(r) for r in res], us
+
+
+class BatchPlan:
+    """fmg_batch_plan_*: a batch set up once (one pool, each instance's kernel sequence
+    captured into HIP graphs) and replayed by run().  Output tensors are allocated once and
+    reused by every run."""
+
+    def __init__(self, problems, options, device="cuda", stream=None):
+        k = len(problems)
+        opts = options if isinstance(options, (list, tuple)) else [options] * k
+        cps = (fmg_problem * k)(*[to_c_problem(p) for p in problems])
+        cos = (fmg_options * k)(*[to_c_options(o) for o in opts])
+        self.problems = list(problems)
+        h = lib().fmg_batch_plan_create(k, cps, cos, _stream(stream))
+        if not h:
+            raise FmgError(_ffi.FMG_EINVAL, lib().fmg_last_error().decode())
+        self._h = h
+        self.us = [torch.empty(_ndof(p), dtype=torch.float64, device=device) for p in problems]
+        self._ptrs = (C.c_void_p * k)(*[u.data_ptr() for u in self.us])
+        self._lens = (C.c_int64 * k)(*[u.numel() for u in self.us])
+
+    def run(self, check=True):
+        """Replay every instance; returns ([Result], [u tensors]) (the tensors are the plan's
+        and are overwritten by the next run)."""
+        k = len(self.problems)
+        res = (fmg_result * k)()
+        rc = lib().fmg_batch_plan_run(self._h, self._ptrs, self._lens, res)
+        if check:
+            _check(rc)
+        return [_result(r) for r in res], self.us
+
+    def close(self):
+        if self._h:
+            lib().fmg_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -27,7 +27,8 @@ class fmg_options(C.Structure):
 
 
 class fmg_tuning(C.Structure):
-    _fields_ = [("vpass3d_variant", C.c_int32), ("vpass3d_min_n", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("vpass3d_variant", C.c_int32), ("vpass3d_min_n", C.c_int32), ("vpass2d_wide_min_n", C.c_int32),
+                ("vbottom2d_max_n", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class fmg_kernel_profile(C.Structure):
@@ -59,6 +60,7 @@ SIGNATURES = {
     "fmg_set_fused_vcycle": (C.c_int, [I32]),
     "fmg_get_tuning": (C.c_int, [P]),
     "fmg_set_tuning": (C.c_int, [P]),
+    "fmg_autotune_vcycle": (C.c_int, [I32, I32, I32, P, P]),
     "fmg_profile_begin": (C.c_int, [I32, I32]),
     "fmg_profile_end": (C.c_int, [P]),
     "fmg_workspace_bytes": (C.c_int, [P, P, C.POINTER(SZ)]),
@@ -68,6 +70,9 @@ SIGNATURES = {
     "fmg_footprint_bytes": (SZ, [P, P]),
     "fmg_set_allocator": (C.c_int, [P, P, P]),
     "fmg_batch_solve": (C.c_int, [I32, P, P, P, P, P, P]),
+    "fmg_batch_plan_create": (P, [I32, P, P, P]),
+    "fmg_batch_plan_run": (C.c_int, [P, P, P, P]),
+    "fmg_batch_plan_destroy": (None, [P]),
     "fmg_server_create": (P, [SZ, I32, P]),
     "fmg_server_submit": (C.c_int, [P, P, P, C.POINTER(C.c_uint64)]),
     "fmg_server_poll": (C.c_int, [P, C.c_uint64, P, P, I64]),

@@ -262,8 +262,12 @@ int64_t compact_len(const fmg_problem* p) {
 
 static bool tol_mode(const SolveJob& j) { return j.opt.tol_lambda > 0.0 && j.lo.L > 1; }
 
+// Each chunk is a body (kernels and the copies of the device state into the host mirror:
+// what a captured graph of the chunk holds), then the outputs of the final chunk and the
+// chunk's event, which depend on the call.
+
 // device state (and the Rayleigh-quotient forms after the final chunk) into the host mirror
-static int end_chunk(SolveJob& j, bool final_chunk) {
+static int copy_state(SolveJob& j, bool final_chunk) {
     SmallState* st = at<SmallState>(j.ws, j.lo.state);
     // a tolerance check needs only the scalars in front of the lambda history
     const size_t bytes = final_chunk ? sizeof(SmallState) : offsetof(SmallState, hist);
@@ -271,31 +275,22 @@ static int end_chunk(SolveJob& j, bool final_chunk) {
     if (final_chunk)
         FMG_HIP_CHECK(hipMemcpyAsync(j.host->forms, at<double>(j.ws, j.lo.forms), sizeof(j.host->forms),
                                      hipMemcpyDeviceToHost, j.s));
-    if (j.ev) FMG_HIP_CHECK(hipEventRecord(j.ev, j.s));
     return 0;
 }
 
-// Rayleigh quotient and residual of the finest u, and the output copy when a target is set
-static int final_chunk(SolveJob& j) {
+// Rayleigh quotient and residual of the finest u
+static int body_final(SolveJob& j) {
     const Layout& lo = j.lo;
     const Grid& gf = lo.g[lo.L - 1];
     double* forms = at<double>(j.ws, lo.forms);
     const double* u = at<double>(j.ws, lo.u[lo.L - 1]);
     launch_forms(gf, make_phys(&j.prob), u, forms + 8, forms, j.s, &at<SmallState>(j.ws, lo.state)->lambda);
-    if (j.u_out) launch_unpack(gf, u, j.u_out, j.s);
-    if (j.u_host) {
-        // host target: compact copy in the finest right-hand-side array (not needed any
-        // more), then one device-to-host copy
-        double* stage = at<double>(j.ws, lo.b[lo.L - 1]);
-        launch_unpack(gf, u, stage, j.s);
-        FMG_HIP_CHECK(hipMemcpyAsync(j.u_host, stage, sizeof(double) * compact_len(&j.prob), hipMemcpyDeviceToHost,
-                                     j.s));
-    }
-    j.phase = 2;
-    return end_chunk(j, true);
+    return copy_state(j, true);
 }
 
-int job_start(SolveJob& j) {
+// state initialisation, Algorithm 3.2 step 1 and every level's p correction steps (and,
+// without a lambda tolerance, the final body)
+static int body_first(SolveJob& j) {
     const Layout& lo = j.lo;
     const fmg_problem* prob = &j.prob;
     const fmg_options* opt = &j.opt;
@@ -303,13 +298,9 @@ int job_start(SolveJob& j) {
     void* ws = j.ws;
     const Phys ph = make_phys(prob);
     const int L = lo.L;
-    j.phase = 0;
-    j.extra = 0;
     // initial state and zeroed level arrays (the Dirichlet rings must be zero)
-    std::memset(&j.host->st, 0, sizeof(SmallState));
-    j.host->st.tol_lambda = opt->tol_lambda;
     SmallState* st = at<SmallState>(ws, lo.state);
-    FMG_HIP_CHECK(hipMemcpyAsync(st, &j.host->st, sizeof(SmallState), hipMemcpyHostToDevice, s));
+    launch_init_state(st, opt->tol_lambda, s);
     launch_fill<double>(at<double>(ws, lo.xc), (int64_t)((lo.mom - lo.xc) / sizeof(double)), 0.0, s);
     // Algorithm 3.2 step 1
     int rc = launch_coarse_newton(prob->dim, prob->n_coarse, ph, opt->newton_max_iter, opt->newton_tol,
@@ -328,24 +319,109 @@ int job_start(SolveJob& j) {
             if ((rc = correction_step(lo, ws, prob, opt, k, flag, cert, s))) return rc;
         }
     }
+    return tol_mode(j) ? copy_state(j, false) : body_final(j);
+}
+
+// one more finest-level correction step (Algorithm 3.1)
+static int body_step(SolveJob& j) {
+    if (int rc = correction_step(j.lo, j.ws, &j.prob, &j.opt, j.lo.L - 1, 1, 2, j.s)) return rc;
+    return copy_state(j, false);
+}
+
+static int run_body(SolveJob& j, int which) {
+    if (j.gx[which]) {
+        FMG_HIP_CHECK(hipGraphLaunch(j.gx[which], j.s));
+        return 0;
+    }
+    return which == 0 ? body_first(j) : (which == 1 ? body_step(j) : body_final(j));
+}
+
+// the outputs of the final chunk: u into the caller's device or host target
+static int outputs(SolveJob& j) {
+    const Layout& lo = j.lo;
+    const Grid& gf = lo.g[lo.L - 1];
+    const double* u = at<double>(j.ws, lo.u[lo.L - 1]);
+    if (j.u_out) launch_unpack(gf, u, j.u_out, j.s);
+    if (j.u_host) {
+        // host target: compact copy in the finest right-hand-side array (not needed any
+        // more), then one device-to-host copy
+        double* stage = at<double>(j.ws, lo.b[lo.L - 1]);
+        launch_unpack(gf, u, stage, j.s);
+        FMG_HIP_CHECK(hipMemcpyAsync(j.u_host, stage, sizeof(double) * compact_len(&j.prob), hipMemcpyDeviceToHost,
+                                     j.s));
+    }
+    return 0;
+}
+
+static int end_chunk(SolveJob& j) {
+    if (j.ev) FMG_HIP_CHECK(hipEventRecord(j.ev, j.s));
+    return 0;
+}
+
+int job_start(SolveJob& j) {
+    j.phase = 0;
+    j.extra = 0;
+    std::memset(&j.host->st, 0, sizeof(SmallState));
+    j.host->st.tol_lambda = j.opt.tol_lambda;
+    if (int rc = run_body(j, 0)) return rc;
     if (tol_mode(j)) {
         j.phase = 1;
-        return end_chunk(j, false);
+    } else {
+        if (int rc = outputs(j)) return rc;
+        j.phase = 2;
     }
-    return final_chunk(j);
+    return end_chunk(j);
 }
 
 int job_step(SolveJob& j) {
     if (j.phase == 1) {
         const SmallState& h = j.host->st;
-        if (h.done || h.status != 0 || j.extra >= j.opt.max_final_steps) return final_chunk(j);
-        // one more finest-level correction step (Algorithm 3.1), then check again
-        if (int rc = correction_step(j.lo, j.ws, &j.prob, &j.opt, j.lo.L - 1, 1, 2, j.s)) return rc;
+        if (h.done || h.status != 0 || j.extra >= j.opt.max_final_steps) {
+            if (int rc = run_body(j, 2)) return rc;
+            if (int rc = outputs(j)) return rc;
+            j.phase = 2;
+            return end_chunk(j);
+        }
+        if (int rc = run_body(j, 1)) return rc;
         ++j.extra;
-        return end_chunk(j, false);
+        return end_chunk(j);
     }
     if (j.phase == 2) j.phase = 3;
     return 0;
+}
+
+int job_capture(SolveJob& j, hipStream_t cs) {
+    job_release(j);
+    const hipStream_t saved = j.s;
+    j.s = cs;
+    int rc = 0;
+    for (int w = 0; w < 3 && !rc; ++w) {
+        if (w > 0 && !tol_mode(j)) break;   // without a tolerance the first body is the whole solve
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            rc = set_error(FMG_EHIP, "hipStreamBeginCapture failed");
+            break;
+        }
+        rc = w == 0 ? body_first(j) : (w == 1 ? body_step(j) : body_final(j));
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (!rc && (e != hipSuccess || !g)) rc = set_error(FMG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        if (!rc && hipGraphInstantiate(&j.gx[w], g, nullptr, nullptr, 0) != hipSuccess) {
+            j.gx[w] = nullptr;
+            rc = set_error(FMG_EHIP, "hipGraphInstantiate failed");
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+    (void)hipGetLastError();
+    j.s = saved;
+    if (rc) job_release(j);
+    return rc;
+}
+
+void job_release(SolveJob& j) {
+    for (auto& g : j.gx) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
 int job_result(const SolveJob& j, fmg_result* out) {
@@ -480,10 +556,13 @@ int fmg_set_fused_vcycle(int32_t enable) {
 int fmg_get_tuning(fmg_tuning* out) {
     if (!out) return set_error(FMG_EINVAL, "tuning is NULL");
     std::memset(out, 0, sizeof(*out));
-    int v = 0, mn = 0;
+    int v = 0, mn = 0, w2 = 0, b2 = 0;
     get_vpass3d_tuning(&v, &mn);
+    get_vpass2d_tuning(&w2, &b2);
     out->vpass3d_variant = v;
     out->vpass3d_min_n = mn;
+    out->vpass2d_wide_min_n = w2;
+    out->vbottom2d_max_n = b2;
     return 0;
 }
 
@@ -491,8 +570,97 @@ int fmg_set_tuning(const fmg_tuning* in) {
     if (!in) return set_error(FMG_EINVAL, "tuning is NULL");
     if (in->vpass3d_variant < 0 || in->vpass3d_variant > 2) return set_error(FMG_EINVAL, "vpass3d_variant must be 0, 1 or 2");
     if (in->vpass3d_min_n < 16) return set_error(FMG_EINVAL, "vpass3d_min_n must be >= 16");
+    if (in->vpass2d_wide_min_n != 0 && in->vpass2d_wide_min_n < 16)
+        return set_error(FMG_EINVAL, "vpass2d_wide_min_n must be 0 or >= 16");
+    if (in->vbottom2d_max_n < -1 || in->vbottom2d_max_n > 64)
+        return set_error(FMG_EINVAL, "vbottom2d_max_n must be in [-1, 64]");
     set_vpass3d_tuning(in->vpass3d_variant, in->vpass3d_min_n);
+    set_vpass2d_tuning(in->vpass2d_wide_min_n, in->vbottom2d_max_n);
     return 0;
+}
+
+int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream, fmg_tuning* out) {
+    if (!out) return set_error(FMG_EINVAL, "tuning is NULL");
+    if (dim != 2 && dim != 3) return set_error(FMG_EINVAL, "dim must be 2 or 3");
+    if (precision != FMG_FP64 && precision != FMG_MIXED) return set_error(FMG_EINVAL, "precision invalid");
+    fmg_tuning cur;
+    fmg_get_tuning(&cur);
+    *out = cur;
+    const int nc_max = dim == 2 ? 31 : 7;
+    int nc = n, levels = 1;
+    while (nc > nc_max && nc % 2 == 0) {
+        nc /= 2;
+        ++levels;
+    }
+    if (dim == 3 && (n < 16 || n > 1024 || nc < 2 || levels < 2))
+        return set_error(FMG_EINVAL, "3D n must be n_c 2^k with 2 <= n_c <= 7 and 16 <= n <= 1024 (got %d)", n);
+    if (dim == 2 && (n < 64 || n > 32768 || nc < 8 || levels < 2))
+        return set_error(FMG_EINVAL, "2D n must be n_c 2^k with 8 <= n_c <= 31 and 64 <= n <= 32768 (got %d)", n);
+    const Layout lo = make_layout(dim, nc, levels, precision == FMG_MIXED, 0);
+    void* ws = nullptr;
+    if (hipMalloc(&ws, lo.total) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FMG_ENOMEM, "hipMalloc of %zu bytes failed", lo.total);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = set_error(FMG_EHIP, "events");
+    const int top = levels - 1, reps = dim == 2 ? 10 : 5;
+    // every array zero (the Dirichlet rings), then the top right-hand side one
+    if (!rc) launch_fill<double>(static_cast<double*>(ws), (int64_t)(lo.total / sizeof(double)), 0.0, s);
+    auto time_cycles = [&](auto zero) -> float {
+        using T = decltype(zero);
+        T* x = sizeof(T) == 8 ? at<T>(ws, lo.u[top]) : at<T>(ws, lo.xv[top]);
+        T* f = sizeof(T) == 8 ? at<T>(ws, lo.b[top]) : at<T>(ws, lo.fv[top]);
+        launch_fill<T>(f, lo.g[top].elems, T(1), s);
+        vcycle<T>(lo, ws, top, x, f, 2, 2, s);   // first launches of this choice
+        float ms = -1.f;
+        if (hipEventRecord(e0, s) != hipSuccess) return ms;
+        for (int r = 0; r < reps; ++r) vcycle<T>(lo, ws, top, x, f, 2, 2, s);
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            ms = -1.f;
+        return ms;
+    };
+    float best = -1.f;
+    auto consider = [&](int a, int b) {
+        if (dim == 3) set_vpass3d_tuning(a, b);
+        else set_vpass2d_tuning(a, b);
+        const float ms = precision == FMG_MIXED ? time_cycles(0.0f) : time_cycles(0.0);
+        if (ms < 0.f) {
+            rc = set_error(FMG_EHIP, "timing failed");
+            return;
+        }
+        if (best < 0.f || ms < best) {
+            best = ms;
+            if (dim == 3) {
+                out->vpass3d_variant = a;
+                out->vpass3d_min_n = b;
+            } else {
+                out->vpass2d_wide_min_n = a;
+                out->vbottom2d_max_n = b;
+            }
+        }
+    };
+    if (dim == 3) {
+        for (int mn = 16; !rc && mn <= 2 * n; mn *= 2)
+            // mn > n: no level on the fused passes (the variant does not matter)
+            for (int v = 0; v < 3 && !rc; ++v)
+                if (mn <= n || v == cur.vpass3d_variant) consider(v, mn);
+    } else {
+        for (int wm = 64; !rc && wm <= n; wm *= 2)   // wm = n: no level on the wide tiles
+            for (int bm : {-1, 16, 32, 64})
+                if (!rc) consider(wm, bm);
+    }
+    set_vpass3d_tuning(cur.vpass3d_variant, cur.vpass3d_min_n);
+    set_vpass2d_tuning(cur.vpass2d_wide_min_n, cur.vbottom2d_max_n);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = set_error(FMG_EHIP, "autotune failed");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(ws);
+    if (rc) *out = cur;
+    return rc;
 }
 
 int fmg_profile_begin(int32_t kernel, int32_t max_launches) {

@@ -12,6 +12,8 @@
 // directions, which are exactly the nonzero parity patterns (i&1, j&1, k&1)).
 #include <hip/hip_ext.h>
 
+#include <cstddef>
+
 #include "dst.h"
 #include "kernels.h"
 
@@ -34,6 +36,18 @@ void launch_fill(T* p, int64_t count, T v, hipStream_t s) {
 }
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);
 template void launch_fill<float>(float*, int64_t, float, hipStream_t);
+
+// every 32-bit word of the state zero except the two of tol_lambda, which take its bits
+__global__ void k_init_state(SmallState* st, double tol) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(st);
+    constexpr int nw = (int)(sizeof(SmallState) / 4), t0 = (int)(offsetof(SmallState, tol_lambda) / 4);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(tol);
+    for (int i = threadIdx.x; i < nw; i += blockDim.x)
+        w[i] = i == t0 ? (uint32_t)b : (i == t0 + 1 ? (uint32_t)(b >> 32) : 0u);
+}
+void launch_init_state(SmallState* st, double tol_lambda, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, st, tol_lambda);
+}
 
 __device__ inline int64_t compact_to_level(const Grid& g, int64_t c) {
     const int64_t m = g.n - 1;

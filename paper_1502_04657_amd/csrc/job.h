@@ -47,6 +47,9 @@ struct SolveJob {
     hipEvent_t ev = nullptr;     // when set, recorded at the end of every chunk
     int phase = 0;               // 1: tolerance check pending, 2: final chunk pending, 3: done
     int extra = 0;               // finest-level correction steps beyond p
+    // captured chunk bodies (job_capture): first chunk, one more finest step, final chunk;
+    // when set they are replayed instead of enqueued kernel by kernel
+    hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
 };
 
 // Enqueue the first chunk: state initialisation, the coarse solve and every level's p
@@ -59,5 +62,11 @@ int job_step(SolveJob& j);
 // Fill *out from the host mirror of a finished job; returns its status (and sets the
 // thread's error message when it is not 0).  seconds is left to the driver.
 int job_result(const SolveJob& j, fmg_result* out);
+// Capture the job's chunk bodies on stream cs (relaxed capture mode) into executable graphs
+// that job_start / job_step then launch on the job's stream.  Needs ws and a pinned host
+// mirror (the graphs copy into them); the outputs (u_out, u_host) and the chunk events stay
+// outside the graphs.  Nothing runs during the capture.
+int job_capture(SolveJob& j, hipStream_t cs);
+void job_release(SolveJob& j);   // destroy the captured graphs
 
 }  // namespace fmg

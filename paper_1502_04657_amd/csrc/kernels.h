@@ -74,6 +74,10 @@ bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post);
 // fused passes (negative / 0: keep the current value)
 void set_vpass3d_tuning(int variant, int min_n);
 void get_vpass3d_tuning(int* variant, int* min_n);
+// 2D: levels with n > wide_min use the wide tiles (0: the default 256); levels with
+// n <= bottom_max run the one-workgroup bottom (0: the default 32, -1: never)
+void set_vpass2d_tuning(int wide_min, int bottom_max);
+void get_vpass2d_tuning(int* wide_min, int* bottom_max);
 template <typename T> T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu,
                                        int zero_x, hipStream_t s, hipEvent_t ev0 = nullptr,
                                        hipEvent_t ev1 = nullptr);
@@ -108,6 +112,8 @@ struct SmallState {
     int32_t fact_total;   // LDL^T factorisations (Newton, chord refreshes, inertia checks)
     double hist[512];
 };
+// zero the state and set its tolerance (a kernel, so that a captured graph can replay it)
+void launch_init_state(SmallState* st, double tol_lambda, hipStream_t s);
 size_t small_arena_bytes(int dim, int nc);
 size_t small_factor_bytes(int dim, int nc);   // persistent Jacobian factor
 // Coarse nonlinear eigenproblem (Algorithm 3.2 step 1) -> x_H written into the coarsest

@@ -279,6 +279,8 @@ int validate(const fmg_problem* p, const fmg_options* o, size_t* bytes) {
 
 constexpr int kMaxSlots = 64;     // streams of a server
 constexpr int kBatchSlots = 8;    // streams of a batch call
+constexpr int kPlanStreams = 16;  // streams of a batch plan
+constexpr int kMaxPlanInstances = 4096;
 
 }  // namespace
 
@@ -322,6 +324,49 @@ struct fmg_server {
             }
         }
         cv.notify_all();
+    }
+};
+
+// ---- batch plans ---------------------------------------------------------------------------
+struct fmg_batch_plan {
+    fmg::Pool pool;
+    std::vector<fmg::SolveJob> jobs;
+    std::vector<hipStream_t> str;
+    std::vector<hipEvent_t> ev;
+    hipStream_t user = nullptr, cap = nullptr;
+    hipEvent_t uev = nullptr;
+    fmg::JobHost* host = nullptr;
+
+    int init(int count) {
+        jobs.resize(count);
+        str.assign(std::min(count, fmg::kPlanStreams), nullptr);
+        ev.assign(count, nullptr);
+        for (auto& s : str) FMG_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        for (auto& e : ev) FMG_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        FMG_HIP_CHECK(hipEventCreateWithFlags(&uev, hipEventDisableTiming));
+        FMG_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        FMG_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&host), sizeof(fmg::JobHost) * count,
+                                    hipHostMallocDefault));
+        return 0;
+    }
+    void destroy() {
+        for (auto& s : str)
+            if (s) (void)hipStreamSynchronize(s);
+        for (auto& j : jobs) fmg::job_release(j);
+        for (auto& s : str)
+            if (s) (void)hipStreamDestroy(s);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (uev) (void)hipEventDestroy(uev);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (host) (void)hipHostFree(host);
+        str.clear();
+        ev.clear();
+        jobs.clear();
+        uev = nullptr;
+        cap = nullptr;
+        host = nullptr;
+        pool.destroy();
     }
 };
 
@@ -429,6 +474,119 @@ int fmg_batch_solve(int32_t count, const fmg_problem* probs, const fmg_options* 
         }
     }
     return first;
+}
+
+fmg_batch_plan* fmg_batch_plan_create(int32_t count, const fmg_problem* probs, const fmg_options* opts,
+                                      void* stream) {
+    if (count < 1 || count > kMaxPlanInstances) {
+        set_error(FMG_EINVAL, "count must be in [1, %d]", kMaxPlanInstances);
+        return nullptr;
+    }
+    if (!probs || !opts) {
+        set_error(FMG_EINVAL, "NULL array argument");
+        return nullptr;
+    }
+    auto plan = std::make_unique<fmg_batch_plan>();
+    plan->user = static_cast<hipStream_t>(stream);
+    std::vector<size_t> bytes(count), off(count);
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        if (int rc = validate(&probs[i], &opts[i], &bytes[i])) {
+            set_error(rc, "instance %d: %s", i, std::string(fmg_last_error()).c_str());
+            return nullptr;
+        }
+        off[i] = total;
+        total += align256(bytes[i]);
+    }
+    if (plan->pool.init(total)) return nullptr;
+    if (plan->init(count) != 0) {
+        plan->destroy();
+        return nullptr;
+    }
+    for (int i = 0; i < count; ++i) {
+        SolveJob& j = plan->jobs[i];
+        j.prob = probs[i];
+        j.opt = opts[i];
+        j.lo = layout_for(&probs[i], &opts[i]);
+        j.ws = plan->pool.base() + off[i];
+        j.host = plan->host + i;
+        j.s = plan->str[i % plan->str.size()];
+        j.ev = plan->ev[i];
+        if (int rc = job_capture(j, plan->cap)) {
+            set_error(rc, "instance %d: %s", i, std::string(fmg_last_error()).c_str());
+            plan->destroy();
+            return nullptr;
+        }
+    }
+    return plan.release();
+}
+
+int fmg_batch_plan_run(fmg_batch_plan* plan, double* const* u_out, const int64_t* u_len, fmg_result* out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!plan || !u_out || !u_len || !out) return set_error(FMG_EINVAL, "NULL argument");
+    const int count = (int)plan->jobs.size();
+    for (int i = 0; i < count; ++i) {
+        if (u_len[i] != compact_len(&plan->jobs[i].prob))
+            return set_error(FMG_EINVAL, "instance %d: u_len %lld != (n-1)^dim = %lld", i, (long long)u_len[i],
+                             (long long)compact_len(&plan->jobs[i].prob));
+        if (!u_out[i] || !is_device_pointer(u_out[i]))
+            return set_error(FMG_EINVAL, "instance %d: u_out must be device memory", i);
+    }
+    // work the caller enqueued on its stream comes first
+    FMG_HIP_CHECK(hipEventRecord(plan->uev, plan->user));
+    for (hipStream_t st : plan->str) FMG_HIP_CHECK(hipStreamWaitEvent(st, plan->uev, 0));
+    std::vector<int> rc(count, 0);
+    std::vector<char> fin(count, 0);
+    std::vector<std::chrono::steady_clock::time_point> t_done(count);
+    int left = count;
+    for (int i = 0; i < count; ++i) {
+        SolveJob& j = plan->jobs[i];
+        j.u_out = u_out[i];
+        j.u_host = nullptr;
+        if ((rc[i] = job_start(j))) {
+            fin[i] = 1;
+            --left;
+            t_done[i] = std::chrono::steady_clock::now();
+        }
+    }
+    while (left > 0) {
+        bool moved = false;
+        for (int i = 0; i < count; ++i) {
+            if (fin[i]) continue;
+            SolveJob& j = plan->jobs[i];
+            const hipError_t q = hipEventQuery(j.ev);
+            if (q == hipErrorNotReady) continue;
+            moved = true;
+            rc[i] = (q == hipSuccess) ? job_step(j) : set_error(FMG_EHIP, "event query failed");
+            if (rc[i] || j.phase == 3) {
+                fin[i] = 1;
+                --left;
+                t_done[i] = std::chrono::steady_clock::now();
+            }
+        }
+        if (!moved) std::this_thread::sleep_for(std::chrono::microseconds(5));
+    }
+    for (hipStream_t st : plan->str) FMG_HIP_CHECK(hipStreamSynchronize(st));
+    int first = 0;
+    for (int i = 0; i < count; ++i) {
+        std::memset(&out[i], 0, sizeof(out[i]));
+        int status = rc[i];
+        if (!status) status = job_result(plan->jobs[i], &out[i]);
+        out[i].status = status;
+        out[i].seconds = std::chrono::duration<double>(t_done[i] - t0).count();
+        out[i].wait_seconds = 0.0;
+        if (status && !first) {
+            first = status;
+            set_error(status, "instance %d: %s", i, std::string(fmg_last_error()).c_str());
+        }
+    }
+    return first;
+}
+
+void fmg_batch_plan_destroy(fmg_batch_plan* plan) {
+    if (!plan) return;
+    plan->destroy();
+    delete plan;
 }
 
 fmg_server* fmg_server_create(size_t hbm_budget, int32_t max_slots, void* stream) {

@@ -15,6 +15,7 @@
 // and unfused paths produce identical bits.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "dst.h"
@@ -285,8 +286,12 @@ __global__ __launch_bounds__(NT) void k_vpost2d(const T* __restrict__ y, T* __re
 // Tile shape by level: 16 x 16 on coarse levels (more workgroups, short sweeps; the halo
 // overhead is irrelevant there); on finer levels the tiles whose padded region is a whole
 // number of 256-pair rounds: post (5 halo rings) 54 x 22 -> 64 x 32 region, 4 pairs per
-// thread; pre (7 rings) 50 x 34 -> 64 x 48 region, 6 pairs per thread.
-constexpr int kSmallLevel = 256;
+// thread; pre (7 rings) 50 x 34 -> 64 x 48 region, 6 pairs per thread.  The level size
+// from which the wide tiles are used, and the largest level of the one-workgroup bottom
+// below, are run-time choices (set_vpass2d_tuning; the autotuner times them).
+constexpr int kWideMinDefault = 256, kBottomMaxDefault = 32;
+static int g_wide_min = kWideMinDefault;       // levels with n > this use the wide tiles
+static int g_bottom_max = kBottomMaxDefault;   // bottom kernel for levels with n <= this (0: off)
 #ifndef FMG_VC_PRE_TILE
 #define FMG_VC_PRE_TILE 50, 34, 256
 #define FMG_VC_POST_TILE 54, 22, 256
@@ -301,7 +306,7 @@ using PostWide = Tile<FMG_VC_POST_TILE>;
 
 template <typename T, int NH>
 void pre_launch(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc, int zero_x, hipStream_t s) {
-    if (g.n <= kSmallLevel) {
+    if (g.n <= g_wide_min) {
         dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
         hipLaunchKernelGGL((k_vpre2d<T, NH, 16, 16, 256>), grd, dim3(256), 0, s, x, y, f, rc, g, gc, zero_x);
     } else {
@@ -313,7 +318,7 @@ void pre_launch(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* 
 template <typename T, int NH>
 void post_launch(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, const T* xc, hipStream_t s,
                  hipEvent_t ev0, hipEvent_t ev1) {
-    if (g.n <= kSmallLevel) {
+    if (g.n <= g_wide_min) {
         dim3 grd(cdiv(g.n - 1, 16), cdiv(g.n - 1, 16));
         hipExtLaunchKernelGGL((k_vpost2d<T, NH, 16, 16, 256>), grd, dim3(256), 0, s, ev0, ev1, 0, y, x, f, xc, g, gc);
     } else {
@@ -338,7 +343,7 @@ void post_launch(const Grid& g, const Grid& gc, const T* y, T* x, const T* f, co
 #define FMG_BOTTOM_THREADS 512
 #endif
 #ifndef FMG_BOTTOM_MAX_N
-#define FMG_BOTTOM_MAX_N 32
+#define FMG_BOTTOM_MAX_N 64
 #endif
 constexpr int kBottomThreads = FMG_BOTTOM_THREADS;
 constexpr int kBottomMaxN = FMG_BOTTOM_MAX_N;
@@ -451,7 +456,16 @@ __global__ __launch_bounds__(kBottomThreads) void k_vbottom2d(T* __restrict__ x,
 
 }  // namespace
 
-bool vpass2d_wide_tiles(const Grid& g) { return g.n > kSmallLevel; }
+bool vpass2d_wide_tiles(const Grid& g) { return g.n > g_wide_min; }
+
+void set_vpass2d_tuning(int wide_min, int bottom_max) {
+    g_wide_min = wide_min > 0 ? wide_min : kWideMinDefault;
+    g_bottom_max = bottom_max > 0 ? std::min(bottom_max, kBottomMaxN) : (bottom_max < 0 ? 0 : kBottomMaxDefault);
+}
+void get_vpass2d_tuning(int* wide_min, int* bottom_max) {
+    *wide_min = g_wide_min;
+    *bottom_max = g_bottom_max > 0 ? g_bottom_max : -1;
+}
 
 template <typename T>
 bool launch_vpre2d(const Grid& g, const Grid& gc, const T* x, T* y, const T* f, T* rc, int nu, int zero_x,
@@ -487,7 +501,8 @@ template <typename T>
 bool launch_vbottom2d(const Grid* levels, int l, T* x, const T* f, int nu_pre, int nu_post, int zero_x,
                       hipStream_t s) {
     const int n0 = levels[0].n;
-    if (l < 1 || l >= kBottomMaxLevels || levels[l].n > kBottomMaxN || levels[l].dim != 2 || nu_pre > 2 || nu_post > 2)
+    if (l < 1 || l >= kBottomMaxLevels || levels[l].n > std::min(kBottomMaxN, g_bottom_max) || levels[l].dim != 2 ||
+        nu_pre > 2 || nu_post > 2)
         return false;
     const size_t bytes = bottom_bytes<T>(n0, l);
     if (bytes > 150 * 1024) return false;

@@ -41,7 +41,11 @@ SMALL = {
     "small_3d_nc6": W.Problem(3, 6, 2, (1.0, 1.0, 1.0), 0.0, 30.0),
     # coarsest h = 1/12 (N_H = 1331): the coarse space chosen for 3D n = 192 at large zeta
     "small_3d_nc12": W.Problem(3, 12, 1, (0.8, 1.3, 1.7), 0.0, 300.0),
+    # coarsest h = 1/16 (N_H = 3375): the coarse space chosen for 3D n = 64 and 128 at the
+    # largest zeta of the serving mix (zeta H^2 = 3.1)
+    "small_3d_nc16": W.Problem(3, 16, 1, (1.3, 0.6, 1.9), 0.0, 800.0),
 }
+BATCH4_PICKS = (62, 22)
 # Arrays too large for JSON go to compressed .npz files next to it.
 MID_2D = W.Problem(2, 16, 5, (1.0, 1.0, 0.0), 0.0, 100.0)        # n = 512
 MID_3D = W.Problem(3, 4, 5, (1.0, 1.0, 1.0), 0.0, 10.0)          # n = 128
@@ -91,7 +95,7 @@ def run(name, prob, fixed=True, samples=64):
         r = fmg.fmg(prob, opts, h)
         out["fixed_history"] = [float(x[2]) for x in r.history]
         out["fixed_lambda"] = float(r.lam)
-        out["fixed_u"] = r.u.tolist() if r.u.size <= 20000 else None
+        out["fixed_u"] = r.u.tolist() if r.u.size <= 40000 else None
     rc = fmg.converged(prob, opts, h)
     l = h.L - 1
     rng = np.random.default_rng(0)
@@ -102,16 +106,22 @@ def run(name, prob, fixed=True, samples=64):
     out["sample_u"] = rc.u[idx].tolist()
     out["norm_M"] = float(rc.u @ (h.M[l] @ rc.u))
     out["int_u4"] = float(fem.integral_of(h.meshes[l], rc.u, 4))
-    out["u_ref"] = rc.u.tolist() if rc.u.size <= 20000 else None
+    out["u_ref"] = rc.u.tolist() if rc.u.size <= 40000 else None
     out["oracle_seconds"] = time.time() - t0
     print(f"{name}: lambda_ref={rc.lam:.15f} steps={rc.steps_total} ({out['oracle_seconds']:.1f}s)", flush=True)
     return out
 
 
-def main(which):
+def main(which, only=None):
     if which == "small":
-        res = {k: run(k, p) for k, p in SMALL.items()}
         path = os.path.join(HERE, "small.json")
+        if only:
+            # recompute the named entries only, keeping the others as stored
+            res = json.load(open(path))
+            for k in only:
+                res[k] = run(k, SMALL[k])
+        else:
+            res = {k: run(k, p) for k, p in SMALL.items()}
     elif which == "mid_2d":
         run_npz("mid_2d", MID_2D)
         return
@@ -121,6 +131,23 @@ def main(which):
     elif which == "large_2d":
         res = {"large_2d": run("large_2d", W.LARGE_2D, fixed=False, samples=256)}
         path = os.path.join(HERE, "large_2d.json")
+    elif which == "batch4":
+        # two instances of the seeded batched workload (64 instances, seed 0): the largest
+        # zeta at n = 256 and at n = 512; converged lambda and u into batch4.npz
+        inst = W.batch_instances(64, 0)
+        arrays = {}
+        for k in BATCH4_PICKS:
+            t0 = time.time()
+            prob = inst[k]
+            rc = fmg.converged(prob, W.Options(), fmg.Hierarchy(prob))
+            arrays[f"u_ref_{k}"] = rc.u
+            arrays[f"lambda_ref_{k}"] = np.float64(rc.lam)
+            arrays[f"meta_{k}"] = np.array(json.dumps({"problem": dataclasses.asdict(prob), "instance": k,
+                                                       "converged_steps": int(rc.steps_total),
+                                                       "oracle_seconds": time.time() - t0}))
+            print(f"batch4_{k}: lambda_ref={rc.lam:.15f} ({time.time() - t0:.1f}s)", flush=True)
+        np.savez_compressed(os.path.join(HERE, "batch4.npz"), **arrays)
+        return
     else:
         raise SystemExit(f"unknown set {which}")
     with open(path, "w") as f:
@@ -129,4 +156,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "small")
+    main(sys.argv[1] if len(sys.argv) > 1 else "small", sys.argv[2:])

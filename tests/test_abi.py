@@ -129,6 +129,19 @@ def test_batch_validates_every_instance_before_any_work(lib):
     assert lib.fmg_batch_solve(-1, None, None, None, None, None, None) == -1
 
 
+def test_batch_plan_validates_before_any_device_work(lib):
+    from paper_1502_04657_amd import _ffi
+    assert lib.fmg_batch_plan_create(0, None, None, None) is None
+    assert b"count" in lib.fmg_last_error()
+    probs = (_ffi.fmg_problem * 1)()
+    opts = (_ffi.fmg_options * 1)()
+    probs[0].dim = 4                                   # invalid dimension
+    assert lib.fmg_batch_plan_create(1, probs, opts, None) is None
+    assert b"instance 0" in lib.fmg_last_error()
+    assert lib.fmg_batch_plan_run(None, None, None, None) == _ffi.FMG_EINVAL
+    lib.fmg_batch_plan_destroy(None)
+
+
 def test_profile_requests_are_validated(lib):
     """Unknown kinds and bad capacities are refused before any event is created, and ending
     a profile that was never begun is an error."""

@@ -146,6 +146,35 @@ def test_fused_vcycle_large_levels_bitwise(ops, nc, levels):
     assert bool(torch.isfinite(got).all())
 
 
+@pytest.mark.parametrize("nc, levels", [(8, 5), (16, 4), (12, 4), (16, 2), (10, 6)])
+@pytest.mark.parametrize("wide_min, bottom_max", [(64, 64), (128, -1), (512, 16), (0, 0)])
+def test_fused_vcycle_2d_tuning_bitwise(ops, nc, levels, wide_min, bottom_max):
+    """Every run-time choice of the 2D passes (the level from which the wide tiles are used,
+    the largest level of the one-workgroup bottom, up to n = 64) gives the bits of the
+    unfused kernel sequence."""
+    import ctypes as C
+    from paper_1502_04657_amd import _ffi, lib
+    saved = _ffi.fmg_tuning()
+    assert lib().fmg_get_tuning(C.byref(saved)) == 0
+    t = _ffi.fmg_tuning()
+    C.memmove(C.byref(t), C.byref(saved), C.sizeof(t))
+    t.vpass2d_wide_min_n, t.vbottom2d_max_n = wide_min, bottom_max
+    assert lib().fmg_set_tuning(C.byref(t)) == 0
+    n = nc << (levels - 1)
+    x0 = W.random_interior(2, n, seed=41)
+    f = W.random_interior(2, n, seed=42)
+    prob = W.Problem(2, nc, levels - 1)
+    try:
+        got = ops.vcycle(prob, W.Options(), dev_level(2, n, x0), dev_level(2, n, f))
+        lib().fmg_set_fused_vcycle(0)
+        unf = ops.vcycle(prob, W.Options(), dev_level(2, n, x0), dev_level(2, n, f))
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+        assert lib().fmg_set_tuning(C.byref(saved)) == 0
+    assert bool(torch.isfinite(got).all())
+    assert torch.equal(got, unf)
+
+
 @pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (3, 6), (5, 5), (4, 4), (4, 3), (8, 2), (2, 4)])
 @pytest.mark.parametrize("nu", [1, 2])
 @pytest.mark.parametrize("variant", [0, 1, 2])

@@ -32,7 +32,7 @@ def _solve(prob, opts):
     return Solver(prob, opts).solve()
 
 
-ALL = ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000", "small_3d_nc6", "small_3d_nc12"]
+ALL = ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000", "small_3d_nc6", "small_3d_nc12", "small_3d_nc16"]
 
 
 @pytest.mark.parametrize("name", ALL)

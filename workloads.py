@@ -91,10 +91,31 @@ def batch_instances(count: int = 64, seed: int = 0) -> list[Problem]:
     return out
 
 
+# Coarse mesh for a 3D request (Theorem 3.1 needs H small enough for the correction steps
+# to contract; the mesh n = n_c 2^k must stay nested and n_c <= 16).  Measured on the
+# anisotropic harmonic problems of the serving mix: the steps contract while
+# zeta H^2 <~ 3.5-3.9 and stall above (n_c = 6: zeta 120 converges, 150 does not;
+# n_c = 8: 200 / 250; n_c = 12: 500 / 700; n_c = 16 converges at 1000).  The rule takes
+# the smallest admissible n_c (4 <= n_c <= 16) with zeta / n_c^2 <= ZETA_H2_MAX, else the
+# largest one.
+ZETA_H2_MAX = 3.2
+
+
+def coarse_cells_3d(n: int, zeta: float) -> int:
+    """n_c for a 3D mesh with n cells per side at this zeta (see ZETA_H2_MAX)."""
+    cands = [c for c in range(4, 17) if n % c == 0 and (n // c) >= 2 and ((n // c) & (n // c - 1)) == 0]
+    if not cands:
+        raise ValueError(f"no nested coarse mesh for n = {n}")
+    for c in cands:
+        if zeta / (c * c) <= ZETA_H2_MAX:
+            return c
+    return cands[-1]
+
+
 def serving_requests(count: int, seed: int = 1, frac_2d: float = 0.7,
                      max_2d_exp: int = 11, sizes_3d=(64, 128, 192)) -> list[Problem]:
     """Mixed request stream: 70% 2D with n = 2^k, k ~ U{7..max_2d_exp} (coarsest 1/16);
-    30% 3D with n ~ U(sizes_3d) (coarsest 1/8, or 1/6 for 192);
+    30% 3D with n ~ U(sizes_3d), coarsest mesh by coarse_cells_3d(n, zeta);
     zeta log-uniform [0.1, 1000]; W = sum a_k x_k^2, a_k ~ U[0.5, 2]."""
     rng = np.random.default_rng(seed)
     out = []
@@ -106,7 +127,7 @@ def serving_requests(count: int, seed: int = 1, frac_2d: float = 0.7,
             out.append(Problem(dim=2, n_coarse=16, n_refine=k - 4, w_quad=a, zeta=zeta))
         else:
             n = int(rng.choice(list(sizes_3d)))
-            nc = 8 if n % 8 == 0 and ((n // 8) & (n // 8 - 1)) == 0 else 6   # n = nc * 2^k
+            nc = coarse_cells_3d(n, zeta)
             a = tuple(float(v) for v in rng.uniform(0.5, 2.0, size=3))
             out.append(Problem(dim=3, n_coarse=nc, n_refine=int(round(math.log2(n // nc))),
                                w_quad=a, zeta=zeta))
