@@ -367,8 +367,8 @@ def bench_batch(steps, warmup, count=64):
 
 def bench_serve(count, budget_gb, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.25)):
     """Config 5: a request stream (workloads.serving_requests, seed 1) through one server,
-    once with the real HBM budget (90 % of the free device memory, or --budget-gb) and once
-    with a 4 GB budget so that admission binds.  Per budget: saturation throughput =
+    with the real HBM budget (90 % of the free device memory, or --budget-gb) at six offered
+    rates, and with a 4 GB budget, so that admission binds, at two.  Per budget: saturation throughput =
     requests / time with all submitted at once; then Poisson arrivals (seed 2) at fractions
     of it.  Latency = submission to completion (device work observed done by the server),
     the admission wait (submission to start) reported separately; failed requests are
@@ -383,7 +383,7 @@ def bench_serve(count, budget_gb, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.25)):
         out = {}
         with Server(hbm_budget=int(budget * (1 << 30)), max_slots=16) as sv:
             t0 = time.perf_counter()
-            pending, i = {}, 0
+            pending, i, shown, last = {}, 0, 0, 0.0
             while len(out) < len(items):
                 now = time.perf_counter() - t0
                 while i < len(items) and arrivals[i] <= now:
@@ -393,6 +393,10 @@ def bench_serve(count, budget_gb, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.25)):
                     r = sv.poll(t, want_u=False, check=False)
                     if r is not None:
                         out[pending.pop(t)] = r[0]
+                # progress every 50 completions, and at least every 30 s
+                if len(out) >= shown + 50 or now - last >= 30.0:
+                    shown, last = len(out) // 50 * 50, now
+                    print(f"bench: serving {len(out)}/{len(items)} done at {now:.1f} s", file=sys.stderr, flush=True)
                 time.sleep(50e-6)
             span = time.perf_counter() - t0
         return span, [out[k] for k in range(len(items))]
@@ -416,18 +420,21 @@ def bench_serve(count, budget_gb, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.25)):
 
     run(reqs[:40], [0.0] * 40, real)   # warm-up
     budgets = []
-    for budget in (real, 4.0):
+    # the 4 GB budget (admission binds) at saturation and two rates
+    for budget, fracs in ((real, rates), (4.0, (0.5, 1.0))):
         print(f"bench: serving, budget {budget:.1f} GB, saturation", file=sys.stderr, flush=True)
         span, res = run(reqs, [0.0] * len(reqs), budget)
         sat = len(reqs) / span
         rows = [row("saturation", span, res)]
+        print("bench: row " + json.dumps(rows[-1]), file=sys.stderr, flush=True)
         rng = np.random.default_rng(2)
-        for f in rates:
+        for f in fracs:
             print(f"bench: serving, budget {budget:.1f} GB, rate {f}", file=sys.stderr, flush=True)
             gaps = rng.exponential(1.0 / (f * sat), size=len(reqs))
             arr = np.cumsum(gaps) - gaps[0]
             span, res = run(reqs, list(arr), budget)
             rows.append(row(f, span, res, f * sat))
+            print("bench: row " + json.dumps(rows[-1]), file=sys.stderr, flush=True)
         budgets.append({"hbm_budget_gb": budget, "saturation_solves_per_s": sat, "rates": rows})
     dofs = sum(p.dofs() for p in reqs)
     return {"metric": "serving: solves/s and p50/p99 latency vs offered rate (mixed precision, 1e-8 lambda)",

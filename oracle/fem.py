@@ -1,7 +1,11 @@
 """Exact P1 finite-element integration on simplices (generic element loops).
 
 Forms of the weak problem (2.2) and its discretisation (2.4):
-  a-hat(w, v) = int grad w . grad v                      (2.5), the stiffness matrix K
+  a-hat(w, v) = int A grad w . grad v                    (2.5), the stiffness matrix K; A = I
+                                                          in the examples, a constant diagonal
+                                                          SPD A = diag(a_1, .., a_d) in general
+                                                          (the framework of Section 2 allows any
+                                                          SPD coefficient)
   b(w, v)     = int w v                                   the mass matrix M
   int W w v                                               the potential part of f(x,u) (Example 4.1)
   int u^3 v                                               the cubic part of f(x,u) (Example 4.1, |u|^2 u = u^3)
@@ -101,11 +105,13 @@ def _assemble_vec(mesh: Mesh, local_fn) -> np.ndarray:
     return out
 
 
-def stiffness(mesh: Mesh) -> sp.csr_matrix:
-    """K_ab = int grad phi_a . grad phi_b  (a-hat of (2.5) with A = I)."""
+def stiffness(mesh: Mesh, diffusion=None) -> sp.csr_matrix:
+    """K_ab = int A grad phi_a . grad phi_b  (a-hat of (2.5)); A = diag(diffusion), default I."""
+    a = np.ones(mesh.dim) if diffusion is None else np.asarray(diffusion, dtype=float)[: mesh.dim]
+
     def loc(sl):
         vol, g = element_geometry(mesh.coords, mesh.elems[sl])
-        return vol[:, None, None] * np.einsum("eak,ebk->eab", g, g)
+        return vol[:, None, None] * np.einsum("eak,k,ebk->eab", g, a, g)
     return _assemble(mesh, loc)
 
 

@@ -36,7 +36,7 @@ class Hierarchy:
         self.L = L
         self.meshes = [Mesh(d, nc << l) for l in range(L)]
         self.W = fem.potential(problem.w_quad, problem.w_const)
-        self.K = [fem.stiffness(m) for m in self.meshes]
+        self.K = [fem.stiffness(m, getattr(problem, "diffusion", None)) for m in self.meshes]
         self.M = [fem.mass(m) for m in self.meshes]
         self.MW = [fem.potential_mass(m, self.W) for m in self.meshes]
         self.mg = MGHierarchy(d, nc, L, meshes=self.meshes, stiff=self.K)

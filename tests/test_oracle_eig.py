@@ -93,6 +93,36 @@ def test_linear_limit_3d():
     assert all(3.8 < err[i] / err[i + 1] < 4.3 for i in range(2))
 
 
+@pytest.mark.parametrize("dim, a, ns", [(2, (0.6, 1.7), (8, 16, 32, 64)), (3, (1.4, 0.5, 0.9), (4, 8, 16))])
+def test_anisotropic_linear_limit_is_pi_squared_times_trace(dim, a, ns):
+    """-div(A grad u) = lambda u with A = diag(a) on the unit cube: the lowest eigenvalue is
+    pi^2 (a_1 + .. + a_d), approached from above at O(h^2) by the discrete pencil; the
+    multigrid scheme reproduces the discrete value."""
+    lams = []
+    for n in ns:
+        m = Mesh(dim, n)
+        w = spla.eigsh(fem.stiffness(m, a).tocsc(), k=1, M=fem.mass(m).tocsc(), sigma=0.0, which="LM")[0]
+        lams.append(float(w[0]))
+    exact = math.pi ** 2 * sum(a)
+    err = [l - exact for l in lams]
+    assert all(e > 0 for e in err)
+    assert all(3.7 < err[i] / err[i + 1] < 4.4 for i in range(len(err) - 1))
+    p = W.Problem(dim, ns[0], 1, (0.0, 0.0, 0.0), 0.0, 0.0, tuple(a) + (1.0,) * (3 - dim))
+    r = fmg.converged(p, OPTS)
+    assert r.lam == pytest.approx(lams[1], rel=1e-11)
+
+
+def test_anisotropic_problem_scales_with_the_domain():
+    """With A = c I the problem on the unit cube is the isotropic one with W / c, zeta / c
+    and lambda / c (divide the equation by c): lambda(c A, c W, c zeta) = c lambda(A, W, zeta)."""
+    base = W.Problem(2, 8, 2, (1.0, 2.0, 0.0), 0.5, 20.0)
+    c = 2.5
+    scaled = W.Problem(2, 8, 2, (2.5, 5.0, 0.0), 1.25, 50.0, (c, c, c))
+    r0 = fmg.converged(base, OPTS)
+    r1 = fmg.converged(scaled, OPTS)
+    assert r1.lam == pytest.approx(c * r0.lam, rel=1e-11)
+
+
 @pytest.fixture(scope="module")
 def small_run():
     p = W.Problem(2, 8, 2, (1.0, 1.0, 0.0), 0.0, 10.0)

@@ -185,6 +185,37 @@ def test_3d_stiffness_and_mass_stencils():
 
 
 @pytest.mark.parametrize("dim", [2, 3])
+def test_anisotropic_stiffness_couples_axis_neighbours_only(dim):
+    """With A = diag(a): on these meshes only the axis-aligned edges carry a_d grad . grad
+    (the edge directions of a right triangle / Kuhn tetrahedron along the path of axes), so
+    the stiffness is the sum of a_d times the second-difference stencil along axis d:
+    2D  [2 (a_x + a_y); -a_x on (+-1, 0), -a_y on (0, +-1)],
+    3D  h [2 (a_x + a_y + a_z); -a_d on +-e_d].  Hand-derived closed form vs assembly."""
+    n = 6
+    a = (0.7, 1.9, 1.3)[:dim]
+    m = Mesh(dim, n)
+    K = fem.stiffness(m, a).toarray()
+    s = n - 1
+    scale = 1.0 if dim == 2 else 1.0 / n
+    i = 2 + s * 2 + (s * s * 2 if dim == 3 else 0)
+    for off in itertools.product((-1, 0, 1), repeat=dim):
+        j = i + off[0] + s * off[1] + (s * s * off[2] if dim == 3 else 0)
+        nz = [d for d in range(dim) if off[d] != 0]
+        if not nz:
+            expect = 2 * sum(a)
+        elif len(nz) == 1:
+            expect = -a[nz[0]]
+        else:
+            expect = 0.0
+        assert K[i, j] == pytest.approx(expect * scale, abs=1e-14), off
+    # A = I reproduces the isotropic matrix, and the form is linear in A
+    assert abs(fem.stiffness(m, (1.0, 1.0, 1.0)) - fem.stiffness(m)).max() == 0.0
+    b = (0.4, 0.8, 2.1)[:dim]
+    Kab = fem.stiffness(m, tuple(x + y for x, y in zip(a, b)))
+    assert abs(Kab - fem.stiffness(m, a) - fem.stiffness(m, b)).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 def test_stiffness_on_quadratic_is_exact(dim):
     """K applied to the interpolant of x_k(1-x_k) equals int 2 phi_i (= 2 h^d) at every node."""
     n = 6 if dim == 3 else 10

@@ -7,8 +7,9 @@ and the HIP path receive what it returns and compute independently.
 Problem family (Example 4.1 / 4.2 of the paper, generalised to 2D and to an
 anisotropic harmonic potential): find (lambda, u) with
 
-    -Laplace(u) + W u + zeta u^3 = lambda u  in  [0,1]^dim,  u = 0 on the boundary,
-    int u^2 = 1,        W(x) = sum_k w_quad[k] x_k^2 + w_const.
+    -div(A grad u) + W u + zeta u^3 = lambda u  in  [0,1]^dim,  u = 0 on the boundary,
+    int u^2 = 1,        W(x) = sum_k w_quad[k] x_k^2 + w_const,
+    A = diag(diffusion) (the identity in the paper's examples).
 
 Meshes are nested uniform meshes: level l (1-based) has n_l = n_coarse * 2^(l-1)
 cells per side; the finest level has n = n_coarse * 2^n_refine.
@@ -29,6 +30,7 @@ class Problem:
     w_quad: tuple = (1.0, 1.0, 1.0)
     w_const: float = 0.0
     zeta: float = 1.0
+    diffusion: tuple = (1.0, 1.0, 1.0)   # diagonal of the SPD coefficient A of a-hat (2.5)
 
     @property
     def n_fine(self) -> int:
