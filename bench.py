@@ -211,7 +211,8 @@ def oracle_check_3d():
     z = np.load(path)
     meta = json.loads(str(z["meta"]))
     p = meta["problem"]
-    prob = W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"])
+    prob = W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"],
+                     tuple(p.get("diffusion", (1.0, 1.0, 1.0))))
     lam_ref = float(z["lambda_ref"])
     u_ref = z["u_ref"]
     if meta["folded_sym3"]:
@@ -283,7 +284,7 @@ def vpost_roofline_2d(prob, steps):
     launch = 8 (3 N_l + N_{l-1}), N_l = 2047^2 fine and N_{l-1} = 1023^2 coarse interior nodes."""
     from paper_1502_04657_amd import _ffi
     p = profile_kernel(prob, W.Options(tol_lambda=TOL), _ffi.FMG_PROF_VPOST2D_F64, steps)
-    return hbm_roofline("k_vpost2d<double, 5, 54, 22, 256>", p, "k_vpost2d_f64_pmc.md", ("vcycle2d.hip",))
+    return hbm_roofline("k_vpost2d<double, 5, 54, 22, 256>", p, "fmg2d_n2048_pmc.md", ("vcycle2d.hip",))
 
 
 def copy_calibration():

@@ -50,8 +50,9 @@ enum {
 enum { FMG_FP64 = 0, FMG_MIXED = 1 };
 enum { FMG_SMOOTH_SGS = 0, FMG_SMOOTH_CG = 1 };
 
-/* The problem of Example 4.1 generalised to dim = 2, 3 and an anisotropic harmonic W.
- * (2.1), (4.1); the mesh sequence of (3.1)-(3.2).                                      */
+/* The problem of Example 4.1 generalised to dim = 2, 3, an anisotropic harmonic W and a
+ * constant diagonal SPD coefficient A in a-hat(w, v) = int A grad w . grad v ((2.1),
+ * (2.5), (4.1)); the mesh sequence of (3.1)-(3.2).                                     */
 typedef struct {
     int32_t dim;          /* 2 or 3; Omega = [0,1]^dim                                    */
     int32_t n_coarse;     /* cells per side of the coarsest mesh T_{h_1} (= T_H), >= 2    */
@@ -60,6 +61,7 @@ typedef struct {
     double  w_quad[3];    /* W(x) = sum_k w_quad[k] x_k^2 + w_const                        */
     double  w_const;
     double  zeta;         /* >= 0, coefficient of u^3                                     */
+    double  diffusion[3]; /* A = diag(diffusion[0..dim-1]), each > 0; all zero: A = I     */
 } fmg_problem;
 
 /* Algorithm 3.1 / 3.2 parameters.                                                        */

@@ -41,6 +41,9 @@ def to_c_problem(p) -> fmg_problem:
         cp.w_quad[k] = float(w[k])
     cp.w_const = float(p.w_const)
     cp.zeta = float(p.zeta)
+    a = list(getattr(p, "diffusion", (1.0, 1.0, 1.0))) + [1.0] * 3
+    for k in range(3):
+        cp.diffusion[k] = float(a[k])
     return cp
 
 

@@ -16,7 +16,8 @@ HISTORY_MAX = 512
 
 class fmg_problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_coarse", C.c_int32), ("n_refine", C.c_int32), ("reserved", C.c_int32),
-                ("w_quad", C.c_double * 3), ("w_const", C.c_double), ("zeta", C.c_double)]
+                ("w_quad", C.c_double * 3), ("w_const", C.c_double), ("zeta", C.c_double),
+                ("diffusion", C.c_double * 3)]
 
 
 class fmg_options(C.Structure):

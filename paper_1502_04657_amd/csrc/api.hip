@@ -60,12 +60,26 @@ bool is_device_pointer(const void* p) {
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// the diagonal of A (all zero in the problem: the identity)
+static void diffusion_of(const fmg_problem* p, double* a) {
+    const bool id = p->diffusion[0] == 0.0 && p->diffusion[1] == 0.0 && p->diffusion[2] == 0.0;
+    for (int k = 0; k < 3; ++k) a[k] = (id || k >= p->dim) ? 1.0 : p->diffusion[k];
+}
+
 static Phys make_phys(const fmg_problem* p) {
     Phys ph;
     for (int k = 0; k < 3; ++k) ph.w[k] = (k < p->dim) ? p->w_quad[k] : 0.0;
     ph.wc = p->w_const;
     ph.zeta = p->zeta;
+    diffusion_of(p, ph.a);
     return ph;
+}
+
+// a level of the problem's mesh sequence, with its coefficient
+static Grid problem_grid(const fmg_problem* p, int n) {
+    double a[3];
+    diffusion_of(p, a);
+    return with_diffusion(make_grid(p->dim, n), a);
 }
 
 int check_problem(const fmg_problem* p) {
@@ -82,6 +96,10 @@ int check_problem(const fmg_problem* p) {
         if (!std::isfinite(p->w_quad[k])) return set_error(FMG_EINVAL, "w_quad[%d] is not finite", k);
     if (!std::isfinite(p->w_const)) return set_error(FMG_EINVAL, "w_const is not finite");
     if (!std::isfinite(p->zeta) || p->zeta < 0.0) return set_error(FMG_EINVAL, "zeta must be finite and >= 0");
+    const bool id = p->diffusion[0] == 0.0 && p->diffusion[1] == 0.0 && p->diffusion[2] == 0.0;
+    for (int k = 0; k < p->dim && !id; ++k)
+        if (!std::isfinite(p->diffusion[k]) || !(p->diffusion[k] > 0.0))
+            return set_error(FMG_EINVAL, "diffusion[%d] must be finite and > 0 (or all zero: A = I)", k);
     return 0;
 }
 
@@ -145,7 +163,12 @@ Layout make_layout(int dim, int nc, int levels, int mixed, int cg) {
 }
 
 Layout layout_for(const fmg_problem* p, const fmg_options* o) {
-    return make_layout(p->dim, p->n_coarse, p->n_refine + 1, o->precision == FMG_MIXED, o->smoother == FMG_SMOOTH_CG);
+    Layout lo = make_layout(p->dim, p->n_coarse, p->n_refine + 1, o->precision == FMG_MIXED,
+                            o->smoother == FMG_SMOOTH_CG);
+    double a[3];
+    diffusion_of(p, a);
+    for (auto& g : lo.g) g = with_diffusion(g, a);
+    return lo;
 }
 
 template <typename T>
@@ -756,7 +779,7 @@ int fmg_unpack(int32_t dim, int32_t n, const double* lv, double* c, void* stream
 int fmg_op_rhs(const fmg_problem* prob, int32_t n, double lambda, const double* u, double* b, void* stream) {
     if (int rc = check_problem(prob)) return rc;
     if (n < 2 || !u || !b) return set_error(FMG_EINVAL, "bad rhs arguments");
-    launch_rhs(make_grid(prob->dim, n), make_phys(prob), u, b, nullptr, lambda, static_cast<hipStream_t>(stream));
+    launch_rhs(problem_grid(prob, n), make_phys(prob), u, b, nullptr, lambda, static_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "rhs launch failed");
 }
 
@@ -868,7 +891,7 @@ int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* ut, double*
     if (n < nc || n % nc || ((n / nc) & (n / nc - 1)) || !ut || !out || !scratch)
         return set_error(FMG_EINVAL, "bad moments arguments");
     if (scratch_bytes < moments_scratch_bytes(prob->dim, nc, n)) return set_error(FMG_ENOMEM, "moments scratch too small");
-    launch_moments(prob->dim, nc, make_grid(prob->dim, n), make_phys(prob), ut, static_cast<double*>(scratch), out,
+    launch_moments(prob->dim, nc, problem_grid(prob, n), make_phys(prob), ut, static_cast<double*>(scratch), out,
                    static_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "moments launch failed");
 }
@@ -957,7 +980,7 @@ int fmg_op_forms(const fmg_problem* prob, int32_t n, const double* u, double* ou
     if (n < 2 || !u || !out4 || !scratch) return set_error(FMG_EINVAL, "bad forms arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* f = static_cast<double*>(scratch);
-    launch_forms(make_grid(prob->dim, n), make_phys(prob), u, f + 8, f, s);
+    launch_forms(problem_grid(prob, n), make_phys(prob), u, f + 8, f, s);
     FMG_HIP_CHECK(hipMemcpyAsync(out4, f, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     FMG_HIP_CHECK(hipStreamSynchronize(s));
     return 0;

@@ -28,7 +28,8 @@ __device__ inline void dst_axis(const double* __restrict__ src, double* __restri
 }
 
 template <typename T>
-__device__ inline void coarse_dst_solve(const T* f, T* x, int64_t pitch, int64_t plane, int n, int D, double* sm) {
+__device__ inline void coarse_dst_solve(const T* f, T* x, int64_t pitch, int64_t plane, int n, int D, const double* aw,
+                                        double* sm) {
     const int m = n - 1;
     const int total = (D == 2) ? m * m : m * m * m;
     double* S = sm;
@@ -64,7 +65,10 @@ __device__ inline void coarse_dst_solve(const T* f, T* x, int64_t pitch, int64_t
     const double scale = (D == 2) ? (2.0 / n) * (2.0 / n) : (2.0 / n) * (2.0 / n) * (2.0 / n) * n;  // 1/h in 3D
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
         int a = t % m, r = t / m;
-        double lam = (D == 2) ? mu[a] + mu[r] : mu[a] + mu[r % m] + mu[r / m];
+        // eigenvalues of K = sum_d a_d K_d: weighted sums of the 1D eigenvalues (fused
+        // multiply-adds written out, so every caller rounds alike)
+        double lam = (D == 2) ? fma(aw[1], mu[r], aw[0] * mu[a])
+                              : fma(aw[2], mu[r / m], fma(aw[1], mu[r % m], aw[0] * mu[a]));
         cur[t] = cur[t] * scale / lam;
     }
     __syncthreads();

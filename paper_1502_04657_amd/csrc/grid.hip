@@ -85,12 +85,12 @@ void launch_unpack(const Grid& g, const double* level, double* compact, hipStrea
 // `color` ((i+j+k) % 2 == color) in row j.  The update expression is fixed so that every
 // implementation of the sweep produces identical bits.
 template <typename T>
-__device__ inline T gs2(T f, T w, T e, T s, T n) {
-    return (f + ((w + e) + (s + n))) * T(0.25);
+__device__ inline T gs2(const Stencil<T>& k, T f, T w, T e, T s, T n) {
+    return gsu2(k, f, w, e, s, n);
 }
 template <typename T>
-__device__ inline T gs3(T f, T inv_h, T w, T e, T s, T n, T b, T t) {
-    return (f * inv_h + (((w + e) + (s + n)) + (b + t))) * T(1.0 / 6.0);
+__device__ inline T gs3(const Stencil<T>& k, T f, T inv_h, T w, T e, T s, T n, T b, T t) {
+    return gsu3(k, f, inv_h, w, e, s, n, b, t);
 }
 
 template <int D, typename T>
@@ -106,11 +106,11 @@ __global__ __launch_bounds__(256) void k_smooth_half(T* __restrict__ x, const T*
     const int64_t P = g.pitch;
     if (D == 2) {
         const int64_t p = i + P * j;
-        x[p] = gs2<T>(f[p], x[p - 1], x[p + 1], x[p - P], x[p + P]);
+        x[p] = gs2<T>(stencil_of<T>(g), f[p], x[p - 1], x[p + 1], x[p - P], x[p + P]);
     } else {
         const int64_t S = g.plane;
         const int64_t p = i + P * j + S * k;
-        x[p] = gs3<T>(f[p], T(n), x[p - 1], x[p + 1], x[p - P], x[p + P], x[p - S], x[p + S]);
+        x[p] = gs3<T>(stencil_of<T>(g), f[p], T(n), x[p - 1], x[p + 1], x[p - P], x[p + P], x[p - S], x[p + S]);
     }
 }
 
@@ -140,10 +140,10 @@ template void launch_smooth<float>(const Grid&, float*, const float*, int, int, 
 // residual r = f - K x on the fine level, restricted by P^T to the coarse level:
 //   r_c(I) = r(2I) + 1/2 sum over the P1 edge neighbours d of r(2I +- d).
 template <int D, typename T>
-__device__ inline T resid_at(const T* __restrict__ x, const T* __restrict__ f, int64_t q, int64_t P, int64_t S,
-                             T h) {
-    if (D == 2) return f[q] - (T(4) * x[q] - ((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P])));
-    return f[q] - h * (T(6) * x[q] - (((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P])) + (x[q - S] + x[q + S])));
+__device__ inline T resid_at(const Stencil<T>& k, const T* __restrict__ x, const T* __restrict__ f, int64_t q,
+                             int64_t P, int64_t S, T h) {
+    if (D == 2) return kres2(k, f[q], x[q], x[q - 1], x[q + 1], x[q - P], x[q + P]);
+    return kres3(k, f[q], h, x[q], x[q - 1], x[q + 1], x[q - P], x[q + P], x[q - S], x[q + S]);
 }
 
 template <int D, typename T>
@@ -156,21 +156,22 @@ __global__ __launch_bounds__(256) void k_resid_restrict(const T* __restrict__ x,
     if (I > nc - 1 || J > nc - 1) return;
     const int64_t P = gf.pitch, S = gf.plane;
     const T h = T(gf.h);
+    const Stencil<T> kst = stencil_of<T>(gf);
     if (D == 2) {
         const int64_t p = 2 * I + P * 2 * J;
-        T c = resid_at<2, T>(x, f, p, P, S, h);
-        T e = (resid_at<2, T>(x, f, p - 1, P, S, h) + resid_at<2, T>(x, f, p + 1, P, S, h)) +
-              (resid_at<2, T>(x, f, p - P, P, S, h) + resid_at<2, T>(x, f, p + P, P, S, h)) +
-              (resid_at<2, T>(x, f, p - 1 - P, P, S, h) + resid_at<2, T>(x, f, p + 1 + P, P, S, h));
+        T c = resid_at<2, T>(kst, x, f, p, P, S, h);
+        T e = (resid_at<2, T>(kst, x, f, p - 1, P, S, h) + resid_at<2, T>(kst, x, f, p + 1, P, S, h)) +
+              (resid_at<2, T>(kst, x, f, p - P, P, S, h) + resid_at<2, T>(kst, x, f, p + P, P, S, h)) +
+              (resid_at<2, T>(kst, x, f, p - 1 - P, P, S, h) + resid_at<2, T>(kst, x, f, p + 1 + P, P, S, h));
         rc[I + gc.pitch * J] = c + T(0.5) * e;
     } else {
         const int64_t p = 2 * I + P * 2 * J + S * 2 * Kz;
         const int64_t d[7] = {1, P, S, 1 + P, P + S, 1 + S, 1 + P + S};
-        T c = resid_at<3, T>(x, f, p, P, S, h);
+        T c = resid_at<3, T>(kst, x, f, p, P, S, h);
         T e = T(0);
 #pragma unroll
         for (int q = 0; q < 7; ++q)
-            e += resid_at<3, T>(x, f, p - d[q], P, S, h) + resid_at<3, T>(x, f, p + d[q], P, S, h);
+            e += resid_at<3, T>(kst, x, f, p - d[q], P, S, h) + resid_at<3, T>(kst, x, f, p + d[q], P, S, h);
         rc[I + gc.pitch * J + gc.plane * Kz] = c + T(0.5) * e;
     }
 }
@@ -230,7 +231,7 @@ template void launch_prolong<float>(const Grid&, const Grid&, const float*, floa
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_solve(const T* __restrict__ f, T* __restrict__ x, Grid g) {
     extern __shared__ double sm[];
-    coarse_dst_solve<T>(f, x, g.pitch, g.plane, g.n, g.dim, sm);
+    coarse_dst_solve<T>(f, x, g.pitch, g.plane, g.n, g.dim, g.a, sm);
 }
 
 template <typename T>
@@ -309,7 +310,8 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
         }
         nl = u0 * (u0 * (4.0 * kStarElems2D * u0 + 3.0 * t1) + 2.0 * t2) + t3;
         Nu = nl * (h * h / 120.0);
-        Ku = 4.0 * u0 - ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P]));
+        const Stencil<double> ks = stencil_of<double>(g);
+        Ku = kdiff(ks, u0, nsum2(ks, u[p - 1], u[p + 1], u[p - P], u[p + P]));
     } else {
         // h_k(u0, a, b, c) = sum_j u0^j h_{k-j}(a, b, c), so the element term is
         // H3 + 2 u0 H2 + 3 u0^2 H1 + 4 u0^3 with H_k = h_k(a, b, c) of the element's other
@@ -329,7 +331,8 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
         }
         nl = t3 + u0 * (2.0 * t2 + u0 * (3.0 * t1 + (4.0 * kStarElems3D) * u0));
         Nu = nl * (h * h * h / 840.0);
-        Ku = h * (6.0 * u0 - (((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P])) + (u[p - S] + u[p + S])));
+        const Stencil<double> ks = stencil_of<double>(g);
+        Ku = h * kdiff(ks, u0, nsum3(ks, u[p - 1], u[p + 1], u[p - P], u[p + P], u[p - S], u[p + S]));
     }
 }
 
@@ -370,11 +373,12 @@ __global__ __launch_bounds__(256) void k_residual_demote(const double* __restric
     if (i > n - 1 || j > n - 1) return;
     const int64_t P = g.pitch, S = g.plane;
     const int64_t p = i + P * j + S * k;
+    const Stencil<double> ks = stencil_of<double>(g);
     double ku;
     if (D == 2)
-        ku = 4.0 * u[p] - ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P]));
+        ku = kdiff(ks, u[p], nsum2(ks, u[p - 1], u[p + 1], u[p - P], u[p + P]));
     else
-        ku = g.h * (6.0 * u[p] - (((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P])) + (u[p - S] + u[p + S])));
+        ku = g.h * kdiff(ks, u[p], nsum3(ks, u[p - 1], u[p + 1], u[p - P], u[p + P], u[p - S], u[p + S]));
     r[p] = (float)(b[p] - ku);
 }
 
@@ -553,9 +557,9 @@ void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partia
 // device, so the host only enqueues.  rr = 0 makes alpha = beta = 0 (x stays put, as an
 // exact solve would leave it).
 template <int D, typename T>
-__device__ inline T apply_K(const T* __restrict__ x, int64_t q, int64_t P, int64_t S, T h) {
-    if (D == 2) return T(4) * x[q] - ((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P]));
-    return h * (T(6) * x[q] - (((x[q - 1] + x[q + 1]) + (x[q - P] + x[q + P])) + (x[q - S] + x[q + S])));
+__device__ inline T apply_K(const Stencil<T>& k, const T* __restrict__ x, int64_t q, int64_t P, int64_t S, T h) {
+    if (D == 2) return kdiff(k, x[q], nsum2(k, x[q - 1], x[q + 1], x[q - P], x[q + P]));
+    return h * kdiff(k, x[q], nsum3(k, x[q - 1], x[q + 1], x[q - P], x[q + P], x[q - S], x[q + S]));
 }
 
 template <int D>
@@ -611,7 +615,7 @@ __global__ __launch_bounds__(256) void k_cg_start(const T* __restrict__ x, const
     double acc = 0.0;
     CG_NODES(D, g) {
         const int64_t q = interior_node<D>(g, t_);
-        const T v = resid_at<D, T>(x, f, q, g.pitch, g.plane, T(g.h));
+        const T v = resid_at<D, T>(stencil_of<T>(g), x, f, q, g.pitch, g.plane, T(g.h));
         r[q] = v;
         p[q] = v;
         acc += (double)v * (double)v;
@@ -626,7 +630,7 @@ __global__ __launch_bounds__(256) void k_cg_apply(const T* __restrict__ p, T* __
     double acc = 0.0;
     CG_NODES(D, g) {
         const int64_t q = interior_node<D>(g, t_);
-        const T v = apply_K<D, T>(p, q, g.pitch, g.plane, T(g.h));
+        const T v = apply_K<D, T>(stencil_of<T>(g), p, q, g.pitch, g.plane, T(g.h));
         qv[q] = v;
         acc += (double)p[q] * (double)v;
     }

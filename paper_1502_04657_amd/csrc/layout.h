@@ -6,7 +6,7 @@
 //   T1[p]   = int_E u~^3 l_p                           T0     = int_E u~^4
 //   B1[p]   = int_E u~ l_p                             B2     = int_E u~^2
 //   AW1[p]  = int_E W u~ l_p                           AW2    = int_E W u~^2
-//   KG[p]   = int_E grad u~ . grad l_p                 Q      = int_E |grad u~|^2
+//   KG[p]   = int_E A grad u~ . grad l_p               Q      = int_E A grad u~ . grad u~
 // which is everything the augmented matrices of (3.6) need beyond the coarse matrices.
 #pragma once
 

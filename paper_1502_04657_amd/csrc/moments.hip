@@ -203,11 +203,11 @@ __device__ __forceinline__ void simplex_cubic_quartic(const double* uc, const do
 
 // Local moments of the cell with corner values uc[] (unit cell), accumulated into L1 (deg
 // <= 3), L2 (deg <= 2), L3 (deg <= 1), L4 and the gradient sums G (int d u~/dY_d), Q
-// (int |grad_Y u~|^2).  WHOLE: all fine simplices of the cell; otherwise the fine simplices
+// (int grad_Y u~ . A grad_Y u~, A = diag(aw)).  WHOLE: all fine simplices of the cell; otherwise the fine simplices
 // of the cell at coarse-local offset a[] that belong to coarse simplex `type`.
 template <int D, bool WHOLE>
-__device__ __forceinline__ void cell_moments(const double* uc, const int* a, int type, double* L1, double* L2,
-                                             double* L3, double& L4, double* G, double& Q) {
+__device__ __forceinline__ void cell_moments(const double* uc, const int* a, int type, const double* aw, double* L1,
+                                             double* L2, double* L3, double& L4, double* G, double& Q) {
     using M = Mono<D>;
     constexpr int V = D + 1;
     constexpr int NF = (D == 2) ? 2 : 6;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
                 });
             });
             double g2 = 0.0;
-            static_for<D>([&](auto d) { g2 += g[d] * g[d]; });
+            static_for<D>([&](auto d) { g2 += aw[d] * g[d] * g[d]; });
             Q += vs * g2;
         });
         L3[0] += k3 * s3;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
                 G[d] += vs * g[d];
             });
             double g2 = 0.0;
-            static_for<D>([&](auto d) { g2 += g[d] * g[d]; });
+            static_for<D>([&](auto d) { g2 += aw[d] * g[d] * g[d]; });
             Q += vs * g2;
         });
         L3[0] += k3 * s3;
@@ -389,23 +389,24 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
 #pragma unroll
     for (int q = 0; q < R::SIZE; ++q) acc[q] = 0.0;
 
-    for (int64_t idx = start + threadIdx.x; idx < end; idx += blockDim.x) {
-        int a[3];
-        if (ties) tie_cell<D>(idx, type, s, a);
-        else interior_cell<D>(idx, type, a);
-        const int64_t base = (C[0] * s + a[0]) + P * (C[1] * s + a[1]) + S * (D == 3 ? C[2] * s + a[2] : 0);
-        double uc[NC];
+    // decode cell id of this block's group and load its corner values
+    auto fetch = [&](int64_t id, int* aa, double* u) {
+        if (ties) tie_cell<D>(id, type, s, aa);
+        else interior_cell<D>(id, type, aa);
+        const int64_t base = (C[0] * s + aa[0]) + P * (C[1] * s + aa[1]) + S * (D == 3 ? C[2] * s + aa[2] : 0);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) uc[c] = ut[base + (c & 1) + P * ((c >> 1) & 1) + S * ((c >> 2) & 1)];
+        for (int c = 0; c < NC; ++c) u[c] = ut[base + (c & 1) + P * ((c >> 1) & 1) + S * ((c >> 2) & 1)];
+    };
+    auto process = [&](const int* a, const double* uc) {
         double L1[M::NM], L2[M::N2], L3[M::N1], L4 = 0.0, G[D], Q = 0.0;
         static_for<M::NM>([&](auto q) { L1[q] = 0.0; });
         static_for<M::N2>([&](auto q) { L2[q] = 0.0; });
         static_for<M::N1>([&](auto q) { L3[q] = 0.0; });
         static_for<D>([&](auto d) { G[d] = 0.0; });
         if (!ties)
-            cell_moments<D, true>(uc, a, type, L1, L2, L3, L4, G, Q);
+            cell_moments<D, true>(uc, a, type, g.a, L1, L2, L3, L4, G, Q);
         else
-            cell_moments<D, false>(uc, a, type, L1, L2, L3, L4, G, Q);
+            cell_moments<D, false>(uc, a, type, g.a, L1, L2, L3, L4, G, Q);
         const double A[3] = {(double)a[0], (double)a[1], (double)a[2]};
         shift_moments<D, M::NM>(L1, A);
         shift_moments<D, M::N2>(L2, A);
@@ -416,6 +417,12 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
         acc[R::P4] += L4;
         static_for<D>([&](auto d) { acc[R::G + d] += G[d]; });
         acc[R::Q] += Q;
+    };
+    for (int64_t idx = start + threadIdx.x; idx < end; idx += blockDim.x) {
+        int a[3];
+        double uc[NC];
+        fetch(idx, a, uc);
+        process(a, uc);
     }
     // block reduction (fixed order), then the scales: unit cells -> h^D, (A + Y)^b -> X^b = s^-|b|,
     // d/dY -> h d/dx
@@ -537,7 +544,7 @@ __global__ __launch_bounds__(64) void k_moments_final(const double* __restrict__
         static_for<NM>([&](auto m) { sw += t1[m] * raw[R::P1 + m]; });
         o[L::AW1 + p] = sw;
         double kg = 0.0;
-        static_for<D>([&](auto d) { kg += lam[p][1 + d] / H * raw[R::G + d]; });
+        static_for<D>([&](auto d) { kg += ph.a[d] * (lam[p][1 + d] / H) * raw[R::G + d]; });
         o[L::KG + p] = kg;
     });
     o[L::T0] = raw[R::P4];

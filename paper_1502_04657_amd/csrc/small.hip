@@ -335,11 +335,14 @@ __device__ __forceinline__ void stencil_ab(const double* X, double H, double Hd,
     constexpr int o1 = (Off<D, S, 0>::value < 0 ? -Off<D, S, 0>::value : Off<D, S, 0>::value) +
                        (Off<D, S, 1>::value < 0 ? -Off<D, S, 1>::value : Off<D, S, 1>::value) +
                        (D == 3 ? (Off<D, S, 2>::value < 0 ? -Off<D, S, 2>::value : Off<D, S, 2>::value) : 0);
+    // the stiffness couples axis neighbours only: diag = 2 sum a_d, -a_d along axis d
+    constexpr int ax1 = Off<D, S, 0>::value != 0 ? 0 : (Off<D, S, 1>::value != 0 ? 1 : 2);
+    const double dg = (D == 2) ? 2.0 * (ph.a[0] + ph.a[1]) : 2.0 * ((ph.a[0] + ph.a[1]) + ph.a[2]);
     double kk;
     if (D == 2)
-        kk = (o1 == 0) ? 4.0 : (o1 == 1 ? -1.0 : 0.0);
+        kk = (o1 == 0) ? dg : (o1 == 1 ? -ph.a[ax1] : 0.0);
     else
-        kk = (o1 == 0) ? 6.0 * H : (o1 == 1 ? -H : 0.0);
+        kk = (o1 == 0) ? dg * H : (o1 == 1 ? -ph.a[ax1] * H : 0.0);
     a = kk + Hd * cw;
     b = Hd * m0;
 }

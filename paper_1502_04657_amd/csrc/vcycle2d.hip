@@ -26,8 +26,8 @@ namespace fmg {
 namespace {
 
 template <typename T>
-__device__ inline T gs2f(T f, T w, T e, T s, T n) {
-    return (f + ((w + e) + (s + n))) * T(0.25);
+__device__ inline T gs2f(const Stencil<T>& k, T f, T w, T e, T s, T n) {
+    return gsu2(k, f, w, e, s, n);
 }
 
 // The LDS region of a workgroup: its TX x TY tile plus HALO rings, RW x RH nodes, region
@@ -60,6 +60,7 @@ struct Planes {
     static constexpr int PL = Rg::RH * Rg::HP;
     T* x;
     int base;   // colour of region node (0, 0)
+    Stencil<T> k;   // the level's stiffness stencil
     __device__ T& at(int c, int r) const { return x[((c + r + base) & 1) * PL + r * Rg::HP + (c >> 1)]; }
     __device__ T& plane(int k, int r, int slot) const { return x[k * PL + r * Rg::HP + slot]; }
 };
@@ -97,8 +98,8 @@ __device__ inline void half_sweep(const Planes<T, TX, TY, HALO, NT>& X, const Pa
             // node (c + sel, r) has colour col; its four neighbours have the other colour:
             // W, E in this row at slots pc - 1 + sel, pc + sel; S, N at slot pc of rows r -+ 1
             const int o = col ^ 1, pc = c >> 1;
-            X.plane(col, r, pc) = gs2f<T>(sel ? fb[k] : fa[k], X.plane(o, r, pc - 1 + sel), X.plane(o, r, pc + sel),
-                                          X.plane(o, r - 1, pc), X.plane(o, r + 1, pc));
+            X.plane(col, r, pc) = gs2f<T>(X.k, sel ? fb[k] : fa[k], X.plane(o, r, pc - 1 + sel),
+                                          X.plane(o, r, pc + sel), X.plane(o, r - 1, pc), X.plane(o, r + 1, pc));
         }
     }
     __syncthreads();
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(NT) void k_vpre2d(const T* __restrict__ x, T* __res
     __shared__ T xs[2 * Rg::RH * Rg::HP];
     const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
     const int n = g.n;
-    const Planes<T, TX, TY, HALO, NT> X{xs, (i0 + j0) & 1};
+    const Planes<T, TX, TY, HALO, NT> X{xs, (i0 + j0) & 1, stencil_of<T>(g)};
     T xa[Rg::K], xb[Rg::K], fa[Rg::K], fb[Rg::K];
     load_pairs<T, TX, TY, HALO, NT>(xa, xb, fa, fb, x, f, g, i0, j0, zero_x);
     put_pairs<T, TX, TY, HALO, NT>(X, xa, xb, i0, j0);
@@ -201,10 +202,10 @@ __global__ __launch_bounds__(NT) void k_vpre2d(const T* __restrict__ x, T* __res
         pair_coords<TX, TY, HALO, NT>(k, i0, j0, c, r, gi, gj, valid);
         if (!valid || gj < ja || gj > jb) continue;
         if (gi >= ia && gi <= ib && interior(gi, gj, n))
-            fa[k] = fa[k] - (T(4) * X.at(c, r) - ((X.at(c - 1, r) + X.at(c + 1, r)) + (X.at(c, r - 1) + X.at(c, r + 1))));
+            fa[k] = kres2(X.k, fa[k], X.at(c, r), X.at(c - 1, r), X.at(c + 1, r), X.at(c, r - 1), X.at(c, r + 1));
         if (gi + 1 >= ia && gi + 1 <= ib && interior(gi + 1, gj, n))
-            fb[k] = fb[k] - (T(4) * X.at(c + 1, r) -
-                             ((X.at(c, r) + X.at(c + 2, r)) + (X.at(c + 1, r - 1) + X.at(c + 1, r + 1))));
+            fb[k] = kres2(X.k, fb[k], X.at(c + 1, r), X.at(c, r), X.at(c + 2, r), X.at(c + 1, r - 1),
+                          X.at(c + 1, r + 1));
     }
     __syncthreads();
     put_pairs<T, TX, TY, HALO, NT>(X, fa, fb, i0, j0);   // the residuals replace x in LDS
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(NT) void k_vpost2d(const T* __restrict__ y, T* __re
             else xa[k] += v;
         }
     }
-    const Planes<T, TX, TY, HALO, NT> X{xs, (i0 + j0) & 1};
+    const Planes<T, TX, TY, HALO, NT> X{xs, (i0 + j0) & 1, stencil_of<T>(g)};
     put_pairs<T, TX, TY, HALO, NT>(X, xa, xb, i0, j0);
     __syncthreads();
     half_sweeps_seq<T, TX, TY, HALO, NT, NH, R>(X, fa, fb, i0, j0, n, std::make_integer_sequence<int, NH>{});
@@ -373,7 +374,7 @@ inline size_t bottom_bytes(int n0, int l) {
 
 // nh alternating half sweeps, colour 0 first, of x <- (f + sum of the 4 neighbours) / 4
 template <typename T>
-__device__ inline void bottom_sweeps(T* X, const T* F, int n, int nh) {
+__device__ inline void bottom_sweeps(const Stencil<T>& k, T* X, const T* F, int n, int nh) {
     const int P = n + 1, half = n / 2;
     for (int h = 0; h < nh; ++h) {
         const int c = h & 1;
@@ -382,21 +383,22 @@ __device__ inline void bottom_sweeps(T* X, const T* F, int n, int nh) {
             const int i = (((1 + j) & 1) == c ? 1 : 2) + 2 * slot;
             if (i > n - 1) continue;
             const int p = i + P * j;
-            X[p] = gs2f<T>(F[p], X[p - 1], X[p + 1], X[p - P], X[p + P]);
+            X[p] = gs2f<T>(k, F[p], X[p - 1], X[p + 1], X[p - P], X[p + P]);
         }
         __syncthreads();
     }
 }
 
 template <typename T>
-__device__ inline T bottom_resid(const T* X, const T* F, int p, int P) {
-    return F[p] - (T(4) * X[p] - ((X[p - 1] + X[p + 1]) + (X[p - P] + X[p + P])));
+__device__ inline T bottom_resid(const Stencil<T>& k, const T* X, const T* F, int p, int P) {
+    return kres2(k, F[p], X[p], X[p - 1], X[p + 1], X[p - P], X[p + P]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBottomThreads) void k_vbottom2d(T* __restrict__ x, const T* __restrict__ f, Grid g,
                                                               int n0, int l, int nh_pre, int nh_post, int zero_x) {
     extern __shared__ double smem[];
+    const Stencil<T> kst = stencil_of<T>(g);   // the coefficient is the same on every level
     // level arrays addressed as offsets from the LDS base (so every access stays an LDS access)
     T* const base = reinterpret_cast<T*>(smem);
     auto X = [&](int q) { return base + bottom_off(n0, q); };
@@ -415,22 +417,22 @@ __global__ __launch_bounds__(kBottomThreads) void k_vbottom2d(T* __restrict__ x,
     // down: pre sweeps, then f_{q-1} = P^T (f_q - K x_q)
     for (int q = l; q >= 1; --q) {
         const int nq = n0 << q, Pq = nq + 1, nc = nq / 2, Pc = nc + 1;
-        bottom_sweeps<T>(X(q), F(q), nq, nh_pre);
+        bottom_sweeps<T>(kst, X(q), F(q), nq, nh_pre);
         const T* Xq = X(q);
         const T* Fq = F(q);
         T* Fc = F(q - 1);
         for (int t = threadIdx.x; t < (nc - 1) * (nc - 1); t += blockDim.x) {
             const int I = 1 + t % (nc - 1), J = 1 + t / (nc - 1);
             const int p = 2 * I + Pq * 2 * J;
-            T c = bottom_resid<T>(Xq, Fq, p, Pq);
-            T e = (bottom_resid<T>(Xq, Fq, p - 1, Pq) + bottom_resid<T>(Xq, Fq, p + 1, Pq)) +
-                  (bottom_resid<T>(Xq, Fq, p - Pq, Pq) + bottom_resid<T>(Xq, Fq, p + Pq, Pq)) +
-                  (bottom_resid<T>(Xq, Fq, p - 1 - Pq, Pq) + bottom_resid<T>(Xq, Fq, p + 1 + Pq, Pq));
+            T c = bottom_resid<T>(kst, Xq, Fq, p, Pq);
+            T e = (bottom_resid<T>(kst, Xq, Fq, p - 1, Pq) + bottom_resid<T>(kst, Xq, Fq, p + 1, Pq)) +
+                  (bottom_resid<T>(kst, Xq, Fq, p - Pq, Pq) + bottom_resid<T>(kst, Xq, Fq, p + Pq, Pq)) +
+                  (bottom_resid<T>(kst, Xq, Fq, p - 1 - Pq, Pq) + bottom_resid<T>(kst, Xq, Fq, p + 1 + Pq, Pq));
             Fc[I + Pc * J] = c + T(0.5) * e;
         }
         __syncthreads();
     }
-    coarse_dst_solve<T>(F(0), X(0), n0 + 1, 0, n0, 2, dsm);
+    coarse_dst_solve<T>(F(0), X(0), n0 + 1, 0, n0, 2, g.a, dsm);
     __syncthreads();
     // up: x_q += P x_{q-1}, then the post sweeps
     for (int q = 1; q <= l; ++q) {
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_vbottom2d(T* __restrict__ x,
             Xq[i + Pq * j] += v;
         }
         __syncthreads();
-        bottom_sweeps<T>(Xq, F(q), nq, nh_post);
+        bottom_sweeps<T>(kst, Xq, F(q), nq, nh_post);
     }
     for (int t = threadIdx.x; t < (n - 1) * (n - 1); t += blockDim.x) {
         const int i = 1 + t % (n - 1), j = 1 + t / (n - 1);

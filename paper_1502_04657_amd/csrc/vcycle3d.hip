@@ -80,8 +80,8 @@ __device__ __forceinline__ void masked_store(T v, __amdgpu_buffer_rsrc_t r, unsi
 }
 
 template <typename T>
-__device__ inline T gs3f(T f, T inv_h, T w, T e, T s, T n, T b, T t) {
-    return (f * inv_h + (((w + e) + (s + n)) + (b + t))) * T(1.0 / 6.0);
+__device__ inline T gs3f(const Stencil<T>& k, T f, T inv_h, T w, T e, T s, T n, T b, T t) {
+    return gsu3(k, f, inv_h, w, e, s, n, b, t);
 }
 
 template <int NS, int MODE, int TX, int TY>
@@ -190,6 +190,7 @@ struct Pass3 {
                                 const Grid& g, const Grid& gc) {
         const int n = cx.n, i0 = cx.i0, j0 = cx.j0, z0 = cx.z0, z1 = cx.z1, base = cx.base;
         const T inv_h = T(n), h = T(g.h);
+        const Stencil<T> kst = stencil_of<T>(g);
         auto lslot = [](int p) { return ((p % W) + W) % W; };
         // ---- plane t (loaded D steps earlier) into the window
         if (t >= cx.tfirst && t <= z1 - 1 + G) {
@@ -242,7 +243,7 @@ struct Pass3 {
                 const T sv = Xo[(r - 1) * HP + m], nv = Xo[(r + 1) * HP + m];
                 const T bv = xs[sd][o * HALF + r * HP + m], tv = xs[su][o * HALF + r * HP + m];
                 const T fv = pick(fw[fs][k][0], fw[fs][k][1], sel);
-                xs[sl][col * HALF + r * HP + m] = gs3f<T>(fv, inv_h, wv, ev, sv, nv, bv, tv);
+                xs[sl][col * HALF + r * HP + m] = gs3f<T>(kst, fv, inv_h, wv, ev, sv, nv, bv, tv);
             }
         });
         // ---- output: plane t - NS of the tile (lanes off the tile or steps off the chunk
@@ -292,9 +293,9 @@ struct Pass3 {
                             T v = T(0);
                             if (gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1) {
                                 const T fv = pick(fw[fs][k][0], fw[fs][k][1], k0 ^ cc);
-                                v = fv - h * (T(6) * X(sl, c, r, p) - (((X(sl, c - 1, r, p) + X(sl, c + 1, r, p)) +
-                                                                        (X(sl, c, r - 1, p) + X(sl, c, r + 1, p))) +
-                                                                       (X(sd, c, r, p - 1) + X(su, c, r, p + 1))));
+                                v = kres3(kst, fv, h, X(sl, c, r, p), X(sl, c - 1, r, p), X(sl, c + 1, r, p),
+                                          X(sl, c, r - 1, p), X(sl, c, r + 1, p), X(sd, c, r, p - 1),
+                                          X(su, c, r, p + 1));
                             }
                             R[(r - (G - 1)) * RRX + (c - (G - 1))] = v;
                         });
@@ -422,7 +423,7 @@ size_t b3_bytes(int n0, int l) {
 
 // nh alternating half sweeps, colour 0 first
 template <typename T>
-__device__ void b3_sweeps(T* X, const T* F, int n, int nh) {
+__device__ void b3_sweeps(const Stencil<T>& kst, T* X, const T* F, int n, int nh) {
     const int P = n + 1, S = P * P, half = n / 2, m = n - 1;
     const T inv_h = T(n);
     for (int hs = 0; hs < nh; ++hs) {
@@ -433,21 +434,22 @@ __device__ void b3_sweeps(T* X, const T* F, int n, int nh) {
             const int i = (((1 + j + k) & 1) == c ? 1 : 2) + 2 * slot;
             if (i > m) continue;
             const int p = i + P * j + S * k;
-            X[p] = gs3f<T>(F[p], inv_h, X[p - 1], X[p + 1], X[p - P], X[p + P], X[p - S], X[p + S]);
+            X[p] = gs3f<T>(kst, F[p], inv_h, X[p - 1], X[p + 1], X[p - P], X[p + P], X[p - S], X[p + S]);
         }
         __syncthreads();
     }
 }
 
 template <typename T>
-__device__ inline T b3_resid(const T* X, const T* F, int q, int P, int S, T h) {
-    return F[q] - h * (T(6) * X[q] - (((X[q - 1] + X[q + 1]) + (X[q - P] + X[q + P])) + (X[q - S] + X[q + S])));
+__device__ inline T b3_resid(const Stencil<T>& kst, const T* X, const T* F, int q, int P, int S, T h) {
+    return kres3(kst, F[q], h, X[q], X[q - 1], X[q + 1], X[q - P], X[q + P], X[q - S], X[q + S]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBottom3Threads) void k_vbottom3d(T* __restrict__ x, const T* __restrict__ f, Grid g,
                                                                int n0, int l, int nh_pre, int nh_post, int zero_x) {
     extern __shared__ double smem[];
+    const Stencil<T> kst = stencil_of<T>(g);   // the coefficient is the same on every level
     T* const base = reinterpret_cast<T*>(smem);
     auto X = [&](int q) { return base + b3_off(n0, q); };
     auto F = [&](int q) { return base + b3_off(n0, q) + b3_elems(n0, q); };
@@ -467,7 +469,7 @@ __global__ __launch_bounds__(kBottom3Threads) void k_vbottom3d(T* __restrict__ x
     for (int q = l; q >= 1; --q) {
         const int nq = n0 << q, Pq = nq + 1, Sq = Pq * Pq, nc = nq / 2, Pc = nc + 1, mc = nc - 1;
         const T hq = T(1.0 / nq);
-        b3_sweeps<T>(X(q), F(q), nq, nh_pre);
+        b3_sweeps<T>(kst, X(q), F(q), nq, nh_pre);
         const T* Xq = X(q);
         const T* Fq = F(q);
         T* Fc = F(q - 1);
@@ -475,16 +477,16 @@ __global__ __launch_bounds__(kBottom3Threads) void k_vbottom3d(T* __restrict__ x
         for (int t = threadIdx.x; t < mc * mc * mc; t += blockDim.x) {
             const int I = 1 + t % mc, J = 1 + (t / mc) % mc, K = 1 + t / (mc * mc);
             const int p = 2 * I + Pq * 2 * J + Sq * 2 * K;
-            const T c = b3_resid<T>(Xq, Fq, p, Pq, Sq, hq);
+            const T c = b3_resid<T>(kst, Xq, Fq, p, Pq, Sq, hq);
             T e = T(0);
 #pragma unroll
             for (int r = 0; r < 7; ++r)
-                e += b3_resid<T>(Xq, Fq, p - d[r], Pq, Sq, hq) + b3_resid<T>(Xq, Fq, p + d[r], Pq, Sq, hq);
+                e += b3_resid<T>(kst, Xq, Fq, p - d[r], Pq, Sq, hq) + b3_resid<T>(kst, Xq, Fq, p + d[r], Pq, Sq, hq);
             Fc[I + Pc * J + Pc * Pc * K] = c + T(0.5) * e;
         }
         __syncthreads();
     }
-    coarse_dst_solve<T>(F(0), X(0), n0 + 1, (int64_t)(n0 + 1) * (n0 + 1), n0, 3, dsm);
+    coarse_dst_solve<T>(F(0), X(0), n0 + 1, (int64_t)(n0 + 1) * (n0 + 1), n0, 3, g.a, dsm);
     __syncthreads();
     // up: x_q += P x_{q-1}, then the post sweeps
     for (int q = 1; q <= l; ++q) {
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(kBottom3Threads) void k_vbottom3d(T* __restrict__ x
             Xq[i + Pq * j + Sq * k] += v;
         }
         __syncthreads();
-        b3_sweeps<T>(Xq, F(q), nq, nh_post);
+        b3_sweeps<T>(kst, Xq, F(q), nq, nh_post);
     }
     const int m = n - 1;
     for (int t = threadIdx.x; t < m * m * m; t += blockDim.x) {

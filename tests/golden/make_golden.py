@@ -44,6 +44,9 @@ SMALL = {
     # coarsest h = 1/16 (N_H = 3375): the coarse space chosen for 3D n = 64 and 128 at the
     # largest zeta of the serving mix (zeta H^2 = 3.1)
     "small_3d_nc16": W.Problem(3, 16, 1, (1.3, 0.6, 1.9), 0.0, 800.0),
+    # a constant diagonal coefficient A = diag(diffusion) in a-hat (2.5)
+    "small_2d_aniso": W.Problem(2, 8, 3, (1.2, 0.7, 0.0), 0.3, 40.0, (0.6, 1.7, 1.0)),
+    "small_3d_aniso": W.Problem(3, 4, 2, (0.9, 1.3, 1.1), 0.0, 25.0, (1.4, 0.5, 0.9)),
 }
 BATCH4_PICKS = (62, 22)
 # Arrays too large for JSON go to compressed .npz files next to it.

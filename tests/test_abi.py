@@ -129,6 +129,23 @@ def test_batch_validates_every_instance_before_any_work(lib):
     assert lib.fmg_batch_solve(-1, None, None, None, None, None, None) == -1
 
 
+def test_diffusion_coefficient_is_validated(lib):
+    """A = diag(diffusion): each entry finite and > 0, or all zero (the identity)."""
+    from paper_1502_04657_amd import _ffi, to_c_problem, to_c_options
+    o = to_c_options(W.Options())
+    nb = C.c_size_t()
+    for a, ok in (((1.0, 2.0, 0.5), True), ((0.0, 0.0, 0.0), True), ((1.0, -1.0, 1.0), False),
+                  ((1.0, float("nan"), 1.0), False), ((0.0, 1.0, 1.0), False)):
+        p = to_c_problem(W.Problem(2, 8, 2))
+        for k in range(3):
+            p.diffusion[k] = a[k]
+        rc = lib.fmg_workspace_bytes(C.byref(p), C.byref(o), C.byref(nb))
+        assert (rc == 0) == ok, a
+    # the third entry is ignored in 2D
+    p = to_c_problem(W.Problem(2, 8, 2, diffusion=(1.0, 2.0, -5.0)))
+    assert lib.fmg_workspace_bytes(C.byref(p), C.byref(o), C.byref(nb)) == 0
+
+
 def test_batch_plan_validates_before_any_device_work(lib):
     from paper_1502_04657_amd import _ffi
     assert lib.fmg_batch_plan_create(0, None, None, None) is None

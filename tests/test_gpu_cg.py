@@ -72,7 +72,8 @@ def test_fixed_schedule_with_cg_smoother_matches_oracle(prob):
 def test_converged_with_cg_smoother(precision):
     rec = GOLD["small_2d"]
     p = rec["problem"]
-    prob = W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"])
+    prob = W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"],
+                     tuple(p.get("diffusion", (1.0, 1.0, 1.0))))
     from paper_1502_04657_amd import Solver
     res, _ = Solver(prob, W.Options(tol_lambda=1e-13, max_final_steps=200, precision=precision, **CG)).solve()
     assert res.status == 0

@@ -27,7 +27,8 @@ def _load(name):
     z = np.load(path)
     meta = json.loads(str(z["meta"]))
     p = meta["problem"]
-    prob = W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"])
+    prob = W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"],
+                     tuple(p.get("diffusion", (1.0, 1.0, 1.0))))
     unfold = (lambda v: _unfold_sym3(prob.n_fine, v)) if meta["folded_sym3"] else (lambda v: v)
     return prob, z["fixed_history"], unfold(z["fixed_u"]), float(z["lambda_ref"]), unfold(z["u_ref"])
 

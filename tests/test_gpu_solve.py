@@ -24,7 +24,8 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "small.j
 
 def _problem(rec):
     p = rec["problem"]
-    return W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"])
+    return W.Problem(p["dim"], p["n_coarse"], p["n_refine"], tuple(p["w_quad"]), p["w_const"], p["zeta"],
+                     tuple(p.get("diffusion", (1.0, 1.0, 1.0))))
 
 
 def _solve(prob, opts):
@@ -32,7 +33,8 @@ def _solve(prob, opts):
     return Solver(prob, opts).solve()
 
 
-ALL = ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000", "small_3d_nc6", "small_3d_nc12", "small_3d_nc16"]
+ALL = ["small_2d", "small_2d_z100", "small_3d", "small_2d_z1000", "small_3d_nc6", "small_3d_nc12", "small_3d_nc16",
+       "small_2d_aniso", "small_3d_aniso"]
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -163,3 +165,38 @@ def test_host_output_and_library_allocated_workspace_match_device_solve():
     u_ah = torch.zeros(s.ndof, dtype=torch.float64)
     r_ah, _ = solve_alloc(prob, opts, u_out=u_ah)
     assert torch.equal(u_ah, u_dev.cpu())
+
+
+@pytest.mark.parametrize("name", ["small_2d_aniso", "small_3d_aniso"])
+def test_anisotropic_unfused_path_matches_oracle(name):
+    """The unfused kernel sequence (every level) with A = diag(a) against the oracle's
+    fixed schedule, step by step."""
+    from paper_1502_04657_amd import lib
+    rec = GOLD[name]
+    prob = _problem(rec)
+    lib().fmg_set_fused_vcycle(0)
+    try:
+        res, _ = _solve(prob, W.Options())
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+    for a, b in zip(res.history, rec["fixed_history"]):
+        assert a == pytest.approx(b, rel=1e-11)
+
+
+@pytest.mark.parametrize("prob", [W.Problem(2, 16, 5, (1.0, 0.6, 0.0), 0.0, 80.0, (0.7, 1.6, 1.0)),
+                                  W.Problem(3, 4, 5, (1.2, 0.8, 1.0), 0.0, 10.0, (1.5, 0.6, 1.1))])
+def test_anisotropic_fused_levels_match_unfused_bitwise(prob):
+    """With A = diag(a), the fused level passes (2D wide tiles at n = 512; 3D z-pipelined
+    passes at n = 128) and both one-workgroup bottoms give the bits of the unfused kernels
+    over a whole solve."""
+    from paper_1502_04657_amd import lib
+    opts = W.Options(tol_lambda=1e-9)
+    r1, u1 = _solve(prob, opts)
+    lib().fmg_set_fused_vcycle(0)
+    try:
+        r0, u0 = _solve(prob, opts)
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+    assert r1.status == 0 and r0.status == 0
+    assert r1.lam == r0.lam and r1.history == r0.history
+    assert torch.equal(u1, u0)
