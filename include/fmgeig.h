@@ -137,7 +137,9 @@ typedef struct {
     int32_t vbottom2d_max_n;  /* 2D levels with at most this many cells per side run the    */
                               /* one-workgroup V-cycle bottom (0: the default 32; -1: never; */
                               /* at most 64)                                                 */
-    int32_t reserved[4];
+    int32_t vpass3d_one_pass; /* 3D V(2,2): 1 = one pass of 5 half sweeps per side (5-ring  */
+                              /* halo), 0 = two passes of 3 + 2                              */
+    int32_t reserved[3];
 } fmg_tuning;
 int fmg_get_tuning(fmg_tuning* out);
 int fmg_set_tuning(const fmg_tuning* in);   /* FMG_EINVAL for values out of range            */

@@ -579,11 +579,12 @@ int fmg_set_fused_vcycle(int32_t enable) {
 int fmg_get_tuning(fmg_tuning* out) {
     if (!out) return set_error(FMG_EINVAL, "tuning is NULL");
     std::memset(out, 0, sizeof(*out));
-    int v = 0, mn = 0, w2 = 0, b2 = 0;
-    get_vpass3d_tuning(&v, &mn);
+    int v = 0, mn = 0, w2 = 0, b2 = 0, one = 0;
+    get_vpass3d_tuning(&v, &mn, &one);
     get_vpass2d_tuning(&w2, &b2);
     out->vpass3d_variant = v;
     out->vpass3d_min_n = mn;
+    out->vpass3d_one_pass = one;
     out->vpass2d_wide_min_n = w2;
     out->vbottom2d_max_n = b2;
     return 0;
@@ -597,7 +598,9 @@ int fmg_set_tuning(const fmg_tuning* in) {
         return set_error(FMG_EINVAL, "vpass2d_wide_min_n must be 0 or >= 16");
     if (in->vbottom2d_max_n < -1 || in->vbottom2d_max_n > 64)
         return set_error(FMG_EINVAL, "vbottom2d_max_n must be in [-1, 64]");
-    set_vpass3d_tuning(in->vpass3d_variant, in->vpass3d_min_n);
+    if (in->vpass3d_one_pass != 0 && in->vpass3d_one_pass != 1)
+        return set_error(FMG_EINVAL, "vpass3d_one_pass must be 0 or 1");
+    set_vpass3d_tuning(in->vpass3d_variant, in->vpass3d_min_n, in->vpass3d_one_pass);
     set_vpass2d_tuning(in->vpass2d_wide_min_n, in->vbottom2d_max_n);
     return 0;
 }
@@ -647,8 +650,8 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
         return ms;
     };
     float best = -1.f;
-    auto consider = [&](int a, int b) {
-        if (dim == 3) set_vpass3d_tuning(a, b);
+    auto consider = [&](int a, int b, int c) {
+        if (dim == 3) set_vpass3d_tuning(a, b, c);
         else set_vpass2d_tuning(a, b);
         const float ms = precision == FMG_MIXED ? time_cycles(0.0f) : time_cycles(0.0);
         if (ms < 0.f) {
@@ -660,6 +663,7 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
             if (dim == 3) {
                 out->vpass3d_variant = a;
                 out->vpass3d_min_n = b;
+                out->vpass3d_one_pass = c;
             } else {
                 out->vpass2d_wide_min_n = a;
                 out->vbottom2d_max_n = b;
@@ -668,15 +672,16 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
     };
     if (dim == 3) {
         for (int mn = 16; !rc && mn <= 2 * n; mn *= 2)
-            // mn > n: no level on the fused passes (the variant does not matter)
+            // mn > n: no level on the fused passes (the variant and pass split do not matter)
             for (int v = 0; v < 3 && !rc; ++v)
-                if (mn <= n || v == cur.vpass3d_variant) consider(v, mn);
+                for (int one = 0; one < 2 && !rc; ++one)
+                    if (mn <= n || (v == cur.vpass3d_variant && one == cur.vpass3d_one_pass)) consider(v, mn, one);
     } else {
         for (int wm = 64; !rc && wm <= n; wm *= 2)   // wm = n: no level on the wide tiles
             for (int bm : {-1, 16, 32, 64})
-                if (!rc) consider(wm, bm);
+                if (!rc) consider(wm, bm, 0);
     }
-    set_vpass3d_tuning(cur.vpass3d_variant, cur.vpass3d_min_n);
+    set_vpass3d_tuning(cur.vpass3d_variant, cur.vpass3d_min_n, cur.vpass3d_one_pass);
     set_vpass2d_tuning(cur.vpass2d_wide_min_n, cur.vbottom2d_max_n);
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = set_error(FMG_EHIP, "autotune failed");
     if (e0) (void)hipEventDestroy(e0);

@@ -72,8 +72,10 @@ template <typename T> bool launch_vpost2d(const Grid& g, const Grid& gc, const T
 bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post);
 // tile variant (0: 256 threads, 1: 512 threads) and the smallest level that takes the
 // fused passes (negative / 0: keep the current value)
-void set_vpass3d_tuning(int variant, int min_n);
-void get_vpass3d_tuning(int* variant, int* min_n);
+// 3D: tile variant, smallest fused level, and for V(2,2) one pass of 5 half sweeps per
+// side (1) or two of 3 + 2 (0); negative values leave a choice as it is
+void set_vpass3d_tuning(int variant, int min_n, int one_pass);
+void get_vpass3d_tuning(int* variant, int* min_n, int* one_pass);
 // 2D: levels with n > wide_min use the wide tiles (0: the default 256); levels with
 // n <= bottom_max run the one-workgroup bottom (0: the default 32, -1: never)
 void set_vpass2d_tuning(int wide_min, int bottom_max);

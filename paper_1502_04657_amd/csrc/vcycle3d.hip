@@ -527,6 +527,7 @@ struct Shape3 {
 
 static int g_var3 = 1;        // tile variant of the fused 3D passes
 static int g_min_n3 = 128;    // smallest level that takes the fused passes
+static int g_one3 = 0;        // nu = 2: one pass of 5 half sweeps per side (1) or 3 + 2 (0)
 static int g_cus = 0;         // compute units of the device (queried once)
 
 // z planes per chunk: all blocks of a pass resident at once (no tail wave of blocks), and
@@ -586,13 +587,15 @@ static void pass3d(const Grid& g, const Grid& gc, const T* xin, T* xout, const T
         pass3d_v<T, NS, MODE, C1, 0>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
 }
 
-void set_vpass3d_tuning(int variant, int min_n) {
+void set_vpass3d_tuning(int variant, int min_n, int one_pass) {
     if (variant >= 0) g_var3 = variant > 2 ? 2 : variant;
     if (min_n > 0) g_min_n3 = min_n;
+    if (one_pass >= 0) g_one3 = one_pass ? 1 : 0;
 }
-void get_vpass3d_tuning(int* variant, int* min_n) {
+void get_vpass3d_tuning(int* variant, int* min_n, int* one_pass) {
     *variant = g_var3;
     *min_n = g_min_n3;
+    *one_pass = g_one3;
 }
 
 bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post) {
@@ -604,6 +607,12 @@ bool vpass3d_applies(const Grid& g, int nu_pre, int nu_post) {
 template <typename T>
 T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu, int zero_x, hipStream_t s,
                  hipEvent_t ev0, hipEvent_t ev1) {
+    if (nu == 2 && g_one3) {
+        // five half sweeps in one pass (5-ring halo), then the residual and its restriction
+        pass3d<T, 5, kPlain, 0>(g, gc, x, y, f, nullptr, nullptr, zero_x, s, ev0, ev1);
+        launch_resid_restrict<T>(g, gc, y, f, rc, s);
+        return y;
+    }
     if (nu == 2) {
         // five half sweeps in two passes; the residual and its restriction then as their own
         // streaming kernel (a pass that also restricts needs a 4-ring halo, which costs more
@@ -622,6 +631,11 @@ T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, i
 template <typename T>
 void launch_vpost3d(const Grid& g, const Grid& gc, T* xs, T* scratch, T* x_out, const T* f, const T* xc, int nu,
                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (nu == 2 && g_one3) {
+        // xs is the scratch array here (the one-pass pre ends in y): y -> x
+        pass3d<T, 5, kPost, 0>(g, gc, xs, x_out, f, nullptr, xc, 0, s, ev0, ev1);
+        return;
+    }
     if (nu == 2) {
         // xs == x_out here (the pre split ends in x): x -> scratch -> x
         pass3d<T, 3, kPost, 0>(g, gc, xs, scratch, f, nullptr, xc, 0, s, ev0, ev1);

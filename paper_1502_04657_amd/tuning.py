@@ -13,7 +13,7 @@ from . import _ffi, lib
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fmgeig", "tuning.json")
 
 
-FIELDS = ("vpass3d_variant", "vpass3d_min_n", "vpass2d_wide_min_n", "vbottom2d_max_n")
+FIELDS = ("vpass3d_variant", "vpass3d_min_n", "vpass3d_one_pass", "vpass2d_wide_min_n", "vbottom2d_max_n")
 
 
 def get() -> dict:
@@ -56,7 +56,7 @@ def autotune(dim: int, n: int, precision: str = "fp64", cache: str | None = DEFA
         prec = _ffi.FMG_MIXED if precision == "mixed" else _ffi.FMG_FP64
         if lib().fmg_autotune_vcycle(dim, n, prec, _stream(stream), C.byref(t)) != 0:
             raise RuntimeError(lib().fmg_last_error().decode())
-        keys = FIELDS[:2] if dim == 3 else FIELDS[2:]
+        keys = FIELDS[:3] if dim == 3 else FIELDS[3:]
         choice = {k: getattr(t, k) for k in keys}
         if cache:
             table[key] = choice

@@ -177,20 +177,20 @@ def test_fused_vcycle_2d_tuning_bitwise(ops, nc, levels, wide_min, bottom_max):
 
 @pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (3, 6), (5, 5), (4, 4), (4, 3), (8, 2), (2, 4)])
 @pytest.mark.parametrize("nu", [1, 2])
-@pytest.mark.parametrize("variant", [0, 1, 2])
-def test_fused_vcycle_3d_bitwise(ops, nc, levels, nu, variant):
+@pytest.mark.parametrize("variant, one_pass", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1)])
+def test_fused_vcycle_3d_bitwise(ops, nc, levels, nu, variant, one_pass):
     """3D levels above n = 16 run the z-pipelined level passes (forced through the tuning
     interface; ragged tiles and z-chunks at n = 96, 80, 160), and levels up to n = 16 with
     everything below them the one-workgroup bottom kernel (the whole V-cycle for n = 16 on
     coarsest meshes of 2, 4 and 8 cells per side): the same bits as the unfused kernel
-    sequence, for V(1,1) (one pass per side) and V(2,2) (two passes per side), with all three
-    tile variants."""
+    sequence, for V(1,1) (one pass per side) and V(2,2) (3 + 2 half sweeps in two passes per
+    side, or 5 in one), with all three tile variants."""
     import ctypes as C
     from paper_1502_04657_amd import _ffi, lib
     saved = _ffi.fmg_tuning()
     assert lib().fmg_get_tuning(C.byref(saved)) == 0
     t = _ffi.fmg_tuning()
-    t.vpass3d_variant, t.vpass3d_min_n = variant, 16
+    t.vpass3d_variant, t.vpass3d_min_n, t.vpass3d_one_pass = variant, 16, one_pass
     assert lib().fmg_set_tuning(C.byref(t)) == 0
     n = nc << (levels - 1)
     x0 = W.random_interior(3, n, seed=31)
