@@ -69,6 +69,13 @@ __host__ __device__ constexpr int qslot_ce(int t, int a, int b) {
     }
     return -1;
 }
+// local index in simplex t of the vertex in stencil slot s seen from vertex a, or -1
+template <int D>
+__host__ __device__ constexpr int slot_vert_ce(int t, int a, int s) {
+    for (int b = 0; b < D + 1; ++b)
+        if (qslot_ce<D>(t, a, b) == s) return b;
+    return -1;
+}
 template <int D, int T, int A, int B>
 struct QSlot {
     static constexpr int value = qslot_ce<D>(T, A, B);
@@ -159,6 +166,7 @@ struct Args {
     double* fac;         // persistent block factor, may be null
     int reuse;           // start from the stored factor when it exists
     double* esc;         // global scratch: per-simplex values of the 3D assembly (kEsc each)
+    int mstage;          // 3D bordered solves: per-simplex moments staged in LDS after the arena
     // dump mode
     const double* xin;
     double* Aout;
@@ -215,6 +223,11 @@ struct Arena {
     double* Dm; double* Fm; double* Rm;            // block factor (nb blocks each)
     double* S1; double* S2;                        // scratch
     bool s_stale = false;                          // Sst, sH, sc[3] not at the current x
+    // moments T3..T0 of simplex e at mo + e * mstride (the global moments, or their LDS
+    // copy) and the per-simplex values of the direct residual (3D)
+    const double* mo = nullptr;
+    int mstride = 0;
+    double* tvs = nullptr;
 
     __device__ void carve(double* base, int nc) {
         z = sizes<D, AUG>(nc);
@@ -252,6 +265,15 @@ __host__ __device__ inline size_t arena_bytes_t(int nc) {
     size_t dbl = 3 * (size_t)z.nb * z.B2 + z.sz1 + (size_t)z.h * z.B2 + N * NS + 8 * (N + 2) + 3 * N + 3 * N + 32 +
                  8 * kWaves;
     return dbl * sizeof(double) + 64;
+}
+
+// LDS stage of the 3D bordered solves, after the arena: the moments T3..T0 of every simplex
+// (the part of the moment layout the Newton iterations read) and the per-simplex values of
+// the direct residual
+template <int D>
+__host__ __device__ inline size_t mstage_doubles(int nc) {
+    const size_t nel = (D == 2) ? (size_t)nc * nc * 2 : (size_t)nc * nc * nc * 6;
+    return nel * (MomLayout<D>::T0 + 1 + (D + 1));
 }
 
 // factor = Dm, Fm, Rm (contiguous at the start of the arena)
@@ -321,6 +343,14 @@ __device__ __forceinline__ int nbr(const int* P, int m) {
     return node_id<D>(Q, m);
 }
 
+// x[j] for a neighbour index j, and 0 where there is none (j < 0): loaded from a clamped
+// address, so the loads of a node's slots do not sit under branches and can be in flight
+// together (adding the zero products leaves every sum unchanged)
+__device__ __forceinline__ double nbr_val(const double* x, int j) {
+    const double v = x[j < 0 ? 0 : j];
+    return j < 0 ? 0.0 : v;
+}
+
 // coarse stencils at node X (coordinates), slot S: a = (K + M_W)_S, b = M_S
 template <int D, int S>
 __device__ __forceinline__ void stencil_ab(const double* X, double H, double Hd, const Phys& ph, double& a, double& b) {
@@ -382,6 +412,43 @@ __device__ __forceinline__ int vert_node(int C0, int C1, int C2, int m) {
     return node_id<D>(P, m);
 }
 
+// Where the Newton iterations find the moments: staged, they are copied once per call from
+// the global moment array into LDS after the arena (lds_base: the arena's start) and the
+// direct residual keeps its per-simplex values there too; otherwise both stay in global
+// memory.
+template <int D, bool AUG>
+__device__ __forceinline__ void bind_moments(Arena<D, AUG>& ar, const Args& a, double* lds_base, bool staged) {
+    using L = MomLayout<D>;
+    constexpr int NM = L::T0 + 1;
+    static_assert(L::T3 == 0 && L::T2 < L::T1 && L::T1 < L::T0, "leading moment block");
+    if (staged) {
+        double* st = lds_base + arena_bytes_t<D, AUG>(a.nc) / sizeof(double);
+        // kB loads in flight per thread before their stores (clamped addresses stay in bounds)
+        constexpr int kB = 8;
+        const int total = ar.z.nel * NM;
+        for (int k0 = threadIdx.x; k0 < total; k0 += kThreads * kB) {
+            double v[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int k = min(k0 + u * kThreads, total - 1);
+                const int e = k / NM, q = k - e * NM;
+                v[u] = a.mom[(size_t)e * L::SIZE + q];
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+                if (k0 + u * kThreads < total) st[k0 + u * kThreads] = v[u];
+        }
+        ar.mo = st;
+        ar.mstride = NM;
+        ar.tvs = st + (size_t)total;
+        __syncthreads();
+    } else {
+        ar.mo = a.mom;
+        ar.mstride = L::SIZE;
+        ar.tvs = a.esc;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // setup: the u~ border a(u~, phi_i), b(u~, phi_i) and the scalars a(u~,u~), b(u~,u~), int u~
 template <int D, bool AUG>
@@ -403,7 +470,7 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
             const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 3) ? P[2] - ((cv >> 2) & 1) : 0;
             if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc))) return;
             const int cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
-            for_simplices<D>([&](auto tc) {
+            static_for<Geo<D>::NE>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 constexpr int v = VertOf<D, t, cv>::value;
                 if constexpr (v >= 0) {
@@ -494,6 +561,63 @@ __device__ __forceinline__ double elem_corner(const double* U, const double* UU,
         s2 += U[p] * mo[L::T1 + p];
     }
     return s1 + 2.0 * c * s2 + c * c * mo[L::T0];
+}
+
+// S(x) on one simplex of a 3D mesh: the upper triangle Se[sym2(a, b)] = int w^2 l_a l_b of
+// the element matrix (w = u_H + c u~, u_H = sum_p U_p l_p) and, with AUG, the border entries
+// sh[a] = int w^2 u~ l_a and the corner int w^2 u~^2 (returned).  The u_H^2 part is the
+// closed form
+//   int u_H^2 l_a l_b = |e| D! / (D+4)! (1 + delta_ab) (p1^2 + p2 + 2 p1 (U_a + U_b) + 2 (U_a^2 + U_a U_b + U_b^2)),
+// p_k = sum_p U_p^k; the parts with u~ are sums of the moments, e.g.
+// int u_H^2 u~ l_a = sum_{p <= r} UU[p, r] T3[p, r, a] (UU: U_p U_r, doubled off the diagonal).
+template <bool AUG>
+__device__ __forceinline__ double simplex_S3(const double* U, const double* UU, const double* mo, double c, double vol,
+                                             double* Se, double* sh) {
+    constexpr int V = 4;
+    using L = MomLayout<3>;
+    double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+    for (int p = 0; p < V; ++p) {
+        p1 += U[p];
+        p2 += U[p] * U[p];
+    }
+    const double kv = vol * (6.0 / 5040.0);
+    const double base = p1 * p1 + p2;
+    static_for<V>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        static_for<V - a>([&](auto bc) {
+            constexpr int b = a + decltype(bc)::value;
+            const double uh = base + 2.0 * p1 * (U[a] + U[b]) + 2.0 * (U[a] * U[a] + U[a] * U[b] + U[b] * U[b]);
+            double v = (a == b ? 2.0 : 1.0) * kv * uh;
+            if (AUG) {
+                double t = 0.0;
+#pragma unroll
+                for (int p = 0; p < V; ++p) t += U[p] * mo[L::T3 + sym3(p, a, b, V)];
+                v += c * (2.0 * t + c * mo[L::T2 + sym2(a, b, V)]);
+            }
+            Se[sym2(a, b, V)] = v;
+        });
+    });
+    double corner = 0.0;
+    if (AUG) {
+        double ct = 0.0, c1 = 0.0;
+        static_for<V>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            double qa = 0.0, ta = 0.0;
+#pragma unroll
+            for (int p = 0; p < V; ++p) {
+#pragma unroll
+                for (int r = p; r < V; ++r) qa += UU[sym2(p, r, V)] * mo[L::T3 + sym3(p, r, a, V)];
+                ta += U[p] * mo[L::T2 + sym2(p, a, V)];
+            }
+            const double t1 = mo[L::T1 + a];
+            sh[a] = qa + c * (2.0 * ta + c * t1);
+            ct += U[a] * ta;
+            c1 += U[a] * t1;
+        });
+        corner = ct + c * (2.0 * c1 + c * mo[L::T0]);
+    }
+    return corner;
 }
 
 // S(x): coarse stencil Sst, border sH, corner sc[3], in one pass.  One thread per coarse
@@ -589,8 +713,9 @@ __device__ __forceinline__ void assemble_S_nodes(Arena<D, AUG>& ar, const Args& 
 // coarse spaces and the per-node version of 2D spills registers):
 //   1. one thread per simplex computes its element matrix of S (the rows of elem_row; 10
 //      unique entries), its border entries (4) and its corner term into the global scratch;
-//   2. one thread per node adds, in a fixed order, the entries of the simplices around it
-//      (the loop structure of assemble_S_nodes), so no colouring and no atomics.
+//   2. one thread per (stencil slot, node) adds, in a fixed order, the entries of the
+//      simplices around the node that couple it to that neighbour, so no colouring and no
+//      atomics.
 constexpr int kEsc = 16;   // per-simplex scratch: 10 matrix entries, 4 border entries, corner
 template <int D, bool AUG>
 __device__ __forceinline__ void assemble_S_simplices(Arena<D, AUG>& ar, const Args& a, const double* x) {
@@ -600,7 +725,7 @@ __device__ __forceinline__ void assemble_S_simplices(Arena<D, AUG>& ar, const Ar
     constexpr int NCV = 1 << D;
     constexpr int NSYM = V * (V + 1) / 2;
     static_assert(NSYM + V + 1 <= kEsc, "per-simplex scratch");
-    using L = MomLayout<D>;
+    static_assert(D == 3, "the 3D assembly");
     const int N = ar.z.N, nc = a.nc, m = ar.z.m;
     const double H = 1.0 / nc;
     const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
@@ -628,54 +753,62 @@ __device__ __forceinline__ void assemble_S_simplices(Arena<D, AUG>& ar, const Ar
             for (int p = 0; p < V; ++p)
 #pragma unroll
                 for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-            const double* mo = AUG ? a.mom + (size_t)e * L::SIZE : nullptr;
+            constexpr int NM = MomLayout<D>::T0 + 1;
+            double mo[NM];
+            if (AUG) {
+                const double* src = ar.mo + (size_t)e * ar.mstride;
+#pragma unroll
+                for (int q = 0; q < NM; ++q) mo[q] = src[q];
+            }
             double* out = es + (size_t)e * kEsc;
-            static_for<V>([&](auto ac) {
-                constexpr int aa = decltype(ac)::value;
-                double Sr[V], sh = 0.0;
-                elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
-                static_for<V - aa>([&](auto bc) {
-                    constexpr int bb = aa + decltype(bc)::value;
-                    out[sym2(aa, bb, V)] = Sr[bb];
-                });
-                if (AUG) out[NSYM + aa] = sh;
-            });
-            if (AUG) sU += elem_corner<D>(U, UU, mo, c);
+            double Se[NSYM], sh[V];
+            const double corner = simplex_S3<AUG>(U, UU, mo, c, vol, Se, sh);
+#pragma unroll
+            for (int q = 0; q < NSYM; ++q) out[q] = Se[q];
+            if (AUG) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) out[NSYM + q] = sh[q];
+                sU += corner;
+            }
         });
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < N; i += kThreads) {
+    // one item per (slot, node), slot-major (s = k / N), so a wavefront covers few slots and
+    // every item's loads are independent; item (s, i) adds, over the cells around node i and
+    // their simplices in a fixed order, the entry coupling node i to its neighbour in slot s
+    // (s = NS: the border entry).  Every entry is loaded (from a clamped simplex where the
+    // cell is off the mesh) and added with a 0/1 factor; adding a zero leaves the sum unchanged.
+    for (int k = threadIdx.x; k < (AUG ? NS + 1 : NS) * N; k += kThreads) {
+        const int s = k / N, i = k - s * N;
         int P[3];
         node_pos<D>(i, m, P);
-        double row[NS];
-        static_for<NS>([&](auto sc_) { row[decltype(sc_)::value] = 0.0; });
-        double shs = 0.0;
-        // every entry is loaded (from a clamped simplex where the cell is off the mesh) and
-        // added with a 0/1 factor, so all loads of the node are independent of branches and
-        // can be in flight together; adding a zero leaves every sum unchanged
-        static_for<NCV>([&](auto cvc) {
-            constexpr int cv = decltype(cvc)::value;
-            // the node is cell vertex cv of the cell with origin P - (cv bits)
-            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 3) ? P[2] - ((cv >> 2) & 1) : 0;
-            const bool cin = !(C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc)));
-            const int cl = cin ? ((D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2)) : 0;
-            for_simplices<D>([&](auto tc) {
-                constexpr int t = decltype(tc)::value;
-                constexpr int aa = VertOf<D, t, cv>::value;
-                if constexpr (aa >= 0) {
-                    const double* in = es + (size_t)(cl * NE + t) * kEsc;
-                    static_for<V>([&](auto bc) {
-                        constexpr int bb = decltype(bc)::value;
-                        const double w = (cin && vert_node<D, t, bb>(C0, C1, C2, m) >= 0) ? 1.0 : 0.0;
-                        row[QSlot<D, t, aa, bb>::value] += w * in[sym2(aa, bb, V)];
-                    });
-                    if (AUG) shs += (cin ? 1.0 : 0.0) * in[NSYM + aa];
-                }
+        dispatch<NS + 1>(s, [&](auto sc_) {
+            constexpr int S = decltype(sc_)::value;
+            double acc = 0.0;
+            static_for<NCV>([&](auto cvc) {
+                constexpr int cv = decltype(cvc)::value;
+                // the node is cell vertex cv of the cell with origin P - (cv bits)
+                const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = P[2] - ((cv >> 2) & 1);
+                const bool cin = !(C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || C2 < 0 || C2 >= nc);
+                const int cl = cin ? C0 + nc * (C1 + nc * C2) : 0;
+                const double w = cin ? 1.0 : 0.0;
+                static_for<NE>([&](auto tc) {
+                    constexpr int t = decltype(tc)::value;
+                    constexpr int aa = VertOf<D, t, cv>::value;
+                    if constexpr (aa >= 0) {
+                        const double* in = es + (size_t)(cl * NE + t) * kEsc;
+                        if constexpr (S == NS) {
+                            acc += w * in[NSYM + aa];
+                        } else {
+                            constexpr int bb = slot_vert_ce<D>(t, aa, S);
+                            if constexpr (bb >= 0) acc += w * in[sym2(aa, bb, V)];
+                        }
+                    }
+                });
             });
+            if constexpr (S < NS) ar.Sst[(size_t)i * NS + S] = nbr<D, S>(P, m) >= 0 ? acc : 0.0;
+            else ar.sH[i] = acc;
         });
-        double* outr = ar.Sst + (size_t)i * NS;
-        static_for<NS>([&](auto sc_) { outr[decltype(sc_)::value] = row[decltype(sc_)::value]; });
-        if (AUG) ar.sH[i] = shs;
     }
     if (AUG) {
         sU = bsum1(ar.red, sU);
@@ -705,15 +838,14 @@ __device__ __forceinline__ void apply(Arena<D, AUG>& ar, const Args& a, double z
         node_pos<D>(i, m, P);
         const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
         double yi = 0.0, zi = 0.0;
-        for_slots<D>([&](auto sc_) {
+        static_for<Geo<D>::NS>([&](auto sc_) {
             constexpr int s = decltype(sc_)::value;
             const int j = nbr<D, s>(P, m);
-            if (j >= 0) {
-                double as, bs;
-                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
-                yi += (as + zs * ar.Sst[(size_t)i * NS + s]) * x[j];
-                zi += bs * x[j];
-            }
+            double as, bs;
+            stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+            const double xj = nbr_val(x, j);
+            yi += (as + zs * ar.Sst[(size_t)i * NS + s]) * xj;
+            zi += bs * xj;
         });
         if (AUG) {
             const double g = ar.aH[i] + zs * ar.sH[i];
@@ -743,11 +875,13 @@ __device__ __forceinline__ void apply(Arena<D, AUG>& ar, const Args& a, double z
     __syncthreads();
 }
 
-// Whether apply_direct can run: 2D bordered solves whose per-simplex values fit the
-// scratch S1, S2 (contiguous; free between factorisations and block solves).
+// Whether apply_direct can run: bordered solves; in 2D the per-simplex values must fit the
+// scratch S1, S2 (contiguous; free between factorisations and block solves), in 3D they go
+// to the global per-simplex scratch (kEsc >= D + 1 values per simplex).
 template <int D, bool AUG>
 __device__ __forceinline__ bool direct_ok(const Arena<D, AUG>& ar) {
-    return D == 2 && AUG && (size_t)ar.z.nel * (D + 1) <= (size_t)ar.z.sz1 + (size_t)ar.z.h * ar.z.B2;
+    if constexpr (D == 3) return AUG;
+    return AUG && (size_t)ar.z.nel * (D + 1) <= (size_t)ar.z.sz1 + (size_t)ar.z.h * ar.z.B2;
 }
 
 // y = (A + zs S) x and z = B x (with borders) as apply() gives them, without the stencil of
@@ -829,12 +963,11 @@ __device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, d
         for_slots<D>([&](auto sc_) {
             constexpr int s = decltype(sc_)::value;
             const int j = nbr<D, s>(P, m);
-            if (j >= 0) {
-                double as, bs;
-                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
-                yi += as * x[j];
-                zi += bs * x[j];
-            }
+            double as, bs;
+            stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+            const double xj = nbr_val(x, j);
+            yi += as * xj;
+            zi += bs * xj;
         });
         static_for<NCV>([&](auto cvc) {
             constexpr int cv = decltype(cvc)::value;
@@ -866,6 +999,157 @@ __device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, d
         ar.sc[5] = v[1] + c * zU;
     }
     __syncthreads();
+}
+
+// The 3D form of apply_direct.  The simplices run in type-major order (the simplex type is a
+// compile-time branch, uniform across a wavefront except where two types meet) and their
+// D + 1 vertex values go to the global per-simplex scratch; the node pass loads the values
+// of the 24 simplices around a node from clamped addresses and adds them with a 0/1 factor,
+// so all its loads are independent of branches (adding a zero leaves every sum unchanged).
+template <int D, bool AUG>
+__device__ __forceinline__ void apply_direct3(Arena<D, AUG>& ar, const Args& a, double zs, const double* x, double* y,
+                                              double* z) {
+    static_assert(D == 3 && AUG, "three-dimensional bordered solves only");
+    constexpr int NE = Geo<D>::NE;
+    constexpr int V = D + 1;
+    constexpr int NCV = 1 << D;
+    static_assert(V <= kEsc, "per-simplex scratch");
+    using L = MomLayout<D>;
+    const int N = ar.z.N, nc = a.nc, m = ar.z.m;
+    const double H = 1.0 / nc;
+    const double Hd = H * H * H;
+    const double vol = H * H * H / 6.0;
+    const double c = x[N];
+    double* tv = ar.tvs;   // nel x V
+    const int ncell = nc * nc * nc;
+    const int nsimp = ncell * NE;
+    double sb = 0.0;
+#ifdef FMG_SMALL_MICRO
+    const unsigned long long tq0 = wall_clock64();
+#endif
+    for (int f = threadIdx.x; f < nsimp; f += kThreads) {
+        const int te = f / ncell, cl = f - te * ncell;
+        const int e = cl * NE + te;
+        const int C0 = cl % nc, C1 = (cl / nc) % nc, C2 = cl / (nc * nc);
+        dispatch<NE>(te, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            double U[V];
+            static_for<V>([&](auto vc) {
+                constexpr int v = decltype(vc)::value;
+                const int nd = vert_node<D, t, v>(C0, C1, C2, m);
+                U[v] = nd >= 0 ? x[nd] : 0.0;
+            });
+            double UU[V * (V + 1) / 2];
+#pragma unroll
+            for (int p = 0; p < V; ++p)
+#pragma unroll
+                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
+            // the moments of the simplex in registers before any store (a store to the
+            // per-simplex values could alias them, which would reload them after it)
+            constexpr int NM = L::T0 + 1;
+            double mo[NM];
+            {
+                const double* src = ar.mo + (size_t)e * ar.mstride;
+#pragma unroll
+                for (int q = 0; q < NM; ++q) mo[q] = src[q];
+            }
+            // int u_H^3 l_a = |e| D! 3! / (D+4)! (h3 + U_a h2 + U_a^2 h1 + U_a^3), h_k the
+            // complete homogeneous symmetric polynomials of the vertex values U
+            double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+            for (int p = 0; p < V; ++p) {
+                const double u2 = U[p] * U[p];
+                p1 += U[p];
+                p2 += u2;
+                p3 += u2 * U[p];
+            }
+            const double h2 = 0.5 * (p1 * p1 + p2);
+            const double h3 = (p1 * (p1 * p1 + 3.0 * p2) + 2.0 * p3) * (1.0 / 6.0);
+            const double kv = vol * (36.0 / 5040.0);
+            double su = 0.0, ra[V];
+            static_for<V>([&](auto ac) {
+                constexpr int aa = decltype(ac)::value;
+                // qa = int u_H^2 u~ l_a, ta = int u_H u~^2 l_a
+                double qa = 0.0, ta = 0.0;
+#pragma unroll
+                for (int p = 0; p < V; ++p) {
+#pragma unroll
+                    for (int r = p; r < V; ++r) qa += UU[sym2(p, r, V)] * mo[L::T3 + sym3(p, r, aa, V)];
+                    ta += U[p] * mo[L::T2 + sym2(p, aa, V)];
+                }
+                const double t1 = mo[L::T1 + aa];
+                const double cub = kv * (h3 + U[aa] * (h2 + U[aa] * (p1 + U[aa])));
+                // int w^3 l_a, w = u_H + c u~
+                ra[aa] = cub + c * (3.0 * qa + c * (3.0 * ta + c * t1));
+                // int w^3 u~ = sum_a U_a (qa + 3 c ta + 3 c^2 t1_a) + c^3 int u~^4
+                su += U[aa] * (qa + c * (3.0 * ta + c * (3.0 * t1)));
+            });
+            sb += su + c * c * c * mo[L::T0];
+#pragma unroll
+            for (int q = 0; q < V; ++q) tv[(size_t)e * V + q] = ra[q];
+        });
+    }
+    __syncthreads();
+#ifdef FMG_SMALL_MICRO
+    const unsigned long long tq1 = wall_clock64();
+#endif
+    double v[5] = {0.0, 0.0, 0.0, 0.0, sb};
+    for (int i = threadIdx.x; i < N; i += kThreads) {
+        int P[3];
+        node_pos<D>(i, m, P);
+        const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
+        double yi = 0.0, zi = 0.0, gi = 0.0;
+        static_for<NCV>([&](auto cvc) {
+            constexpr int cv = decltype(cvc)::value;
+            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = P[2] - ((cv >> 2) & 1);
+            const bool cin = !(C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || C2 < 0 || C2 >= nc);
+            const int cl = cin ? C0 + nc * (C1 + nc * C2) : 0;
+            const double w = cin ? 1.0 : 0.0;
+            static_for<Geo<D>::NE>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                constexpr int aa = VertOf<D, t, cv>::value;
+                if constexpr (aa >= 0) gi += w * tv[(size_t)(cl * NE + t) * V + aa];
+            });
+        });
+        static_for<Geo<D>::NS>([&](auto sc_) {
+            constexpr int s = decltype(sc_)::value;
+            const int j = nbr<D, s>(P, m);
+            double as, bs;
+            stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+            const double xj = nbr_val(x, j);
+            yi += as * xj;
+            zi += bs * xj;
+        });
+        yi += zs * gi + ar.aH[i] * c;
+        zi += ar.bH[i] * c;
+        v[2] += ar.aH[i] * x[i];
+        v[3] += ar.bH[i] * x[i];
+        y[i] = yi;
+        z[i] = zi;
+        v[0] += x[i] * yi;
+        v[1] += x[i] * zi;
+    }
+#ifdef FMG_SMALL_MICRO
+    __syncthreads();
+    const unsigned long long tq2 = wall_clock64();
+#endif
+    bsum<5>(ar.red, v);
+    if (threadIdx.x == 0) {
+        const double yU = v[2] + ar.sc[0] * c + zs * v[4];
+        const double zU = v[3] + ar.sc[1] * c;
+        y[N] = yU;
+        z[N] = zU;
+        ar.sc[4] = v[0] + c * yU;
+        ar.sc[5] = v[1] + c * zU;
+    }
+    __syncthreads();
+#ifdef FMG_SMALL_MICRO
+    if (threadIdx.x == 0) {
+        atomicAdd(&g_small_t[13], tq1 - tq0);
+        atomicAdd(&g_small_t[14], tq2 - tq1);
+        atomicAdd(&g_small_t[15], wall_clock64() - tq2);
+    }
+#endif
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1365,7 +1649,7 @@ __device__ __forceinline__ int bcr_factor(Arena<D, AUG>& ar, const Args& a, doub
         node_pos<D>(i, m, P);
         const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
         const int blk = i / bs, r = i - blk * bs;
-        for_slots<D>([&](auto sc_) {
+        static_for<Geo<D>::NS>([&](auto sc_) {
             constexpr int s = decltype(sc_)::value;
             const int j = nbr<D, s>(P, m);
             if (j >= 0) {
@@ -1556,14 +1840,12 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
             node_pos<D>(i, m, P);
             const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
             double zi = 0.0;
-            for_slots<D>([&](auto sc_) {
+            static_for<Geo<D>::NS>([&](auto sc_) {
                 constexpr int s = decltype(sc_)::value;
                 const int j = nbr<D, s>(P, m);
-                if (j >= 0) {
-                    double as, bs;
-                    stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
-                    zi += bs * ar.x[j];
-                }
+                double as, bs;
+                stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
+                zi += bs * nbr_val(ar.x, j);
             });
             v[0] += ar.x[i] * zi;
             if (AUG) v[1] += ar.bH[i] * ar.x[i];
@@ -1590,6 +1872,9 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         FMG_T0(t_ap);
         if constexpr (D == 2 && AUG) {
             if (direct) apply_direct<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
+            else apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
+        } else if constexpr (D == 3 && AUG) {
+            if (direct) apply_direct3<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
             else apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
         } else {
             apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
@@ -1867,6 +2152,7 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     if (AUG && a.st->done) return;   // tolerance loop already satisfied
     FMG_T0(t_all);
     FMG_T0(t_setup);
+    if (AUG) bind_moments<D, AUG>(ar, a, lds, LDS && a.mstage);
     setup<D, AUG>(ar, a);
     FMG_TACC(0, t_setup);
     const int N = ar.z.N, m = ar.z.m;
@@ -1990,7 +2276,14 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         } else {
             tu[1] = tu[2] = tu[3] = tu[0];
         }
+        unsigned long long td0 = wall_clock64(), td1 = td0;
+        if constexpr (D == 3 && AUG) {
+            for (int r = 0; r < reps; ++r) apply_direct3<D, AUG>(ar, a, a.ph.zeta, ar.x, ar.y, ar.z2);
+            __syncthreads();
+            td1 = wall_clock64();
+        }
         if (threadIdx.x == 0) {
+            atomicAdd(&g_small_t[12], td1 - td0);
             for (int k = 0; k < 3; ++k) atomicAdd(&g_small_t[9 + k], tu[k + 1] - tu[k]);
             for (int k = 0; k < 7; ++k) atomicAdd(&g_small_t[k], tt[k + 1] - tt[k]);
             atomicAdd(&g_small_t[7], 1ull);
@@ -2014,6 +2307,7 @@ __global__ __launch_bounds__(kThreads) void k_aug_dump(Args a) {
     Arena<D, true> ar;
     if constexpr (LDS) ar.carve(lds, a.nc);
     else ar.carve(a.arena, a.nc);
+    bind_moments<D, true>(ar, a, lds, false);
     setup<D, true>(ar, a);
     constexpr int NS = Geo<D>::NS;
     const int N = ar.z.N, N1 = N + 1, m = ar.z.m;
@@ -2158,7 +2452,11 @@ int launch_aug_newton(int dim, int nc, const Phys& ph, int max_iter, int fixed_i
         return small_blocks(2, nc, b) ? launch_small(k_newton<2, true, true, true>, k_newton<2, true, true, true>, b, a, s)
                                       : launch_small(k_newton<2, true, true, false>, k_newton<2, true, false, false>, b, a, s);
     }
-    const size_t b = arena_bytes_t<3, true>(nc);
+    // the moments go to LDS after the arena when both fit
+    const size_t b0 = arena_bytes_t<3, true>(nc);
+    const size_t bst = b0 + mstage_doubles<3>(nc) * sizeof(double);
+    a.mstage = bst <= kLdsLimit ? 1 : 0;
+    const size_t b = a.mstage ? bst : b0;
     return small_blocks(3, nc, b) ? launch_small(k_newton<3, true, true, true>, k_newton<3, true, true, true>, b, a, s)
                                   : launch_small(k_newton<3, true, true, false>, k_newton<3, true, false, false>, b, a, s);
 }
