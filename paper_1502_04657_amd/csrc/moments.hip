@@ -308,62 +308,88 @@ __device__ __forceinline__ void cell_moments(const double* uc, const int* a, int
     }
 }
 
+// Inverses of the triangular numbers i (i + 1) / 2 and the tetrahedral numbers
+// i (i + 1) (i + 2) / 6, in 32-bit integers (cell ids and edge counts stay below 2^31 and
+// 1625 for every admissible mesh): a single-precision estimate from the hardware square root
+// or logarithm and exponential, then exact integer corrections.
+__device__ inline unsigned tri_num(unsigned i) { return i * (i + 1) / 2; }
+__device__ inline unsigned tet_num(unsigned i) { return i * (i + 1) * (i + 2) / 6; }
+// largest i with tri_num(i) <= t: (sqrt(8 t + 1) - 1) / 2 truncated is i up to the rounding
+// of the estimate, which one step down and one step up absorb
+__device__ inline unsigned tri_root(unsigned t) {
+    const float e = (__builtin_amdgcn_sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f;
+    unsigned i = e > 0.0f ? (unsigned)e : 0u;
+    i -= (i > 0 && tri_num(i) > t) ? 1u : 0u;
+    i += tri_num(i + 1) <= t ? 1u : 0u;
+    return i;
+}
+// largest i with tet_num(i) <= t: for tet_num(i) <= t < tet_num(i + 1), (6 t + 1)^(1/3) lies
+// in [i + 1 - 1/(3 (i + 1)), i + 2), so its truncation is i or i + 1 (up to the rounding of
+// the estimate): one step down and one step up
+__device__ inline unsigned tet_root(unsigned t) {
+    const float e = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(6.0f * (float)t + 1.0f) * (1.0f / 3.0f));
+    unsigned i = e > 0.0f ? (unsigned)e : 0u;
+    i -= (i > 0 && tet_num(i) > t) ? 1u : 0u;
+    i -= (i > 0 && tet_num(i) > t) ? 1u : 0u;
+    i += tet_num(i + 1) <= t ? 1u : 0u;
+    return i;
+}
+
+// axes of coarse simplex type `type` (3D): type 2 p0 + q, p0 the largest coordinate's axis,
+// q = 1 puts the larger remaining axis second
+__device__ inline void type_axes(int type, int& p0, int& p1, int& p2) {
+    p0 = type >> 1;
+    const int o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
+    p1 = (type & 1) ? o2 : o1;
+    p2 = (type & 1) ? o1 : o2;
+}
+
 // coarse-local cell offset of interior cell t (strictly ordered coordinates)
 template <int D>
-__device__ inline void interior_cell(int64_t t, int type, int* a) {
+__device__ inline void interior_cell(unsigned t, int type, int* a) {
     if (D == 2) {
         // t -> (i', j'), i' >= j' >= 0 (triangular numbers); (hi, lo) = (i' + 1, j')
-        int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while ((int64_t)i * (i + 1) / 2 > t) --i;
-        while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
-        const int j = (int)(t - (int64_t)i * (i + 1) / 2);
-        const int hi = i + 1, lo = j;
+        const unsigned i = tri_root(t);
+        const int hi = (int)i + 1, lo = (int)(t - tri_num(i));
         a[0] = type == 0 ? hi : lo;
         a[1] = type == 0 ? lo : hi;
         a[2] = 0;
     } else {
         // t -> sorted triple i' >= j' >= k' (tetrahedral, then triangular numbers);
         // (i, j, k) = (i' + 2, j' + 1, k') is strictly decreasing
-        int i = (int)cbrt(6.0 * (double)t);
-        while ((int64_t)i * (i + 1) * (i + 2) / 6 > t) --i;
-        while ((int64_t)(i + 1) * (i + 2) * (i + 3) / 6 <= t) ++i;
-        const int r = (int)(t - (int64_t)i * (i + 1) * (i + 2) / 6);
-        int j = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
-        while (j * (j + 1) / 2 > r) --j;
-        while ((j + 1) * (j + 2) / 2 <= r) ++j;
-        const int k = r - j * (j + 1) / 2;
-        // type 2 p0 + q: largest axis p0; q = 1 puts the larger remaining axis second
-        const int p0 = type >> 1, o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
-        const int p1 = (type & 1) ? o2 : o1, p2 = (type & 1) ? o1 : o2;
-        a[p0] = i + 2;
-        a[p1] = j + 1;
+        const unsigned i = tet_root(t);
+        const unsigned r = t - tet_num(i);
+        const unsigned j = tri_root(r);
+        const int k = (int)(r - tri_num(j));
+        int p0, p1, p2;
+        type_axes(type, p0, p1, p2);
+        a[p0] = (int)i + 2;
+        a[p1] = (int)j + 1;
         a[p2] = k;
     }
 }
 
 // coarse-local cell offset of tie cell t (s: fine cells per coarse edge)
 template <int D>
-__device__ inline void tie_cell(int64_t t, int type, int s, int* a) {
+__device__ inline void tie_cell(unsigned t, int type, int s, int* a) {
     if (D == 2) {
         a[0] = a[1] = (int)t;
         a[2] = 0;
     } else {
         // three groups: i = j > k (s (s - 1) / 2 cells), i > j = k (as many), i = j = k (s)
-        const int64_t half = (int64_t)s * (s - 1) / 2;
+        const unsigned half = tri_num((unsigned)s - 1);
         int i, j, k;
         if (t < 2 * half) {
-            const int64_t r = t < half ? t : t - half;
-            int p = (int)((sqrt(8.0 * (double)r + 1.0) - 1.0) * 0.5);   // p >= q >= 0 over s - 1
-            while ((int64_t)p * (p + 1) / 2 > r) --p;
-            while ((int64_t)(p + 1) * (p + 2) / 2 <= r) ++p;
-            const int q = (int)(r - (int64_t)p * (p + 1) / 2);
-            if (t < half) { i = j = p + 1; k = q; }
-            else { i = p + 1; j = k = q; }
+            const unsigned r = t < half ? t : t - half;
+            const unsigned p = tri_root(r);   // p >= q >= 0 over s - 1
+            const int q = (int)(r - tri_num(p));
+            if (t < half) { i = j = (int)p + 1; k = q; }
+            else { i = (int)p + 1; j = k = q; }
         } else {
             i = j = k = (int)(t - 2 * half);
         }
-        const int p0 = type >> 1, o1 = p0 == 0 ? 1 : 0, o2 = p0 == 2 ? 1 : 2;
-        const int p1 = (type & 1) ? o2 : o1, p2 = (type & 1) ? o1 : o2;
+        int p0, p1, p2;
+        type_axes(type, p0, p1, p2);
         a[p0] = i;
         a[p1] = j;
         a[p2] = k;
@@ -391,9 +417,11 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
 
     // decode cell id of this block's group and load its corner values
     auto fetch = [&](int64_t id, int* aa, double* u) {
-        if (ties) tie_cell<D>(id, type, s, aa);
-        else interior_cell<D>(id, type, aa);
-        const int64_t base = (C[0] * s + aa[0]) + P * (C[1] * s + aa[1]) + S * (D == 3 ? C[2] * s + aa[2] : 0);
+        if (ties) tie_cell<D>((unsigned)id, type, s, aa);
+        else interior_cell<D>((unsigned)id, type, aa);
+        // 32 x 32 -> 64-bit products (row and plane indices and strides are below 2^32)
+        const int64_t base = (int64_t)(C[0] * s + aa[0]) + (int64_t)(uint32_t)(C[1] * s + aa[1]) * (uint32_t)P +
+                             (D == 3 ? (int64_t)(uint32_t)(C[2] * s + aa[2]) * (uint32_t)S : 0);
 #pragma unroll
         for (int c = 0; c < NC; ++c) u[c] = ut[base + (c & 1) + P * ((c >> 1) & 1) + S * ((c >> 2) & 1)];
     };
