@@ -52,10 +52,12 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 #   |grad u~|^2 (6 tetrahedra x 10) 60,
 #   shift to coarse-local coordinates (45 + 15 + 3 FMA and 9 powers) 141, accumulation 39.
 MOMENTS3D_FLOPS_PER_CELL = 320 + 48 + 567 + 424 + 60 + 141 + 39
-# k_rhs<3>, per interior node: 15-point star sums against the mass moments (7 FMA each) 210,
-#   position weights of M_W 35, scales 4, nonlinear term over the 24 tetrahedra of the star
-#   (15 each) and its polynomial in u_i 369, stiffness row 8, combination 4.
-RHS3D_FLOPS_PER_NODE = 210 + 35 + 4 + 369 + 8 + 4
+# k_rhs3_rows, per interior node: sums and differences of the 7 opposite stencil pairs 14,
+#   mass-moment sums m0, M1, M2 over them (1 + 7, 12 and 3 + 21 FMA) 84, position weights of
+#   M_W 32, scales 4, the nonlinear term from the star's 14 outer vertices (powers and 3 FMA)
+#   112, 36 edges (product, two adds, FMA; doubled at the end) 184 and 24 triangles (FMA) 48,
+#   its polynomial in u_i 8, scale 2, combination 4.
+RHS3D_FLOPS_PER_NODE = 14 + 84 + 32 + 4 + 112 + 184 + 48 + 8 + 2 + 4
 
 
 def _pct(xs, q):
@@ -267,7 +269,7 @@ def bench_fmg3d(args):
     summary = "fmg3d_n256_pmc.md"
     out["roofline"] = alu_roofline("k_moments_raw<3>", pm, MOMENTS3D_FLOPS_PER_CELL, summary,
                                    ("moments.hip", "moment_tables.h"))
-    out["rhs_roofline"] = alu_roofline("k_rhs<3>", pr, RHS3D_FLOPS_PER_NODE, summary, ("grid.hip", "tables.h"))
+    out["rhs_roofline"] = alu_roofline("k_rhs3_rows", pr, RHS3D_FLOPS_PER_NODE, summary, ("grid.hip", "tables.h"))
     out["vcycle_roofline"] = [hbm_roofline("k_vpass3d<double, 3, 0, 0, 26, 26, 512>", ppre, summary,
                                            ("vcycle3d.hip", "grid.hip")),
                               hbm_roofline("k_vpass3d<double, 3, 2, 0, 26, 26, 512>", ppost, summary,
@@ -600,7 +602,7 @@ def rocpd_stats(db, top=25):
               f"{d[0][3]} |")
 
 
-PMC_KERNELS = {"k_moments_raw<3>": ("moments.hip", "moment_tables.h"), "k_rhs<3>": ("grid.hip", "tables.h"),
+PMC_KERNELS = {"k_moments_raw<3>": ("moments.hip", "moment_tables.h"), "k_rhs3_rows": ("grid.hip", "tables.h"),
                "k_newton<3, true, true, true>": ("small.hip",),
                "k_vpass3d<double, 3, 0, 0, 26, 26, 512>": ("vcycle3d.hip", "grid.hip"),
                "k_vpass3d<double, 3, 2, 0, 26, 26, 512>": ("vcycle3d.hip", "grid.hip"),

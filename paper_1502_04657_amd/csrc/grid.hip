@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include <cstddef>
+#include <utility>
 
 #include "dst.h"
 #include "kernels.h"
@@ -350,15 +351,194 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ u, doubl
     b[i + g.pitch * j + g.plane * k] = lam * Mu - MWu - ph.zeta * Nu;
 }
 
+// The 3D right-hand side with kRhsNX consecutive nodes along x per thread.  The 15-point
+// star of a node spans seven grid rows (dy, dz); a thread loads the segments of those rows
+// covering its nodes and their x-neighbours once (7 (kRhsNX + 2) values instead of 15 per
+// node) and evaluates each node from registers, with the arithmetic of node_forms in the
+// same order.
+constexpr int kRhsNX = 4;
+static constexpr int kRhsRows3D[7][2] = {{0, 0}, {-1, 0}, {0, -1}, {1, 0}, {0, 1}, {-1, -1}, {1, 1}};
+__host__ __device__ constexpr int rhs_row3(int dy, int dz) {
+    for (int r = 0; r < 7; ++r)
+        if (kRhsRows3D[r][0] == dy && kRhsRows3D[r][1] == dz) return r;
+    return -1;
+}
+__host__ __device__ constexpr int star_slot3(int dx, int dy, int dz) {
+    for (int s = 0; s < kStencil3D; ++s)
+        if (kOff3D[s][0] == dx && kOff3D[s][1] == dy && kOff3D[s][2] == dz) return s;
+    return -1;
+}
+template <typename F, int... I>
+__device__ __forceinline__ void rhs_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void rhs_for(F&& f) {
+    rhs_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+static_assert(rhs_row3(0, 0) == 0, "row table");
+
+// The star of a node as a surface: its 14 outer vertices (stencil slots 1..14), each in
+// deg[s] of the 24 tetrahedra, the 36 edges (ea, eb) between them, each shared by em
+// tetrahedra, and the 24 triangles (edge tri_e, third vertex tri_c).  Summed over the star,
+// the complete homogeneous sums of a tetrahedron's outer vertex values (a, b, c) are
+//   sum h1 = sum_s deg_s u_s,   sum h2 = sum_s deg_s u_s^2 + sum_e em_e u_a u_b,
+//   sum h3 = sum_s deg_s u_s^3 + sum_e em_e u_a u_b (u_a + u_b) + sum_t u_a u_b u_c.
+struct StarLinks3 {
+    int ne = 0;
+    int ea[48] = {}, eb[48] = {}, em[48] = {};
+    int deg[kStencil3D] = {};
+    int tri_e[kStarElems3D] = {}, tri_c[kStarElems3D] = {};
+};
+__host__ __device__ constexpr StarLinks3 make_star_links3() {
+    StarLinks3 L{};
+    for (int e = 0; e < kStarElems3D; ++e) {
+        int v[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) v[k] = star_slot3(kStarElem3D[e][k][0], kStarElem3D[e][k][1], kStarElem3D[e][k][2]);
+        for (int k = 0; k < 3; ++k) L.deg[v[k]] += 1;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                const int a = v[p] < v[q] ? v[p] : v[q], b = v[p] < v[q] ? v[q] : v[p];
+                int f = -1;
+                for (int x = 0; x < L.ne; ++x)
+                    if (L.ea[x] == a && L.eb[x] == b) f = x;
+                if (f < 0) {
+                    f = L.ne++;
+                    L.ea[f] = a;
+                    L.eb[f] = b;
+                }
+                L.em[f] += 1;
+                if (p == 0 && q == 1) L.tri_e[e] = f;
+            }
+        L.tri_c[e] = v[2];
+    }
+    return L;
+}
+static constexpr StarLinks3 kStarLinks3 = make_star_links3();
+static_assert(kStarLinks3.ne == 36 && kStarLinks3.deg[0] == 0, "star of a Kuhn vertex: 36 outer edges");
+
+// the stencil slot of the offset opposite to slot s (the star is centrally symmetric)
+__host__ __device__ constexpr int opposite3(int s) { return star_slot3(-kOff3D[s][0], -kOff3D[s][1], -kOff3D[s][2]); }
+// the pairs (p, opposite) with p the member whose first nonzero offset is negative
+__host__ __device__ constexpr bool neg_member3(int s) {
+    return kOff3D[s][0] != 0 ? kOff3D[s][0] < 0 : (kOff3D[s][1] != 0 ? kOff3D[s][1] < 0 : kOff3D[s][2] < 0);
+}
+__host__ __device__ constexpr bool mass_moments_symmetric3() {
+    for (int s = 1; s < kStencil3D; ++s) {
+        const int t = opposite3(s);
+        if (t < 0 || kM0_3D[s] != kM0_3D[t]) return false;
+        for (int a = 0; a < 3; ++a)
+            if (kM2_3D[a][s] != kM2_3D[a][t] || kM1_3D[a][s] != -kM1_3D[a][t]) return false;
+    }
+    return true;
+}
+static_assert(mass_moments_symmetric3(), "m0, M2 even and M1 odd under the point reflection of the star");
+
+__global__ __launch_bounds__(256) void k_rhs3_rows(const double* __restrict__ u, double* __restrict__ b, Grid g,
+                                                   Phys ph, const double* __restrict__ lam_dev, double lam_host) {
+    constexpr int NX = kRhsNX;
+    const int i0 = 1 + (int)(blockIdx.x * 64 + threadIdx.x) * NX;
+    const int j = 1 + (int)blockIdx.y * 4 + (int)threadIdx.y;
+    const int k = 1 + (int)blockIdx.z;
+    const int n = g.n;
+    if (i0 > n - 1 || j > n - 1) return;
+    const double lam = lam_dev ? *lam_dev : lam_host;
+    const int64_t P = g.pitch, S = g.plane;
+    // seg[r][c]: row r at x = i0 - 1 + c (clamped to the boundary node n; values past it are
+    // loaded but belong to no node of this thread)
+    double seg[7][NX + 2];
+    rhs_for<7>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        const double* row = u + P * (j + kRhsRows3D[r][0]) + S * (k + kRhsRows3D[r][1]);
+        rhs_for<NX + 2>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            seg[r][c] = row[min(i0 - 1 + c, n)];
+        });
+    });
+    const double h = g.h;
+    const double hd = h * h * h;
+    const double X1 = j * h, X2 = k * h;
+    rhs_for<NX>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if (i0 + q > n - 1) return;
+        // value at stencil offset (dx, dy, dz) of node i0 + q
+        auto U = [&](auto sc) -> double {
+            constexpr int s = decltype(sc)::value;
+            return seg[rhs_row3(kOff3D[s][1], kOff3D[s][2])][q + 1 + kOff3D[s][0]];
+        };
+        const double X[3] = {(i0 + q) * h, X1, X2};
+        const double u0 = U(std::integral_constant<int, 0>{});
+        // the stencil sums of u against m0 and M2 (even) over the sums of opposite values,
+        // against M1 (odd) over their differences
+        double mu = kM0_3D[0] * u0, s1[3] = {0.0, 0.0, 0.0}, s2[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s2[a] = kM2_3D[a][0] * u0;
+        rhs_for<kStencil3D>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            if constexpr (p > 0 && neg_member3(p)) {
+                constexpr int t = opposite3(p);
+                const double up = U(pc), ut = U(std::integral_constant<int, t>{});
+                const double sp = up + ut, dp = ut - up;
+                mu += kM0_3D[p] * sp;
+                rhs_for<3>([&](auto ac) {
+                    constexpr int a = decltype(ac)::value;
+                    if constexpr (kM1_3D[a][t] != 0.0) s1[a] += kM1_3D[a][t] * dp;
+                    s2[a] += kM2_3D[a][p] * sp;
+                });
+            }
+        });
+        double mw = ph.wc * mu;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mw += ph.w[a] * (X[a] * X[a] * mu + 2.0 * X[a] * h * s1[a] + h * h * s2[a]);
+        const double Mu = hd * mu;
+        const double MWu = hd * mw;
+        // sums over the star of the complete homogeneous polynomials h1, h2, h3 of each
+        // tetrahedron's outer vertex values, from its vertices, edges and triangles
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        rhs_for<kStencil3D>([&](auto sc) {
+            constexpr int sl = decltype(sc)::value;
+            if constexpr (kStarLinks3.deg[sl] > 0) {
+                constexpr double dg = kStarLinks3.deg[sl];
+                const double us = U(sc), u2 = us * us;
+                t1 += dg * us;
+                t2 += dg * u2;
+                t3 += dg * (u2 * us);
+            }
+        });
+        // every outer edge lies in two tetrahedra (the star's boundary is a closed surface)
+        double ep[kStarLinks3.ne], e2 = 0.0, e3 = 0.0;
+        rhs_for<kStarLinks3.ne>([&](auto ec) {
+            constexpr int x = decltype(ec)::value;
+            static_assert(kStarLinks3.em[x] == 2, "edge multiplicity");
+            const double ua = U(std::integral_constant<int, kStarLinks3.ea[x]>{});
+            const double ub = U(std::integral_constant<int, kStarLinks3.eb[x]>{});
+            ep[x] = ua * ub;
+            e2 += ep[x];
+            e3 += ep[x] * (ua + ub);
+        });
+        t2 += 2.0 * e2;
+        t3 += 2.0 * e3;
+        rhs_for<kStarElems3D>([&](auto tc) {
+            constexpr int e = decltype(tc)::value;
+            t3 += ep[kStarLinks3.tri_e[e]] * U(std::integral_constant<int, kStarLinks3.tri_c[e]>{});
+        });
+        const double nl = t3 + u0 * (2.0 * t2 + u0 * (3.0 * t1 + (4.0 * kStarElems3D) * u0));
+        const double Nu = nl * (h * h * h / 840.0);
+        b[(i0 + q) + P * j + S * k] = lam * Mu - MWu - ph.zeta * Nu;
+    });
+}
+
 void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev, double lam_host,
                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int n = g.n;
     dim3 blk(64, 4, 1);
-    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
-    if (g.dim == 2)
+    if (g.dim == 2) {
+        dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), 1);
         hipExtLaunchKernelGGL(k_rhs<2>, grd, blk, 0, s, ev0, ev1, 0, u, b, g, ph, lam_dev, lam_host);
-    else
-        hipExtLaunchKernelGGL(k_rhs<3>, grd, blk, 0, s, ev0, ev1, 0, u, b, g, ph, lam_dev, lam_host);
+    } else {
+        dim3 grd(cdiv(n - 1, 64 * kRhsNX), cdiv(n - 1, 4), n - 1);
+        hipExtLaunchKernelGGL(k_rhs3_rows, grd, blk, 0, s, ev0, ev1, 0, u, b, g, ph, lam_dev, lam_host);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
