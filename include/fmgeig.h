@@ -139,14 +139,19 @@ typedef struct {
                               /* at most 64)                                                 */
     int32_t vpass3d_one_pass; /* 3D V(2,2): 1 = one pass of 5 half sweeps per side (5-ring  */
                               /* halo), 0 = two passes of 3 + 2                              */
-    int32_t reserved[3];
+    int32_t vtile3d;          /* 3D levels between the one-workgroup bottom (n <= 16) and    */
+                              /* vpass3d_min_n: 1 (or 0: the default) = the half sweeps of a */
+                              /* side in LDS tiles of 8^3 nodes, 3 + 2 per launch; -1 = one  */
+                              /* launch per half sweep                                       */
+    int32_t reserved[2];
 } fmg_tuning;
 int fmg_get_tuning(fmg_tuning* out);
 int fmg_set_tuning(const fmg_tuning* in);   /* FMG_EINVAL for values out of range            */
 /* Tile autotuner: times whole V(2,2) cycles (every level down to the exact coarsest solve)
  * of a level with n cells per side, in FP64 (precision FMG_FP64) or FP32 (FMG_MIXED), on a
  * scratch hierarchy it allocates and frees, and returns the fastest choice in *out: in 3D
- * over every pass variant and smallest fused level (16, 32, ... up to "none"), in 2D over
+ * over every pass variant, smallest fused level (16, 32, ... up to "none") and the small
+ * levels' LDS tiles or per-half-sweep launches, in 2D over
  * the level from which the wide tiles are used (64 .. n, or none) and the largest level of
  * the one-workgroup bottom (none, 16, 32, 64).  The other dimension's fields keep their
  * current values.  The current tuning is left as it was; apply the result with

@@ -29,7 +29,8 @@ class fmg_options(C.Structure):
 
 class fmg_tuning(C.Structure):
     _fields_ = [("vpass3d_variant", C.c_int32), ("vpass3d_min_n", C.c_int32), ("vpass2d_wide_min_n", C.c_int32),
-                ("vbottom2d_max_n", C.c_int32), ("vpass3d_one_pass", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("vbottom2d_max_n", C.c_int32), ("vpass3d_one_pass", C.c_int32), ("vtile3d", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class fmg_kernel_profile(C.Structure):

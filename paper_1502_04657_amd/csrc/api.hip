@@ -219,6 +219,24 @@ static void vcycle(const Layout& lo, void* ws, int l, T* x, const T* f, int nu_p
         if (rpost) prof_add((3.0 * nf + ncs) * sizeof(double), nf);
         return;
     }
+    if (lo.dim == 3 && g_fused && !lo.cg && vtile3d_applies(g, nu_pre, nu_post)) {
+        // levels below the z-pipelined passes: the 2 nu + 1 half sweeps of a side in LDS
+        // tiles, out of place (V(2,2): 3 + 2, x -> y -> x; V(1,1): 3, x -> y, then y -> x)
+        T* y = at<T>(ws, lo.tv[l]);
+        T* xs = nu_pre == 2 ? x : y;
+        launch_vtile3d<T>(g, x, y, f, 3, 0, zero_x ? 1 : 0, s);
+        if (nu_pre == 2) launch_vtile3d<T>(g, y, x, f, 2, 1, 0, s);
+        launch_resid_restrict<T>(g, lo.g[l - 1], xs, f, fc, s);
+        vcycle<T>(lo, ws, l - 1, xc, fc, nu_pre, nu_post, s, true);
+        launch_prolong<T>(lo.g[l - 1], g, xc, xs, 1, s);
+        if (nu_post == 2) {
+            launch_vtile3d<T>(g, x, y, f, 3, 0, 0, s);
+            launch_vtile3d<T>(g, y, x, f, 2, 1, 0, s);
+        } else {
+            launch_vtile3d<T>(g, y, x, f, 3, 0, 0, s);
+        }
+        return;
+    }
     // unfused: red-black SGS (nu sweeps = 2 nu + 1 half sweeps) or nu CG steps
     auto smooth = [&](int nu) {
         if (nu <= 0) return;
@@ -587,6 +605,7 @@ int fmg_get_tuning(fmg_tuning* out) {
     out->vpass3d_one_pass = one;
     out->vpass2d_wide_min_n = w2;
     out->vbottom2d_max_n = b2;
+    out->vtile3d = get_vtile3d_tuning() ? 1 : -1;
     return 0;
 }
 
@@ -600,8 +619,10 @@ int fmg_set_tuning(const fmg_tuning* in) {
         return set_error(FMG_EINVAL, "vbottom2d_max_n must be in [-1, 64]");
     if (in->vpass3d_one_pass != 0 && in->vpass3d_one_pass != 1)
         return set_error(FMG_EINVAL, "vpass3d_one_pass must be 0 or 1");
+    if (in->vtile3d < -1 || in->vtile3d > 1) return set_error(FMG_EINVAL, "vtile3d must be -1, 0 or 1");
     set_vpass3d_tuning(in->vpass3d_variant, in->vpass3d_min_n, in->vpass3d_one_pass);
     set_vpass2d_tuning(in->vpass2d_wide_min_n, in->vbottom2d_max_n);
+    set_vtile3d_tuning(in->vtile3d >= 0 ? 1 : 0);
     return 0;
 }
 
@@ -650,9 +671,13 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
         return ms;
     };
     float best = -1.f;
-    auto consider = [&](int a, int b, int c) {
-        if (dim == 3) set_vpass3d_tuning(a, b, c);
-        else set_vpass2d_tuning(a, b);
+    auto consider = [&](int a, int b, int c, int tl) {
+        if (dim == 3) {
+            set_vpass3d_tuning(a, b, c);
+            set_vtile3d_tuning(tl > 0 ? 1 : 0);
+        } else {
+            set_vpass2d_tuning(a, b);
+        }
         const float ms = precision == FMG_MIXED ? time_cycles(0.0f) : time_cycles(0.0);
         if (ms < 0.f) {
             rc = set_error(FMG_EHIP, "timing failed");
@@ -664,6 +689,7 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
                 out->vpass3d_variant = a;
                 out->vpass3d_min_n = b;
                 out->vpass3d_one_pass = c;
+                out->vtile3d = tl;
             } else {
                 out->vpass2d_wide_min_n = a;
                 out->vbottom2d_max_n = b;
@@ -672,15 +698,20 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
     };
     if (dim == 3) {
         for (int mn = 16; !rc && mn <= 2 * n; mn *= 2)
-            // mn > n: no level on the fused passes (the variant and pass split do not matter)
+            // mn > n: no level on the fused passes (the variant and pass split do not matter);
+            // the LDS tiles apply to the levels between the bottom (16) and mn
             for (int v = 0; v < 3 && !rc; ++v)
                 for (int one = 0; one < 2 && !rc; ++one)
-                    if (mn <= n || (v == cur.vpass3d_variant && one == cur.vpass3d_one_pass)) consider(v, mn, one);
+                    for (int tl : {1, -1})
+                        if (!rc && (mn <= n || (v == cur.vpass3d_variant && one == cur.vpass3d_one_pass)) &&
+                            (mn > 32 || tl == cur.vtile3d))
+                            consider(v, mn, one, tl);
     } else {
         for (int wm = 64; !rc && wm <= n; wm *= 2)   // wm = n: no level on the wide tiles
             for (int bm : {-1, 16, 32, 64})
-                if (!rc) consider(wm, bm, 0);
+                if (!rc) consider(wm, bm, 0, 0);
     }
+    set_vtile3d_tuning(cur.vtile3d >= 0 ? 1 : 0);
     set_vpass3d_tuning(cur.vpass3d_variant, cur.vpass3d_min_n, cur.vpass3d_one_pass);
     set_vpass2d_tuning(cur.vpass2d_wide_min_n, cur.vbottom2d_max_n);
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = set_error(FMG_EHIP, "autotune failed");

@@ -80,6 +80,13 @@ void get_vpass3d_tuning(int* variant, int* min_n, int* one_pass);
 // n <= bottom_max run the one-workgroup bottom (0: the default 32, -1: never)
 void set_vpass2d_tuning(int wide_min, int bottom_max);
 void get_vpass2d_tuning(int* wide_min, int* bottom_max);
+// levels between the bottom and the z-pipelined passes: half_sweeps (2 or 3) red-black half
+// sweeps from colour `first` in LDS tiles, xin (zero_x: taken as zero) -> xout
+bool vtile3d_applies(const Grid& g, int nu_pre, int nu_post);
+void set_vtile3d_tuning(int enable);
+int get_vtile3d_tuning();
+template <typename T> void launch_vtile3d(const Grid& g, const T* xin, T* xout, const T* f, int half_sweeps,
+                                          int first, int zero_x, hipStream_t s);
 template <typename T> T* launch_vpre3d(const Grid& g, const Grid& gc, T* x, T* y, const T* f, T* rc, int nu,
                                        int zero_x, hipStream_t s, hipEvent_t ev0 = nullptr,
                                        hipEvent_t ev1 = nullptr);

@@ -511,6 +511,78 @@ __global__ __launch_bounds__(kBottom3Threads) void k_vbottom3d(T* __restrict__ x
     }
 }
 
+
+// ---- small levels: red-black half sweeps in LDS tiles ---------------------------------------
+// Levels between the one-workgroup bottom and the z-pipelined passes have too few planes for
+// the march along z to pay.  There a workgroup owns a cube of kTile^3 interior nodes and
+// loads it with NS rings of halo (x and f) into LDS; half sweep s updates the nodes of its
+// colour that lie at least s + 1 rings inside the region, so after NS half sweeps the cube
+// holds the values of the unfused sequence (the halo is recomputed by every workgroup that
+// needs it) and is written out of place.  NS half sweeps in one launch instead of NS, with
+// the node expression of the unfused kernel (same bits).
+constexpr int kTile = 8;
+constexpr int kTileThreads = 256;
+
+template <typename T, int NS>
+__global__ __launch_bounds__(kTileThreads) void k_vtile3d(const T* __restrict__ xin, T* __restrict__ xout,
+                                                          const T* __restrict__ f, Grid g, int first, int zero_x) {
+    constexpr int R = kTile + 2 * NS, RR = R * R, RV = RR * R;
+    constexpr int NL = (RV + kTileThreads - 1) / kTileThreads;
+    __shared__ T xs[RV];
+    __shared__ T fs[RV];
+    const int n = g.n;
+    const int i0 = 1 + (int)blockIdx.x * kTile - NS, j0 = 1 + (int)blockIdx.y * kTile - NS,
+              k0 = 1 + (int)blockIdx.z * kTile - NS;   // node of region cell (0, 0, 0)
+    const int64_t P = g.pitch, S = g.plane;
+    // every load of the region in flight before the stores to LDS (nodes off the mesh: 0)
+    T vx[NL], vf[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int t = (int)threadIdx.x + u * kTileThreads;
+        const int a = t % R, b = (t / R) % R, c = t / RR;
+        const int i = i0 + a, j = j0 + b, k = k0 + c;
+        const bool in = t < RV && i >= 0 && i <= n && j >= 0 && j <= n && k >= 0 && k <= n;
+        const int64_t p = in ? i + P * j + S * k : 0;
+        const T x0 = xin[zero_x ? 0 : p], f0 = f[p];
+        vx[u] = (in && !zero_x) ? x0 : T(0);
+        vf[u] = in ? f0 : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int t = (int)threadIdx.x + u * kTileThreads;
+        if (t < RV) {
+            xs[t] = vx[u];
+            fs[t] = vf[u];
+        }
+    }
+    __syncthreads();
+    const Stencil<T> kst = stencil_of<T>(g);
+    const T inv_h = T(n);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        // nodes of colour c ((i + j + k) & 1 == c) with region coordinates in [s + 1, R - 2 - s]
+        const int c = (first + s) & 1;
+        const int lo = s + 1, w = R - 2 * (s + 1), hw = (w + 1) / 2;
+        for (int t = threadIdx.x; t < hw * w * w; t += kTileThreads) {
+            const int m = t % hw, b = lo + (t / hw) % w, cz = lo + t / (hw * w);
+            const int j = j0 + b, k = k0 + cz;
+            // first region column of the colour in this row
+            const int a = lo + ((i0 + lo + j + k + c) & 1) + 2 * m;
+            const int i = i0 + a;
+            if (a > R - 2 - s || i < 1 || i > n - 1 || j < 1 || j > n - 1 || k < 1 || k > n - 1) continue;
+            const int q = a + R * b + RR * cz;
+            xs[q] = gs3f<T>(kst, fs[q], inv_h, xs[q - 1], xs[q + 1], xs[q - R], xs[q + R], xs[q - RR], xs[q + RR]);
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < kTile * kTile * kTile; t += kTileThreads) {
+        const int a = NS + t % kTile, b = NS + (t / kTile) % kTile, cz = NS + t / (kTile * kTile);
+        const int i = i0 + a, j = j0 + b, k = k0 + cz;
+        if (i > n - 1 || j > n - 1 || k > n - 1) continue;
+        xout[i + P * j + S * k] = xs[a + R * b + RR * cz];
+    }
+}
+
 }  // namespace
 
 // ---- launch --------------------------------------------------------------------------------
@@ -678,5 +750,28 @@ bool launch_vbottom3d(const Grid* levels, int l, T* x, const T* f, int nu_pre, i
 }
 template bool launch_vbottom3d<double>(const Grid*, int, double*, const double*, int, int, int, hipStream_t);
 template bool launch_vbottom3d<float>(const Grid*, int, float*, const float*, int, int, int, hipStream_t);
+
+static int g_tile3 = 1;   // levels below the z-pipelined passes: LDS tiles (1) or one launch per half sweep (0)
+
+void set_vtile3d_tuning(int enable) { g_tile3 = enable ? 1 : 0; }
+int get_vtile3d_tuning() { return g_tile3; }
+
+bool vtile3d_applies(const Grid& g, int nu_pre, int nu_post) {
+    return g_tile3 && g.dim == 3 && g.n > kBottom3MaxN && g.n < g_min_n3 && nu_pre == nu_post &&
+           (nu_pre == 1 || nu_pre == 2);
+}
+
+template <typename T>
+void launch_vtile3d(const Grid& g, const T* xin, T* xout, const T* f, int half_sweeps, int first, int zero_x,
+                    hipStream_t s) {
+    const int nt = (int)cdiv(g.n - 1, kTile);
+    const dim3 grd(nt, nt, nt);
+    if (half_sweeps == 3)
+        hipLaunchKernelGGL((k_vtile3d<T, 3>), grd, dim3(kTileThreads), 0, s, xin, xout, f, g, first, zero_x);
+    else
+        hipLaunchKernelGGL((k_vtile3d<T, 2>), grd, dim3(kTileThreads), 0, s, xin, xout, f, g, first, zero_x);
+}
+template void launch_vtile3d<double>(const Grid&, const double*, double*, const double*, int, int, int, hipStream_t);
+template void launch_vtile3d<float>(const Grid&, const float*, float*, const float*, int, int, int, hipStream_t);
 
 }  // namespace fmg

@@ -1,4 +1,4 @@
-"""Run-time tile choices of the 3D V-cycle passes: the library's autotuner
+"""Run-time tile choices of the V-cycle passes: the library's autotuner
 (fmg_autotune_vcycle) and a JSON cache of its results, keyed by device name, dimension,
 level size and precision, so that later processes apply a measured choice without timing
 again.  The choices change speed only: every choice gives the same bits."""
@@ -13,7 +13,8 @@ from . import _ffi, lib
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fmgeig", "tuning.json")
 
 
-FIELDS = ("vpass3d_variant", "vpass3d_min_n", "vpass3d_one_pass", "vpass2d_wide_min_n", "vbottom2d_max_n")
+FIELDS = ("vpass3d_variant", "vpass3d_min_n", "vpass3d_one_pass", "vtile3d", "vpass2d_wide_min_n", "vbottom2d_max_n")
+N3D = 4   # the first N3D fields are the 3D choices, the rest the 2D ones
 
 
 def get() -> dict:
@@ -56,7 +57,7 @@ def autotune(dim: int, n: int, precision: str = "fp64", cache: str | None = DEFA
         prec = _ffi.FMG_MIXED if precision == "mixed" else _ffi.FMG_FP64
         if lib().fmg_autotune_vcycle(dim, n, prec, _stream(stream), C.byref(t)) != 0:
             raise RuntimeError(lib().fmg_last_error().decode())
-        keys = FIELDS[:3] if dim == 3 else FIELDS[3:]
+        keys = FIELDS[:N3D] if dim == 3 else FIELDS[N3D:]
         choice = {k: getattr(t, k) for k in keys}
         if cache:
             table[key] = choice

@@ -159,6 +159,29 @@ def test_batch_plan_validates_before_any_device_work(lib):
     lib.fmg_batch_plan_destroy(None)
 
 
+def test_small_level_tile_choice_round_trips(lib):
+    """The tuning field of the 3D small levels' LDS tiles: 0 selects the default (on), 1 and
+    -1 are kept, anything else is refused and changes nothing."""
+    import ctypes as C
+    from paper_1502_04657_amd import _ffi
+    saved = _ffi.fmg_tuning()
+    assert lib.fmg_get_tuning(C.byref(saved)) == 0
+    try:
+        for v, want in ((0, 1), (-1, -1), (1, 1)):
+            t = _ffi.fmg_tuning()
+            assert lib.fmg_get_tuning(C.byref(t)) == 0
+            t.vtile3d = v
+            assert lib.fmg_set_tuning(C.byref(t)) == 0
+            got = _ffi.fmg_tuning()
+            assert lib.fmg_get_tuning(C.byref(got)) == 0 and got.vtile3d == want
+        t.vtile3d = 2
+        assert lib.fmg_set_tuning(C.byref(t)) == _ffi.FMG_EINVAL
+        got = _ffi.fmg_tuning()
+        assert lib.fmg_get_tuning(C.byref(got)) == 0 and got.vtile3d == 1
+    finally:
+        assert lib.fmg_set_tuning(C.byref(saved)) == 0
+
+
 def test_profile_requests_are_validated(lib):
     """Unknown kinds and bad capacities are refused before any event is created, and ending
     a profile that was never begun is an error."""

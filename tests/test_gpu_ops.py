@@ -208,6 +208,37 @@ def test_fused_vcycle_3d_bitwise(ops, nc, levels, nu, variant, one_pass):
     assert torch.equal(got, unf)
 
 
+@pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (5, 5), (3, 5), (7, 3)])
+@pytest.mark.parametrize("nu", [1, 2])
+def test_tiled_small_levels_3d_bitwise(ops, nc, levels, nu):
+    """3D levels between the one-workgroup bottom and the z-pipelined passes run the half
+    sweeps of a side in LDS tiles of 8^3 nodes (3 + 2 per launch; here every level above 16,
+    the z-pipelined passes being moved to n >= 4096): the same bits as the unfused kernel
+    sequence, with ragged tiles at n = 96, 80, 48, 40, 28, 24, 20."""
+    import ctypes as C
+    from paper_1502_04657_amd import _ffi, lib
+    saved = _ffi.fmg_tuning()
+    assert lib().fmg_get_tuning(C.byref(saved)) == 0
+    t = _ffi.fmg_tuning()
+    assert lib().fmg_get_tuning(C.byref(t)) == 0
+    t.vpass3d_min_n, t.vtile3d = 4096, 1
+    assert lib().fmg_set_tuning(C.byref(t)) == 0
+    n = nc << (levels - 1)
+    x0 = W.random_interior(3, n, seed=41)
+    f = W.random_interior(3, n, seed=42)
+    prob = W.Problem(3, nc, levels - 1)
+    opts = W.Options(nu_pre=nu, nu_post=nu)
+    try:
+        got = ops.vcycle(prob, opts, dev_level(3, n, x0), dev_level(3, n, f))
+        lib().fmg_set_fused_vcycle(0)
+        unf = ops.vcycle(prob, opts, dev_level(3, n, x0), dev_level(3, n, f))
+    finally:
+        lib().fmg_set_fused_vcycle(1)
+        assert lib().fmg_set_tuning(C.byref(saved)) == 0
+    assert bool(torch.isfinite(got).all())
+    assert torch.equal(got, unf)
+
+
 RHS_CASES = [W.Problem(2, 4, 2, (1.5, 0.5, 0.0), 0.25, 7.0), W.Problem(2, 12, 3, (1.0, 2.0, 0.0), 0.0, 100.0),
              W.Problem(3, 2, 2, (1.0, 0.5, 2.0), 0.3, 10.0), W.Problem(3, 3, 2, (1.0, 1.0, 1.0), 0.0, 1.0)]
 
