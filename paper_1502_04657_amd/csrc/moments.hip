@@ -38,7 +38,10 @@ namespace fmg {
 
 int moments_per_element(int dim) { return dim == 2 ? MomLayout<2>::SIZE : MomLayout<3>::SIZE; }
 
-static constexpr int kChunkCells = 2048;
+// cells per chunk: at most kChunkCells, the cells of a group split into equal chunks (a
+// block's fixed cost, the reduction of its partial sums, is then spread over as many cells as
+// possible without a short last chunk)
+static constexpr int kChunkCells = 8192;
 
 static int64_t ipow(int64_t b, int e) {
     int64_t r = 1;
@@ -51,9 +54,10 @@ static int64_t ipow(int64_t b, int e) {
 //             3D the cells with a_p0 > a_p1 > a_p2 for the type's axis order, s (s-1) (s-2) / 6;
 //   ties:     2D the s diagonal cells; 3D the s^2 cells with a_p0 = a_p1 >= a_p2 or
 //             a_p0 >= a_p1 = a_p2.
-// Chunks of kChunkCells cells: the interior chunks first, then the tie chunks.
+// Chunks of k_int (interior) and k_tie (tie) cells: the interior chunks first, then the tie
+// chunks.
 struct ChunkShape {
-    int64_t ncell, n_int, n_tie, c_int, c_tie;
+    int64_t ncell, n_int, n_tie, c_int, c_tie, k_int, k_tie;
 };
 static ChunkShape chunk_shape(int dim, int nc, int n) {
     const int64_t s = n / nc;
@@ -63,6 +67,8 @@ static ChunkShape chunk_shape(int dim, int nc, int n) {
     c.n_tie = dim == 2 ? s : s * s;
     c.c_int = (c.n_int + kChunkCells - 1) / kChunkCells;
     c.c_tie = (c.n_tie + kChunkCells - 1) / kChunkCells;
+    c.k_int = c.c_int > 0 ? (c.n_int + c.c_int - 1) / c.c_int : 1;
+    c.k_tie = c.c_tie > 0 ? (c.n_tie + c.c_tie - 1) / c.c_tie : 1;
     return c;
 }
 
@@ -398,7 +404,8 @@ __device__ inline void tie_cell(unsigned t, int type, int s, int* a) {
 
 template <int D>
 __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ ut, Grid g, int nc, int64_t n_int,
-                                                     int64_t n_tie, int c_int, int s, double* __restrict__ partial) {
+                                                     int64_t n_tie, int c_int, int64_t k_int, int64_t k_tie, int s,
+                                                     double* __restrict__ partial) {
     using R = RawLayout<D>;
     using M = Mono<D>;
     constexpr int NC = 1 << D;
@@ -407,8 +414,9 @@ __global__ __launch_bounds__(256) void k_moments_raw(const double* __restrict__ 
     const int type = blockIdx.z;
     const int64_t nchunk = gridDim.y;
     const bool ties = chunk >= c_int;
-    const int64_t start = (int64_t)(ties ? chunk - c_int : chunk) * kChunkCells;
-    const int64_t end = min(ties ? n_tie : n_int, start + (int64_t)kChunkCells);
+    const int64_t kc = ties ? k_tie : k_int;
+    const int64_t start = (int64_t)(ties ? chunk - c_int : chunk) * kc;
+    const int64_t end = min(ties ? n_tie : n_int, start + kc);
     const int C[3] = {(int)(cell % nc), (int)((cell / nc) % nc), D == 3 ? (int)(cell / ((int64_t)nc * nc)) : 0};
     const int64_t P = g.pitch, S = g.plane;
     double acc[R::SIZE];
@@ -590,12 +598,12 @@ void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double
     const unsigned nchunk = (unsigned)(c.c_int + c.c_tie);
     if (dim == 2) {
         hipExtLaunchKernelGGL(k_moments_raw<2>, dim3((unsigned)c.ncell, nchunk, 2), dim3(256), 0, s, ev0, ev1, 0, ut, g,
-                              nc, c.n_int, c.n_tie, (int)c.c_int, sc, scratch);
+                              nc, c.n_int, c.n_tie, (int)c.c_int, c.k_int, c.k_tie, sc, scratch);
         hipLaunchKernelGGL(k_moments_final<2>, dim3(cdiv(c.ncell * 2, 64)), dim3(64), 0, s, scratch, nc,
                            (int64_t)nchunk, ph, out);
     } else {
         hipExtLaunchKernelGGL(k_moments_raw<3>, dim3((unsigned)c.ncell, nchunk, 6), dim3(256), 0, s, ev0, ev1, 0, ut, g,
-                              nc, c.n_int, c.n_tie, (int)c.c_int, sc, scratch);
+                              nc, c.n_int, c.n_tie, (int)c.c_int, c.k_int, c.k_tie, sc, scratch);
         hipLaunchKernelGGL(k_moments_final<3>, dim3(cdiv(c.ncell * 6, 64)), dim3(64), 0, s, scratch, nc,
                            (int64_t)nchunk, ph, out);
     }
