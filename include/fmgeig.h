@@ -378,6 +378,16 @@ int fmg_moments_layout(int32_t dim, int32_t n_coarse, int32_t n, int32_t* per_el
                        size_t* scratch_bytes);
 int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* d_ut, double* d_out,
                    void* d_scratch, size_t scratch_bytes, void* stream);
+/* The same with the fine cells of each coarse simplex split into blocks of at most
+ * chunk_cells cells (0: the default of fmg_op_moments and fmg_solve, 8192), for tests of the
+ * block decomposition: the partial sums are added in another order, so results agree to
+ * rounding, not bit for bit.  With s = n / n_c, a coarse simplex has s (s-1) / 2 (2D) or
+ * s (s-1) (s-2) / 6 (3D) interior cells and s (2D) or s^2 (3D) cells on its internal faces,
+ * each group split into ceil(cells / chunk_cells) blocks; every block writes 23 (2D) or 39
+ * (3D) doubles of scratch.  FMG_EINVAL for chunk_cells outside [0, 2^20], FMG_ENOMEM when
+ * scratch_bytes is smaller than that.                                                      */
+int fmg_op_moments_chunked(const fmg_problem* prob, int32_t n, const double* d_ut, double* d_out,
+                           void* d_scratch, size_t scratch_bytes, int32_t chunk_cells, void* stream);
 
 /* Device scratch (bytes) of the small nonlinear solves on the coarsest space.             */
 int fmg_small_scratch_bytes(int32_t dim, int32_t n_coarse, size_t* bytes);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "fmg_op_vcycle": (C.c_int, [I32, I32, I32, I32, I32, P, P, P, SZ, P]),
     "fmg_moments_layout": (C.c_int, [I32, I32, I32, C.POINTER(I32), C.POINTER(SZ)]),
     "fmg_op_moments": (C.c_int, [P, I32, P, P, P, SZ, P]),
+    "fmg_op_moments_chunked": (C.c_int, [P, I32, P, P, P, SZ, I32, P]),
     "fmg_small_scratch_bytes": (C.c_int, [I32, I32, C.POINTER(SZ)]),
     "fmg_op_augmented_matrices": (C.c_int, [P, P, P, P, P, P, P, SZ, P]),
     "fmg_op_augmented_solve": (C.c_int, [P, P, P, P, P, SZ, P, C.POINTER(D), C.POINTER(D), C.POINTER(I32),

@@ -920,16 +920,23 @@ int fmg_moments_layout(int32_t dim, int32_t n_coarse, int32_t n, int32_t* per_el
     return 0;
 }
 
-int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* ut, double* out, void* scratch,
-                   size_t scratch_bytes, void* stream) {
+int fmg_op_moments_chunked(const fmg_problem* prob, int32_t n, const double* ut, double* out, void* scratch,
+                           size_t scratch_bytes, int32_t chunk_cells, void* stream) {
     if (int rc = check_problem(prob)) return rc;
     const int nc = prob->n_coarse;
     if (n < nc || n % nc || ((n / nc) & (n / nc - 1)) || !ut || !out || !scratch)
         return set_error(FMG_EINVAL, "bad moments arguments");
-    if (scratch_bytes < moments_scratch_bytes(prob->dim, nc, n)) return set_error(FMG_ENOMEM, "moments scratch too small");
+    if (chunk_cells < 0 || chunk_cells > (1 << 20)) return set_error(FMG_EINVAL, "chunk_cells must be in [0, 2^20]");
+    if (scratch_bytes < moments_scratch_bytes(prob->dim, nc, n, chunk_cells))
+        return set_error(FMG_ENOMEM, "moments scratch too small");
     launch_moments(prob->dim, nc, problem_grid(prob, n), make_phys(prob), ut, static_cast<double*>(scratch), out,
-                   static_cast<hipStream_t>(stream));
+                   static_cast<hipStream_t>(stream), nullptr, nullptr, chunk_cells);
     return hipGetLastError() == hipSuccess ? 0 : set_error(FMG_EHIP, "moments launch failed");
+}
+
+int fmg_op_moments(const fmg_problem* prob, int32_t n, const double* ut, double* out, void* scratch,
+                   size_t scratch_bytes, void* stream) {
+    return fmg_op_moments_chunked(prob, n, ut, out, scratch, scratch_bytes, 0, stream);
 }
 
 static size_t small_scratch(int dim, int nc) {

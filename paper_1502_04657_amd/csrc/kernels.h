@@ -96,9 +96,10 @@ template <typename T> void launch_vpost3d(const Grid& g, const Grid& gc, T* xs, 
 
 // ---- moments.hip ------------------------------------------------------------------------
 int moments_per_element(int dim);            // doubles per coarse element in the output
-size_t moments_scratch_bytes(int dim, int nc, int n);
+// chunk_cells: most fine cells one block integrates (0: the default, 8192)
+size_t moments_scratch_bytes(int dim, int nc, int n, int chunk_cells = 0);
 void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double* ut, double* scratch,
-                    double* out, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    double* out, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int chunk_cells = 0);
 
 // ---- small.hip --------------------------------------------------------------------------
 struct SmallState {

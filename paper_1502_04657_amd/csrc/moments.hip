@@ -59,21 +59,22 @@ static int64_t ipow(int64_t b, int e) {
 struct ChunkShape {
     int64_t ncell, n_int, n_tie, c_int, c_tie, k_int, k_tie;
 };
-static ChunkShape chunk_shape(int dim, int nc, int n) {
+static ChunkShape chunk_shape(int dim, int nc, int n, int target) {
+    const int64_t kChunk = target > 0 ? target : kChunkCells;
     const int64_t s = n / nc;
     ChunkShape c;
     c.ncell = ipow(nc, dim);
     c.n_int = dim == 2 ? s * (s - 1) / 2 : s * (s - 1) * (s - 2) / 6;
     c.n_tie = dim == 2 ? s : s * s;
-    c.c_int = (c.n_int + kChunkCells - 1) / kChunkCells;
-    c.c_tie = (c.n_tie + kChunkCells - 1) / kChunkCells;
+    c.c_int = (c.n_int + kChunk - 1) / kChunk;
+    c.c_tie = (c.n_tie + kChunk - 1) / kChunk;
     c.k_int = c.c_int > 0 ? (c.n_int + c.c_int - 1) / c.c_int : 1;
     c.k_tie = c.c_tie > 0 ? (c.n_tie + c.c_tie - 1) / c.c_tie : 1;
     return c;
 }
 
-size_t moments_scratch_bytes(int dim, int nc, int n) {
-    const ChunkShape c = chunk_shape(dim, nc, n);
+size_t moments_scratch_bytes(int dim, int nc, int n, int chunk_cells) {
+    const ChunkShape c = chunk_shape(dim, nc, n, chunk_cells);
     const int raw = dim == 2 ? RawLayout<2>::SIZE : RawLayout<3>::SIZE;
     const int ne = dim == 2 ? 2 : 6;
     return sizeof(double) * (size_t)(c.ncell * ne * (c.c_int + c.c_tie) * raw);
@@ -592,8 +593,8 @@ __global__ __launch_bounds__(64) void k_moments_final(const double* __restrict__
 }
 
 void launch_moments(int dim, int nc, const Grid& g, const Phys& ph, const double* ut, double* scratch, double* out,
-                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    const ChunkShape c = chunk_shape(dim, nc, g.n);
+                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int chunk_cells) {
+    const ChunkShape c = chunk_shape(dim, nc, g.n, chunk_cells);
     const int sc = g.n / nc;
     const unsigned nchunk = (unsigned)(c.c_int + c.c_tie);
     if (dim == 2) {

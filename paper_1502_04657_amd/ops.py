@@ -98,14 +98,24 @@ def moments_layout(dim, n_coarse, n):
     return per.value, scr.value
 
 
-def moments(problem, n, ut_level):
+def moments(problem, n, ut_level, chunk_cells=0):
+    """fmg_op_moments (chunk_cells = 0) or fmg_op_moments_chunked."""
     per, scr = moments_layout(problem.dim, problem.n_coarse, n)
     ncell = problem.n_coarse ** problem.dim
     ne = 2 if problem.dim == 2 else 6
     out = torch.zeros(ncell * ne * per, dtype=torch.float64, device=ut_level.device)
+    if chunk_cells:
+        s = n // problem.n_coarse
+        groups = (s * (s - 1) // 2, s) if problem.dim == 2 else (s * (s - 1) * (s - 2) // 6, s * s)
+        blocks = ncell * ne * sum(-(-g // chunk_cells) for g in groups)
+        scr = max(scr, blocks * (23 if problem.dim == 2 else 39) * 8)
     scratch = torch.empty(scr // 8 + 32, dtype=torch.float64, device=ut_level.device)
-    _check(lib().fmg_op_moments(C.byref(to_c_problem(problem)), n, _ptr(ut_level), _ptr(out), _ptr(scratch),
-                                C.c_size_t(scratch.numel() * 8), _stream()))
+    if chunk_cells:
+        _check(lib().fmg_op_moments_chunked(C.byref(to_c_problem(problem)), n, _ptr(ut_level), _ptr(out),
+                                            _ptr(scratch), C.c_size_t(scratch.numel() * 8), chunk_cells, _stream()))
+    else:
+        _check(lib().fmg_op_moments(C.byref(to_c_problem(problem)), n, _ptr(ut_level), _ptr(out), _ptr(scratch),
+                                    C.c_size_t(scratch.numel() * 8), _stream()))
     return out.view(ncell * ne, per)
 
 

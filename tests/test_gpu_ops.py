@@ -310,6 +310,38 @@ def test_moments_match_oracle_per_coarse_simplex(ops, prob):
     assert off == mom.shape[1]
 
 
+@pytest.mark.parametrize("prob, chunk", [(W.Problem(3, 2, 3, (0.6, 1.4, 1.1), 0.2, 5.0), 16),
+                                         (W.Problem(3, 2, 3, (0.6, 1.4, 1.1), 0.2, 5.0), 7),
+                                         (W.Problem(2, 2, 5, (1.2, 0.8, 0.0), 0.1, 5.0), 16)])
+def test_moments_split_into_many_blocks(ops, prob, chunk):
+    """The moment pass with the cells of every coarse simplex split into blocks of at most
+    `chunk` cells (3D n = 16 over 2^3 coarse cells: 56 interior and 64 tie cells per coarse
+    tetrahedron in 4 or 8 and 4 or 10 blocks, a short last tie block for chunk 7; 2D n = 64:
+    496 and 32 cells in 31 and 2 blocks): the oracle's moments to 1e-12, as with the default
+    blocks, and the default result to rounding."""
+    from oracle import fem
+    h = oracle_hierarchy(prob)
+    l = h.L - 1
+    n, dim = prob.n_fine, prob.dim
+    ut = W.smooth_interior(dim, n, seed=15) + 0.02 * W.random_interior(dim, n, seed=16)
+    ref = fem.coarse_simplex_moments(h.meshes[0], h.meshes[l], ut, h.W)
+    got = ops.moments(prob, n, dev_level(dim, n, ut), chunk_cells=chunk).cpu().numpy()
+    base = ops.moments(prob, n, dev_level(dim, n, ut)).cpu().numpy()
+    ne = 2 if dim == 2 else 6
+    ncell = prob.n_coarse ** dim
+    perm = np.array([t * ncell + c for c in range(ncell) for t in range(ne)])
+    cols = [("T3", _unique(ref["T3"], 3)), ("T2", _unique(ref["T2"], 2)), ("T1", ref["T1"]), ("T0", ref["T0"][:, None]),
+            ("B1", ref["B1"]), ("B2", ref["B2"][:, None]), ("AW1", ref["AW1"]), ("AW2", ref["AW2"][:, None]),
+            ("KG", ref["KG"]), ("Q", ref["Q"][:, None])]
+    off = 0
+    for name, arr in cols:
+        k = arr.shape[1]
+        assert rel_err(got[:, off:off + k], arr[perm]) < 1e-12, name
+        assert rel_err(got[:, off:off + k], base[:, off:off + k]) < 1e-13, name
+        off += k
+    assert off == got.shape[1]
+
+
 @pytest.mark.parametrize("prob", AUG_CASES)
 @pytest.mark.parametrize("variant", ["coarse_only", "u_tilde_only", "full"])
 def test_moments_build_the_augmented_matrices(ops, prob, variant):
