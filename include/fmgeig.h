@@ -130,7 +130,8 @@ int fmg_set_fused_vcycle(int32_t enable);
  * from fmg_autotune_vcycle or a cache of its results.                                    */
 typedef struct {
     int32_t vpass3d_variant;  /* 3D pass tiles (region columns x rows, threads): 0 = 32 x 16,  */
-                              /* 256; 1 = 32 x 32, 512; 2 = 64 x 16, 512                      */
+                              /* 256; 1 = 32 x 32, 512; 2 = 64 x 16, 512; 3 = 64 x 32, 512   */
+                              /* (two region pairs per thread)                                */
     int32_t vpass3d_min_n;    /* smallest 3D level (cells per side) on the fused passes      */
     int32_t vpass2d_wide_min_n; /* 2D levels with more cells per side use the wide tiles    */
                                 /* (0 in fmg_set_tuning: the default 256)                    */

@@ -611,7 +611,8 @@ int fmg_get_tuning(fmg_tuning* out) {
 
 int fmg_set_tuning(const fmg_tuning* in) {
     if (!in) return set_error(FMG_EINVAL, "tuning is NULL");
-    if (in->vpass3d_variant < 0 || in->vpass3d_variant > 2) return set_error(FMG_EINVAL, "vpass3d_variant must be 0, 1 or 2");
+    if (in->vpass3d_variant < 0 || in->vpass3d_variant > 3)
+        return set_error(FMG_EINVAL, "vpass3d_variant must be 0, 1, 2 or 3");
     if (in->vpass3d_min_n < 16) return set_error(FMG_EINVAL, "vpass3d_min_n must be >= 16");
     if (in->vpass2d_wide_min_n != 0 && in->vpass2d_wide_min_n < 16)
         return set_error(FMG_EINVAL, "vpass2d_wide_min_n must be 0 or >= 16");
@@ -700,7 +701,7 @@ int fmg_autotune_vcycle(int32_t dim, int32_t n, int32_t precision, void* stream,
         for (int mn = 16; !rc && mn <= 2 * n; mn *= 2)
             // mn > n: no level on the fused passes (the variant and pass split do not matter);
             // the LDS tiles apply to the levels between the bottom (16) and mn
-            for (int v = 0; v < 3 && !rc; ++v)
+            for (int v = 0; v < 4 && !rc; ++v)
                 for (int one = 0; one < 2 && !rc; ++one)
                     for (int tl : {1, -1})
                         if (!rc && (mn <= n || (v == cur.vpass3d_variant && one == cur.vpass3d_one_pass)) &&

@@ -586,13 +586,15 @@ __global__ __launch_bounds__(kTileThreads) void k_vtile3d(const T* __restrict__ 
 }  // namespace
 
 // ---- launch --------------------------------------------------------------------------------
-// Tile shapes: one region pair per thread ((TX + 2G) / 2 * (TY + 2G) = NT), in two sizes:
-// variant 0: 256 threads, 32 x 16 region; variant 1: 512 threads, 32 x 32; variant 2: 512
-// threads, 64 x 16 (longer contiguous rows per plane).
+// Tile shapes: one region pair per thread ((TX + 2G) / 2 * (TY + 2G) = NT) in variant 0:
+// 256 threads, 32 x 16 region; variant 1: 512 threads, 32 x 32; variant 2: 512 threads,
+// 64 x 16 (longer contiguous rows per plane); and two pairs per thread in variant 3: 512
+// threads, 64 x 32 (less halo per tile; the register windows double).
 template <int G, int V>
 struct Shape3 {
     static constexpr int NT = V ? 512 : 256;
-    static constexpr int RX = V == 2 ? 64 : 32, RY = 2 * NT / RX;   // RX / 2 pairs per region row
+    // RX / 2 pairs per region row; variant 3 holds two pairs per thread
+    static constexpr int RX = (V == 2 || V == 3) ? 64 : 32, RY = V == 3 ? 32 : 2 * NT / RX;
     static constexpr int TX = RX - 2 * G, TY = RY - 2 * G;
     static_assert(TX > 0 && TY > 0 && TX % 2 == 0, "tile shape");
 };
@@ -651,7 +653,9 @@ static void pass3d_v(const Grid& g, const Grid& gc, const T* xin, T* xout, const
 template <typename T, int NS, int MODE, int C1>
 static void pass3d(const Grid& g, const Grid& gc, const T* xin, T* xout, const T* f, T* rc, const T* xc,
                    int zero_x, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (g_var3 == 2)
+    if (g_var3 == 3)
+        pass3d_v<T, NS, MODE, C1, 3>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
+    else if (g_var3 == 2)
         pass3d_v<T, NS, MODE, C1, 2>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
     else if (g_var3 == 1)
         pass3d_v<T, NS, MODE, C1, 1>(g, gc, xin, xout, f, rc, xc, zero_x, s, ev0, ev1);
@@ -660,7 +664,7 @@ static void pass3d(const Grid& g, const Grid& gc, const T* xin, T* xout, const T
 }
 
 void set_vpass3d_tuning(int variant, int min_n, int one_pass) {
-    if (variant >= 0) g_var3 = variant > 2 ? 2 : variant;
+    if (variant >= 0) g_var3 = variant > 3 ? 3 : variant;
     if (min_n > 0) g_min_n3 = min_n;
     if (one_pass >= 0) g_one3 = one_pass ? 1 : 0;
 }

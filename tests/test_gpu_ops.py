@@ -177,14 +177,14 @@ def test_fused_vcycle_2d_tuning_bitwise(ops, nc, levels, wide_min, bottom_max):
 
 @pytest.mark.parametrize("nc, levels", [(4, 6), (6, 5), (3, 6), (5, 5), (4, 4), (4, 3), (8, 2), (2, 4)])
 @pytest.mark.parametrize("nu", [1, 2])
-@pytest.mark.parametrize("variant, one_pass", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1)])
+@pytest.mark.parametrize("variant, one_pass", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 1), (2, 1), (3, 1)])
 def test_fused_vcycle_3d_bitwise(ops, nc, levels, nu, variant, one_pass):
     """3D levels above n = 16 run the z-pipelined level passes (forced through the tuning
     interface; ragged tiles and z-chunks at n = 96, 80, 160), and levels up to n = 16 with
     everything below them the one-workgroup bottom kernel (the whole V-cycle for n = 16 on
     coarsest meshes of 2, 4 and 8 cells per side): the same bits as the unfused kernel
     sequence, for V(1,1) (one pass per side) and V(2,2) (3 + 2 half sweeps in two passes per
-    side, or 5 in one), with all three tile variants."""
+    side, or 5 in one), with all four tile variants."""
     import ctypes as C
     from paper_1502_04657_amd import _ffi, lib
     saved = _ffi.fmg_tuning()
