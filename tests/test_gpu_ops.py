@@ -263,7 +263,9 @@ def test_rhs_and_forms(ops, prob):
 
 AUG_CASES = [W.Problem(2, 4, 3, (1.5, 0.5, 0.0), 0.25, 7.0), W.Problem(2, 8, 1, (1.0, 1.0, 0.0), 0.0, 100.0),
              W.Problem(2, 16, 2, (0.7, 1.9, 0.0), 0.0, 1000.0), W.Problem(3, 2, 2, (1.0, 0.5, 2.0), 0.3, 10.0),
-             W.Problem(3, 4, 1, (1.0, 1.0, 1.0), 0.0, 1.0)]
+             W.Problem(3, 4, 1, (1.0, 1.0, 1.0), 0.0, 1.0),
+             # 3D coarsest h = 1/6: 25 x 25 blocks, arena in LDS, moments in global memory
+             W.Problem(3, 6, 1, (1.0, 0.8, 1.2), 0.0, 30.0)]
 
 
 def _oracle_aug(h, l, ut, x):
