@@ -460,7 +460,8 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
     if (!AUG) return;
     double v3[3] = {0.0, 0.0, 0.0};
     // one pass: each node gathers its border entries from the simplices around it in a fixed
-    // order; the scalars are summed over the simplices by a second loop
+    // order (from clamped addresses with a 0/1 factor, so that all loads are in flight
+    // together); the scalars are summed over the simplices by a second loop
     for (int i = threadIdx.x; i < N; i += kThreads) {
         int P[3];
         node_pos<D>(i, m, P);
@@ -468,15 +469,16 @@ __device__ __forceinline__ void setup(Arena<D, AUG>& ar, const Args& a) {
         static_for<(1 << D)>([&](auto cvc) {
             constexpr int cv = decltype(cvc)::value;
             const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 3) ? P[2] - ((cv >> 2) & 1) : 0;
-            if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc))) return;
-            const int cl = (D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2);
+            const bool cin = !(C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || (D == 3 && (C2 < 0 || C2 >= nc)));
+            const int cl = cin ? ((D == 2) ? C0 + nc * C1 : C0 + nc * (C1 + nc * C2)) : 0;
+            const double w = cin ? 1.0 : 0.0;
             static_for<Geo<D>::NE>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 constexpr int v = VertOf<D, t, cv>::value;
                 if constexpr (v >= 0) {
                     const double* mo = a.mom + (size_t)(cl * NE + t) * L::SIZE;
-                    sa += mo[L::KG + v] + mo[L::AW1 + v];
-                    sb += mo[L::B1 + v];
+                    sa += w * (mo[L::KG + v] + mo[L::AW1 + v]);
+                    sb += w * mo[L::B1 + v];
                 }
             });
         });
@@ -887,150 +889,46 @@ __device__ __forceinline__ bool direct_ok(const Arena<D, AUG>& ar) {
 // y = (A + zs S) x and z = B x (with borders) as apply() gives them, without the stencil of
 // S(x).  With w = c u~ + u_H, row i of S(x) x plus c times the border column is the integral
 // of w^3 phi_i, and the border row's share is the integral of w^3 u~.  One pass over the
-// simplices evaluates the first for each vertex (into S1, S2) and sums the second; a pass
-// over the nodes then adds the values of the simplices around each node in a fixed order.
-// The chord steps need this residual but not the Jacobian, so S(x) is assembled only when
-// the Jacobian is refactored or its border columns are frozen again.
+// simplices evaluates the first for each vertex and sums the second; a pass over the nodes
+// then adds the values of the simplices around each node in a fixed order.  The chord steps
+// need this residual but not the Jacobian, so S(x) is assembled only when the Jacobian is
+// refactored or its border columns are frozen again.
+//
+// The simplices run in type-major order (the simplex type is a compile-time branch, uniform
+// across a wavefront except where two types meet).  Their D + 1 vertex values go to the LDS
+// scratch S1, S2 in 2D and to the per-simplex scratch (LDS or global) in 3D.  In 2D the
+// moments come from global memory and each thread loads those of its two simplices before it
+// uses either.  The node pass loads the values of the simplices around a node from clamped
+// addresses and adds them with a 0/1 factor, so all its loads are independent of branches
+// (adding a zero leaves every sum unchanged).
 template <int D, bool AUG>
 __device__ __forceinline__ void apply_direct(Arena<D, AUG>& ar, const Args& a, double zs, const double* x, double* y,
                                              double* z) {
-    static_assert(D == 2 && AUG, "two-dimensional bordered solves only");
+    static_assert(AUG, "bordered solves only");
     constexpr int NE = Geo<D>::NE;
     constexpr int V = D + 1;
     constexpr int NCV = 1 << D;
+    static_assert(D == 2 || V <= kEsc, "per-simplex scratch");
     using L = MomLayout<D>;
-    const int N = ar.z.N, nc = a.nc, m = ar.z.m;
-    const double H = 1.0 / nc;
-    const double Hd = H * H;
-    const double vol = 0.5 * H * H;
-    const double c = x[N];
-    double* tv = ar.S1;   // nel x V
-    double sb = 0.0;
     constexpr int NM = L::T0 + 1;   // the moments used here: T3, T2, T1, T0 (leading entries)
     static_assert(L::T3 == 0 && L::T2 < L::T1 && L::T1 < L::T0, "leading moment block");
-    auto simplex = [&](int e, const double* mo) {
-        const int cl = e / NE, te = e - cl * NE;
-        const int C0 = cl % nc, C1 = cl / nc;
-        dispatch<NE>(te, [&](auto tc) {
-            constexpr int t = decltype(tc)::value;
-            double U[V];
-            static_for<V>([&](auto vc) {
-                constexpr int v = decltype(vc)::value;
-                const int nd = vert_node<D, t, v>(C0, C1, 0, m);
-                U[v] = nd >= 0 ? x[nd] : 0.0;
-            });
-            double UU[V * (V + 1) / 2];
-#pragma unroll
-            for (int p = 0; p < V; ++p)
-#pragma unroll
-                for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-            double su = 0.0;
-            static_for<V>([&](auto ac) {
-                constexpr int aa = decltype(ac)::value;
-                double Sr[V], sh = 0.0;
-                elem_row<D, AUG, aa>(U, UU, mo, c, vol, Sr, sh);
-                double r = c * sh;
-#pragma unroll
-                for (int b = 0; b < V; ++b) r += Sr[b] * U[b];
-                tv[(size_t)e * V + aa] = r;
-                su += U[aa] * sh;
-            });
-            sb += su + c * elem_corner<D>(U, UU, mo, c);
-        });
-    };
-    // two simplices per thread and pass, the moments of both loaded before either is used
-    for (int e0 = threadIdx.x; e0 < ar.z.nel; e0 += 2 * kThreads) {
-        const int e1 = e0 + kThreads;
-        const bool two = e1 < ar.z.nel;
-        const double* m0 = a.mom + (size_t)e0 * L::SIZE;
-        const double* m1 = a.mom + (size_t)(two ? e1 : e0) * L::SIZE;
-        double M0[NM], M1[NM];
-#pragma unroll
-        for (int q = 0; q < NM; ++q) {
-            M0[q] = m0[q];
-            M1[q] = m1[q];
-        }
-        simplex(e0, M0);
-        if (two) simplex(e1, M1);
-    }
-    __syncthreads();
-    double v[5] = {0.0, 0.0, 0.0, 0.0, sb};
-    for (int i = threadIdx.x; i < N; i += kThreads) {
-        int P[3];
-        node_pos<D>(i, m, P);
-        const double X[3] = {P[0] * H, P[1] * H, 0.0};
-        double yi = 0.0, zi = 0.0, gi = 0.0;
-        for_slots<D>([&](auto sc_) {
-            constexpr int s = decltype(sc_)::value;
-            const int j = nbr<D, s>(P, m);
-            double as, bs;
-            stencil_ab<D, s>(X, H, Hd, a.ph, as, bs);
-            const double xj = nbr_val(x, j);
-            yi += as * xj;
-            zi += bs * xj;
-        });
-        static_for<NCV>([&](auto cvc) {
-            constexpr int cv = decltype(cvc)::value;
-            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1);
-            if (C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc) return;
-            const int cl = C0 + nc * C1;
-            for_simplices<D>([&](auto tc) {
-                constexpr int t = decltype(tc)::value;
-                constexpr int aa = VertOf<D, t, cv>::value;
-                if constexpr (aa >= 0) gi += tv[(size_t)(cl * NE + t) * V + aa];
-            });
-        });
-        yi += zs * gi + ar.aH[i] * c;
-        zi += ar.bH[i] * c;
-        v[2] += ar.aH[i] * x[i];
-        v[3] += ar.bH[i] * x[i];
-        y[i] = yi;
-        z[i] = zi;
-        v[0] += x[i] * yi;
-        v[1] += x[i] * zi;
-    }
-    bsum<5>(ar.red, v);
-    if (threadIdx.x == 0) {
-        const double yU = v[2] + ar.sc[0] * c + zs * v[4];
-        const double zU = v[3] + ar.sc[1] * c;
-        y[N] = yU;
-        z[N] = zU;
-        ar.sc[4] = v[0] + c * yU;
-        ar.sc[5] = v[1] + c * zU;
-    }
-    __syncthreads();
-}
-
-// The 3D form of apply_direct.  The simplices run in type-major order (the simplex type is a
-// compile-time branch, uniform across a wavefront except where two types meet) and their
-// D + 1 vertex values go to the global per-simplex scratch; the node pass loads the values
-// of the 24 simplices around a node from clamped addresses and adds them with a 0/1 factor,
-// so all its loads are independent of branches (adding a zero leaves every sum unchanged).
-template <int D, bool AUG>
-__device__ __forceinline__ void apply_direct3(Arena<D, AUG>& ar, const Args& a, double zs, const double* x, double* y,
-                                              double* z) {
-    static_assert(D == 3 && AUG, "three-dimensional bordered solves only");
-    constexpr int NE = Geo<D>::NE;
-    constexpr int V = D + 1;
-    constexpr int NCV = 1 << D;
-    static_assert(V <= kEsc, "per-simplex scratch");
-    using L = MomLayout<D>;
+    // simplices per thread and round whose moments are loaded together
+    constexpr int KS = (D == 2) ? 2 : 1;
     const int N = ar.z.N, nc = a.nc, m = ar.z.m;
     const double H = 1.0 / nc;
-    const double Hd = H * H * H;
-    const double vol = H * H * H / 6.0;
+    const double Hd = (D == 2) ? H * H : H * H * H;
+    const double vol = (D == 2) ? 0.5 * H * H : H * H * H / 6.0;
+    // int lambda^alpha over a simplex, |alpha| = 4: |e| D! alpha! / (D + 4)!
+    const double kv = vol * ((D == 2) ? 12.0 / 720.0 : 36.0 / 5040.0);
     const double c = x[N];
-    double* tv = ar.tvs;   // nel x V
-    const int ncell = nc * nc * nc;
+    double* tv = (D == 2) ? ar.S1 : ar.tvs;   // nel x V
+    const int ncell = (D == 2) ? nc * nc : nc * nc * nc;
     const int nsimp = ncell * NE;
     double sb = 0.0;
-#ifdef FMG_SMALL_MICRO
-    const unsigned long long tq0 = wall_clock64();
-#endif
-    for (int f = threadIdx.x; f < nsimp; f += kThreads) {
+    auto simplex = [&](int f, const double* mo) {
         const int te = f / ncell, cl = f - te * ncell;
         const int e = cl * NE + te;
-        const int C0 = cl % nc, C1 = (cl / nc) % nc, C2 = cl / (nc * nc);
+        const int C0 = cl % nc, C1 = (D == 2) ? cl / nc : (cl / nc) % nc, C2 = (D == 2) ? 0 : cl / (nc * nc);
         dispatch<NE>(te, [&](auto tc) {
             constexpr int t = decltype(tc)::value;
             double U[V];
@@ -1044,15 +942,6 @@ __device__ __forceinline__ void apply_direct3(Arena<D, AUG>& ar, const Args& a, 
             for (int p = 0; p < V; ++p)
 #pragma unroll
                 for (int r = p; r < V; ++r) UU[sym2(p, r, V)] = (p == r ? 1.0 : 2.0) * U[p] * U[r];
-            // the moments of the simplex in registers before any store (a store to the
-            // per-simplex values could alias them, which would reload them after it)
-            constexpr int NM = L::T0 + 1;
-            double mo[NM];
-            {
-                const double* src = ar.mo + (size_t)e * ar.mstride;
-#pragma unroll
-                for (int q = 0; q < NM; ++q) mo[q] = src[q];
-            }
             // int u_H^3 l_a = |e| D! 3! / (D+4)! (h3 + U_a h2 + U_a^2 h1 + U_a^3), h_k the
             // complete homogeneous symmetric polynomials of the vertex values U
             double p1 = 0.0, p2 = 0.0, p3 = 0.0;
@@ -1065,7 +954,6 @@ __device__ __forceinline__ void apply_direct3(Arena<D, AUG>& ar, const Args& a, 
             }
             const double h2 = 0.5 * (p1 * p1 + p2);
             const double h3 = (p1 * (p1 * p1 + 3.0 * p2) + 2.0 * p3) * (1.0 / 6.0);
-            const double kv = vol * (36.0 / 5040.0);
             double su = 0.0, ra[V];
             static_for<V>([&](auto ac) {
                 constexpr int aa = decltype(ac)::value;
@@ -1088,6 +976,25 @@ __device__ __forceinline__ void apply_direct3(Arena<D, AUG>& ar, const Args& a, 
 #pragma unroll
             for (int q = 0; q < V; ++q) tv[(size_t)e * V + q] = ra[q];
         });
+    };
+#ifdef FMG_SMALL_MICRO
+    const unsigned long long tq0 = wall_clock64();
+#endif
+    for (int f0 = threadIdx.x; f0 < nsimp; f0 += KS * kThreads) {
+        // the moments of the simplices in registers before any store (a store to the
+        // per-simplex values could alias them, which would reload them after it)
+        double mo[KS][NM];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int f = min(f0 + k * kThreads, nsimp - 1);
+            const int te = f / ncell, cl = f - te * ncell;
+            const double* src = ar.mo + (size_t)(cl * NE + te) * ar.mstride;
+#pragma unroll
+            for (int q = 0; q < NM; ++q) mo[k][q] = src[q];
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            if (f0 + k * kThreads < nsimp) simplex(f0 + k * kThreads, mo[k]);
     }
     __syncthreads();
 #ifdef FMG_SMALL_MICRO
@@ -1097,11 +1004,11 @@ __device__ __forceinline__ void apply_direct3(Arena<D, AUG>& ar, const Args& a, 
     for (int i = threadIdx.x; i < N; i += kThreads) {
         int P[3];
         node_pos<D>(i, m, P);
-        const double X[3] = {P[0] * H, P[1] * H, P[2] * H};
+        const double X[3] = {P[0] * H, P[1] * H, (D == 2) ? 0.0 : P[2] * H};
         double yi = 0.0, zi = 0.0, gi = 0.0;
         static_for<NCV>([&](auto cvc) {
             constexpr int cv = decltype(cvc)::value;
-            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = P[2] - ((cv >> 2) & 1);
+            const int C0 = P[0] - (cv & 1), C1 = P[1] - ((cv >> 1) & 1), C2 = (D == 2) ? 0 : P[2] - ((cv >> 2) & 1);
             const bool cin = !(C0 < 0 || C0 >= nc || C1 < 0 || C1 >= nc || C2 < 0 || C2 >= nc);
             const int cl = cin ? C0 + nc * (C1 + nc * C2) : 0;
             const double w = cin ? 1.0 : 0.0;
@@ -1829,7 +1736,13 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
     const int N = ar.z.N, N1 = ar.z.N1, m = ar.z.m;
     const int tid = threadIdx.x;
     FMG_TCNT(9);
-    {
+    if constexpr (AUG) {
+        // the bordered solve starts from u = c u~ (x_H = 0): ||x||_B^2 = c^2 b(u~, u~)
+        const double c = ar.x[N];
+        const double sN = 1.0 / sqrt(c * (ar.sc[1] * c));
+        for (int i = tid; i < N1; i += kThreads) ar.x[i] *= sN;
+        __syncthreads();
+    } else {
         // x <- x / ||x||_B  (B needs no assembly)
         const double H = 1.0 / a.nc;
         const double Hd = (D == 2) ? H * H : H * H * H;
@@ -1870,11 +1783,8 @@ __device__ __forceinline__ int newton(Arena<D, AUG>& ar, const Args& a, double z
         ar.s_stale = direct;
         FMG_TACC(1, t_as);
         FMG_T0(t_ap);
-        if constexpr (D == 2 && AUG) {
+        if constexpr (AUG) {
             if (direct) apply_direct<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
-            else apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
-        } else if constexpr (D == 3 && AUG) {
-            if (direct) apply_direct3<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
             else apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
         } else {
             apply<D, AUG>(ar, a, zs, ar.x, ar.y, ar.z2);
@@ -2161,8 +2071,17 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
     // a stored factor of the coarse Jacobian block (previous call) seeds chord steps
     bool have = false;
     if (a.reuse && a.fac && a.st->fac_valid) {
+        // kB loads in flight per thread before their stores (clamped addresses stay in bounds)
+        constexpr int kB = 16;
         const int n = 3 * ar.z.nb * ar.z.B2;
-        for (int t = tid; t < n; t += kThreads) ar.Dm[t] = a.fac[t];
+        for (int t0 = tid; t0 < n; t0 += kThreads * kB) {
+            double v[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) v[u] = a.fac[min(t0 + u * kThreads, n - 1)];
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+                if (t0 + u * kThreads < n) ar.Dm[t0 + u * kThreads] = v[u];
+        }
         have = true;
     }
     __syncthreads();
@@ -2278,11 +2197,52 @@ __global__ __launch_bounds__(kThreads) void k_newton(Args a) {
         }
         unsigned long long td0 = wall_clock64(), td1 = td0;
         if constexpr (D == 3 && AUG) {
-            for (int r = 0; r < reps; ++r) apply_direct3<D, AUG>(ar, a, a.ph.zeta, ar.x, ar.y, ar.z2);
+            for (int r = 0; r < reps; ++r) apply_direct<D, AUG>(ar, a, a.ph.zeta, ar.x, ar.y, ar.z2);
             __syncthreads();
             td1 = wall_clock64();
         }
+        unsigned long long te[5];
+        te[0] = wall_clock64();
+        if constexpr (D == 2 && AUG) {
+            if (direct_ok<D, AUG>(ar))
+                for (int r = 0; r < reps; ++r) apply_direct<D, AUG>(ar, a, a.ph.zeta, ar.x, ar.y, ar.z2);
+        }
+        __syncthreads();
+        te[1] = wall_clock64();
+        if (a.fac) {
+            const int nf = 3 * ar.z.nb * ar.z.B2;
+            for (int r = 0; r < 10; ++r) {
+                constexpr int kB = 16;
+                for (int t0 = threadIdx.x; t0 < nf; t0 += kThreads * kB) {
+                    double vv[kB];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) vv[u] = a.fac[min(t0 + u * kThreads, nf - 1)];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u)
+                        if (t0 + u * kThreads < nf) ar.Dm[t0 + u * kThreads] = vv[u];
+                }
+                __syncthreads();
+            }
+        }
+        te[2] = wall_clock64();
+        for (int r = 0; r < 10; ++r) setup<D, AUG>(ar, a);
+        __syncthreads();
+        te[3] = wall_clock64();
+        for (int r = 0; r < reps; ++r) {
+            double fz[2] = {0.0, 0.0};
+            for (int i = threadIdx.x; i < ar.z.N1; i += kThreads) {
+                const double f = ar.y[i] - 1.5 * ar.z2[i];
+                ar.F[i] = f;
+                fz[0] += f * f;
+                fz[1] += ar.z2[i] * ar.z2[i];
+            }
+            bsum<2>(ar.red, fz);
+            acc += fz[0] * 1e-300;
+        }
+        __syncthreads();
+        te[4] = wall_clock64();
         if (threadIdx.x == 0) {
+            for (int k = 0; k < 4; ++k) atomicAdd(&g_small_t[16 + k], te[k + 1] - te[k]);
             atomicAdd(&g_small_t[12], td1 - td0);
             for (int k = 0; k < 3; ++k) atomicAdd(&g_small_t[9 + k], tu[k + 1] - tu[k]);
             for (int k = 0; k < 7; ++k) atomicAdd(&g_small_t[k], tt[k + 1] - tt[k]);
