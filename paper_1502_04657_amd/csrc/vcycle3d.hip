@@ -401,7 +401,9 @@ __global__ __launch_bounds__(NT) void k_vpass3d(const T* __restrict__ xin, T* __
 // prolongation and the post half sweeps of the unfused kernel sequence (grid.hip), node by
 // node with the same expressions, so the result has the same bits, in one launch instead of
 // about a dozen per level.  The coarsest-solve scratch follows the level arrays.
-constexpr int kBottom3Threads = 512;
+// 16 wavefronts (100 VGPRs each fit four per SIMD): the n = 16 half sweeps take two items per
+// thread instead of four
+constexpr int kBottom3Threads = 1024;
 constexpr int kBottom3MaxN = 16;
 constexpr size_t kBottom3MaxBytes = 150 * 1024;
 
