@@ -423,8 +423,9 @@ __device__ __forceinline__ void bind_moments(Arena<D, AUG>& ar, const Args& a, d
     static_assert(L::T3 == 0 && L::T2 < L::T1 && L::T1 < L::T0, "leading moment block");
     if (staged) {
         double* st = lds_base + arena_bytes_t<D, AUG>(a.nc) / sizeof(double);
-        // kB loads in flight per thread before their stores (clamped addresses stay in bounds)
-        constexpr int kB = 8;
+        // kB loads in flight per thread before their stores (clamped addresses stay in bounds;
+        // 28 takes the 384 x 35 moments of the 4^3 mesh in two rounds)
+        constexpr int kB = 28;
         const int total = ar.z.nel * NM;
         for (int k0 = threadIdx.x; k0 < total; k0 += kThreads * kB) {
             double v[kB];
