@@ -434,6 +434,92 @@ __host__ __device__ constexpr bool mass_moments_symmetric3() {
 }
 static_assert(mass_moments_symmetric3(), "m0, M2 even and M1 odd under the point reflection of the star");
 
+// Rows of the 3D right-hand-side and forms passes: seg[r][c] is row r (offsets
+// kRhsRows3D[r]) at x = i0 - 1 + c, clamped to the boundary node n (values past it are
+// loaded but belong to no node of the thread).
+template <int NX>
+__device__ __forceinline__ void rhs3_rows_load(const double* __restrict__ u, const Grid& g, int i0, int j, int k,
+                                               double (&seg)[7][NX + 2]) {
+    const int n = g.n;
+    const int64_t P = g.pitch, S = g.plane;
+    rhs_for<7>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        const double* row = u + P * (j + kRhsRows3D[r][0]) + S * (k + kRhsRows3D[r][1]);
+        rhs_for<NX + 2>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            seg[r][c] = row[min(i0 - 1 + c, n)];
+        });
+    });
+}
+
+// (M u)_i, (M_W u)_i and (N(u) u)_i of node i = i0 + q (position X) from the rows
+template <int NX, int q>
+__device__ __forceinline__ void rhs3_node(const double (&seg)[7][NX + 2], const Phys& ph, double h, double hd,
+                                          const double (&X)[3], double& Mu, double& MWu, double& Nu) {
+    // value at stencil offset (dx, dy, dz) of node i0 + q
+    auto U = [&](auto sc) -> double {
+        constexpr int s = decltype(sc)::value;
+        return seg[rhs_row3(kOff3D[s][1], kOff3D[s][2])][q + 1 + kOff3D[s][0]];
+    };
+    const double u0 = U(std::integral_constant<int, 0>{});
+    // the stencil sums of u against m0 and M2 (even) over the sums of opposite values,
+    // against M1 (odd) over their differences
+    double mu = kM0_3D[0] * u0, s1[3] = {0.0, 0.0, 0.0}, s2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s2[a] = kM2_3D[a][0] * u0;
+    rhs_for<kStencil3D>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        if constexpr (p > 0 && neg_member3(p)) {
+            constexpr int t = opposite3(p);
+            const double up = U(pc), ut = U(std::integral_constant<int, t>{});
+            const double sp = up + ut, dp = ut - up;
+            mu += kM0_3D[p] * sp;
+            rhs_for<3>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                if constexpr (kM1_3D[a][t] != 0.0) s1[a] += kM1_3D[a][t] * dp;
+                s2[a] += kM2_3D[a][p] * sp;
+            });
+        }
+    });
+    double mw = ph.wc * mu;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mw += ph.w[a] * (X[a] * X[a] * mu + 2.0 * X[a] * h * s1[a] + h * h * s2[a]);
+    Mu = hd * mu;
+    MWu = hd * mw;
+    // sums over the star of the complete homogeneous polynomials h1, h2, h3 of each
+    // tetrahedron's outer vertex values, from its vertices, edges and triangles
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    rhs_for<kStencil3D>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        if constexpr (kStarLinks3.deg[sl] > 0) {
+            constexpr double dg = kStarLinks3.deg[sl];
+            const double us = U(sc), u2 = us * us;
+            t1 += dg * us;
+            t2 += dg * u2;
+            t3 += dg * (u2 * us);
+        }
+    });
+    // every outer edge lies in two tetrahedra (the star's boundary is a closed surface)
+    double ep[kStarLinks3.ne], e2 = 0.0, e3 = 0.0;
+    rhs_for<kStarLinks3.ne>([&](auto ec) {
+        constexpr int x = decltype(ec)::value;
+        static_assert(kStarLinks3.em[x] == 2, "edge multiplicity");
+        const double ua = U(std::integral_constant<int, kStarLinks3.ea[x]>{});
+        const double ub = U(std::integral_constant<int, kStarLinks3.eb[x]>{});
+        ep[x] = ua * ub;
+        e2 += ep[x];
+        e3 += ep[x] * (ua + ub);
+    });
+    t2 += 2.0 * e2;
+    t3 += 2.0 * e3;
+    rhs_for<kStarElems3D>([&](auto tc) {
+        constexpr int e = decltype(tc)::value;
+        t3 += ep[kStarLinks3.tri_e[e]] * U(std::integral_constant<int, kStarLinks3.tri_c[e]>{});
+    });
+    const double nl = t3 + u0 * (2.0 * t2 + u0 * (3.0 * t1 + (4.0 * kStarElems3D) * u0));
+    Nu = nl * (h * h * h / 840.0);
+}
+
 __global__ __launch_bounds__(256) void k_rhs3_rows(const double* __restrict__ u, double* __restrict__ b, Grid g,
                                                    Phys ph, const double* __restrict__ lam_dev, double lam_host) {
     constexpr int NX = kRhsNX;
@@ -444,88 +530,85 @@ __global__ __launch_bounds__(256) void k_rhs3_rows(const double* __restrict__ u,
     if (i0 > n - 1 || j > n - 1) return;
     const double lam = lam_dev ? *lam_dev : lam_host;
     const int64_t P = g.pitch, S = g.plane;
-    // seg[r][c]: row r at x = i0 - 1 + c (clamped to the boundary node n; values past it are
-    // loaded but belong to no node of this thread)
     double seg[7][NX + 2];
-    rhs_for<7>([&](auto rc) {
-        constexpr int r = decltype(rc)::value;
-        const double* row = u + P * (j + kRhsRows3D[r][0]) + S * (k + kRhsRows3D[r][1]);
-        rhs_for<NX + 2>([&](auto cc) {
-            constexpr int c = decltype(cc)::value;
-            seg[r][c] = row[min(i0 - 1 + c, n)];
-        });
-    });
+    rhs3_rows_load<NX>(u, g, i0, j, k, seg);
     const double h = g.h;
     const double hd = h * h * h;
     const double X1 = j * h, X2 = k * h;
     rhs_for<NX>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if (i0 + q > n - 1) return;
-        // value at stencil offset (dx, dy, dz) of node i0 + q
-        auto U = [&](auto sc) -> double {
-            constexpr int s = decltype(sc)::value;
-            return seg[rhs_row3(kOff3D[s][1], kOff3D[s][2])][q + 1 + kOff3D[s][0]];
-        };
         const double X[3] = {(i0 + q) * h, X1, X2};
-        const double u0 = U(std::integral_constant<int, 0>{});
-        // the stencil sums of u against m0 and M2 (even) over the sums of opposite values,
-        // against M1 (odd) over their differences
-        double mu = kM0_3D[0] * u0, s1[3] = {0.0, 0.0, 0.0}, s2[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) s2[a] = kM2_3D[a][0] * u0;
-        rhs_for<kStencil3D>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            if constexpr (p > 0 && neg_member3(p)) {
-                constexpr int t = opposite3(p);
-                const double up = U(pc), ut = U(std::integral_constant<int, t>{});
-                const double sp = up + ut, dp = ut - up;
-                mu += kM0_3D[p] * sp;
-                rhs_for<3>([&](auto ac) {
-                    constexpr int a = decltype(ac)::value;
-                    if constexpr (kM1_3D[a][t] != 0.0) s1[a] += kM1_3D[a][t] * dp;
-                    s2[a] += kM2_3D[a][p] * sp;
-                });
-            }
-        });
-        double mw = ph.wc * mu;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) mw += ph.w[a] * (X[a] * X[a] * mu + 2.0 * X[a] * h * s1[a] + h * h * s2[a]);
-        const double Mu = hd * mu;
-        const double MWu = hd * mw;
-        // sums over the star of the complete homogeneous polynomials h1, h2, h3 of each
-        // tetrahedron's outer vertex values, from its vertices, edges and triangles
-        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-        rhs_for<kStencil3D>([&](auto sc) {
-            constexpr int sl = decltype(sc)::value;
-            if constexpr (kStarLinks3.deg[sl] > 0) {
-                constexpr double dg = kStarLinks3.deg[sl];
-                const double us = U(sc), u2 = us * us;
-                t1 += dg * us;
-                t2 += dg * u2;
-                t3 += dg * (u2 * us);
-            }
-        });
-        // every outer edge lies in two tetrahedra (the star's boundary is a closed surface)
-        double ep[kStarLinks3.ne], e2 = 0.0, e3 = 0.0;
-        rhs_for<kStarLinks3.ne>([&](auto ec) {
-            constexpr int x = decltype(ec)::value;
-            static_assert(kStarLinks3.em[x] == 2, "edge multiplicity");
-            const double ua = U(std::integral_constant<int, kStarLinks3.ea[x]>{});
-            const double ub = U(std::integral_constant<int, kStarLinks3.eb[x]>{});
-            ep[x] = ua * ub;
-            e2 += ep[x];
-            e3 += ep[x] * (ua + ub);
-        });
-        t2 += 2.0 * e2;
-        t3 += 2.0 * e3;
-        rhs_for<kStarElems3D>([&](auto tc) {
-            constexpr int e = decltype(tc)::value;
-            t3 += ep[kStarLinks3.tri_e[e]] * U(std::integral_constant<int, kStarLinks3.tri_c[e]>{});
-        });
-        const double nl = t3 + u0 * (2.0 * t2 + u0 * (3.0 * t1 + (4.0 * kStarElems3D) * u0));
-        const double Nu = nl * (h * h * h / 840.0);
+        double Mu, MWu, Nu;
+        rhs3_node<NX, q>(seg, ph, h, hd, X, Mu, MWu, Nu);
         b[(i0 + q) + P * j + S * k] = lam * Mu - MWu - ph.zeta * Nu;
     });
+}
+
+// The forms of a 3D level array from the same rows: u.Ku, u.M_W u, u.Mu, u.N(u)u and, with
+// lam, |Ku + M_W u + zeta N(u)u - lam Mu|^2 and |lam Mu|^2, per workgroup into partial.
+// kReduceBlocks workgroups (64 x 4 threads; two per CU at this kernel's register count)
+// stride over the row groups of the rhs grid.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_forms3_rows(const double* __restrict__ u, Grid g, Phys ph,
+                                                     const double* __restrict__ lam, double* __restrict__ partial) {
+    constexpr int NX = kRhsNX;
+    const int n = g.n, m = n - 1;
+    const int gx = (m + 64 * NX - 1) / (64 * NX), gy = (m + 3) / 4;
+    const int groups = gx * gy * m;
+    const double lv = (NQ > 4) ? *lam : 0.0;
+    const double h = g.h;
+    const double hd = h * h * h;
+    const Stencil<double> ks = stencil_of<double>(g);
+    double a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = 0.0;
+    for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const int bx = grp % gx, rest = grp / gx, by = rest % gy, bz = rest / gy;
+        const int i0 = 1 + (bx * 64 + (int)threadIdx.x) * NX;
+        const int j = 1 + by * 4 + (int)threadIdx.y;
+        const int k = 1 + bz;
+        if (i0 > n - 1 || j > n - 1) continue;
+        double seg[7][NX + 2];
+        rhs3_rows_load<NX>(u, g, i0, j, k, seg);
+        const double X1 = j * h, X2 = k * h;
+        rhs_for<NX>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if (i0 + q > n - 1) return;
+            const double X[3] = {(i0 + q) * h, X1, X2};
+            double Mu, MWu, Nu;
+            rhs3_node<NX, q>(seg, ph, h, hd, X, Mu, MWu, Nu);
+            // the stiffness couples the axis neighbours only
+            constexpr int r0 = rhs_row3(0, 0), ym = rhs_row3(-1, 0), yp = rhs_row3(1, 0), zm = rhs_row3(0, -1),
+                          zp = rhs_row3(0, 1);
+            const double u0 = seg[r0][q + 1];
+            const double Ku = h * kdiff(ks, u0, nsum3(ks, seg[r0][q], seg[r0][q + 2], seg[ym][q + 1], seg[yp][q + 1],
+                                                      seg[zm][q + 1], seg[zp][q + 1]));
+            a[0] += u0 * Ku;
+            a[1] += u0 * MWu;
+            a[2] += u0 * Mu;
+            a[3] += u0 * Nu;
+            if constexpr (NQ > 4) {
+                const double lm = lv * Mu, r = (Ku + MWu + ph.zeta * Nu) - lm;
+                a[4] += r * r;
+                a[5] += lm * lm;
+            }
+        });
+    }
+    // blockDim (64, 4): wavefront threadIdx.y, lane threadIdx.x
+    __shared__ double red[4][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double v = wave_sum(a[q]);
+        if (threadIdx.x == 0) red[threadIdx.y][q] = v;
+    }
+    __syncthreads();
+    const int t = (int)threadIdx.x + 64 * (int)threadIdx.y;
+    if (t < NQ) {
+        double v = 0.0;
+        for (int w = 0; w < 4; ++w) v += red[w][t];
+        partial[blockIdx.x * NQ + t] = v;
+    }
 }
 
 void launch_rhs(const Grid& g, const Phys& ph, const double* u, double* b, const double* lam_dev, double lam_host,
@@ -714,19 +797,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 
 void launch_forms(const Grid& g, const Phys& ph, const double* u, double* partial, double* out, hipStream_t s,
                   const double* lam) {
-    if (lam) {
-        if (g.dim == 2)
-            hipLaunchKernelGGL((k_forms<2, 6>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
-        else
-            hipLaunchKernelGGL((k_forms<3, 6>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, kReduceBlocks, 6, out);
-        return;
-    }
-    if (g.dim == 2)
+    const dim3 blk3(64, 4, 1);
+    if (g.dim == 2 && lam)
+        hipLaunchKernelGGL((k_forms<2, 6>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
+    else if (g.dim == 2)
         hipLaunchKernelGGL((k_forms<2, 4>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
+    else if (lam)
+        hipLaunchKernelGGL((k_forms3_rows<6>), dim3(kReduceBlocks), blk3, 0, s, u, g, ph, lam, partial);
     else
-        hipLaunchKernelGGL((k_forms<3, 4>), dim3(kReduceBlocks), dim3(256), 0, s, u, g, ph, lam, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, kReduceBlocks, 4, out);
+        hipLaunchKernelGGL((k_forms3_rows<4>), dim3(kReduceBlocks), blk3, 0, s, u, g, ph, lam, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, kReduceBlocks, lam ? 6 : 4, out);
 }
 
 // ------------------------------------------------------------------------------------------
