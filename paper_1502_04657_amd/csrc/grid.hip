@@ -656,14 +656,43 @@ __global__ __launch_bounds__(256) void k_add_promote(double* __restrict__ u, con
     u[p] += (double)e[p];
 }
 
+// The 3D form: each thread walks a column of up to kDemoteZ nodes along z and keeps u at
+// k - 1, k and k + 1 in registers, so only the in-plane neighbours come through the caches;
+// the node expression is that of k_residual_demote (same bits).
+constexpr int kDemoteZ = 16;
+__global__ __launch_bounds__(256) void k_residual_demote3_z(const double* __restrict__ u,
+                                                            const double* __restrict__ b, float* __restrict__ r,
+                                                            Grid g) {
+    const int i = 1 + blockIdx.x * 64 + threadIdx.x;
+    const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+    const int k0 = 1 + (int)blockIdx.z * kDemoteZ;
+    const int n = g.n;
+    if (i > n - 1 || j > n - 1) return;
+    const int k1 = min(k0 + kDemoteZ, n);   // exclusive; k0 <= n - 1 by the grid
+    const int64_t P = g.pitch, S = g.plane;
+    const Stencil<double> ks = stencil_of<double>(g);
+    int64_t p = i + P * j + S * k0;
+    double um = u[p - S], uc = u[p];
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k, p += S) {
+        const double up = u[p + S];
+        const double ku = g.h * kdiff(ks, uc, nsum3(ks, u[p - 1], u[p + 1], u[p - P], u[p + P], um, up));
+        r[p] = (float)(b[p] - ku);
+        um = uc;
+        uc = up;
+    }
+}
+
 void launch_residual_demote(const Grid& g, const double* u, const double* b, float* r, hipStream_t s) {
     const int n = g.n;
     dim3 blk(64, 4, 1);
-    dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), g.dim == 3 ? n - 1 : 1);
-    if (g.dim == 2)
+    if (g.dim == 2) {
+        dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), 1);
         hipLaunchKernelGGL(k_residual_demote<2>, grd, blk, 0, s, u, b, r, g);
-    else
-        hipLaunchKernelGGL(k_residual_demote<3>, grd, blk, 0, s, u, b, r, g);
+    } else {
+        dim3 grd(cdiv(n - 1, 64), cdiv(n - 1, 4), cdiv(n - 1, kDemoteZ));
+        hipLaunchKernelGGL(k_residual_demote3_z, grd, blk, 0, s, u, b, r, g);
+    }
 }
 void launch_add_promote(const Grid& g, double* u, const float* e, hipStream_t s) {
     const int n = g.n;
