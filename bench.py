@@ -655,6 +655,35 @@ def rocpd_pmc(fetch_db, write_db, copy_fetch_db, copy_write_db):
     print("\n".join(lines))
 
 
+def rocpd_counters(db):
+    """Per-dispatch means of every counter of a rocprofv3 --pmc database (one or more
+    counters per pass), for the kernels of PMC_KERNELS and the 3D residual-restriction and
+    form-u kernels, over each kernel's dispatches with its largest grid."""
+    import collections
+    import sqlite3
+    c = sqlite3.connect(db)
+    want = set(PMC_KERNELS) | {"k_resid_restrict<3, double>", "k_form_u<3>"}
+    st = collections.defaultdict(lambda: collections.defaultdict(list))
+    durs = collections.defaultdict(dict)
+    for name, cn, gs, val, disp, dur in c.execute(
+            "select kernel_name, counter_name, grid_size, value, dispatch_id, duration from counters_collection"):
+        k = short_name(name)
+        if k in want:
+            st[k][cn].append((gs, val))
+            durs[k][disp] = (gs, dur)
+    names = sorted({cn for d in st.values() for cn in d})
+    print("| kernel | grid | dispatches | duration us | " + " | ".join(names) + " |")
+    print("|---|---:|---:|---:|" + "---:|" * len(names))
+    for k in sorted(st):
+        g = max(x[0] for v in st[k].values() for x in v)
+        ds = [d for gs, d in durs[k].values() if gs == g]
+        cells = []
+        for cn in names:
+            vals = [x[1] for x in st[k].get(cn, []) if x[0] == g]
+            cells.append(f"{sum(vals) / len(vals):,.0f}" if vals else "")
+        print(f"| `{k}` | {g} | {len(ds)} | {sum(ds) / len(ds) / 1e3:.1f} | " + " | ".join(cells) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -668,6 +697,8 @@ def main():
     ap.add_argument("--rocpd-stats", metavar="DB", help="print the kernel summary of a rocprofv3 database and exit")
     ap.add_argument("--rocpd-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="print the scaled FETCH/WRITE traffic of the 3D kernels from four --pmc databases")
+    ap.add_argument("--rocpd-counters", metavar="DB",
+                    help="print per-kernel means of every counter of a rocprofv3 --pmc database")
     ap.add_argument("--workload", choices=["fmg3d", "fmg2d", "batch", "serve", "omega", "paper"], default="fmg3d",
                     help="fmg3d: the default line (3D 256^3); fmg2d: 2D n = 2048; batch / serve: the batched "
                          "and serving workloads")
@@ -680,6 +711,9 @@ def main():
         return
     if args.rocpd_pmc:
         rocpd_pmc(*args.rocpd_pmc)
+        return
+    if args.rocpd_counters:
+        rocpd_counters(args.rocpd_counters)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: independent instances shard across GPUs with no communication, "
