@@ -149,6 +149,29 @@ def test_result_reports_residual_and_contraction():
     assert fixed.residual > res.residual
 
 
+@pytest.mark.parametrize("prob", [W.Problem(3, 2, 2, (1.0, 0.5, 2.0), 0.3, 10.0),
+                                  W.Problem(3, 3, 2, (1.0, 1.0, 1.0), 0.0, 30.0)])
+def test_3d_result_forms_match_oracle_operators(prob):
+    """The norm, Rayleigh quotient and relative nodal residual a 3D solve reports (the
+    row-based forms pass over the final u; n = 8 and a ragged n = 12) against the oracle's
+    operators applied to the returned u: b(u,u) = u^T M u, (a(u,u) + zeta int u^4) / b(u,u)
+    with a = K + M_W, and |K u - (lambda M u - M_W u - zeta N(u))| / |lambda M u|."""
+    res, u = _solve(prob, W.Options(tol_lambda=1e-9))
+    assert res.status == 0
+    h = oracle_hierarchy(prob)
+    l = h.L - 1
+    x = u.cpu().numpy()
+    a_uu, b_uu, q4 = h.energy_terms(l, x)
+    assert res.norm == pytest.approx(b_uu, rel=1e-12)
+    assert res.lambda_rq == pytest.approx((a_uu + prob.zeta * q4) / b_uu, rel=1e-12)
+    r = h.K[l] @ x - h.rhs(l, res.lam, x)
+    lm = res.lam * (h.M[l] @ x)
+    want = math.sqrt(float(r @ r) / float(lm @ lm))
+    # the residual is a difference of terms about 1e8 times larger: rounding of either
+    # side moves it by about 1e-16 / 1e-8 relative
+    assert res.residual == pytest.approx(want, rel=1e-5)
+
+
 def test_host_output_and_library_allocated_workspace_match_device_solve():
     from paper_1502_04657_amd import Solver, solve_alloc
     prob = _problem(GOLD["small_3d"])
