@@ -263,9 +263,12 @@ __device__ inline void interior_ijk(int n, int D, int64_t t, int& i, int& j, int
     k = (D == 3) ? (int)kk + 1 : 0;
 }
 
+// The per-node terms (M u)_i, (M_W u)_i, (N(u) u)_i and (K u)_i of a 2D level array (the 3D
+// terms come from row segments: rhs3_node).
 template <int D>
 __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, const Phys& ph, int i, int j, int k,
                                   double& Mu, double& MWu, double& Nu, double& Ku) {
+    static_assert(D == 2, "3D levels use the row kernels");
     const int64_t P = g.pitch, S = g.plane;
     const int64_t p = i + P * j + S * k;
     const double h = g.h;
@@ -313,27 +316,6 @@ __device__ inline void node_forms(const double* __restrict__ u, const Grid& g, c
         Nu = nl * (h * h / 120.0);
         const Stencil<double> ks = stencil_of<double>(g);
         Ku = kdiff(ks, u0, nsum2(ks, u[p - 1], u[p + 1], u[p - P], u[p + P]));
-    } else {
-        // h_k(u0, a, b, c) = sum_j u0^j h_{k-j}(a, b, c), so the element term is
-        // H3 + 2 u0 H2 + 3 u0^2 H1 + 4 u0^3 with H_k = h_k(a, b, c) of the element's other
-        // vertices; with the elementary symmetric e1, e2, e3 of (a, b, c): H1 = e1,
-        // H2 = e1^2 - e2, H3 = e1 (e1^2 - 2 e2) + e3.  The H_k are summed over the star first.
-        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-#pragma unroll
-        for (int e = 0; e < kStarElems3D; ++e) {
-            const double a = u[p + kStarElem3D[e][0][0] + P * kStarElem3D[e][0][1] + S * kStarElem3D[e][0][2]];
-            const double b = u[p + kStarElem3D[e][1][0] + P * kStarElem3D[e][1][1] + S * kStarElem3D[e][1][2]];
-            const double c = u[p + kStarElem3D[e][2][0] + P * kStarElem3D[e][2][1] + S * kStarElem3D[e][2][2]];
-            const double ab = a * b, apb = a + b;
-            const double e1 = apb + c, e2 = c * apb + ab, e3 = ab * c, e11 = e1 * e1;
-            t1 += e1;
-            t2 += e11 - e2;
-            t3 += e1 * (e11 - 2.0 * e2) + e3;
-        }
-        nl = t3 + u0 * (2.0 * t2 + u0 * (3.0 * t1 + (4.0 * kStarElems3D) * u0));
-        Nu = nl * (h * h * h / 840.0);
-        const Stencil<double> ks = stencil_of<double>(g);
-        Ku = h * kdiff(ks, u0, nsum3(ks, u[p - 1], u[p + 1], u[p - P], u[p + P], u[p - S], u[p + S]));
     }
 }
 
@@ -354,8 +336,9 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ u, doubl
 // The 3D right-hand side with kRhsNX consecutive nodes along x per thread.  The 15-point
 // star of a node spans seven grid rows (dy, dz); a thread loads the segments of those rows
 // covering its nodes and their x-neighbours once (7 (kRhsNX + 2) values instead of 15 per
-// node) and evaluates each node from registers, with the arithmetic of node_forms in the
-// same order.
+// node) and evaluates each node from registers (rhs3_node): the mass moments over the sums
+// and differences of opposite neighbours, the nonlinear term from the star's vertices,
+// edges and triangles.
 constexpr int kRhsNX = 4;
 static constexpr int kRhsRows3D[7][2] = {{0, 0}, {-1, 0}, {0, -1}, {1, 0}, {0, 1}, {-1, -1}, {1, 1}};
 __host__ __device__ constexpr int rhs_row3(int dy, int dz) {
@@ -757,8 +740,9 @@ void launch_form_u(const Grid& gf, const Grid& gc, double* u, const double* xc_l
 }
 
 // ------------------------------------------------------------------------------------------
-// Rayleigh-quotient pieces: (u^T K u, u^T M_W u, u^T M u, int u^4 = u^T N(u)), block sums
-// in a fixed grid, then one block adds the partials in index order (deterministic).  With
+// Rayleigh-quotient pieces of a 2D level (3D: k_forms3_rows): (u^T K u, u^T M_W u, u^T M u,
+// int u^4 = u^T N(u)), block sums in a fixed grid, then one block adds the partials in index
+// order (deterministic).  With
 // lam set, two more sums: |r|^2 and |lam M u|^2 of the nodal residual of the discrete
 // problem (2.4), r = K u + M_W u + zeta N(u) - lam M u.
 template <int D, int NQ>
